@@ -1,0 +1,202 @@
+/*
+ * stdg: space-time hp-DG residual of the time-dependent Maxwell equations on
+ * one AMD MI355X (gfx950).  C ABI.
+ *
+ * Method: Lilienthal, Schnepp, Weiland, "Non-dissipative space-time
+ * hp-discontinuous Galerkin method for the time-dependent Maxwell equations"
+ * (arXiv 1307.5310).  The problem is eq. (maxwell) of Section 1 with PEC walls
+ * (n x E = 0, g = 0); one time slab I_n = (t_{n-1}, t_n] at a time (Section 2.2)
+ * with one temporal element per slab; local spaces of eq. (spaces:local):
+ * trial P_q (time) x [Q_p]^3, test P_{q-1} x [Q_p]^3; covariant element maps
+ * (Section 2.3); the slab form B_h = C_h + S_h of Section 2.5 / 4.1 with
+ * centred fluxes; the residual R_h(V) = B_h(U_h, V) - L(V) of Section 5
+ * (eq. residual); the bases of Section 5.1.
+ *
+ * Conventions used by every call
+ * ------------------------------
+ * Status: every function returns 0 (STDG_OK) or a negative stdg_status; the
+ * message of the last failure on the calling thread is stdg_last_error().
+ * No exception crosses this ABI.
+ *
+ * Element vertex order: local vertex v = b0 + 2 b1 + 4 b2 sits at reference
+ * corner (b0, b1, b2) of [0,1]^3 (x-hat fastest).  Local face 2*alpha + side
+ * lies on x-hat_alpha = side.
+ *
+ * Coefficient layouts (element-major in mesh order, FP32 or FP64):
+ *   a = p + 1, s = j + a*(k + a*l) with (j, k, l) the Legendre degrees in
+ *   (x-hat, y-hat, z-hat); field 0 = E, 1 = H; comp 0..2 = reference
+ *   component c of the covariant pull-back E-hat = DF^T E o F.
+ *   full trial U : per element [field][comp][m = 0..q][s], 6(q+1)a^3 scalars,
+ *                  m the integrated-Legendre time level l_m (eq. def:ilegendre)
+ *   unknowns x   : per element [field][comp][m = 1..q][s], 6 q a^3 scalars
+ *   residual y   : per element [field][comp][i = 0..q-1][s], 6 q a^3 scalars,
+ *                  i the orthonormal-Legendre test level L_i
+ *   state        : per element [field][comp][s], 6 a^3 scalars (fields at one
+ *                  time; the l_0 block of a slab is the state at its start and
+ *                  the l_1 block the state at its end)
+ * Element offsets are prefix sums of these sizes (stdg_mesh_offsets).
+ *
+ * Ownership: the library owns contexts, meshes and servers and their device
+ * tables; the caller frees them with the matching call.  Host arrays passed
+ * in are copied during the call.  Device vectors passed in are caller-owned
+ * and must stay alive until the stream work that uses them has finished.
+ *
+ * Streams: `stream` arguments are hipStream_t values (NULL = the null
+ * stream).  Calls taking a stream are asynchronous unless stated otherwise.
+ */
+#ifndef STDG_H
+#define STDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STDG_OK = 0,
+  STDG_E_ARG = -1,           /* invalid argument (null, size, range)           */
+  STDG_E_UNSUPPORTED = -2,   /* valid but not implemented (e.g. face orientation) */
+  STDG_E_NOMEM = -3,         /* device or host allocation failed                */
+  STDG_E_DEVICE = -4,        /* HIP runtime error or missing GPU                */
+  STDG_E_NOT_CONVERGED = -5, /* solver hit its iteration limit (info is filled) */
+  STDG_E_NOT_READY = -6,     /* serving ticket not finished yet                 */
+  STDG_E_CAPACITY = -7       /* request larger than the HBM budget              */
+} stdg_status;
+
+typedef enum { STDG_FP64 = 0, STDG_FP32 = 1 } stdg_prec;
+
+/* Residual evaluation modes (Section 5, eq. residual; Section 5.4, eq. preconditioner). */
+typedef enum {
+  STDG_OPERATOR = 0,         /* y = B_h x : x = unknowns (m >= 1), l_0 block taken as 0, no load   */
+  STDG_RESIDUAL = 1,         /* y = B_h U - L : U = full trial incl. the l_0 block; L may be NULL  */
+  STDG_OPERATOR_PRECOND = 2  /* y = B_h P^{-1} x with P the time-derivative terms (eq. preconditioner) */
+} stdg_mode;
+
+typedef struct stdg_ctx stdg_ctx;
+typedef struct stdg_mesh stdg_mesh;
+typedef struct stdg_server stdg_server;
+
+/* Library version, (major << 16) | minor. */
+int stdg_version(void);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char* stdg_last_error(void);
+
+/* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the
+ * device memory the context's meshes, solvers and servers may allocate
+ * (0 = 90% of the device's free memory).  Fails with STDG_E_DEVICE when no
+ * GPU is present. */
+int stdg_init(int hip_device, size_t hbm_budget_bytes, stdg_ctx** out);
+int stdg_finalize(stdg_ctx* ctx);
+
+/* Mesh and discretisation (Section 2.2-2.3; degrees of eq. spaces:local;
+ * elementwise constant eps, mu as in Thm 3.1).  Host arrays, copied. */
+typedef struct {
+  int64_t n_vertices;
+  const double* vertices;   /* [n_vertices][3]                                     */
+  int64_t n_elements;
+  const int64_t* hexes;     /* [n_elements][8] vertex ids, order above            */
+  const int32_t* p;         /* [n_elements] spatial degree, 1 <= p <= 8           */
+  const int32_t* q;         /* [n_elements] temporal degree, 1 <= q <= 6          */
+  const double* eps;        /* [n_elements] permittivity > 0                      */
+  const double* mu;         /* [n_elements] permeability > 0                      */
+} stdg_mesh_desc;
+
+typedef struct {
+  int64_t n_elements, n_vertices;
+  int64_t n_interior_faces, n_boundary_faces;
+  int64_t trial_size, unknown_size, state_size;  /* scalars in each layout      */
+  int32_t n_groups;          /* (p, q, affine) kernel groups                     */
+  int32_t n_affine, n_nonaffine, n_diagonal_mass;
+  int32_t p_max, q_max;
+  int64_t device_bytes;      /* device memory held by the mesh                  */
+} stdg_mesh_info_t;
+
+/* Build faces and neighbours (matching sorted vertex ids), check that every
+ * interior face is conforming with canonical orientation (neighbour across
+ * face (alpha, side) touches it with its face (alpha, 1 - side) and the same
+ * vertex order; else STDG_E_UNSUPPORTED), classify elements as affine
+ * (parallelepiped) or trilinear, group them by (p, q, affine), compute offsets
+ * and copy everything to the device.  Faces on exactly one element are PEC
+ * boundary faces. */
+int stdg_mesh_upload(stdg_ctx* ctx, const stdg_mesh_desc* desc, stdg_mesh** out);
+int stdg_mesh_info(const stdg_mesh* mesh, stdg_mesh_info_t* out);
+/* Host copies of the element offsets (n_elements + 1 entries each, any may be NULL). */
+int stdg_mesh_offsets(const stdg_mesh* mesh, int64_t* trial_off, int64_t* unknown_off,
+                      int64_t* state_off);
+int stdg_mesh_free(stdg_mesh* mesh);
+
+/* The hot path: the matrix-free space-time residual of one slab (Section 5,
+ * eq. residual; evaluation of Section 5.2: mass, curl and flux terms).
+ *   dt    slab length (> 0)
+ *   prec  STDG_FP64 (double vectors) or STDG_FP32 (float vectors, FP32 accumulation)
+ *   mode  stdg_mode above; x_dev layout = unknowns (OPERATOR*) or full trial (RESIDUAL)
+ *   load_dev  residual-layout load vector L (RESIDUAL mode only; NULL = 0)
+ *   y_dev residual layout, overwritten.  x_dev and y_dev must not overlap.
+ * Device pointers; asynchronous on `stream`. */
+int stdg_residual_apply(const stdg_mesh* mesh, double dt, int prec, int mode,
+                        const void* x_dev, const void* load_dev, void* y_dev, void* stream);
+
+/* Current density of the load L(V) = (J, v) (eq. bilinearform:C):
+ * kind 0 = none; kind 1 = J(x,t) = dir * amp * exp(-|x - center|^2 / (2 sigma_x^2))
+ *                          * sin(2 pi f0 (t - t0)) * exp(-(t - t0)^2 / (2 sigma_t^2)). */
+typedef struct {
+  int32_t kind;
+  double amp;
+  double center[3];
+  double sigma_x, f0, t0, sigma_t;
+  double dir[3];
+} stdg_source;
+
+/* L_E[c,i,s] = int_{I_n} int_K J . (DF^{-T} e_c phi_s) L_i dx dt by tensor Gauss
+ * quadrature (p + 3 points per space direction, q + 3 in time); L_H = 0 (g = 0).
+ * Writes the residual-layout FP64 vector load_dev for the slab (t0, t0 + dt]. */
+int stdg_load_assemble(const stdg_mesh* mesh, const stdg_source* src, double t0, double dt,
+                       double* load_dev, void* stream);
+
+/* Cavity-mode superposition initial field on the unit cube,
+ * E = sum_r (A_r cos(m pi x) sin(n pi y) sin(l pi z), B_r sin cos sin, C_r sin sin cos), H = 0,
+ * L2-projected onto the covariant discrete space: state_dev (FP64 state layout).
+ * Affine elements only. */
+int stdg_project_modes(const stdg_mesh* mesh, int32_t n_modes, const int32_t* mnl,
+                       const double* abc, double* state_dev, void* stream);
+
+/* Slab solve (Section 3 eq. weakform / Section 4 eq. weakform_stabilized) by
+ * right-preconditioned restarted GMRES (Section 5.4, eq. preconditioner). */
+typedef struct {
+  int32_t inner_prec;  /* STDG_FP64: plain FP64 GMRES; STDG_FP32: FP32 operator inside
+                          FP64 iterative refinement                              */
+  int32_t restart;     /* GMRES restart length (default 10)                      */
+  int32_t max_iters;   /* total inner iterations allowed (default 500)           */
+  int32_t max_refine;  /* outer refinement sweeps (FP32 inner only; default 10)  */
+  double rtol;         /* stop when ||L - B U||_2 <= rtol ||L - B U_0||_2 (FP64)  */
+  double inner_rtol;   /* relative tolerance of each inner GMRES (FP32 inner)    */
+} stdg_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* inner GMRES iterations (operator applications)        */
+  int32_t refinements;  /* outer FP64 residual evaluations                      */
+  double rel_res;       /* final ||L - B U|| / ||L - B U_0|| in FP64             */
+  double energy_start;  /* discrete energy (eq. stability:energydef) at t0      */
+  double energy_end;    /* ... at t0 + dt                                       */
+} stdg_solve_info;
+
+/* state_dev (FP64 state layout) holds the fields at t0 on entry and at t0 + dt
+ * on return (the l_1 block, i.e. continuity in time between slabs).
+ * load_dev: residual-layout FP64 load of this slab, or NULL (J = 0).
+ * slab_U_dev: optional FP64 full-trial output of the slab solution (NULL = none).
+ * Synchronises `stream`.  STDG_E_NOT_CONVERGED still fills *info and state. */
+int stdg_slab_solve(const stdg_mesh* mesh, double t0, double dt, const double* load_dev,
+                    const stdg_solve_opts* opts, double* state_dev, double* slab_U_dev,
+                    stdg_solve_info* info, void* stream);
+
+/* Discrete energy 1/2 int (eps E.E + mu H.H) of an FP64 state (eq. stability:energydef). */
+int stdg_energy(const stdg_mesh* mesh, const double* state_dev, double* energy_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STDG_H */

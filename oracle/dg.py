@@ -365,11 +365,13 @@ class Discretisation:
         return self.residual(self.embed_unknowns(x), dt, None, elements)
 
     # -- preconditioner (Section 5.4, eq. preconditioner) -----------------------
-    def precond_solve(self, y):
+    def precond_solve(self, y, elements=None):
         """P^{-1} y with P the time-derivative terms restricted to the unknowns:
-        block diagonal D (identity on m >= 1) kron the element mass matrix."""
+        block diagonal D (identity on m >= 1) kron the element mass matrix.
+        With ``elements`` only those blocks are computed (others left 0)."""
         out = np.zeros_like(y)
-        for e in range(self.ne):
+        for e in (range(self.ne) if elements is None else elements):
+            e = int(e)
             a3 = int(self.a[e]) ** 3
             qe = int(self.q[e])
             blk = y[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, qe, a3)

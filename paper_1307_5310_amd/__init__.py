@@ -1,0 +1,117 @@
+"""stdg: MI355X-native space-time hp-DG residual for the time-dependent Maxwell
+equations (Lilienthal, Schnepp, Weiland, arXiv 1307.5310).
+
+Thin Python binding of the C ABI in include/stdg.h: the functions below have
+the same names as the C entry points and only marshal arguments (numpy host
+arrays, torch device tensors, torch streams).  See the header for layouts,
+ownership and error behaviour.
+"""
+import ctypes
+
+import numpy as np
+
+from ._lib import (StdgError, STDG_FP32, STDG_FP64, STDG_OPERATOR, STDG_RESIDUAL,
+                   STDG_OPERATOR_PRECOND, MeshDesc, MeshInfo, Source, SolveOpts, SolveInfo,
+                   lib, check, ptr, stream_handle, exported_symbols)
+
+__all__ = ["StdgError", "STDG_FP32", "STDG_FP64", "STDG_OPERATOR", "STDG_RESIDUAL",
+           "STDG_OPERATOR_PRECOND", "stdg_version", "stdg_init", "stdg_finalize",
+           "stdg_mesh_upload", "stdg_mesh_info", "stdg_mesh_offsets", "stdg_mesh_free",
+           "stdg_residual_apply", "stdg_load_assemble", "stdg_project_modes",
+           "stdg_slab_solve", "stdg_energy", "exported_symbols"]
+
+
+def stdg_version():
+    return lib().stdg_version()
+
+
+def stdg_init(device=0, hbm_budget_bytes=0):
+    h = ctypes.c_void_p()
+    check(lib().stdg_init(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
+    return h
+
+
+def stdg_finalize(ctx):
+    check(lib().stdg_finalize(ctx))
+
+
+def stdg_mesh_upload(ctx, vertices, hexes, p, q, eps, mu):
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    h = np.ascontiguousarray(hexes, dtype=np.int64)
+    p = np.ascontiguousarray(p, dtype=np.int32)
+    q = np.ascontiguousarray(q, dtype=np.int32)
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    d = MeshDesc(v.shape[0], v.ctypes.data, h.shape[0], h.ctypes.data, p.ctypes.data,
+                 q.ctypes.data, eps.ctypes.data, mu.ctypes.data)
+    out = ctypes.c_void_p()
+    check(lib().stdg_mesh_upload(ctx, ctypes.byref(d), ctypes.byref(out)))
+    return out
+
+
+def stdg_mesh_info(mesh):
+    info = MeshInfo()
+    check(lib().stdg_mesh_info(mesh, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in MeshInfo._fields_}
+
+
+def stdg_mesh_offsets(mesh):
+    n = stdg_mesh_info(mesh)["n_elements"] + 1
+    t, u, s = (np.zeros(n, dtype=np.int64) for _ in range(3))
+    check(lib().stdg_mesh_offsets(mesh, t.ctypes.data, u.ctypes.data, s.ctypes.data))
+    return t, u, s
+
+
+def stdg_mesh_free(mesh):
+    check(lib().stdg_mesh_free(mesh))
+
+
+def stdg_residual_apply(mesh, dt, prec, mode, x, load, y, stream=None):
+    check(lib().stdg_residual_apply(mesh, float(dt), int(prec), int(mode), ptr(x), ptr(load),
+                                    ptr(y), stream_handle(stream)))
+
+
+def _source(src):
+    s = Source()
+    if src is None:
+        s.kind = 0
+        return s
+    s.kind = int(src.kind)
+    s.amp = float(src.amp)
+    s.center[:] = [float(c) for c in src.center]
+    s.sigma_x, s.f0, s.t0, s.sigma_t = float(src.sigma_x), float(src.f0), float(src.t0), float(src.sigma_t)
+    s.dir[:] = [float(c) for c in src.dir]
+    return s
+
+
+def stdg_load_assemble(mesh, src, t0, dt, load, stream=None):
+    s = _source(src)
+    check(lib().stdg_load_assemble(mesh, ctypes.byref(s), float(t0), float(dt), ptr(load),
+                                   stream_handle(stream)))
+
+
+def stdg_project_modes(mesh, mnl, abc, state, stream=None):
+    mnl = np.ascontiguousarray(mnl, dtype=np.int32).reshape(-1, 3)
+    abc = np.ascontiguousarray(abc, dtype=np.float64).reshape(-1, 3)
+    check(lib().stdg_project_modes(mesh, mnl.shape[0], mnl.ctypes.data, abc.ctypes.data,
+                                   ptr(state), stream_handle(stream)))
+
+
+def stdg_slab_solve(mesh, t0, dt, load, state, inner_prec=STDG_FP64, restart=10, max_iters=500,
+                    max_refine=10, rtol=1e-12, inner_rtol=1e-4, slab_U=None, stream=None):
+    o = SolveOpts(int(inner_prec), int(restart), int(max_iters), int(max_refine), float(rtol),
+                  float(inner_rtol))
+    info = SolveInfo()
+    st = lib().stdg_slab_solve(mesh, float(t0), float(dt), ptr(load), ctypes.byref(o), ptr(state),
+                               ptr(slab_U), ctypes.byref(info), stream_handle(stream))
+    res = {name: getattr(info, name) for name, _ in SolveInfo._fields_}
+    res["status"] = st
+    if st not in (0, -5):
+        check(st)
+    return res
+
+
+def stdg_energy(mesh, state, stream=None):
+    out = ctypes.c_double()
+    check(lib().stdg_energy(mesh, ptr(state), ctypes.byref(out), stream_handle(stream)))
+    return out.value

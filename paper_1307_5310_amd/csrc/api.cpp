@@ -1,0 +1,166 @@
+// C-ABI entry points: contexts, errors, meshes, and the residual apply.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace stdg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int status, const std::string& msg) {
+  set_error(msg);
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error(std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ") in " + what);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return STDG_E_NOMEM;
+  return STDG_E_DEVICE;
+}
+
+int dev_alloc(Ctx* ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (ctx->used + bytes > ctx->budget)
+    return fail(STDG_E_CAPACITY, "allocation of " + std::to_string(bytes) + " bytes exceeds the HBM budget (" +
+                                     std::to_string(ctx->used) + " of " + std::to_string(ctx->budget) + " used)");
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_fail(e, "hipMalloc");
+  }
+  ctx->used += bytes;
+  return STDG_OK;
+}
+
+void dev_free(Ctx* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  if (bytes == 0) bytes = 256;
+  (void)hipFree(p);
+  ctx->used = ctx->used >= bytes ? ctx->used - bytes : 0;
+}
+
+int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m);
+void release_mesh(Mesh* m);
+
+}  // namespace stdg
+
+using namespace stdg;
+
+extern "C" {
+
+int stdg_version(void) { return (1 << 16) | 0; }
+
+const char* stdg_last_error(void) { return g_last_error.c_str(); }
+
+int stdg_init(int hip_device, size_t hbm_budget_bytes, stdg_ctx** out) {
+  if (!out) return fail(STDG_E_ARG, "stdg_init: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) return fail(STDG_E_DEVICE, "stdg_init: no HIP device available");
+  if (hip_device < 0 || hip_device >= n) return fail(STDG_E_ARG, "stdg_init: device index out of range");
+  STDG_HIP(hipSetDevice(hip_device));
+  hipDeviceProp_t prop;
+  STDG_HIP(hipGetDeviceProperties(&prop, hip_device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(STDG_E_DEVICE, std::string("stdg_init: built for gfx950, device is ") + prop.gcnArchName);
+  size_t free_b = 0, total_b = 0;
+  STDG_HIP(hipMemGetInfo(&free_b, &total_b));
+  stdg_ctx* c = new (std::nothrow) stdg_ctx;
+  if (!c) return fail(STDG_E_NOMEM, "stdg_init: host allocation failed");
+  c->c.device = hip_device;
+  c->c.budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+  c->c.used = 0;
+  *out = c;
+  return STDG_OK;
+}
+
+int stdg_finalize(stdg_ctx* ctx) {
+  if (!ctx) return fail(STDG_E_ARG, "stdg_finalize: ctx is NULL");
+  delete ctx;
+  return STDG_OK;
+}
+
+int stdg_mesh_upload(stdg_ctx* ctx, const stdg_mesh_desc* desc, stdg_mesh** out) {
+  if (!ctx || !desc || !out) return fail(STDG_E_ARG, "stdg_mesh_upload: NULL argument");
+  *out = nullptr;
+  if (desc->n_elements <= 0 || desc->n_vertices <= 0 || !desc->vertices || !desc->hexes || !desc->p ||
+      !desc->q || !desc->eps || !desc->mu)
+    return fail(STDG_E_ARG, "stdg_mesh_upload: empty mesh or NULL array");
+  if (desc->n_elements > (int64_t)INT32_MAX) return fail(STDG_E_ARG, "stdg_mesh_upload: too many elements");
+  STDG_HIP(hipSetDevice(ctx->c.device));
+  stdg_mesh* m = new (std::nothrow) stdg_mesh;
+  if (!m) return fail(STDG_E_NOMEM, "stdg_mesh_upload: host allocation failed");
+  int rc;
+  try {
+    rc = build_mesh(&ctx->c, desc, &m->m);
+  } catch (const std::bad_alloc&) {
+    rc = fail(STDG_E_NOMEM, "stdg_mesh_upload: host allocation failed");
+  }
+  if (rc != STDG_OK) {
+    release_mesh(&m->m);
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return STDG_OK;
+}
+
+int stdg_mesh_info(const stdg_mesh* mesh, stdg_mesh_info_t* out) {
+  if (!mesh || !out) return fail(STDG_E_ARG, "stdg_mesh_info: NULL argument");
+  const Mesh& m = mesh->m;
+  std::memset(out, 0, sizeof(*out));
+  out->n_elements = m.ne;
+  out->n_vertices = m.nv;
+  out->n_interior_faces = m.n_int_faces;
+  out->n_boundary_faces = m.n_bnd_faces;
+  out->trial_size = m.trial_off.back();
+  out->unknown_size = m.unk_off.back();
+  out->state_size = m.state_off.back();
+  out->n_groups = (int32_t)m.groups.size();
+  out->n_affine = m.n_affine;
+  out->n_nonaffine = m.n_nonaffine;
+  out->n_diagonal_mass = m.n_diag;
+  out->p_max = m.p_max;
+  out->q_max = m.q_max;
+  out->device_bytes = (int64_t)m.device_bytes;
+  return STDG_OK;
+}
+
+int stdg_mesh_offsets(const stdg_mesh* mesh, int64_t* trial_off, int64_t* unknown_off, int64_t* state_off) {
+  if (!mesh) return fail(STDG_E_ARG, "stdg_mesh_offsets: mesh is NULL");
+  const Mesh& m = mesh->m;
+  size_t n = sizeof(int64_t) * (m.ne + 1);
+  if (trial_off) std::memcpy(trial_off, m.trial_off.data(), n);
+  if (unknown_off) std::memcpy(unknown_off, m.unk_off.data(), n);
+  if (state_off) std::memcpy(state_off, m.state_off.data(), n);
+  return STDG_OK;
+}
+
+int stdg_mesh_free(stdg_mesh* mesh) {
+  if (!mesh) return fail(STDG_E_ARG, "stdg_mesh_free: mesh is NULL");
+  release_mesh(&mesh->m);
+  delete mesh;
+  return STDG_OK;
+}
+
+int stdg_residual_apply(const stdg_mesh* mesh, double dt, int prec, int mode, const void* x_dev,
+                        const void* load_dev, void* y_dev, void* stream) {
+  if (!mesh) return fail(STDG_E_ARG, "stdg_residual_apply: mesh is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(STDG_E_ARG, "stdg_residual_apply: dt must be finite and > 0");
+  if (prec != STDG_FP64 && prec != STDG_FP32) return fail(STDG_E_ARG, "stdg_residual_apply: unknown precision");
+  if (mode != STDG_OPERATOR && mode != STDG_RESIDUAL && mode != STDG_OPERATOR_PRECOND)
+    return fail(STDG_E_ARG, "stdg_residual_apply: unknown mode");
+  if (!x_dev || !y_dev) return fail(STDG_E_ARG, "stdg_residual_apply: x or y is NULL");
+  if (load_dev && mode != STDG_RESIDUAL) return fail(STDG_E_ARG, "stdg_residual_apply: load only in RESIDUAL mode");
+  if (x_dev == y_dev) return fail(STDG_E_ARG, "stdg_residual_apply: x and y must not alias");
+  ApplyArgs a{&mesh->m, dt, prec, mode, x_dev, load_dev, y_dev, (hipStream_t)stream};
+  return launch_residual(a);
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/stdg.h"
+
+namespace stdg {
+
+constexpr int kMaxA = 9;   // p <= 8
+constexpr int kMaxQ = 6;
+
+// Thread-local error reporting.
+void set_error(const std::string& msg);
+int fail(int status, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define STDG_HIP(call)                                         \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return ::stdg::hip_fail(e_, #call);  \
+  } while (0)
+
+// Element flags.
+enum : int32_t {
+  kAffine = 1,        // parallelepiped: constant metric
+  kDiagMass = 2,      // metric diagonal (axis-aligned box)
+  kBoundaryBase = 8,  // bit 3 + f: face f is a PEC boundary face
+};
+
+// Per-element record read by the kernels (64 bytes).
+struct ElemInfo {
+  int32_t a, q, flags, pad;
+  int64_t trial_off, unk_off;
+  int32_t nb[6];
+  int32_t pad2[2];
+};
+static_assert(sizeof(ElemInfo) == 64, "ElemInfo layout");
+
+// Per-element metric coefficients, FP64: symmetric 3x3 as xx, yy, zz, xy, xz, yz.
+//   m[0..5]  = eps |J| DF^{-1} DF^{-T}      (mass of E, constant part)
+//   m[6..11] = mu  |J| DF^{-1} DF^{-T}
+//   m[12..17], m[18..23] = inverses of the two (preconditioner)
+// For trilinear elements these are taken at the element centre (used by the
+// preconditioner only); the exact mass uses the vertices.
+struct ElemMetric {
+  double m[24];
+};
+
+// 1D tables passed by value to kernels (kernel-argument segment).
+template <typename T>
+struct Tables {
+  T N[kMaxQ][kMaxQ + 1];   // N[i][m] = int_0^1 L_i l_m
+  T Dh[kMaxA][kMaxA];      // Dh[n][j] = int_0^1 L_n L_j'
+  T tr0[kMaxA], tr1[kMaxA];// L_j(0), L_j(1)
+};
+
+void fill_tables_f64(Tables<double>* t);
+void fill_tables_f32(Tables<float>* t);
+
+// Kernel work group of elements with the same (a, q, affine).
+struct Group {
+  int a, q, affine;
+  int64_t count;
+  int32_t* d_list;  // element ids, locality order
+};
+
+struct Ctx {
+  int device;
+  size_t budget;
+  size_t used;
+};
+
+struct Mesh {
+  Ctx* ctx;
+  int64_t ne, nv;
+  int64_t n_int_faces, n_bnd_faces;
+  std::vector<int32_t> p, q;
+  std::vector<int64_t> trial_off, unk_off, state_off;
+  std::vector<ElemInfo> info;
+  std::vector<ElemMetric> metric;
+  std::vector<double> verts;   // [ne][8][3] element vertex coordinates
+  std::vector<Group> groups;
+  int n_affine, n_nonaffine, n_diag;
+  int p_max, q_max;
+  // device copies
+  ElemInfo* d_info = nullptr;
+  ElemMetric* d_metric = nullptr;
+  double* d_verts = nullptr;
+  size_t device_bytes = 0;
+  int64_t* d_state_off = nullptr;
+  // scratch for preconditioned applies on non-diagonal meshes (lazily sized)
+  void* d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+};
+
+// Kernel launchers (residual.hip).
+struct ApplyArgs {
+  const Mesh* mesh;
+  double dt;
+  int prec;
+  int mode;
+  const void* x;
+  const void* load;
+  void* y;
+  hipStream_t stream;
+};
+int launch_residual(const ApplyArgs& a);
+int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s);
+
+// Allocation against the context budget.
+int dev_alloc(Ctx* ctx, void** p, size_t bytes);
+void dev_free(Ctx* ctx, void* p, size_t bytes);
+
+}  // namespace stdg
+
+struct stdg_ctx { stdg::Ctx c; };
+struct stdg_mesh { stdg::Mesh m; };

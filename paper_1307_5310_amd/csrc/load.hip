@@ -1,0 +1,358 @@
+// Once-per-slab kernels around the residual: the load L(V) = (J, v)
+// (eq. bilinearform:C), the L2 projection of cavity-mode initial fields, and
+// the discrete energy 1/2 int (eps E.E + mu H.H) (eq. stability:energydef),
+// all in FP64.
+#include <cmath>
+
+#include "internal.h"
+
+namespace stdg {
+
+namespace {
+
+// n-point Gauss-Legendre rule on [0, 1] (n <= 16) by Newton iteration on P_n.
+__host__ __device__ void gauss01(int n, double* xs, double* ws) {
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double pn = 0.0, pm = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      pn = p1;
+      pm = n == 1 ? 1.0 : p0;
+      double dp = n * (z * pn - pm) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    pn = p1;
+    pm = n == 1 ? 1.0 : p0;
+    double dp = n * (z * pn - pm) / (z * z - 1.0);
+    xs[i] = 0.5 * (1.0 - z);
+    ws[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+struct LoadParams {
+  const ElemInfo* info;
+  const double* verts;
+  double* out;
+  stdg_source src;
+  double t0, dt;
+};
+
+__device__ double leg(int j, double xi) {
+  // orthonormal Legendre on [0,1] by Bonnet's recurrence
+  double u = 2.0 * xi - 1.0, p0 = 1.0, p1 = u;
+  if (j == 0) return 1.0;
+  for (int k = 1; k < j; ++k) {
+    double p2 = ((2.0 * k + 1.0) * u * p1 - k * p0) / (k + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  return sqrt(2.0 * j + 1.0) * p1;
+}
+
+__device__ void trilinear(const double* X, double x, double y, double z, double F[3], double DF[3][3]) {
+  for (int c = 0; c < 3; ++c) {
+    F[c] = 0.0;
+    DF[c][0] = DF[c][1] = DF[c][2] = 0.0;
+  }
+  for (int v = 0; v < 8; ++v) {
+    const int b0 = v & 1, b1 = (v >> 1) & 1, b2 = (v >> 2) & 1;
+    const double fx = b0 ? x : 1.0 - x, fy = b1 ? y : 1.0 - y, fz = b2 ? z : 1.0 - z;
+    const double sx = b0 ? 1.0 : -1.0, sy = b1 ? 1.0 : -1.0, sz = b2 ? 1.0 : -1.0;
+    const double N = fx * fy * fz;
+    const double d0 = sx * fy * fz, d1 = fx * sy * fz, d2 = fx * fy * sz;
+    for (int c = 0; c < 3; ++c) {
+      const double Xc = X[3 * v + c];
+      F[c] += N * Xc;
+      DF[c][0] += d0 * Xc;
+      DF[c][1] += d1 * Xc;
+      DF[c][2] += d2 * Xc;
+    }
+  }
+}
+
+__device__ double inv3(const double A[3][3], double B[3][3]) {
+  double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+               A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  double id = 1.0 / det;
+  B[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) * id;
+  B[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+  B[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+  B[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) * id;
+  B[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+  B[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+  B[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) * id;
+  B[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+  B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+  return det;
+}
+
+__device__ void source_at(const stdg_source& s, const double x[3], double t, double J[3]) {
+  if (s.kind != 1) {
+    J[0] = J[1] = J[2] = 0.0;
+    return;
+  }
+  const double dx = x[0] - s.center[0], dy = x[1] - s.center[1], dz = x[2] - s.center[2];
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double tt = t - s.t0;
+  const double g = s.amp * exp(-r2 / (2.0 * s.sigma_x * s.sigma_x)) * sin(2.0 * M_PI * s.f0 * tt) *
+                   exp(-tt * tt / (2.0 * s.sigma_t * s.sigma_t));
+  J[0] = g * s.dir[0];
+  J[1] = g * s.dir[1];
+  J[2] = g * s.dir[2];
+}
+
+// One block per element; thread per output (c, s): accumulate over the tensor
+// rule the space-time integral against L_i(tau) for all test levels i.
+__global__ void load_kernel(LoadParams P) {
+  const int e = blockIdx.x;
+  const ElemInfo I = P.info[e];
+  const int a = I.a, q = I.q, a3 = a * a * a;
+  __shared__ double rxx[16], rxw[16], rtx[16], rtw[16];
+  const int nx = a + 2, nt = q + 3;
+  if (threadIdx.x == 0) {
+    gauss01(nx, rxx, rxw);
+    gauss01(nt, rtx, rtw);
+  }
+  __syncthreads();
+  const double* X = P.verts + 24 * e;
+  double* out = P.out + I.unk_off;
+  for (int idx = threadIdx.x; idx < 3 * a3; idx += blockDim.x) {
+    const int c = idx / a3, s = idx - c * a3;
+    const int sj = s % a, sk = (s / a) % a, sl = s / (a * a);
+    double acc[kMaxQ];
+    for (int i = 0; i < kMaxQ; ++i) acc[i] = 0.0;
+    for (int gz = 0; gz < nx; ++gz)
+      for (int gy = 0; gy < nx; ++gy)
+        for (int gx = 0; gx < nx; ++gx) {
+          double F[3], DF[3][3], Di[3][3];
+          trilinear(X, rxx[gx], rxx[gy], rxx[gz], F, DF);
+          const double det = inv3(DF, Di);
+          const double phi = leg(sj, rxx[gx]) * leg(sk, rxx[gy]) * leg(sl, rxx[gz]);
+          const double wsp = rxw[gx] * rxw[gy] * rxw[gz] * det * phi;
+          for (int gt = 0; gt < nt; ++gt) {
+            double J[3];
+            source_at(P.src, F, P.t0 + rtx[gt] * P.dt, J);
+            // J . DF^{-T} e_c = (DF^{-1} J)_c
+            const double jc = Di[c][0] * J[0] + Di[c][1] * J[1] + Di[c][2] * J[2];
+            const double base = P.dt * rtw[gt] * wsp * jc;
+            for (int i = 0; i < q; ++i) acc[i] += base * leg(i, rtx[gt]);
+          }
+        }
+    for (int i = 0; i < q; ++i) {
+      out[((int64_t)c * q + i) * a3 + s] = acc[i];          // E part
+      out[((int64_t)(3 + c) * q + i) * a3 + s] = 0.0;       // H part: g = 0
+    }
+  }
+}
+
+struct ProjParams {
+  const ElemInfo* info;
+  const ElemMetric* metric;
+  const int64_t* state_off;
+  const double* verts;
+  double* out;
+  int n_modes;
+  const int32_t* mnl;
+  const double* abc;
+};
+
+__global__ void project_kernel(ProjParams P) {
+  const int e = blockIdx.x;
+  const ElemInfo I = P.info[e];
+  const int a = I.a, a3 = a * a * a;
+  __shared__ double rxx[16], rxw[16];
+  const int nx = a + 3;
+  if (threadIdx.x == 0) gauss01(nx, rxx, rxw);
+  __syncthreads();
+  const double* X = P.verts + 24 * e;
+  double* out = P.out + P.state_off[e];
+  for (int s = threadIdx.x; s < a3; s += blockDim.x) {
+    const int sj = s % a, sk = (s / a) % a, sl = s / (a * a);
+    double b[3] = {0.0, 0.0, 0.0};
+    double G[3][3] = {{0}};
+    for (int gz = 0; gz < nx; ++gz)
+      for (int gy = 0; gy < nx; ++gy)
+        for (int gx = 0; gx < nx; ++gx) {
+          double F[3], DF[3][3], Di[3][3];
+          trilinear(X, rxx[gx], rxx[gy], rxx[gz], F, DF);
+          const double det = inv3(DF, Di);
+          const double phi = leg(sj, rxx[gx]) * leg(sk, rxx[gy]) * leg(sl, rxx[gz]);
+          double E[3] = {0.0, 0.0, 0.0};
+          for (int r = 0; r < P.n_modes; ++r) {
+            const double kx = M_PI * P.mnl[3 * r] * F[0], ky = M_PI * P.mnl[3 * r + 1] * F[1],
+                         kz = M_PI * P.mnl[3 * r + 2] * F[2];
+            E[0] += P.abc[3 * r] * cos(kx) * sin(ky) * sin(kz);
+            E[1] += P.abc[3 * r + 1] * sin(kx) * cos(ky) * sin(kz);
+            E[2] += P.abc[3 * r + 2] * sin(kx) * sin(ky) * cos(kz);
+          }
+          const double w = rxw[gx] * rxw[gy] * rxw[gz] * det;
+          for (int c = 0; c < 3; ++c) b[c] += w * phi * (Di[c][0] * E[0] + Di[c][1] * E[1] + Di[c][2] * E[2]);
+          // unit-coefficient metric |J| DF^{-1} DF^{-T} integrated over the element
+          for (int c = 0; c < 3; ++c)
+            for (int d = 0; d < 3; ++d)
+              G[c][d] += w * (Di[c][0] * Di[d][0] + Di[c][1] * Di[d][1] + Di[c][2] * Di[d][2]);
+        }
+    // affine elements: unit-coefficient mass = G (x) I, so c_s = G^{-1} b_s
+    double Gi[3][3];
+    inv3(G, Gi);
+    for (int c = 0; c < 3; ++c) {
+      out[(int64_t)c * a3 + s] = Gi[c][0] * b[0] + Gi[c][1] * b[1] + Gi[c][2] * b[2];
+      out[(int64_t)(3 + c) * a3 + s] = 0.0;
+    }
+  }
+}
+
+// per-element energy 1/2 (e^T M_eps e + h^T M_mu h) for affine elements
+__global__ void energy_kernel(const ElemInfo* info, const ElemMetric* metric, const int64_t* state_off, int64_t ne,
+                              const double* state, double* partial) {
+  const int64_t e = blockIdx.x;
+  if (e >= ne) return;
+  const ElemInfo I = info[e];
+  const int a3 = I.a * I.a * I.a;
+  const double* m = metric[e].m;
+  const double* st = state + state_off[e];
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int s = threadIdx.x; s < a3; s += blockDim.x) {
+    for (int f = 0; f < 2; ++f) {
+      const double* M = m + 6 * f;
+      const double v0 = st[(3 * f + 0) * a3 + s], v1 = st[(3 * f + 1) * a3 + s], v2 = st[(3 * f + 2) * a3 + s];
+      acc += M[0] * v0 * v0 + M[1] * v1 * v1 + M[2] * v2 * v2 + 2.0 * (M[3] * v0 * v1 + M[4] * v0 * v2 + M[5] * v1 * v2);
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[e] = 0.5 * red[0];
+}
+
+// fixed-order sum of n values by one block (deterministic)
+__global__ void sum_kernel(const double* v, int64_t n, double* out) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += v[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+}  // namespace
+
+int energy_async(const Mesh* m, const double* state, double* d_partial, double* d_out, hipStream_t s) {
+  hipLaunchKernelGGL(energy_kernel, dim3((unsigned)m->ne), dim3(128), 0, s, m->d_info, m->d_metric, m->d_state_off,
+                     m->ne, state, d_partial);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1024), 0, s, d_partial, m->ne, d_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "energy kernels");
+  return STDG_OK;
+}
+
+int ensure_state_off(Mesh* m) {
+  if (m->d_state_off) return STDG_OK;
+  int rc = dev_alloc(m->ctx, (void**)&m->d_state_off, sizeof(int64_t) * (m->ne + 1));
+  if (rc != STDG_OK) return rc;
+  m->device_bytes += sizeof(int64_t) * (m->ne + 1);
+  STDG_HIP(hipMemcpy(m->d_state_off, m->state_off.data(), sizeof(int64_t) * (m->ne + 1), hipMemcpyHostToDevice));
+  return STDG_OK;
+}
+
+}  // namespace stdg
+
+using namespace stdg;
+
+extern "C" {
+
+int stdg_load_assemble(const stdg_mesh* mesh, const stdg_source* src, double t0, double dt, double* load_dev,
+                       void* stream) {
+  if (!mesh || !src || !load_dev) return fail(STDG_E_ARG, "stdg_load_assemble: NULL argument");
+  if (!(dt > 0.0)) return fail(STDG_E_ARG, "stdg_load_assemble: dt must be > 0");
+  if (src->kind != 0 && src->kind != 1) return fail(STDG_E_ARG, "stdg_load_assemble: unknown source kind");
+  if (src->kind == 1 && (!(src->sigma_x > 0.0) || !(src->sigma_t > 0.0)))
+    return fail(STDG_E_ARG, "stdg_load_assemble: sigma_x and sigma_t must be > 0");
+  const Mesh& m = mesh->m;
+  LoadParams P;
+  P.info = m.d_info;
+  P.verts = m.d_verts;
+  P.out = load_dev;
+  P.src = *src;
+  P.t0 = t0;
+  P.dt = dt;
+  hipLaunchKernelGGL(load_kernel, dim3((unsigned)m.ne), dim3(128), 0, (hipStream_t)stream, P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "load kernel");
+  return STDG_OK;
+}
+
+int stdg_project_modes(const stdg_mesh* mesh, int32_t n_modes, const int32_t* mnl, const double* abc,
+                       double* state_dev, void* stream) {
+  if (!mesh || !state_dev || n_modes < 0 || (n_modes > 0 && (!mnl || !abc)))
+    return fail(STDG_E_ARG, "stdg_project_modes: invalid argument");
+  Mesh& m = const_cast<stdg_mesh*>(mesh)->m;
+  if (m.n_nonaffine > 0) return fail(STDG_E_UNSUPPORTED, "stdg_project_modes: affine elements only");
+  int rc = ensure_state_off(&m);
+  if (rc != STDG_OK) return rc;
+  int32_t* d_mnl = nullptr;
+  double* d_abc = nullptr;
+  size_t nb = sizeof(int32_t) * 3 * (n_modes > 0 ? n_modes : 1), nd = sizeof(double) * 3 * (n_modes > 0 ? n_modes : 1);
+  STDG_HIP(hipMalloc(&d_mnl, nb));
+  STDG_HIP(hipMalloc(&d_abc, nd));
+  if (n_modes > 0) {
+    STDG_HIP(hipMemcpy(d_mnl, mnl, sizeof(int32_t) * 3 * n_modes, hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(d_abc, abc, sizeof(double) * 3 * n_modes, hipMemcpyHostToDevice));
+  }
+  ProjParams P;
+  P.info = m.d_info;
+  P.metric = m.d_metric;
+  P.state_off = m.d_state_off;
+  P.verts = m.d_verts;
+  P.out = state_dev;
+  P.n_modes = n_modes;
+  P.mnl = d_mnl;
+  P.abc = d_abc;
+  hipLaunchKernelGGL(project_kernel, dim3((unsigned)m.ne), dim3(128), 0, (hipStream_t)stream, P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "project kernel");
+  STDG_HIP(hipStreamSynchronize((hipStream_t)stream));
+  STDG_HIP(hipFree(d_mnl));
+  STDG_HIP(hipFree(d_abc));
+  return STDG_OK;
+}
+
+int stdg_energy(const stdg_mesh* mesh, const double* state_dev, double* energy_out, void* stream) {
+  if (!mesh || !state_dev || !energy_out) return fail(STDG_E_ARG, "stdg_energy: NULL argument");
+  Mesh& m = const_cast<stdg_mesh*>(mesh)->m;
+  if (m.n_nonaffine > 0) return fail(STDG_E_UNSUPPORTED, "stdg_energy: affine elements only");
+  int rc = ensure_state_off(&m);
+  if (rc != STDG_OK) return rc;
+  double* d_tmp = nullptr;
+  STDG_HIP(hipMalloc(&d_tmp, sizeof(double) * (m.ne + 1)));
+  rc = energy_async(&m, state_dev, d_tmp, d_tmp + m.ne, (hipStream_t)stream);
+  if (rc != STDG_OK) return rc;
+  STDG_HIP(hipMemcpyAsync(energy_out, d_tmp + m.ne, sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  STDG_HIP(hipStreamSynchronize((hipStream_t)stream));
+  STDG_HIP(hipFree(d_tmp));
+  return STDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,309 @@
+// Mesh builder: faces and neighbours, orientation check, affine detection,
+// metric coefficients, (p, q, affine) groups in locality order, offsets, and
+// the device copies (Section 2.2-2.4 of the paper: hexahedral triangulation,
+// covariant element maps, interior / boundary faces).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "internal.h"
+
+namespace stdg {
+
+namespace {
+
+// the 4 local vertices of face (alpha, side), ordered by the tangential
+// reference coordinates (u = smaller remaining axis, fastest)
+std::array<int, 4> face_local_vertices(int face) {
+  int alpha = face / 2, side = face % 2;
+  int t0 = alpha == 0 ? 1 : 0;
+  int t1 = alpha == 2 ? 1 : 2;
+  std::array<int, 4> out{};
+  int n = 0;
+  for (int bv = 0; bv < 2; ++bv)
+    for (int bu = 0; bu < 2; ++bu) {
+      int b[3] = {0, 0, 0};
+      b[alpha] = side;
+      b[t0] = bu;
+      b[t1] = bv;
+      out[n++] = b[0] + 2 * b[1] + 4 * b[2];
+    }
+  return out;
+}
+
+struct FaceRec {
+  std::array<int64_t, 4> key;
+  int64_t elem;
+  int32_t face;
+  bool operator<(const FaceRec& o) const {
+    if (key != o.key) return key < o.key;
+    if (elem != o.elem) return elem < o.elem;
+    return face < o.face;
+  }
+};
+
+void inv3(const double A[3][3], double B[3][3], double* det_out) {
+  double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+               A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+               A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  double id = 1.0 / det;
+  B[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) * id;
+  B[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+  B[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+  B[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) * id;
+  B[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+  B[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+  B[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) * id;
+  B[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+  B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+  *det_out = det;
+}
+
+// G = |J| DF^{-1} DF^{-T} (symmetric) packed xx yy zz xy xz yz
+void metric_of(const double DF[3][3], double G[6], double* det) {
+  double Di[3][3];
+  inv3(DF, Di, det);
+  double M[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += Di[i][k] * Di[j][k];
+      M[i][j] = *det * s;
+    }
+  G[0] = M[0][0]; G[1] = M[1][1]; G[2] = M[2][2];
+  G[3] = M[0][1]; G[4] = M[0][2]; G[5] = M[1][2];
+}
+
+void sym_inverse(const double G[6], double out[6]) {
+  double A[3][3] = {{G[0], G[3], G[4]}, {G[3], G[1], G[5]}, {G[4], G[5], G[2]}};
+  double B[3][3], det;
+  inv3(A, B, &det);
+  out[0] = B[0][0]; out[1] = B[1][1]; out[2] = B[2][2];
+  out[3] = B[0][1]; out[4] = B[0][2]; out[5] = B[1][2];
+}
+
+uint64_t spread3(uint64_t v) {
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+
+}  // namespace
+
+int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m) {
+  const int64_t ne = d->n_elements, nv = d->n_vertices;
+  m->ctx = ctx;
+  m->ne = ne;
+  m->nv = nv;
+  m->p.assign(d->p, d->p + ne);
+  m->q.assign(d->q, d->q + ne);
+  for (int64_t e = 0; e < ne; ++e) {
+    if (m->p[e] < 1 || m->p[e] > kMaxA - 1)
+      return fail(STDG_E_ARG, "element " + std::to_string(e) + ": p must be in 1..8");
+    if (m->q[e] < 1 || m->q[e] > kMaxQ)
+      return fail(STDG_E_ARG, "element " + std::to_string(e) + ": q must be in 1..6");
+    if (!(d->eps[e] > 0.0) || !(d->mu[e] > 0.0) || !std::isfinite(d->eps[e]) || !std::isfinite(d->mu[e]))
+      return fail(STDG_E_ARG, "element " + std::to_string(e) + ": eps and mu must be finite and > 0");
+    for (int v = 0; v < 8; ++v) {
+      int64_t id = d->hexes[8 * e + v];
+      if (id < 0 || id >= nv) return fail(STDG_E_ARG, "element " + std::to_string(e) + ": vertex id out of range");
+    }
+  }
+  for (int64_t i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(d->vertices[i])) return fail(STDG_E_ARG, "non-finite vertex coordinate");
+
+  // offsets
+  m->trial_off.assign(ne + 1, 0);
+  m->unk_off.assign(ne + 1, 0);
+  m->state_off.assign(ne + 1, 0);
+  for (int64_t e = 0; e < ne; ++e) {
+    int64_t a3 = (int64_t)(m->p[e] + 1) * (m->p[e] + 1) * (m->p[e] + 1);
+    m->trial_off[e + 1] = m->trial_off[e] + 6 * (m->q[e] + 1) * a3;
+    m->unk_off[e + 1] = m->unk_off[e] + 6 * m->q[e] * a3;
+    m->state_off[e + 1] = m->state_off[e] + 6 * a3;
+  }
+
+  // faces
+  std::vector<FaceRec> faces;
+  faces.reserve(6 * ne);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int f = 0; f < 6; ++f) {
+      auto lv = face_local_vertices(f);
+      FaceRec r;
+      for (int k = 0; k < 4; ++k) r.key[k] = d->hexes[8 * e + lv[k]];
+      std::sort(r.key.begin(), r.key.end());
+      r.elem = e;
+      r.face = f;
+      faces.push_back(r);
+    }
+  std::sort(faces.begin(), faces.end());
+  m->info.assign(ne, ElemInfo{});
+  for (int64_t e = 0; e < ne; ++e) {
+    ElemInfo& I = m->info[e];
+    I.a = m->p[e] + 1;
+    I.q = m->q[e];
+    I.flags = 0;
+    I.trial_off = m->trial_off[e];
+    I.unk_off = m->unk_off[e];
+    for (int f = 0; f < 6; ++f) I.nb[f] = -1;
+  }
+  m->n_int_faces = m->n_bnd_faces = 0;
+  for (size_t i = 0; i < faces.size();) {
+    size_t j = i + 1;
+    while (j < faces.size() && faces[j].key == faces[i].key) ++j;
+    if (j - i == 1) {
+      m->info[faces[i].elem].flags |= (kBoundaryBase << faces[i].face);
+      ++m->n_bnd_faces;
+    } else if (j - i == 2) {
+      const FaceRec &A = faces[i], &B = faces[i + 1];
+      if (A.elem == B.elem) return fail(STDG_E_ARG, "element touches itself across a face");
+      bool ok = (A.face / 2 == B.face / 2) && (A.face % 2 != B.face % 2);
+      if (ok) {
+        auto la = face_local_vertices(A.face), lb = face_local_vertices(B.face);
+        for (int k = 0; k < 4; ++k)
+          if (d->hexes[8 * A.elem + la[k]] != d->hexes[8 * B.elem + lb[k]]) ok = false;
+      }
+      if (!ok)
+        return fail(STDG_E_UNSUPPORTED, "face between elements " + std::to_string(A.elem) + " and " +
+                                            std::to_string(B.elem) + " is not in canonical orientation");
+      if (A.elem > INT32_MAX || B.elem > INT32_MAX) return fail(STDG_E_ARG, "too many elements");
+      m->info[A.elem].nb[A.face] = (int32_t)B.elem;
+      m->info[B.elem].nb[B.face] = (int32_t)A.elem;
+      ++m->n_int_faces;
+    } else {
+      return fail(STDG_E_ARG, "non-manifold face shared by more than two elements");
+    }
+    i = j;
+  }
+
+  // geometry
+  m->metric.assign(ne, ElemMetric{});
+  m->verts.assign(ne * 24, 0.0);
+  m->n_affine = m->n_nonaffine = m->n_diag = 0;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  std::vector<std::array<double, 3>> cen(ne);
+  for (int64_t e = 0; e < ne; ++e) {
+    double X[8][3];
+    for (int v = 0; v < 8; ++v)
+      for (int c = 0; c < 3; ++c) {
+        X[v][c] = d->vertices[3 * d->hexes[8 * e + v] + c];
+        m->verts[24 * e + 3 * v + c] = X[v][c];
+      }
+    double scale = 0.0;
+    for (int v = 0; v < 8; ++v)
+      for (int c = 0; c < 3; ++c) scale = std::max(scale, std::fabs(X[v][c] - X[0][c]));
+    bool affine = true;
+    for (int v = 0; v < 8; ++v) {
+      int b0 = v & 1, b1 = (v >> 1) & 1, b2 = (v >> 2) & 1;
+      for (int c = 0; c < 3; ++c) {
+        double pred = X[0][c] + b0 * (X[1][c] - X[0][c]) + b1 * (X[2][c] - X[0][c]) + b2 * (X[4][c] - X[0][c]);
+        if (std::fabs(pred - X[v][c]) > 1e-12 * scale) affine = false;
+      }
+    }
+    // DF at the element centre (exact for affine elements)
+    double DF[3][3] = {{0}};
+    for (int v = 0; v < 8; ++v) {
+      int b[3] = {v & 1, (v >> 1) & 1, (v >> 2) & 1};
+      for (int mdir = 0; mdir < 3; ++mdir) {
+        double dN = (b[mdir] ? 1.0 : -1.0) * 0.25;
+        for (int c = 0; c < 3; ++c) DF[c][mdir] += dN * X[v][c];
+      }
+    }
+    double G[6], det;
+    metric_of(DF, G, &det);
+    if (!(det > 0.0)) return fail(STDG_E_ARG, "element " + std::to_string(e) + " is inverted or degenerate");
+    ElemMetric& M = m->metric[e];
+    for (int k = 0; k < 6; ++k) {
+      M.m[k] = d->eps[e] * G[k];
+      M.m[6 + k] = d->mu[e] * G[k];
+    }
+    sym_inverse(M.m, M.m + 12);
+    sym_inverse(M.m + 6, M.m + 18);
+    bool diag = affine && std::fabs(G[3]) <= 1e-13 * (G[0] + G[1] + G[2]) &&
+                std::fabs(G[4]) <= 1e-13 * (G[0] + G[1] + G[2]) && std::fabs(G[5]) <= 1e-13 * (G[0] + G[1] + G[2]);
+    if (diag) {
+      M.m[3] = M.m[4] = M.m[5] = M.m[9] = M.m[10] = M.m[11] = 0.0;
+      M.m[15] = M.m[16] = M.m[17] = M.m[21] = M.m[22] = M.m[23] = 0.0;
+    }
+    ElemInfo& I = m->info[e];
+    if (affine) { I.flags |= kAffine; ++m->n_affine; } else { ++m->n_nonaffine; }
+    if (diag) { I.flags |= kDiagMass; ++m->n_diag; }
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int v = 0; v < 8; ++v) s += X[v][c];
+      cen[e][c] = s / 8.0;
+      lo[c] = std::min(lo[c], cen[e][c]);
+      hi[c] = std::max(hi[c], cen[e][c]);
+    }
+  }
+
+  // groups in Morton order of the element centroids
+  std::map<std::tuple<int, int, int>, std::vector<std::pair<uint64_t, int32_t>>> gm;
+  for (int64_t e = 0; e < ne; ++e) {
+    uint64_t code = 0;
+    for (int c = 0; c < 3; ++c) {
+      double span = hi[c] - lo[c];
+      double t = span > 0 ? (cen[e][c] - lo[c]) / span : 0.0;
+      uint64_t iv = (uint64_t)std::min(1048575.0, std::max(0.0, std::floor(t * 1048575.0)));
+      code |= spread3(iv) << c;
+    }
+    auto key = std::make_tuple(m->p[e] + 1, m->q[e], (m->info[e].flags & kAffine) ? 1 : 0);
+    gm[key].push_back({code, (int32_t)e});
+  }
+  m->p_max = *std::max_element(m->p.begin(), m->p.end());
+  m->q_max = *std::max_element(m->q.begin(), m->q.end());
+
+  // device copies
+  size_t bytes_info = sizeof(ElemInfo) * ne, bytes_metric = sizeof(ElemMetric) * ne;
+  size_t bytes_verts = sizeof(double) * 24 * ne;
+  int rc;
+  if ((rc = dev_alloc(ctx, (void**)&m->d_info, bytes_info)) != STDG_OK) return rc;
+  if ((rc = dev_alloc(ctx, (void**)&m->d_metric, bytes_metric)) != STDG_OK) return rc;
+  if ((rc = dev_alloc(ctx, (void**)&m->d_verts, bytes_verts)) != STDG_OK) return rc;
+  m->device_bytes = bytes_info + bytes_metric + bytes_verts;
+  STDG_HIP(hipMemcpy(m->d_info, m->info.data(), bytes_info, hipMemcpyHostToDevice));
+  STDG_HIP(hipMemcpy(m->d_metric, m->metric.data(), bytes_metric, hipMemcpyHostToDevice));
+  STDG_HIP(hipMemcpy(m->d_verts, m->verts.data(), bytes_verts, hipMemcpyHostToDevice));
+  for (auto& kv : gm) {
+    auto& lst = kv.second;
+    std::sort(lst.begin(), lst.end());
+    std::vector<int32_t> ids(lst.size());
+    for (size_t i = 0; i < lst.size(); ++i) ids[i] = lst[i].second;
+    Group g;
+    g.a = std::get<0>(kv.first);
+    g.q = std::get<1>(kv.first);
+    g.affine = std::get<2>(kv.first);
+    g.count = (int64_t)ids.size();
+    if ((rc = dev_alloc(ctx, (void**)&g.d_list, sizeof(int32_t) * ids.size())) != STDG_OK) return rc;
+    m->device_bytes += sizeof(int32_t) * ids.size();
+    STDG_HIP(hipMemcpy(g.d_list, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice));
+    m->groups.push_back(g);
+  }
+  return STDG_OK;
+}
+
+void release_mesh(Mesh* m) {
+  Ctx* ctx = m->ctx;
+  if (m->d_info) dev_free(ctx, m->d_info, sizeof(ElemInfo) * m->ne);
+  if (m->d_metric) dev_free(ctx, m->d_metric, sizeof(ElemMetric) * m->ne);
+  if (m->d_verts) dev_free(ctx, m->d_verts, sizeof(double) * 24 * m->ne);
+  for (auto& g : m->groups)
+    if (g.d_list) dev_free(ctx, g.d_list, sizeof(int32_t) * g.count);
+  if (m->d_scratch) dev_free(ctx, m->d_scratch, m->scratch_bytes);
+  if (m->d_state_off) dev_free(ctx, m->d_state_off, sizeof(int64_t) * (m->ne + 1));
+  m->d_state_off = nullptr;
+  m->d_info = nullptr;
+  m->d_metric = nullptr;
+  m->d_verts = nullptr;
+  m->groups.clear();
+  m->d_scratch = nullptr;
+}
+
+}  // namespace stdg

@@ -1,0 +1,86 @@
+// Dispatch of the residual kernels over the (a, q, affine) groups of a mesh.
+#include "residual_kernel.h"
+
+namespace stdg {
+
+#define STDG_DECL(R, AA) int launch_affine_##R##AA(int q, const KParams<R>& P, int64_t n, hipStream_t s);
+#define STDG_DECL_ALL(R) STDG_DECL(R, 2) STDG_DECL(R, 3) STDG_DECL(R, 4) STDG_DECL(R, 5) \
+  STDG_DECL(R, 6) STDG_DECL(R, 7) STDG_DECL(R, 8) STDG_DECL(R, 9)
+STDG_DECL_ALL(float)
+STDG_DECL_ALL(double)
+#undef STDG_DECL_ALL
+#undef STDG_DECL
+
+template <typename T>
+using Launcher = int (*)(int, const KParams<T>&, int64_t, hipStream_t);
+
+static Launcher<float> affine_f32[kMaxA + 1] = {nullptr, nullptr, launch_affine_float2, launch_affine_float3,
+                                                launch_affine_float4, launch_affine_float5, launch_affine_float6,
+                                                launch_affine_float7, launch_affine_float8, launch_affine_float9};
+static Launcher<double> affine_f64[kMaxA + 1] = {nullptr, nullptr, launch_affine_double2, launch_affine_double3,
+                                                 launch_affine_double4, launch_affine_double5, launch_affine_double6,
+                                                 launch_affine_double7, launch_affine_double8, launch_affine_double9};
+
+template <typename T>
+static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* load, T* y, hipStream_t s,
+                      Launcher<T>* table) {
+  KParams<T> P;
+  P.info = m->d_info;
+  P.metric = m->d_metric;
+  P.x = x;
+  P.load = load;
+  P.y = y;
+  P.dt = (T)dt;
+  P.mode = mode;
+  if constexpr (sizeof(T) == 8) fill_tables_f64(&P.tab); else fill_tables_f32(&P.tab);
+  for (const Group& g : m->groups) {
+    if (g.count == 0) continue;
+    if (!g.affine) return fail(STDG_E_UNSUPPORTED, "trilinear (non-affine) elements are not supported by this apply");
+    P.list = g.d_list;
+    int rc = table[g.a](g.q, P, g.count, s);
+    if (rc != STDG_OK) return rc;
+  }
+  return STDG_OK;
+}
+
+int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s) {
+  const dim3 grid((unsigned)m->ne), block(256);
+  if (prec == STDG_FP64)
+    hipLaunchKernelGGL(precond_scale_kernel<double>, grid, block, 0, s, m->d_info, m->d_metric, m->ne,
+                       (const double*)x, (double*)z);
+  else
+    hipLaunchKernelGGL(precond_scale_kernel<float>, grid, block, 0, s, m->d_info, m->d_metric, m->ne,
+                       (const float*)x, (float*)z);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "precond_scale launch");
+  return STDG_OK;
+}
+
+int launch_residual(const ApplyArgs& a) {
+  const Mesh* m = a.mesh;
+  int mode = a.mode;
+  const void* x = a.x;
+  if (mode == STDG_OPERATOR_PRECOND && m->n_diag != m->ne) {
+    // non-diagonal metric somewhere: scale into the mesh's scratch, then plain operator
+    Mesh* mm = const_cast<Mesh*>(m);
+    size_t need = (size_t)m->unk_off.back() * (a.prec == STDG_FP64 ? 8 : 4);
+    if (mm->scratch_bytes < need) {
+      if (mm->d_scratch) dev_free(mm->ctx, mm->d_scratch, mm->scratch_bytes);
+      mm->d_scratch = nullptr;
+      mm->scratch_bytes = 0;
+      int rc = dev_alloc(mm->ctx, &mm->d_scratch, need);
+      if (rc != STDG_OK) return rc;
+      mm->scratch_bytes = need;
+    }
+    int rc = launch_precond_scale(m, a.prec, x, mm->d_scratch, a.stream);
+    if (rc != STDG_OK) return rc;
+    x = mm->d_scratch;
+    mode = STDG_OPERATOR;
+  }
+  if (a.prec == STDG_FP64)
+    return run_groups<double>(m, a.dt, mode, (const double*)x, (const double*)a.load, (double*)a.y, a.stream,
+                              affine_f64);
+  return run_groups<float>(m, a.dt, mode, (const float*)x, (const float*)a.load, (float*)a.y, a.stream, affine_f32);
+}
+
+}  // namespace stdg

@@ -1,0 +1,150 @@
+"""GPU parity of stdg_residual_apply (the slab residual, Section 5 eq. residual)
+against the FP64 oracle on the same seeded inputs, through the C ABI.
+
+Bars: FP64 relative 2-norm error <= 1e-12; raw FP32 apply <= 1e-5 (the FP32
+inputs are the float32 roundings of the FP64 ones and the oracle is run on
+exactly those values)."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import Lib, note, oracle_disc, random_mixed_mesh, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return Lib()
+
+
+def _check_all_modes(lib, mesh, dt, seed, name, precs=(0, 1), with_precond=True, elements=None):
+    stdg = lib.stdg
+    d = oracle_disc(mesh)
+    mh = lib.upload(mesh)
+    rng = np.random.default_rng(seed)
+    nu, nt = d.unk_off[-1], d.trial_off[-1]
+    x = rng.standard_normal(nu)
+    U = rng.standard_normal(nt)
+    L = rng.standard_normal(nu)
+    try:
+        for prec in precs:
+            cast = (lambda v: v) if prec == 0 else (lambda v: v.astype(np.float32).astype(np.float64))
+            xs, Us, Ls = cast(x), cast(U), cast(L)
+            note("%s prec=%d operator" % (name, prec))
+            got = lib.apply(mh, dt, prec, stdg.STDG_OPERATOR, xs)
+            ref = d.operator(xs, dt)
+            assert rel_err(got, ref) < TOL[prec], (name, prec, "operator", rel_err(got, ref))
+            note("%s prec=%d residual" % (name, prec))
+            got = lib.apply(mh, dt, prec, stdg.STDG_RESIDUAL, Us, Ls)
+            ref = d.residual(Us, dt, Ls)
+            assert rel_err(got, ref) < TOL[prec], (name, prec, "residual", rel_err(got, ref))
+            got = lib.apply(mh, dt, prec, stdg.STDG_RESIDUAL, Us, None)
+            ref = d.residual(Us, dt)
+            assert rel_err(got, ref) < TOL[prec], (name, prec, "residual-noload", rel_err(got, ref))
+            if with_precond:
+                note("%s prec=%d precond" % (name, prec))
+                got = lib.apply(mh, dt, prec, stdg.STDG_OPERATOR_PRECOND, xs)
+                ref = d.operator(d.precond_solve(xs), dt)
+                assert rel_err(got, ref) < TOL[prec], (name, prec, "precond", rel_err(got, ref))
+    finally:
+        stdg.stdg_mesh_free(mh)
+
+
+def test_cavity_4cubed_p2_q1(lib):
+    cfg = synth.cavity_small()
+    _check_all_modes(lib, cfg["mesh"], cfg["dt"], 0, "cavity4")
+
+
+def test_operator_on_seed0_vector_cavity_4cubed(lib):
+    # the small workload's apply on N(0,1) coefficients, seed 0, full trial vector
+    cfg = synth.cavity_small()
+    m = cfg["mesh"]
+    d = oracle_disc(m)
+    U = synth.random_vector(d.trial_off[-1], 0)
+    mh = lib.upload(m)
+    got = lib.apply(mh, cfg["dt"], 0, lib.stdg.STDG_RESIDUAL, U)
+    lib.stdg.stdg_mesh_free(mh)
+    assert rel_err(got, d.residual(U, cfg["dt"])) < 1e-12
+
+
+@pytest.mark.parametrize("p,q", [(1, 1), (3, 2), (4, 3), (5, 4), (6, 4), (7, 5), (8, 6)])
+def test_uniform_degrees_ragged_count(lib, p, q):
+    # 3 x 2 x 2 = 12 elements: not a multiple of the 8-way block interleave
+    v, h = synth.box_mesh((3, 2, 2), hi=(0.9, 0.5, 0.7))
+    ne = h.shape[0]
+    rng = np.random.default_rng(p * 10 + q)
+    mesh = synth.Mesh(v, h, np.full(ne, p, np.int32), np.full(ne, q, np.int32),
+                      rng.uniform(1, 4, ne), rng.uniform(1, 2, ne))
+    _check_all_modes(lib, mesh, 0.037, 100 + p, "uniform p%d q%d" % (p, q))
+
+
+def test_mixed_p_and_q(lib):
+    mesh = random_mixed_mesh((3, 3, 2), 5, 4, seed=5)
+    _check_all_modes(lib, mesh, 0.05, 6, "mixed")
+
+
+def test_single_element(lib):
+    v, h = synth.box_mesh((1, 1, 1))
+    mesh = synth.Mesh(v, h, np.array([3], np.int32), np.array([2], np.int32), np.array([2.0]), np.array([0.5]))
+    _check_all_modes(lib, mesh, 0.1, 7, "single")
+
+
+def test_sheared_affine_nondiagonal_metric(lib):
+    v, h = synth.box_mesh((2, 2, 3))
+    A = np.array([[1.0, 0.3, -0.2], [0.1, 0.9, 0.25], [-0.15, 0.2, 1.1]])
+    v = synth.affine_transform(v, A)
+    ne = h.shape[0]
+    rng = np.random.default_rng(11)
+    mesh = synth.Mesh(v, h, rng.integers(1, 4, ne).astype(np.int32), rng.integers(1, 4, ne).astype(np.int32),
+                      rng.uniform(1, 3, ne), rng.uniform(1, 3, ne))
+    _check_all_modes(lib, mesh, 0.08, 12, "sheared")
+
+
+def test_deterministic_bitwise(lib):
+    cfg = synth.cavity_two_material(n=6, p=4, q=3)
+    m = cfg["mesh"]
+    mh = lib.upload(m)
+    x = synth.random_vector(m.unknown_size(), 3)
+    for prec in (0, 1):
+        a = lib.apply(mh, 0.01, prec, lib.stdg.STDG_OPERATOR, x)
+        b = lib.apply(mh, 0.01, prec, lib.stdg.STDG_OPERATOR, x)
+        assert np.array_equal(a, b)
+    lib.stdg.stdg_mesh_free(mh)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_material_32cubed_sampled(lib, prec):
+    """Full-size 32^3, p = 4, q = 3 two-material cavity, in the launch
+    configuration the benchmark times; the oracle checks sampled elements
+    (an element's output depends only on it and its face neighbours)."""
+    stdg = lib.stdg
+    cfg = synth.cavity_two_material()
+    m = cfg["mesh"]
+    dt = cfg["dt"]
+    note("32^3 prec=%d: generating inputs" % prec)
+    x = synth.random_vector(m.unknown_size(), 0)
+    if prec == 1:
+        x = x.astype(np.float32).astype(np.float64)
+    mh = lib.upload(m)
+    d = oracle_disc(m)
+    n = m.shape[0]
+    rng = np.random.default_rng(42)
+    sample = [int(e) for e in rng.choice(m.n_elements, 48, replace=False)]
+    # corners, both sides of the material interface x = 0.5
+    sample += [0, n - 1, n * n - 1, n ** 3 - 1, n // 2 - 1 + n * (n // 2) + n * n * 3, n // 2 + n * 5 + n * n * 7]
+    needed = sorted(set(sample) | {int(k) for e in sample for k in d.nb[e] if k >= 0})
+    for mode in (stdg.STDG_OPERATOR, stdg.STDG_OPERATOR_PRECOND):
+        note("32^3 prec=%d mode=%d: apply" % (prec, mode))
+        y = lib.apply(mh, dt, prec, mode, x)
+        assert np.all(np.isfinite(y))
+        xin = d.precond_solve(x, needed) if mode == stdg.STDG_OPERATOR_PRECOND else x
+        U = d.embed_unknowns(xin)
+        rows = d.apply_rows(U, dt, sample)
+        got = np.concatenate([y[d.unk_off[e]:d.unk_off[e + 1]] for e in sample])
+        ref = np.concatenate([rows[e] for e in sample])
+        note("32^3 prec=%d mode=%d rel err %.3e" % (prec, mode, rel_err(got, ref)))
+        assert rel_err(got, ref) < TOL[prec]
+    stdg.stdg_mesh_free(mh)
