@@ -1,0 +1,225 @@
+"""Benchmark of the space-time DG slab residual on one MI355X.
+
+Workload: PEC unit-cube cavity, 32^3 axis-aligned hexahedra, p = 4, q = 3,
+two materials (eps = 1 for x < 0.5, else 4; mu = 1), dt = 0.01; inputs are
+seeded N(0, 1) coefficient vectors, resident in HBM before timing starts.
+
+A step is one residual apply over the whole mesh (the operator the slab's
+GMRES applies every iteration: mass, curl, centred fluxes, P^{-1} fused),
+in FP32 (the apply used inside FP64 iterative refinement).  The same apply in
+FP64 (the plain FP64 path) is timed right after, on the same inputs, and the
+FP32+refinement and plain-FP64 slab solves are timed on the first slab of the
+workload's mode-superposition initial field.
+
+Prints one JSON line.  value = trial degrees of freedom 6 (q+1)(p+1)^3 n_el per
+apply / seconds per apply, in GDoF/s.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=32, help="mesh is n^3 elements")
+    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--q", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="elements in the oracle's timed sample (0 = sized to ~15 s)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    return ap.parse_args()
+
+
+def time_applies(stdg, torch, mh, dt, prec, mode, x, y, steps, warmup):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        stdg.stdg_residual_apply(mh, dt, prec, mode, x, None, y, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        stdg.stdg_residual_apply(mh, dt, prec, mode, x, None, y, stream)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([a.elapsed_time(b) for a, b in ev])  # ms, per launch (one kernel per apply here)
+    return wall, per
+
+
+def cpu_baseline(cfg, sample_n):
+    """The oracle as it stands, on a bounded sample of the workload's elements."""
+    from oracle.dg import Discretisation
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    m = cfg["mesh"]
+    d = Discretisation(m.vertices, m.hexes, m.p, m.q, m.eps, m.mu)
+    import synth
+    x = synth.random_vector(m.unknown_size(), 0)
+    U = d.embed_unknowns(x)
+    rng = np.random.default_rng(7)
+    # warm the oracle's caches (reference matrices) outside the timing
+    d.apply_rows(U, cfg["dt"], [0])
+    if sample_n <= 0:
+        t = time.perf_counter()
+        d.apply_rows(U, cfg["dt"], list(rng.choice(m.n_elements, 16, replace=False)))
+        per = (time.perf_counter() - t) / 16
+        sample_n = int(min(m.n_elements, max(16, 15.0 / max(per, 1e-6))))
+    sample = list(rng.choice(m.n_elements, sample_n, replace=False))
+    t = time.perf_counter()
+    d.apply_rows(U, cfg["dt"], sample)
+    el = time.perf_counter() - t
+    a = int(m.p[0]) + 1
+    q = int(m.q[0])
+    dof = 6 * (q + 1) * a ** 3 * sample_n
+    return {"value": dof / el / 1e9, "unit": "GDoF/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d random elements of the %d-element mesh, operator apply (dense local blocks), %.1f s"
+                      % (sample_n, m.n_elements, el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1307_5310_amd as stdg
+    import synth
+
+    cfg = synth.cavity_two_material(n=args.n, p=args.p, q=args.q)
+    m = cfg["mesh"]
+    dt = cfg["dt"]
+    a, q, ne = args.p + 1, args.q, m.n_elements
+    trial_dof = 6 * (q + 1) * a ** 3 * ne
+    log("workload %s: %d elements, %.1f M trial DoF" % (cfg["name"], ne, trial_dof / 1e6))
+    ctx = stdg.stdg_init(0, 0)
+    mh = stdg.stdg_mesh_upload(ctx, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu)
+    info = stdg.stdg_mesh_info(mh)
+    nu = info["unknown_size"]
+    x64 = torch.from_numpy(synth.random_vector(nu, 0)).cuda()
+    x32 = x64.float()
+    y32 = torch.empty(nu, dtype=torch.float32, device="cuda")
+    y64 = torch.empty(nu, dtype=torch.float64, device="cuda")
+    mode = stdg.STDG_OPERATOR_PRECOND
+
+    if args.calib_copy_mib > 0:
+        nbytes = args.calib_copy_mib * (1 << 20)
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").normal_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy of %d MiB done" % args.calib_copy_mib)
+        del src, dst
+
+    log("FP32 apply: %d warmup + %d timed" % (args.warmup, args.steps))
+    torch.cuda.synchronize()
+    wall32, per32 = time_applies(stdg, torch, mh, dt, stdg.STDG_FP32, mode, x32, y32, args.steps, args.warmup)
+    log("FP64 apply: %d warmup + %d timed" % (args.warmup, args.steps))
+    wall64, per64 = time_applies(stdg, torch, mh, dt, stdg.STDG_FP64, mode, x64, y64, args.steps, args.warmup)
+    ms32 = wall32 * 1e3 / args.steps
+    ms64 = wall64 * 1e3 / args.steps
+    k32 = float(per32.mean())
+    k64 = float(per64.mean())
+    bytes32 = 12 * q * a ** 3 * 4 * ne
+    bytes64 = 12 * q * a ** 3 * 8 * ne
+    achieved = bytes32 / (k32 * 1e-3) / 1e9
+    gdofs32 = trial_dof / (ms32 * 1e-3) / 1e9
+    gdofs64 = trial_dof / (ms64 * 1e-3) / 1e9
+    log("FP32 %.3f ms/apply (kernel %.3f ms), FP64 %.3f ms/apply (kernel %.3f ms)" % (ms32, k32, ms64, k64))
+
+    solve = None
+    if not args.no_solve:
+        try:
+            solve = time_solves(stdg, torch, mh, m, cfg)
+        except Exception as e:  # solver reported separately; the apply line still prints
+            log("slab solve skipped: %s" % e)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline on a bounded sample")
+        cpu = cpu_baseline(cfg, args.cpu_sample)
+
+    out = {
+        "metric": "Residual GDoF/s at p=4,q=3 (FP32+refine vs FP64); slab solves/s, p99 latency",
+        "value": round(gdofs32, 2),
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "PEC cavity %d^3 affine hex, p=%d q=%d, eps 1|4 split at x=0.5, dt=%g; "
+                               "preconditioned operator apply on N(0,1) coefficients (seed 0)"
+                               % (args.n, args.p, args.q, dt),
+                   "elements": ne, "trial_dof": trial_dof, "unknowns": nu},
+        "fp64": {"value": round(gdofs64, 2), "unit": "GDoF/s", "ms_per_step": round(ms64, 5),
+                 "kernel_ms": round(k64, 5),
+                 "hbm_frac": round(bytes64 / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "fp32_over_fp64": round(gdofs32 / gdofs64, 3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "residual_affine_kernel<float,5,3>", "kernel_ms": round(k32, 5),
+                     "algorithmic_bytes": bytes32},
+        "cpu_baseline": cpu,
+    }
+    if solve is not None:
+        out["slab_solve"] = solve
+    print(json.dumps(out), flush=True)
+    stdg.stdg_mesh_free(mh)
+    stdg.stdg_finalize(ctx)
+
+
+def time_solves(stdg, torch, mh, m, cfg):
+    """FP32-apply + FP64 refinement vs plain FP64: one slab from the projected
+    mode superposition, to rtol 1e-10."""
+    info = stdg.stdg_mesh_info(mh)
+    modes = cfg["init"]
+    res = {}
+    for name, inner in (("fp32_refine", stdg.STDG_FP32), ("fp64", stdg.STDG_FP64)):
+        state = torch.zeros(info["state_size"], dtype=torch.float64, device="cuda")
+        stdg.stdg_project_modes(mh, modes.mnl, modes.abc, state)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, state, inner_prec=inner, rtol=1e-10,
+                                 max_iters=3000, max_refine=300)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"s_per_solve": round(el, 4), "solves_per_s": round(1.0 / el, 3), "iters": r["iters"],
+                     "refinements": r["refinements"], "rel_res": r["rel_res"],
+                     "energy_drift": (r["energy_end"] - r["energy_start"]) / max(r["energy_start"], 1e-300)}
+        log("slab solve %s: %.3f s, %d iters" % (name, el, r["iters"]))
+    res["speedup_fp32_refine"] = round(res["fp64"]["s_per_solve"] / res["fp32_refine"]["s_per_solve"], 3)
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -170,7 +170,8 @@ typedef struct {
                           FP64 iterative refinement                              */
   int32_t restart;     /* GMRES restart length (default 10)                      */
   int32_t max_iters;   /* total inner iterations allowed (default 500)           */
-  int32_t max_refine;  /* outer refinement sweeps (FP32 inner only; default 10)  */
+  int32_t max_refine;  /* FP64 residual re-evaluations allowed with FP32 inner    
+                          applies (one per restart cycle; default 100)           */
   double rtol;         /* stop when ||L - B U||_2 <= rtol ||L - B U_0||_2 (FP64)  */
   double inner_rtol;   /* relative tolerance of each inner GMRES (FP32 inner)    */
 } stdg_solve_opts;

@@ -98,7 +98,7 @@ def stdg_project_modes(mesh, mnl, abc, state, stream=None):
 
 
 def stdg_slab_solve(mesh, t0, dt, load, state, inner_prec=STDG_FP64, restart=10, max_iters=500,
-                    max_refine=10, rtol=1e-12, inner_rtol=1e-4, slab_U=None, stream=None):
+                    max_refine=100, rtol=1e-12, inner_rtol=1e-4, slab_U=None, stream=None):
     o = SolveOpts(int(inner_prec), int(restart), int(max_iters), int(max_refine), float(rtol),
                   float(inner_rtol))
     info = SolveInfo()

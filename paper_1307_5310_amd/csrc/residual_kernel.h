@@ -43,7 +43,7 @@ namespace stdg {
 template <int A>
 struct KCfg {
   static constexpr int A2 = A * A, A3 = A * A * A;
-  static constexpr int NT = A <= 5 ? 64 : (A <= 7 ? 128 : 256);
+  static constexpr int NT = A <= 5 ? 64 : (A <= 7 ? 128 : (A == 8 ? 256 : 512));
   static constexpr int R = (A3 + NT - 1) / NT;
   static constexpr int NI = 24 * A2;
   static constexpr int IPL = (NI + NT - 1) / NT;
@@ -135,6 +135,34 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
   }
   __syncthreads();
 
+  // neighbour table, uniform per block (scalar loads): id, degrees, offset, P^{-1} diagonal
+  int nb_id[6], nb_a[6], nb_q[6];
+  int64_t nb_off[6];
+  T nb_sc[6][6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    nb_id[f] = Ip->nb[f];
+    nb_a[f] = A;
+    nb_q[f] = Q;
+    nb_off[f] = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nb_sc[f][k] = T(1);
+    if (nb_id[f] >= 0) {
+      const ElemInfo* Np = P.info + nb_id[f];
+      nb_a[f] = Np->a;
+      nb_q[f] = Np->q;
+      nb_off[f] = resid ? Np->trial_off : Np->unk_off;
+      if (pre) {
+        const double* mm = P.metric[nb_id[f]].m;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          nb_sc[f][k] = (T)mm[12 + k];
+          nb_sc[f][3 + k] = (T)mm[18 + k];
+        }
+      }
+    }
+  }
+
   // neighbour traces, contracted in time: acc[k][i]
   T acc[IPL][Q];
   int nbk[IPL];
@@ -150,24 +178,56 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
     const int tc = rem / A2;
     const int t = rem - tc * A2;
     const int alpha = phi >> 1, side = phi & 1;
-    const int nbe = Ip->nb[phi];
-    nbk[k] = nbe;
-    if (nbe < 0) continue;
-    const ElemInfo* Np = P.info + nbe;
-    const int na = Np->a, nq = Np->q;
-    const int u = t % A, v = t / A;
-    if (u >= na || v >= na) continue;
     const int f = tc >> 1;
     const int c = (alpha + 1 + (tc & 1)) % 3;
+    // select this item's face from the uniform table
+    int nbe = -1, na = A, nq = Q;
+    int64_t noff = 0;
+    T scale = T(1);
+#pragma unroll
+    for (int g = 0; g < 6; ++g)
+      if (phi == g) {
+        nbe = nb_id[g];
+        na = nb_a[g];
+        nq = nb_q[g];
+        noff = nb_off[g];
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk)
+          if (3 * f + c == kk) scale = nb_sc[g][kk];
+      }
+    nbk[k] = nbe;
+    if (nbe < 0) continue;
+    const int u = t % A, v = t / A;
+    if (u >= na || v >= na) continue;
     const int na2 = na * na, na3 = na2 * na;
     int tb, ns;
     if (alpha == 0) { tb = na * u + na2 * v; ns = 1; }
     else if (alpha == 1) { tb = u + na2 * v; ns = na; }
     else { tb = u + na * v; ns = na2; }
     const int nnlev = resid ? nq + 1 : nq;
-    const T* xb = P.x + (resid ? Np->trial_off : Np->unk_off) + (int64_t)(3 * f + c) * nnlev * na3 + tb;
+    const T* xb = P.x + noff + (int64_t)(3 * f + c) * nnlev * na3 + tb;
     const T* tau = side ? s_t0 : s_t1;  // neighbour's face sits at 1 - side
-    const T scale = pre ? (T)P.metric[nbe].m[12 + 6 * f + c] : T(1);
+    if (na == A && nq == Q) {
+      // same degrees (the common case): compile-time trip counts, so every load
+      // of the item is in flight before the reductions start
+      T vals[Q + 1][A];
+#pragma unroll
+      for (int mp = 0; mp <= Q; ++mp)
+#pragma unroll
+        for (int l = 0; l < A; ++l)
+          vals[mp][l] = (mp >= m0) ? xb[(int64_t)(mp - m0) * A3 + l * ns] : T(0);
+#pragma unroll
+      for (int mp = 0; mp <= Q; ++mp) {
+        T tr = T(0);
+#pragma unroll
+        for (int l = 0; l < A; ++l) tr += tau[l] * vals[mp][l];
+        tr *= scale;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          if (nnzN(i, mp)) acc[k][i] += P.tab.N[i][mp] * tr;
+      }
+      continue;
+    }
 #pragma unroll
     for (int mp = 0; mp <= kMaxQ; ++mp) {
       if (mp < m0 || mp > nq) continue;
