@@ -14,15 +14,20 @@
 
 namespace stdg {
 
+template <int QQ>
+static constexpr size_t shmem_bytes() {
+  return sizeof(STDG_REAL) * KCfg<STDG_A>::template lds_elems<STDG_REAL, QQ>();
+}
+
 int STDG_CAT(STDG_CAT(launch_affine_, STDG_REAL), STDG_A)(int q, const KParams<STDG_REAL>& P, int64_t n,
                                                          hipStream_t stream) {
   using Cf = KCfg<STDG_A>;
-  const size_t shmem = sizeof(STDG_REAL) * Cf::LDS_ELEMS;
   const dim3 grid((unsigned)n), block(Cf::NT);
   switch (q) {
-#define STDG_CASE(QQ)                                                                            \
-  case QQ:                                                                                     \
-    hipLaunchKernelGGL((residual_affine_kernel<STDG_REAL, STDG_A, QQ>), grid, block, shmem, stream, P); \
+#define STDG_CASE(QQ)                                                                                    \
+  case QQ:                                                                                             \
+    hipLaunchKernelGGL((residual_affine_kernel<STDG_REAL, STDG_A, QQ>), grid, block, shmem_bytes<QQ>(), stream, \
+                       P);                                                                             \
     break;
     STDG_CASE(1)
     STDG_CASE(2)

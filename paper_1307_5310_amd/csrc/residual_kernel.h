@@ -11,7 +11,7 @@
 // covariant maps curl and flux are geometry-free in reference coordinates.
 //
 // Curl (from (curl E, w) and -(H, curl v), eq. bilinearform:C), with
-// Dh[n][j] = int L_n L_j' = 2 sqrt(2n+1) sqrt(2j+1) for n < j, j - n odd:
+// Dh[n][j] = int L_n L_j' = 2 rho_n rho_j for n < j, j - n odd, rho_j = sqrt(2j+1):
 //   R_H[c] += sum_n Dh[s_c1][n] E_c2(s_c1 -> n) - sum_n Dh[s_c2][n] E_c1(s_c2 -> n)
 //   R_E[c] += sum_n Dh[n][s_c1] H_c2(s_c1 -> n) - sum_n Dh[n][s_c2] H_c1(s_c2 -> n)
 // (c1, c2) = (c+1, c+2) mod 3; "s_m -> n" replaces the index along axis m.
@@ -27,13 +27,20 @@
 //   R_H[c] -= sigma eps(c,d,alpha) L_{s_alpha}(side) G_d,  d = 3 - c - alpha.
 // Faces with different p couple only the tangential modes < min(a, a').
 //
-// Thread layout: NT lanes per element; lane owns positions s = tid + NT r
-// (all 6 components, all levels, in registers) and face items
-// (face, tangential component, tangential mode) it = tid + NT k.  The
-// neighbour traces are reduced straight from global memory (the neighbour
-// blocks are read through L2, which the locality-ordered work list and the
-// XCD-aware block mapping keep warm); per test level the contracted field and
-// the face fluxes are staged in LDS.
+// Work layout: NT = a^3 rounded up to a multiple of 64 threads per element.
+// Thread s owns spatial position s: all 6 components and all time levels in
+// registers, so the time contraction, the mass term, the loads and the stores
+// need no exchange.  For faces, thread (tc, t) < 4 a^2 owns tangential
+// component tc and tangential mode t; the loops over faces are unrolled, so
+// every neighbour parameter is a uniform scalar and every load is a uniform
+// base plus a per-thread offset plus a compile-time immediate.  Neighbour
+// blocks come through L2, kept warm by the locality-ordered work list and the
+// XCD-aware block order.  Contracted levels are staged in LDS scaled by
+// w(s) = rho_j rho_k rho_l, which turns the curl contractions and the own
+// face traces into plain (alternating) sums with one factor per position or
+// face mode; the curl sums use 0/1 masks instead of branches, and all their
+// reads stay inside the staged level because the E-test reads H components
+// below its position and the H-test reads E components above it.
 #pragma once
 
 #include "internal.h"
@@ -43,11 +50,17 @@ namespace stdg {
 template <int A>
 struct KCfg {
   static constexpr int A2 = A * A, A3 = A * A * A;
-  static constexpr int NT = A <= 5 ? 64 : (A <= 7 ? 128 : (A == 8 ? 256 : 512));
-  static constexpr int R = (A3 + NT - 1) / NT;
-  static constexpr int NI = 24 * A2;
-  static constexpr int IPL = (NI + NT - 1) / NT;
-  static constexpr int LDS_ELEMS = 6 * A3 + 24 * A2 + 3 * kMaxA;
+  static constexpr int NT = ((A3 + 63) / 64) * 64;  // one spatial position per thread
+  static constexpr int NF = 4 * A2;                 // face items per face
+  static constexpr int ND = A / 2;                  // odd offsets 1, 3, .. < A
+  static constexpr int LVL = 6 * A3 + 24 * A2;      // staged level: E~', H~' then fluxes
+  template <typename T, int Q>
+  static constexpr int LC() {  // test levels staged per LDS pass (about 16 KB)
+    constexpr int c = 16384 / (LVL * (int)sizeof(T));
+    return c < 1 ? 1 : (c > Q ? Q : c);
+  }
+  template <typename T, int Q>
+  static constexpr int lds_elems() { return LC<T, Q>() * LVL; }
 };
 
 template <typename T>
@@ -72,16 +85,29 @@ __device__ __forceinline__ T symget(const T* M, int c, int d) {
   return c == d ? M[c] : ((c + d == 1) ? M[3] : ((c + d == 2) ? M[4] : M[5]));
 }
 
+template <typename T>
+__device__ __forceinline__ T dsqrt(T v) {
+  return sqrt(v);
+}
+template <>
+__device__ __forceinline__ float dsqrt<float>(float v) {
+  return __fsqrt_rn(v);
+}
+
+// stride along the normal and base offset of tangential mode (u, v) on a
+// face normal to alpha, in a block of edge n (x-hat index fastest)
+__host__ __device__ constexpr int face_stride(int alpha, int n) { return alpha == 0 ? 1 : (alpha == 1 ? n : n * n); }
+__device__ __forceinline__ int face_base(int alpha, int u, int v, int n) {
+  return alpha == 0 ? n * u + n * n * v : (alpha == 1 ? u + n * n * v : u + n * v);
+}
+
 template <typename T, int A, int Q>
 __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T> P) {
   using C = KCfg<A>;
-  constexpr int A2 = C::A2, A3 = C::A3, NT = C::NT, R = C::R, NI = C::NI, IPL = C::IPL;
+  constexpr int A2 = C::A2, A3 = C::A3, NF = C::NF, ND = C::ND, LVL = C::LVL;
+  constexpr int LC = C::template LC<T, Q>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* Et = reinterpret_cast<T*>(smem_raw);  // [6][A3] contracted level
-  T* Fl = Et + 6 * A3;                     // [6 faces][4][A2] fluxes
-  T* s_rho = Fl + 24 * A2;                 // sqrt(2j+1)
-  T* s_t0 = s_rho + kMaxA;                 // L_j(0)
-  T* s_t1 = s_t0 + kMaxA;                  // L_j(1)
+  T* sm = reinterpret_cast<T*>(smem_raw);
 
   const int tid = threadIdx.x;
   // XCD-aware block order: consecutive work-list entries run on the same XCD
@@ -94,34 +120,106 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
   const int mode = P.mode;
   const bool resid = mode == 1, pre = mode == 2;
   const int m0 = resid ? 0 : 1;
-  const int64_t xoff = resid ? Ip->trial_off : Ip->unk_off;
-  const int64_t yoff = Ip->unk_off;
   const int nlev = resid ? Q + 1 : Q;
+  const T* xe = P.x + (resid ? Ip->trial_off : Ip->unk_off);
+  T* ye = P.y + Ip->unk_off;
 
+  // neighbour table, uniform per block
+  int nb_id[6], nb_a[6], nb_q[6];
+  const T* nb_x[6];
+  bool fast = true;
 #pragma unroll
-  for (int j = 0; j < kMaxA; ++j)
-    if (tid == j) {
-      s_rho[j] = P.tab.tr1[j];
-      s_t0[j] = P.tab.tr0[j];
-      s_t1[j] = P.tab.tr1[j];
+  for (int g = 0; g < 6; ++g) {
+    nb_id[g] = Ip->nb[g];
+    nb_a[g] = A;
+    nb_q[g] = Q;
+    nb_x[g] = xe;
+    if (nb_id[g] >= 0) {
+      const ElemInfo* Np = P.info + nb_id[g];
+      nb_a[g] = Np->a;
+      nb_q[g] = Np->q;
+      nb_x[g] = P.x + (resid ? Np->trial_off : Np->unk_off);
+      fast = fast && nb_a[g] == A && nb_q[g] == Q;
     }
+  }
 
-  // own block into registers
-  const T* xe = P.x + xoff;
-  T xr[6][Q + 1][R];
+  const bool pos_lane = tid < A3;
+  const uint32_t s = pos_lane ? (uint32_t)tid : 0u;
+  const bool face_lane = tid < NF;
+  const int tc = face_lane ? tid / A2 : 0;  // tangential component slot 0..3
+  const int t = face_lane ? tid - tc * A2 : 0;
+  const int fu = t % A, fv = t / A;        // tangential mode (u, v)
+  const int tf = tc >> 1;                  // field of that component
+
+  // ---- own block: all components and levels of position s ------------------
+  T xr[6][Q + 1];
 #pragma unroll
   for (int fc = 0; fc < 6; ++fc)
 #pragma unroll
     for (int m = 0; m <= Q; ++m)
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int s = tid + NT * r;
-        T v = T(0);
-        if ((R * NT == A3 || s < A3) && m >= m0) v = xe[(int64_t)(fc * nlev + m - m0) * A3 + s];
-        xr[fc][m][r] = v;
-      }
+      xr[fc][m] = (pos_lane && m >= m0) ? xe[s + (uint32_t)((fc * nlev + m - m0) * A3)] : T(0);
 
-  // metric of K (uniform loads)
+  // ---- neighbour traces, contracted in time: acc[face][i] --------------------
+  T acc[6][Q];
+#pragma unroll
+  for (int g = 0; g < 6; ++g)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) acc[g][i] = T(0);
+
+#pragma unroll
+  for (int g = 0; g < 6; ++g) {
+    const int alpha = g >> 1, side = g & 1;
+    if (nb_id[g] < 0 || !face_lane) continue;
+    const int c = (alpha + 1 + (tc & 1)) % 3;
+    const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
+    if (fast) {
+      const int ns = face_stride(alpha, A);
+      const uint32_t lo = (uint32_t)((3 * tf + c) * nlev * A3 + face_base(alpha, fu, fv, A));
+      const T* xb = nb_x[g];
+      T vals[Q + 1][A];
+#pragma unroll
+      for (int mp = 0; mp <= Q; ++mp)
+#pragma unroll
+        for (int l = 0; l < A; ++l)
+          vals[mp][l] = (mp >= m0) ? xb[lo + (uint32_t)((mp - m0) * A3 + l * ns)] : T(0);
+      // the neighbour's face sits at 1 - side: weights L_l(1 - side)
+#pragma unroll
+      for (int mp = 0; mp <= Q; ++mp) {
+        T tr = T(0);
+#pragma unroll
+        for (int l = 0; l < A; ++l) tr += (side ? P.tab.tr0[l] : P.tab.tr1[l]) * vals[mp][l];
+        tr *= scale;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
+      }
+    } else {
+      // different degrees across this element's faces: p-truncated coupling,
+      // S_h on test levels i >= min(q, q')
+      const int na = nb_a[g], nq = nb_q[g];
+      if (fu >= na || fv >= na) continue;
+      const int na3 = na * na * na;
+      const int ns = face_stride(alpha, na);
+      const int nnlev = resid ? nq + 1 : nq;
+      const T* xb = nb_x[g] + (int64_t)(3 * tf + c) * nnlev * na3 + face_base(alpha, fu, fv, na);
+#pragma unroll
+      for (int mp = 0; mp <= kMaxQ; ++mp) {
+        if (mp < m0 || mp > nq) continue;
+        const T* xl = xb + (int64_t)(mp - m0) * na3;
+        T tr = T(0);
+        for (int l = 0; l < na; ++l) {
+          const T rho = dsqrt<T>(T(2 * l + 1));
+          tr += ((side && (l & 1)) ? -rho : rho) * xl[l * ns];
+        }
+        tr *= scale;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          if (nnzN(i, mp) && i < nq) acc[g][i] += P.tab.N[i][mp] * tr;
+      }
+    }
+  }
+
+  // ---- metric (uniform), per-position and per-face-mode constants ------------
   T Me[6], Mh[6], Ie[6], Ih[6];
   {
     const double* mm = P.metric[e].m;
@@ -133,260 +231,170 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
       Ih[k] = (T)mm[18 + k];
     }
   }
-  __syncthreads();
-
-  // neighbour table, uniform per block (scalar loads): id, degrees, offset, P^{-1} diagonal
-  int nb_id[6], nb_a[6], nb_q[6];
-  int64_t nb_off[6];
-  T nb_sc[6][6];
+  int sidx[3];
+  sidx[0] = (int)(s % A);
+  sidx[1] = (int)((s / A) % A);
+  sidx[2] = (int)(s / A2);
+  T rsm[3], sg[3], cf[3], mE[3][ND > 0 ? ND : 1], mH[3][ND > 0 ? ND : 1];
+  T w = T(1);
 #pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    nb_id[f] = Ip->nb[f];
-    nb_a[f] = A;
-    nb_q[f] = Q;
-    nb_off[f] = 0;
+  for (int m = 0; m < 3; ++m) {
+    rsm[m] = dsqrt<T>(T(2 * sidx[m] + 1));
+    sg[m] = (sidx[m] & 1) ? T(-1) : T(1);
+    w *= rsm[m];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) nb_sc[f][k] = T(1);
-    if (nb_id[f] >= 0) {
-      const ElemInfo* Np = P.info + nb_id[f];
-      nb_a[f] = Np->a;
-      nb_q[f] = Np->q;
-      nb_off[f] = resid ? Np->trial_off : Np->unk_off;
-      if (pre) {
-        const double* mm = P.metric[nb_id[f]].m;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          nb_sc[f][k] = (T)mm[12 + k];
-          nb_sc[f][3 + k] = (T)mm[18 + k];
-        }
-      }
+    for (int dd = 0; dd < ND; ++dd) {
+      mE[m][dd] = sidx[m] >= 2 * dd + 1 ? T(1) : T(0);
+      mH[m][dd] = sidx[m] + 2 * dd + 1 < A ? T(1) : T(0);
     }
   }
-
-  // neighbour traces, contracted in time: acc[k][i]
-  T acc[IPL][Q];
-  int nbk[IPL];
+  const T winv = T(1) / w;
+  // Dh[n][s_m] X(s_m -> n) = 2 rho_{s_m}^2 / w(s) * (w X)(s_m -> n)
 #pragma unroll
-  for (int k = 0; k < IPL; ++k) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) acc[k][i] = T(0);
-    nbk[k] = -1;
-    const int it = tid + NT * k;
-    if (NI % NT != 0 && it >= NI) continue;
-    const int phi = it / (4 * A2);
-    const int rem = it - phi * (4 * A2);
-    const int tc = rem / A2;
-    const int t = rem - tc * A2;
-    const int alpha = phi >> 1, side = phi & 1;
-    const int f = tc >> 1;
-    const int c = (alpha + 1 + (tc & 1)) % 3;
-    // select this item's face from the uniform table
-    int nbe = -1, na = A, nq = Q;
-    int64_t noff = 0;
-    T scale = T(1);
-#pragma unroll
-    for (int g = 0; g < 6; ++g)
-      if (phi == g) {
-        nbe = nb_id[g];
-        na = nb_a[g];
-        nq = nb_q[g];
-        noff = nb_off[g];
-#pragma unroll
-        for (int kk = 0; kk < 6; ++kk)
-          if (3 * f + c == kk) scale = nb_sc[g][kk];
-      }
-    nbk[k] = nbe;
-    if (nbe < 0) continue;
-    const int u = t % A, v = t / A;
-    if (u >= na || v >= na) continue;
-    const int na2 = na * na, na3 = na2 * na;
-    int tb, ns;
-    if (alpha == 0) { tb = na * u + na2 * v; ns = 1; }
-    else if (alpha == 1) { tb = u + na2 * v; ns = na; }
-    else { tb = u + na * v; ns = na2; }
-    const int nnlev = resid ? nq + 1 : nq;
-    const T* xb = P.x + noff + (int64_t)(3 * f + c) * nnlev * na3 + tb;
-    const T* tau = side ? s_t0 : s_t1;  // neighbour's face sits at 1 - side
-    if (na == A && nq == Q) {
-      // same degrees (the common case): compile-time trip counts, so every load
-      // of the item is in flight before the reductions start
-      T vals[Q + 1][A];
-#pragma unroll
-      for (int mp = 0; mp <= Q; ++mp)
-#pragma unroll
-        for (int l = 0; l < A; ++l)
-          vals[mp][l] = (mp >= m0) ? xb[(int64_t)(mp - m0) * A3 + l * ns] : T(0);
-#pragma unroll
-      for (int mp = 0; mp <= Q; ++mp) {
-        T tr = T(0);
-#pragma unroll
-        for (int l = 0; l < A; ++l) tr += tau[l] * vals[mp][l];
-        tr *= scale;
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-          if (nnzN(i, mp)) acc[k][i] += P.tab.N[i][mp] * tr;
-      }
-      continue;
-    }
-#pragma unroll
-    for (int mp = 0; mp <= kMaxQ; ++mp) {
-      if (mp < m0 || mp > nq) continue;
-      const T* xl = xb + (int64_t)(mp - m0) * na3;
-      T tr = T(0);
-      for (int l = 0; l < na; ++l) tr += tau[l] * xl[l * ns];
-      tr *= scale;
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-        if (nnzN(i, mp) && i < nq) acc[k][i] += P.tab.N[i][mp] * tr;
-    }
-  }
+  for (int m = 0; m < 3; ++m) cf[m] = T(2 * (2 * sidx[m] + 1)) * winv;
+  // sum_l L_l(side) X_l = (1 / (rho_u rho_v)) sum_l (+-1)^l (w X)_l
+  const T iuv = T(1) / (dsqrt<T>(T(2 * fu + 1)) * dsqrt<T>(T(2 * fv + 1)));
+  const int tgt[3] = {sidx[1] + A * sidx[2], sidx[0] + A * sidx[2], sidx[0] + A * sidx[1]};
+  constexpr int stride[3] = {1, A, A2};
 
   const T dt = P.dt;
-  const T* ld = (resid && P.load) ? P.load + yoff : nullptr;
-  T* ye = P.y + yoff;
+  const T* ld = (resid && P.load) ? P.load + Ip->unk_off : nullptr;
 
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    // (a) contracted level E~_i, H~_i into LDS
+  for (int i0 = 0; i0 < Q; i0 += LC) {
+    // (a) contracted levels, scaled by w(s), into LDS
+    if (pos_lane) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int s = tid + NT * r;
-      if (!(R * NT == A3 || s < A3)) continue;
-      T et[6];
+      for (int ii = 0; ii < LC; ++ii) {
+        const int i = i0 + ii;
+        if (i >= Q) break;
 #pragma unroll
-      for (int fc = 0; fc < 6; ++fc) {
-        T v = T(0);
+        for (int f = 0; f < 2; ++f) {
+          T et[3];
 #pragma unroll
-        for (int m = 0; m <= Q; ++m)
-          if (nnzN(i, m)) v += P.tab.N[i][m] * xr[fc][m][r];
-        et[fc] = v;
-      }
-      if (pre) {
-        T z[6];
+          for (int c = 0; c < 3; ++c) {
+            T v = T(0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          z[c] = symget(Ie, c, 0) * et[0] + symget(Ie, c, 1) * et[1] + symget(Ie, c, 2) * et[2];
-          z[3 + c] = symget(Ih, c, 0) * et[3] + symget(Ih, c, 1) * et[4] + symget(Ih, c, 2) * et[5];
+            for (int m = 0; m <= Q; ++m)
+              if (nnzN(i, m)) v += P.tab.N[i][m] * xr[3 * f + c][m];
+            et[c] = v;
+          }
+          if (pre) {
+            const T* Mi = f == 0 ? Ie : Ih;
+            T z[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              z[c] = symget(Mi, c, 0) * et[0] + symget(Mi, c, 1) * et[1] + symget(Mi, c, 2) * et[2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) et[c] = z[c];
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c) sm[ii * LVL + (3 * f + c) * A3 + s] = w * et[c];
         }
-#pragma unroll
-        for (int fc = 0; fc < 6; ++fc) et[fc] = z[fc];
       }
-#pragma unroll
-      for (int fc = 0; fc < 6; ++fc) Et[fc * A3 + s] = et[fc];
     }
     __syncthreads();
 
-    // (b) face fluxes into LDS
+    // (b) face fluxes: own traces of both faces of an axis from one pass, plus
+    //     the neighbour traces
+    if (face_lane) {
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-      const int it = tid + NT * k;
-      if (NI % NT != 0 && it >= NI) continue;
-      const int phi = it / (4 * A2);
-      const int rem = it - phi * (4 * A2);
-      const int tc = rem / A2;
-      const int t = rem - tc * A2;
-      const int alpha = phi >> 1, side = phi & 1;
-      const int f = tc >> 1;
-      const int c = (alpha + 1 + (tc & 1)) % 3;
-      int tb, ns;
-      if (alpha == 0) { tb = A * t; ns = 1; }
-      else if (alpha == 1) { tb = (t % A) + A2 * (t / A); ns = A; }
-      else { tb = t; ns = A2; }
-      const T* tau = side ? s_t1 : s_t0;
-      const T* src = Et + (3 * f + c) * A3 + tb;
-      T ts = T(0);
+      for (int alpha = 0; alpha < 3; ++alpha) {
+        const int c = (alpha + 1 + (tc & 1)) % 3;
+        const int ns = face_stride(alpha, A);
+        const int base = (3 * tf + c) * A3 + face_base(alpha, fu, fv, A);
 #pragma unroll
-      for (int l = 0; l < A; ++l) ts += tau[l] * src[l * ns];
-      T val;
-      if (nbk[k] >= 0) val = (f == 0 ? T(-0.5) : T(0.5)) * ts + T(0.5) * acc[k][i];
-      else val = (f == 0 ? T(-1) : T(1)) * ts;
-      Fl[it] = val;
+        for (int ii = 0; ii < LC; ++ii) {
+          const int i = i0 + ii;
+          if (i >= Q) break;
+          const T* src = sm + ii * LVL + base;
+          T s1 = T(0), s0 = T(0);
+#pragma unroll
+          for (int l = 0; l < A; ++l) {
+            const T v = src[l * ns];
+            s1 += v;
+            s0 += (l & 1) ? -v : v;
+          }
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int g = 2 * alpha + side;
+            const bool has = nb_id[g] >= 0;
+            const T ws = has ? T(0.5) : T(1);
+            T val = (tf == 0 ? -ws : ws) * iuv * (side ? s1 : s0);  // G = -w T(E), F = w T(H)
+            if (has) val += T(0.5) * acc[g][i];
+            sm[ii * LVL + 6 * A3 + (g * 4 + tc) * A2 + t] = val;
+          }
+        }
+      }
     }
     __syncthreads();
 
     // (c) outputs: mass + dt (curl + lift) - load
+    if (pos_lane) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int s = tid + NT * r;
-      if (!(R * NT == A3 || s < A3)) continue;
-      const int sj = s % A, sk = (s / A) % A, sl = s / A2;
-      const int sidx[3] = {sj, sk, sl};
-      const int tgt[3] = {sk + A * sl, sj + A * sl, sj + A * sk};  // tangential index per normal axis
-      const T rho_s[3] = {s_rho[sj], s_rho[sk], s_rho[sl]};
-      const T tr0s[3] = {s_t0[sj], s_t0[sk], s_t0[sl]};
-      const T tr1s[3] = {s_t1[sj], s_t1[sk], s_t1[sl]};
+      for (int ii = 0; ii < LC; ++ii) {
+        const int i = i0 + ii;
+        if (i >= Q) break;
+        const T* Et = sm + ii * LVL;
+        const T* Fl = Et + 6 * A3;
 #pragma unroll
-      for (int f = 0; f < 2; ++f) {
+        for (int f = 0; f < 2; ++f) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-          constexpr int stride[3] = {1, A, A2};
-          T cu = T(0);
-          if (f == 0) {
-            // + sum_{n < s_c1} Dh[n][s_c1] H_c2(s_c1 -> n) - sum_{n < s_c2} Dh[n][s_c2] H_c1(s_c2 -> n)
-            const T* H2 = Et + (3 + c2) * A3;
-            const T* H1 = Et + (3 + c1) * A3;
+          for (int c = 0; c < 3; ++c) {
+            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            // curl: the other field's components c2 (along axis c1) and c1 (along axis c2)
+            const T* X2 = Et + ((f == 0 ? 3 : 0) + c2) * A3 + s;
+            const T* X1 = Et + ((f == 0 ? 3 : 0) + c1) * A3 + s;
             T p1 = T(0), p2 = T(0);
 #pragma unroll
-            for (int d = 1; d < A; d += 2) {
-              const int n1 = sidx[c1] - d;
-              if (n1 >= 0) p1 += s_rho[n1] * H2[s - d * stride[c1]];
-              const int n2 = sidx[c2] - d;
-              if (n2 >= 0) p2 += s_rho[n2] * H1[s - d * stride[c2]];
+            for (int dd = 0; dd < ND; ++dd) {
+              const int d = 2 * dd + 1;
+              if (f == 0) {
+                p1 += mE[c1][dd] * X2[-d * stride[c1]];
+                p2 += mE[c2][dd] * X1[-d * stride[c2]];
+              } else {
+                p1 += mH[c1][dd] * X2[d * stride[c1]];
+                p2 += mH[c2][dd] * X1[d * stride[c2]];
+              }
             }
-            cu = T(2) * (rho_s[c1] * p1 - rho_s[c2] * p2);
-          } else {
-            // + sum_{n > s_c1} Dh[s_c1][n] E_c2(s_c1 -> n) - sum_{n > s_c2} Dh[s_c2][n] E_c1(s_c2 -> n)
-            const T* E2 = Et + c2 * A3;
-            const T* E1 = Et + c1 * A3;
-            T p1 = T(0), p2 = T(0);
+            const T cu = cf[c1] * p1 - cf[c2] * p2;
+            // lifts from the four faces whose normal is not c
+            T lift = T(0);
 #pragma unroll
-            for (int d = 1; d < A; d += 2) {
-              const int n1 = sidx[c1] + d;
-              if (n1 < A) p1 += s_rho[n1] * E2[s + d * stride[c1]];
-              const int n2 = sidx[c2] + d;
-              if (n2 < A) p2 += s_rho[n2] * E1[s + d * stride[c2]];
+            for (int wv = 0; wv < 2; ++wv) {
+              const int alpha = wv == 0 ? c1 : c2;
+              const int dcomp = wv == 0 ? c2 : c1;
+              const T epsv = (alpha == c2) ? T(1) : T(-1);  // eps(c, d, alpha)
+              const int tcd = (dcomp == (alpha + 1) % 3 ? 0 : 1) + (f == 0 ? 2 : 0);
+              const T v0 = Fl[((2 * alpha + 0) * 4 + tcd) * A2 + tgt[alpha]];
+              const T v1 = Fl[((2 * alpha + 1) * 4 + tcd) * A2 + tgt[alpha]];
+              // sigma L_{s_alpha}(side): +rho on side 1, -(-1)^{s_alpha} rho on side 0
+              const T lv = rsm[alpha] * (v1 - sg[alpha] * v0);
+              lift += (f == 0 ? epsv : -epsv) * lv;
             }
-            cu = T(2) * (rho_s[c1] * p1 - rho_s[c2] * p2);
-          }
-          // lifts from the four faces whose normal is not c
-          T lift = T(0);
-#pragma unroll
-          for (int w = 0; w < 2; ++w) {
-            const int alpha = w == 0 ? c1 : c2;
-            const int dcomp = w == 0 ? c2 : c1;
-            const T epsv = (alpha == c2) ? T(1) : T(-1);  // eps(c, d, alpha)
-            const int tcd = (dcomp == (alpha + 1) % 3 ? 0 : 1) + (f == 0 ? 2 : 0);
-            const int t = tgt[alpha];
-            const T v0 = Fl[((2 * alpha + 0) * 4 + tcd) * A2 + t];
-            const T v1 = Fl[((2 * alpha + 1) * 4 + tcd) * A2 + t];
-            // sigma = -1 on side 0, +1 on side 1
-            const T l = tr1s[alpha] * v1 - tr0s[alpha] * v0;
-            lift += (f == 0 ? epsv : -epsv) * l;
-          }
-          // mass: the time-derivative factor is the shift delta_{m,i+1} - delta_{i0} delta_{m0}
-          T mass;
-          const int fo = 3 * f;
-          if (pre) {
-            mass = xr[fo + c][i + 1][r];
-          } else {
-            const T* Mm = f == 0 ? Me : Mh;
-            T v0 = xr[fo + 0][i + 1][r], v1 = xr[fo + 1][i + 1][r], v2 = xr[fo + 2][i + 1][r];
-            if (i == 0) {
-              v0 -= xr[fo + 0][0][r];
-              v1 -= xr[fo + 1][0][r];
-              v2 -= xr[fo + 2][0][r];
+            // mass: the time-derivative factor is the shift delta_{m,i+1} - delta_{i0} delta_{m0}
+            T mass;
+            if (pre) {
+              mass = xr[3 * f + c][i + 1];
+            } else {
+              const T* Mm = f == 0 ? Me : Mh;
+              T v0 = xr[3 * f + 0][i + 1], v1 = xr[3 * f + 1][i + 1], v2 = xr[3 * f + 2][i + 1];
+              if (i == 0) {
+                v0 -= xr[3 * f + 0][0];
+                v1 -= xr[3 * f + 1][0];
+                v2 -= xr[3 * f + 2][0];
+              }
+              mass = symget(Mm, c, 0) * v0 + symget(Mm, c, 1) * v1 + symget(Mm, c, 2) * v2;
             }
-            mass = symget(Mm, c, 0) * v0 + symget(Mm, c, 1) * v1 + symget(Mm, c, 2) * v2;
+            T out = mass + dt * (cu + lift);
+            const uint32_t o = s + (uint32_t)(((3 * f + c) * Q + i) * A3);
+            if (ld) out -= ld[o];
+            ye[o] = out;
           }
-          T out = mass + dt * (cu + lift);
-          const int64_t o = (int64_t)((fo + c) * Q + i) * A3 + s;
-          if (ld) out -= ld[o];
-          ye[o] = out;
         }
       }
     }
-    __syncthreads();
+    if (i0 + LC < Q) __syncthreads();
   }
 }
 
