@@ -59,8 +59,17 @@ struct KCfg {
     constexpr int c = 16384 / (LVL * (int)sizeof(T));
     return c < 1 ? 1 : (c > Q ? Q : c);
   }
+  // neighbour blocks are staged through LDS a face at a time (4 tangential
+  // component blocks of up to q + 1 levels, double-buffered) when one face
+  // fits in 24 KB; larger ones are gathered straight from global memory
   template <typename T, int Q>
-  static constexpr int lds_elems() { return LC<T, Q>() * LVL; }
+  static constexpr bool stage() { return 4 * (Q + 1) * A3 * (int)sizeof(T) <= 24576; }
+  template <typename T, int Q>
+  static constexpr int lds_elems() {
+    // staged contracted levels, or (aliased, used earlier) the staging buffers
+    constexpr int a = LC<T, Q>() * LVL, b = stage<T, Q>() ? 2 * 4 * (Q + 1) * A3 : 0;
+    return a > b ? a : b;
+  }
 };
 
 template <typename T>
@@ -72,7 +81,7 @@ struct KParams {
   const T* load;
   T* y;
   T dt;
-  int mode;  // 0 operator, 1 residual, 2 operator with P^{-1} (diagonal metrics)
+  int mode;  // kept for launch bookkeeping; the kernels take the mode as a template argument
   Tables<T> tab;
 };
 
@@ -94,6 +103,29 @@ __device__ __forceinline__ float dsqrt<float>(float v) {
   return __fsqrt_rn(v);
 }
 
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off);
+template <>
+__device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)byte_off, 0, 0);
+}
+
 // stride along the normal and base offset of tangential mode (u, v) on a
 // face normal to alpha, in a block of edge n (x-hat index fastest)
 __host__ __device__ constexpr int face_stride(int alpha, int n) { return alpha == 0 ? 1 : (alpha == 1 ? n : n * n); }
@@ -101,11 +133,16 @@ __device__ __forceinline__ int face_base(int alpha, int u, int v, int n) {
   return alpha == 0 ? n * u + n * n * v : (alpha == 1 ? u + n * n * v : u + n * v);
 }
 
-template <typename T, int A, int Q>
+template <typename T, int A, int Q, int MODE>
 __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T> P) {
   using C = KCfg<A>;
   constexpr int A2 = C::A2, A3 = C::A3, NF = C::NF, ND = C::ND, LVL = C::LVL;
   constexpr int LC = C::template LC<T, Q>();
+  constexpr bool resid = MODE == 1, pre = MODE == 2;  // operator / residual / operator with P^{-1}
+  constexpr int m0 = resid ? 0 : 1;                   // first trial level stored in x
+  constexpr int NL = Q + 1 - m0;                      // trial levels stored per component
+  constexpr int BLK = 6 * NL * A3 * (int)sizeof(T);   // bytes of one element block of x
+  constexpr int WORDS = (int)sizeof(T) / 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
 
@@ -117,10 +154,6 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
   const uint32_t logical = xcd * qq + (xcd < rr ? xcd : rr) + idx;
   const int e = P.list[logical];
   const ElemInfo* Ip = P.info + e;
-  const int mode = P.mode;
-  const bool resid = mode == 1, pre = mode == 2;
-  const int m0 = resid ? 0 : 1;
-  const int nlev = resid ? Q + 1 : Q;
   const T* xe = P.x + (resid ? Ip->trial_off : Ip->unk_off);
   T* ye = P.y + Ip->unk_off;
 
@@ -146,18 +179,24 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
   const bool pos_lane = tid < A3;
   const uint32_t s = pos_lane ? (uint32_t)tid : 0u;
   const bool face_lane = tid < NF;
-  const int tc = face_lane ? tid / A2 : 0;  // tangential component slot 0..3
-  const int t = face_lane ? tid - tc * A2 : 0;
+  // face item of this thread; threads past the items compute offsets beyond
+  // the block, which the buffer range check turns into zero loads
+  const int tc = tid / A2;                 // tangential component slot 0..3
+  const int t = tid - tc * A2;
   const int fu = t % A, fv = t / A;        // tangential mode (u, v)
   const int tf = tc >> 1;                  // field of that component
 
   // ---- own block: all components and levels of position s ------------------
   T xr[6][Q + 1];
+  {
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)xe, (short)0, BLK, 0x00020000);
+    const uint32_t so = (uint32_t)tid * (uint32_t)sizeof(T);
 #pragma unroll
-  for (int fc = 0; fc < 6; ++fc)
+    for (int fc = 0; fc < 6; ++fc)
 #pragma unroll
-    for (int m = 0; m <= Q; ++m)
-      xr[fc][m] = (pos_lane && m >= m0) ? xe[s + (uint32_t)((fc * nlev + m - m0) * A3)] : T(0);
+      for (int m = 0; m <= Q; ++m)
+        xr[fc][m] = m >= m0 ? buf_load<T>(rsrc, so + (uint32_t)(((fc * NL + m - m0) * A3) * (int)sizeof(T))) : T(0);
+  }
 
   // ---- neighbour traces, contracted in time: acc[face][i] --------------------
   T acc[6][Q];
@@ -166,36 +205,113 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
 #pragma unroll
     for (int i = 0; i < Q; ++i) acc[g][i] = T(0);
 
+  if (fast && C::template stage<T, Q>()) {
+    // Neighbour blocks are read with unit-stride (coalesced) loads - thread
+    // tid takes entries tid, tid + NT, ... of each tangential component block -
+    // for a batch of GB faces at once, then passed face by face through a
+    // double-buffered LDS staging area where the face lanes reduce them.
+    constexpr int CH = NL * A3;                     // entries per component block
+    constexpr int KC = (CH + C::NT - 1) / C::NT;    // loads per thread per block
+    constexpr int GBC0 = 96 / (4 * KC * WORDS);
+    constexpr int GBC = GBC0 < 1 ? 1 : (GBC0 > 6 ? 6 : GBC0);
+    int nstaged = 0;  // staged faces so far (uniform): buffers strictly alternate
 #pragma unroll
-  for (int g = 0; g < 6; ++g) {
-    const int alpha = g >> 1, side = g & 1;
-    if (nb_id[g] < 0 || !face_lane) continue;
-    const int c = (alpha + 1 + (tc & 1)) % 3;
-    const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
-    if (fast) {
+    for (int g0 = 0; g0 < 6; g0 += GBC) {
+      T nbv[GBC][4][KC];
+#pragma unroll
+      for (int gg = 0; gg < GBC; ++gg) {
+        const int g = g0 + gg;
+        if (g >= 6) break;
+        if (nb_id[g] < 0) continue;
+        const int alpha = g >> 1;
+        const __amdgpu_buffer_rsrc_t rsrc =
+            __builtin_amdgcn_make_buffer_rsrc((void*)nb_x[g], (short)0, BLK, 0x00020000);
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int fc = 3 * (q4 >> 1) + (alpha + 1 + (q4 & 1)) % 3;
+#pragma unroll
+          for (int k = 0; k < KC; ++k)
+            nbv[gg][q4][k] = buf_load<T>(rsrc, (uint32_t)((fc * CH + k * C::NT) * (int)sizeof(T)) +
+                                                   (uint32_t)tid * (uint32_t)sizeof(T));
+        }
+      }
+#pragma unroll
+      for (int gg = 0; gg < GBC; ++gg) {
+        const int g = g0 + gg;
+        if (g >= 6) break;
+        if (nb_id[g] < 0) continue;
+        const int alpha = g >> 1, side = g & 1;
+        T* stg = sm + (nstaged & 1) * (4 * CH);
+        ++nstaged;
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+          for (int k = 0; k < KC; ++k) {
+            const int p = tid + k * C::NT;
+            if (CH % C::NT == 0 || p < CH) stg[q4 * CH + p] = nbv[gg][q4][k];
+          }
+        __syncthreads();
+        if (face_lane) {
+          const int c = (alpha + 1 + (tc & 1)) % 3;
+          const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
+          const int ns = face_stride(alpha, A);
+          const T* src = stg + tc * CH + face_base(alpha, fu, fv, A);
+          // the neighbour's face sits at 1 - side: weights L_l(1 - side)
+#pragma unroll
+          for (int ml = 0; ml < NL; ++ml) {
+            const int mp = ml + m0;
+            T tr = T(0);
+#pragma unroll
+            for (int l = 0; l < A; ++l) tr += (side ? P.tab.tr0[l] : P.tab.tr1[l]) * src[ml * A3 + l * ns];
+            tr *= scale;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+              if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
+          }
+        }
+      }
+    }
+    __syncthreads();  // staging area is reused for the contracted levels
+  } else if (fast) {
+    // faces too large to stage: gather each face item straight from global
+    // memory (one buffer descriptor per face, compile-time immediates)
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+      if (nb_id[g] < 0) continue;
+      const int alpha = g >> 1, side = g & 1;
+      const int c = (alpha + 1 + (tc & 1)) % 3;
       const int ns = face_stride(alpha, A);
-      const uint32_t lo = (uint32_t)((3 * tf + c) * nlev * A3 + face_base(alpha, fu, fv, A));
-      const T* xb = nb_x[g];
-      T vals[Q + 1][A];
+      const __amdgpu_buffer_rsrc_t rsrc =
+          __builtin_amdgcn_make_buffer_rsrc((void*)nb_x[g], (short)0, BLK, 0x00020000);
+      const uint32_t lo = (uint32_t)(((3 * tf + c) * NL * A3 + face_base(alpha, fu, fv, A)) * (int)sizeof(T));
+      T vals[NL][A];
 #pragma unroll
-      for (int mp = 0; mp <= Q; ++mp)
+      for (int ml = 0; ml < NL; ++ml)
 #pragma unroll
-        for (int l = 0; l < A; ++l)
-          vals[mp][l] = (mp >= m0) ? xb[lo + (uint32_t)((mp - m0) * A3 + l * ns)] : T(0);
-      // the neighbour's face sits at 1 - side: weights L_l(1 - side)
+        for (int l = 0; l < A; ++l) vals[ml][l] = buf_load<T>(rsrc, lo + (uint32_t)((ml * A3 + l * ns) * (int)sizeof(T)));
+      if (!face_lane) continue;
+      const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
 #pragma unroll
-      for (int mp = 0; mp <= Q; ++mp) {
+      for (int ml = 0; ml < NL; ++ml) {
+        const int mp = ml + m0;
         T tr = T(0);
 #pragma unroll
-        for (int l = 0; l < A; ++l) tr += (side ? P.tab.tr0[l] : P.tab.tr1[l]) * vals[mp][l];
+        for (int l = 0; l < A; ++l) tr += (side ? P.tab.tr0[l] : P.tab.tr1[l]) * vals[ml][l];
         tr *= scale;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
           if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
       }
-    } else {
-      // different degrees across this element's faces: p-truncated coupling,
-      // S_h on test levels i >= min(q, q')
+    }
+  } else if (face_lane) {
+    // different degrees around this element: p-truncated coupling, and S_h
+    // drops the neighbour term on test levels i >= min(q, q')
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+      const int alpha = g >> 1, side = g & 1;
+      if (nb_id[g] < 0) continue;
+      const int c = (alpha + 1 + (tc & 1)) % 3;
+      const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
       const int na = nb_a[g], nq = nb_q[g];
       if (fu >= na || fv >= na) continue;
       const int na3 = na * na * na;
@@ -258,7 +374,12 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
   constexpr int stride[3] = {1, A, A2};
 
   const T dt = P.dt;
-  const T* ld = (resid && P.load) ? P.load + Ip->unk_off : nullptr;
+  const bool has_load = resid && P.load != nullptr;
+  const __amdgpu_buffer_rsrc_t yrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)ye, (short)0, 6 * Q * A3 * (int)sizeof(T), 0x00020000);
+  const __amdgpu_buffer_rsrc_t lrs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(has_load ? P.load + Ip->unk_off : ye), (short)0, 6 * Q * A3 * (int)sizeof(T), 0x00020000);
+  const uint32_t so = (uint32_t)tid * (uint32_t)sizeof(T);
 
 #pragma unroll
   for (int i0 = 0; i0 < Q; i0 += LC) {
@@ -276,7 +397,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
             T v = T(0);
 #pragma unroll
             for (int m = 0; m <= Q; ++m)
-              if (nnzN(i, m)) v += P.tab.N[i][m] * xr[3 * f + c][m];
+              if (nnzN(i, m) && m >= m0) v += P.tab.N[i][m] * xr[3 * f + c][m];
             et[c] = v;
           }
           if (pre) {
@@ -379,7 +500,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
             } else {
               const T* Mm = f == 0 ? Me : Mh;
               T v0 = xr[3 * f + 0][i + 1], v1 = xr[3 * f + 1][i + 1], v2 = xr[3 * f + 2][i + 1];
-              if (i == 0) {
+              if (resid && i == 0) {
                 v0 -= xr[3 * f + 0][0];
                 v1 -= xr[3 * f + 1][0];
                 v2 -= xr[3 * f + 2][0];
@@ -387,9 +508,9 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
               mass = symget(Mm, c, 0) * v0 + symget(Mm, c, 1) * v1 + symget(Mm, c, 2) * v2;
             }
             T out = mass + dt * (cu + lift);
-            const uint32_t o = s + (uint32_t)(((3 * f + c) * Q + i) * A3);
-            if (ld) out -= ld[o];
-            ye[o] = out;
+            const uint32_t o = so + (uint32_t)((((3 * f + c) * Q + i) * A3) * (int)sizeof(T));
+            if (has_load) out -= buf_load<T>(lrs, o);
+            buf_store<T>(out, yrs, o);
           }
         }
       }
