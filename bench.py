@@ -67,6 +67,28 @@ def time_applies(stdg, torch, mh, dt, prec, mode, x, y, steps, warmup):
     return wall, per
 
 
+def measured_traffic(prec):
+    """HBM bytes per launch of the timed kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current kernel
+    source (else None)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("residual_kernel.h", "residual_inst.hip"):
+        with open(os.path.join(ROOT, "paper_1307_5310_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    path = os.path.join(ROOT, "profiles", "residual_apply_cavity32_p4q3_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if ("sha256[:16] (residual_kernel.h + residual_inst.hip): " + h.hexdigest()[:16]) not in text:
+        return None
+    key = "traffic_bytes_%s = " % ("fp32" if prec == 1 else "fp64")
+    for line in text.splitlines():
+        if line.startswith(key):
+            return float(line[len(key):])
+    return None
+
+
 def cpu_baseline(cfg, sample_n):
     """The oracle as it stands, on a bounded sample of the workload's elements."""
     from oracle.dg import Discretisation
@@ -186,7 +208,8 @@ def main():
                  "hbm_frac": round(bytes64 / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "fp32_over_fp64": round(gdofs32 / gdofs64, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(1) if (args.n, args.p, args.q) == (32, 4, 3) else None,
                      "kernel": "residual_affine_kernel<float,5,3>", "kernel_ms": round(k32, 5),
                      "algorithmic_bytes": bytes32},
         "cpu_baseline": cpu,
