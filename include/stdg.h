@@ -73,6 +73,11 @@ typedef enum {
   STDG_RESIDUAL = 1,         /* y = B_h U - L : U = full trial incl. the l_0 block; L may be NULL  */
   STDG_OPERATOR_PRECOND = 2  /* y = B_h P^{-1} x with P the time-derivative terms (eq. preconditioner) */
 } stdg_mode;
+/* P is block diagonal: per element and level, the 3x3-per-spatial-mode mass
+ * eps|J|DF^{-1}DF^{-T} (mu for H), exact on affine elements and taken at the
+ * element centre on trilinear ones.  On axis-aligned meshes P^{-1} is fused
+ * into the apply; otherwise the first such call allocates an unknown-sized
+ * scratch vector owned by the mesh (STDG_E_NOMEM past the context budget). */
 
 typedef struct stdg_ctx stdg_ctx;
 typedef struct stdg_mesh stdg_mesh;
@@ -130,6 +135,10 @@ int stdg_mesh_free(stdg_mesh* mesh);
 
 /* The hot path: the matrix-free space-time residual of one slab (Section 5,
  * eq. residual; evaluation of Section 5.2: mass, curl and flux terms).
+ * Affine elements use their constant metric; trilinear elements integrate the
+ * mass term with the tensor Gauss-Legendre rule of p + 2 points per direction
+ * (Section 5.2, non-affine mass), curl and flux being geometry-free for
+ * covariant maps on conforming faces.
  *   dt    slab length (> 0)
  *   prec  STDG_FP64 (double vectors) or STDG_FP32 (float vectors, FP32 accumulation)
  *   mode  stdg_mode above; x_dev layout = unknowns (OPERATOR*) or full trial (RESIDUAL)
@@ -193,7 +202,8 @@ int stdg_slab_solve(const stdg_mesh* mesh, double t0, double dt, const double* l
                     const stdg_solve_opts* opts, double* state_dev, double* slab_U_dev,
                     stdg_solve_info* info, void* stream);
 
-/* Discrete energy 1/2 int (eps E.E + mu H.H) of an FP64 state (eq. stability:energydef). */
+/* Discrete energy 1/2 int (eps E.E + mu H.H) of an FP64 state (eq. stability:energydef);
+ * on trilinear elements with the mass rule of the residual (p + 2 Gauss points per direction). */
 int stdg_energy(const stdg_mesh* mesh, const double* state_dev, double* energy_out, void* stream);
 
 #ifdef __cplusplus

@@ -384,6 +384,28 @@ class Discretisation:
             out[self.unk_off[e]:self.unk_off[e + 1]] = res.ravel()
         return out
 
+    def precond_centre_solve(self, y, elements=None):
+        """P_c^{-1} y with P_c the block mass taken with the metric at the element
+        centre: kappa G(1/2, 1/2, 1/2) (x) I per level, G = |J| DF^{-1} DF^{-T}.
+        On affine elements this is the exact P (orthonormal basis, constant
+        metric); on trilinear ones it is the cheaper approximation of the block
+        mass that the preconditioner may use (Section 5.4 leaves P's
+        evaluation open; the converged slab solution does not depend on it)."""
+        out = np.zeros_like(y)
+        for e in (range(self.ne) if elements is None else elements):
+            e = int(e)
+            a3 = int(self.a[e]) ** 3
+            qe = int(self.q[e])
+            DF = jacobian(self.X(e), np.array([[0.5, 0.5, 0.5]]))[0]
+            Di = np.linalg.inv(DF)
+            G = np.linalg.det(DF) * Di @ Di.T
+            blk = y[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, qe * a3)
+            res = np.empty_like(blk)
+            res[0] = np.linalg.solve(self.eps[e] * G, blk[0])
+            res[1] = np.linalg.solve(self.mu[e] * G, blk[1])
+            out[self.unk_off[e]:self.unk_off[e + 1]] = res.ravel()
+        return out
+
     # -- energy (eq. stability:energydef) -------------------------------------
     def energy(self, state):
         """1/2 int (eps E.E + mu H.H) of a state [field][comp][s] per element."""

@@ -2,7 +2,7 @@
 
 Every call recompiles every source (objects go to ``_build/`` next to this
 file; the library is ``libstdg.so`` in this package directory).  The residual
-kernels are compiled once per (precision, a = p + 1) slice so the slices build
+kernels are compiled once per (precision, a = p + 1, affine or trilinear) slice so the slices build
 in parallel.
 """
 import os
@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libstdg.so")
 
 HOST_SOURCES = ["api.cpp", "mesh.cpp", "tables.cpp", "solver.cpp", "serve.cpp"]
 HIP_SOURCES = ["residual.hip", "blas.hip", "load.hip"]
-SLICES = [(real, a) for real in ("float", "double") for a in range(2, 10)]
+SLICES = [(real, a, aff) for real in ("float", "double") for a in range(2, 10) for aff in (1, 0)]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -52,9 +52,10 @@ def build(jobs=None, verbose=False):
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmds.append([hipcc] + COMMON + lang + ["-c", path, "-o", obj])
         objs.append(obj)
-    for real, a in SLICES:
-        obj = os.path.join(BUILD, "residual_%s_a%d.o" % (real, a))
+    for real, a, aff in SLICES:
+        obj = os.path.join(BUILD, "residual_%s_a%d_%s.o" % (real, a, "aff" if aff else "tri"))
         cmds.append([hipcc] + COMMON + ["-x", "hip", "-DSTDG_REAL=%s" % real, "-DSTDG_A=%d" % a,
+                                        "-DSTDG_AFF=%d" % aff,
                                         "-c", os.path.join(CSRC, "residual_inst.hip"), "-o", obj])
         objs.append(obj)
     jobs = jobs or min(16, os.cpu_count() or 4)

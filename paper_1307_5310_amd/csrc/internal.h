@@ -46,9 +46,10 @@ static_assert(sizeof(ElemInfo) == 64, "ElemInfo layout");
 //   m[6..11] = mu  |J| DF^{-1} DF^{-T}
 //   m[12..17], m[18..23] = inverses of the two (preconditioner)
 // For trilinear elements these are taken at the element centre (used by the
-// preconditioner only); the exact mass uses the vertices.
+// preconditioner only); the mass itself is integrated from the vertices.
 struct ElemMetric {
   double m[24];
+  double eps, mu;  // material coefficients
 };
 
 // 1D tables passed by value to kernels (kernel-argument segment).
@@ -61,6 +62,19 @@ struct Tables {
 
 void fill_tables_f64(Tables<double>* t);
 void fill_tables_f32(Tables<float>* t);
+
+// Mass quadrature of trilinear elements: Gauss-Legendre with n = a + 1 points
+// per direction on [0, 1]; B[g * a + j] = sqrt(w_g) L_j(x_g), x[g] = x_g.
+template <typename T>
+struct QTables {
+  T B[(kMaxA + 1) * kMaxA];
+  T x[kMaxA + 1];
+};
+void fill_qtables_f64(int a, QTables<double>* t);
+void fill_qtables_f32(int a, QTables<float>* t);
+
+// n-point Gauss-Legendre rule on [0, 1] (n <= 16), Newton iteration on P_n.
+void gauss_rule01(int n, double* x, double* w);
 
 // Kernel work group of elements with the same (a, q, affine).
 struct Group {
@@ -93,6 +107,9 @@ struct Mesh {
   double* d_verts = nullptr;
   size_t device_bytes = 0;
   int64_t* d_state_off = nullptr;
+  // mass rules of trilinear elements, indexed by a (QTables<double>, QTables<float>)
+  void* d_qt64 = nullptr;
+  void* d_qt32 = nullptr;
   // scratch for preconditioned applies on non-diagonal meshes (lazily sized)
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;

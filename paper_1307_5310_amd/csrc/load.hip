@@ -216,22 +216,64 @@ __global__ void project_kernel(ProjParams P) {
   }
 }
 
-// per-element energy 1/2 (e^T M_eps e + h^T M_mu h) for affine elements
-__global__ void energy_kernel(const ElemInfo* info, const ElemMetric* metric, const int64_t* state_off, int64_t ne,
-                              const double* state, double* partial) {
+// per-element energy 1/2 (e^T M_eps e + h^T M_mu h): affine elements from the
+// constant metric, trilinear ones with the mass rule of the residual (Gauss,
+// a + 1 points per direction): 1/2 sum_g w_g (eps E.G E + mu H.G H)(x_g) in
+// reference coordinates, G = |J| DF^{-1} DF^{-T}
+__global__ void energy_kernel(const ElemInfo* info, const ElemMetric* metric, const double* verts,
+                              const int64_t* state_off, int64_t ne, const double* state, double* partial) {
   const int64_t e = blockIdx.x;
   if (e >= ne) return;
   const ElemInfo I = info[e];
-  const int a3 = I.a * I.a * I.a;
+  const int a = I.a, a3 = a * a * a;
   const double* m = metric[e].m;
   const double* st = state + state_off[e];
   __shared__ double red[256];
+  __shared__ double qx[kMaxA + 1], qw[kMaxA + 1], Bt[(kMaxA + 1) * kMaxA];
   double acc = 0.0;
-  for (int s = threadIdx.x; s < a3; s += blockDim.x) {
-    for (int f = 0; f < 2; ++f) {
-      const double* M = m + 6 * f;
-      const double v0 = st[(3 * f + 0) * a3 + s], v1 = st[(3 * f + 1) * a3 + s], v2 = st[(3 * f + 2) * a3 + s];
-      acc += M[0] * v0 * v0 + M[1] * v1 * v1 + M[2] * v2 * v2 + 2.0 * (M[3] * v0 * v1 + M[4] * v0 * v2 + M[5] * v1 * v2);
+  if (I.flags & kAffine) {
+    for (int s = threadIdx.x; s < a3; s += blockDim.x) {
+      for (int f = 0; f < 2; ++f) {
+        const double* M = m + 6 * f;
+        const double v0 = st[(3 * f + 0) * a3 + s], v1 = st[(3 * f + 1) * a3 + s], v2 = st[(3 * f + 2) * a3 + s];
+        acc += M[0] * v0 * v0 + M[1] * v1 * v1 + M[2] * v2 * v2 +
+               2.0 * (M[3] * v0 * v1 + M[4] * v0 * v2 + M[5] * v1 * v2);
+      }
+    }
+  } else {
+    const int nq = a + 1, nq3 = nq * nq * nq;
+    if (threadIdx.x == 0) gauss01(nq, qx, qw);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nq * a; k += blockDim.x) {
+      const int g = k / a, j = k - g * a;
+      Bt[k] = sqrt(qw[g]) * leg(j, qx[g]);
+    }
+    __syncthreads();
+    const double kap[2] = {metric[e].eps, metric[e].mu};
+    for (int pt = threadIdx.x; pt < nq3; pt += blockDim.x) {
+      const int g1 = pt % nq, g2 = (pt / nq) % nq, g3 = pt / (nq * nq);
+      double F[3], DF[3][3], Di[3][3];
+      trilinear(verts + 24 * e, qx[g1], qx[g2], qx[g3], F, DF);
+      const double det = inv3(DF, Di);
+      double G[3][3];
+      for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) G[c][d] = det * (Di[c][0] * Di[d][0] + Di[c][1] * Di[d][1] + Di[c][2] * Di[d][2]);
+      for (int f = 0; f < 2; ++f) {
+        double u[3] = {0.0, 0.0, 0.0};
+        for (int l = 0; l < a; ++l)
+          for (int k = 0; k < a; ++k) {
+            const double bkl = Bt[g3 * a + l] * Bt[g2 * a + k];
+            for (int j = 0; j < a; ++j) {
+              const double b = bkl * Bt[g1 * a + j];
+              const int s = (l * a + k) * a + j;
+              for (int c = 0; c < 3; ++c) u[c] += b * st[(3 * f + c) * a3 + s];
+            }
+          }
+        double q = 0.0;
+        for (int c = 0; c < 3; ++c)
+          for (int d = 0; d < 3; ++d) q += u[c] * G[c][d] * u[d];
+        acc += kap[f] * q;
+      }
     }
   }
   red[threadIdx.x] = acc;
@@ -260,8 +302,8 @@ __global__ void sum_kernel(const double* v, int64_t n, double* out) {
 }  // namespace
 
 int energy_async(const Mesh* m, const double* state, double* d_partial, double* d_out, hipStream_t s) {
-  hipLaunchKernelGGL(energy_kernel, dim3((unsigned)m->ne), dim3(128), 0, s, m->d_info, m->d_metric, m->d_state_off,
-                     m->ne, state, d_partial);
+  hipLaunchKernelGGL(energy_kernel, dim3((unsigned)m->ne), dim3(128), 0, s, m->d_info, m->d_metric, m->d_verts,
+                     m->d_state_off, m->ne, state, d_partial);
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1024), 0, s, d_partial, m->ne, d_out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "energy kernels");
@@ -342,7 +384,6 @@ int stdg_project_modes(const stdg_mesh* mesh, int32_t n_modes, const int32_t* mn
 int stdg_energy(const stdg_mesh* mesh, const double* state_dev, double* energy_out, void* stream) {
   if (!mesh || !state_dev || !energy_out) return fail(STDG_E_ARG, "stdg_energy: NULL argument");
   Mesh& m = const_cast<stdg_mesh*>(mesh)->m;
-  if (m.n_nonaffine > 0) return fail(STDG_E_UNSUPPORTED, "stdg_energy: affine elements only");
   int rc = ensure_state_off(&m);
   if (rc != STDG_OK) return rc;
   double* d_tmp = nullptr;

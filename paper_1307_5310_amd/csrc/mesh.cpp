@@ -220,6 +220,8 @@ int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m) {
     metric_of(DF, G, &det);
     if (!(det > 0.0)) return fail(STDG_E_ARG, "element " + std::to_string(e) + " is inverted or degenerate");
     ElemMetric& M = m->metric[e];
+    M.eps = d->eps[e];
+    M.mu = d->mu[e];
     for (int k = 0; k < 6; ++k) {
       M.m[k] = d->eps[e] * G[k];
       M.m[6 + k] = d->mu[e] * G[k];
@@ -271,6 +273,20 @@ int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m) {
   STDG_HIP(hipMemcpy(m->d_info, m->info.data(), bytes_info, hipMemcpyHostToDevice));
   STDG_HIP(hipMemcpy(m->d_metric, m->metric.data(), bytes_metric, hipMemcpyHostToDevice));
   STDG_HIP(hipMemcpy(m->d_verts, m->verts.data(), bytes_verts, hipMemcpyHostToDevice));
+  {
+    std::vector<QTables<double>> q64(kMaxA + 1);
+    std::vector<QTables<float>> q32(kMaxA + 1);
+    for (int a = 1; a <= kMaxA; ++a) {
+      fill_qtables_f64(a, &q64[a]);
+      fill_qtables_f32(a, &q32[a]);
+    }
+    size_t b64 = sizeof(QTables<double>) * (kMaxA + 1), b32 = sizeof(QTables<float>) * (kMaxA + 1);
+    if ((rc = dev_alloc(ctx, &m->d_qt64, b64)) != STDG_OK) return rc;
+    if ((rc = dev_alloc(ctx, &m->d_qt32, b32)) != STDG_OK) return rc;
+    m->device_bytes += b64 + b32;
+    STDG_HIP(hipMemcpy(m->d_qt64, q64.data(), b64, hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d_qt32, q32.data(), b32, hipMemcpyHostToDevice));
+  }
   for (auto& kv : gm) {
     auto& lst = kv.second;
     std::sort(lst.begin(), lst.end());
@@ -294,6 +310,9 @@ void release_mesh(Mesh* m) {
   if (m->d_info) dev_free(ctx, m->d_info, sizeof(ElemInfo) * m->ne);
   if (m->d_metric) dev_free(ctx, m->d_metric, sizeof(ElemMetric) * m->ne);
   if (m->d_verts) dev_free(ctx, m->d_verts, sizeof(double) * 24 * m->ne);
+  if (m->d_qt64) dev_free(ctx, m->d_qt64, sizeof(QTables<double>) * (kMaxA + 1));
+  if (m->d_qt32) dev_free(ctx, m->d_qt32, sizeof(QTables<float>) * (kMaxA + 1));
+  m->d_qt64 = m->d_qt32 = nullptr;
   for (auto& g : m->groups)
     if (g.d_list) dev_free(ctx, g.d_list, sizeof(int32_t) * g.count);
   if (m->d_scratch) dev_free(ctx, m->d_scratch, m->scratch_bytes);

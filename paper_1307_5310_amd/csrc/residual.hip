@@ -3,41 +3,48 @@
 
 namespace stdg {
 
-#define STDG_DECL(R, AA) int launch_affine_##R##AA(int q, const KParams<R>& P, int64_t n, hipStream_t s);
-#define STDG_DECL_ALL(R) STDG_DECL(R, 2) STDG_DECL(R, 3) STDG_DECL(R, 4) STDG_DECL(R, 5) \
-  STDG_DECL(R, 6) STDG_DECL(R, 7) STDG_DECL(R, 8) STDG_DECL(R, 9)
-STDG_DECL_ALL(float)
-STDG_DECL_ALL(double)
+#define STDG_DECL(K, R, AA) int launch_##K##R##AA(int q, const KParams<R>& P, int64_t n, hipStream_t s);
+#define STDG_DECL_ALL(K, R) STDG_DECL(K, R, 2) STDG_DECL(K, R, 3) STDG_DECL(K, R, 4) STDG_DECL(K, R, 5) \
+  STDG_DECL(K, R, 6) STDG_DECL(K, R, 7) STDG_DECL(K, R, 8) STDG_DECL(K, R, 9)
+STDG_DECL_ALL(affine_, float)
+STDG_DECL_ALL(affine_, double)
+STDG_DECL_ALL(trilinear_, float)
+STDG_DECL_ALL(trilinear_, double)
 #undef STDG_DECL_ALL
 #undef STDG_DECL
 
 template <typename T>
 using Launcher = int (*)(int, const KParams<T>&, int64_t, hipStream_t);
 
-static Launcher<float> affine_f32[kMaxA + 1] = {nullptr, nullptr, launch_affine_float2, launch_affine_float3,
-                                                launch_affine_float4, launch_affine_float5, launch_affine_float6,
-                                                launch_affine_float7, launch_affine_float8, launch_affine_float9};
-static Launcher<double> affine_f64[kMaxA + 1] = {nullptr, nullptr, launch_affine_double2, launch_affine_double3,
-                                                 launch_affine_double4, launch_affine_double5, launch_affine_double6,
-                                                 launch_affine_double7, launch_affine_double8, launch_affine_double9};
+#define STDG_TABLE(K, R) \
+  { nullptr, nullptr, launch_##K##R##2, launch_##K##R##3, launch_##K##R##4, launch_##K##R##5, \
+    launch_##K##R##6, launch_##K##R##7, launch_##K##R##8, launch_##K##R##9 }
+static Launcher<float> affine_f32[kMaxA + 1] = STDG_TABLE(affine_, float);
+static Launcher<double> affine_f64[kMaxA + 1] = STDG_TABLE(affine_, double);
+static Launcher<float> trilinear_f32[kMaxA + 1] = STDG_TABLE(trilinear_, float);
+static Launcher<double> trilinear_f64[kMaxA + 1] = STDG_TABLE(trilinear_, double);
+#undef STDG_TABLE
 
 template <typename T>
 static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* load, T* y, hipStream_t s,
-                      Launcher<T>* table) {
+                      Launcher<T>* affine, Launcher<T>* trilinear, const QTables<T>* d_qt) {
   KParams<T> P;
   P.info = m->d_info;
   P.metric = m->d_metric;
   P.x = x;
   P.load = load;
   P.y = y;
+  P.verts = m->d_verts;
   P.dt = (T)dt;
   P.mode = mode;
   if constexpr (sizeof(T) == 8) fill_tables_f64(&P.tab); else fill_tables_f32(&P.tab);
   for (const Group& g : m->groups) {
     if (g.count == 0) continue;
-    if (!g.affine) return fail(STDG_E_UNSUPPORTED, "trilinear (non-affine) elements are not supported by this apply");
+    if (!g.affine && mode == STDG_OPERATOR_PRECOND)
+      return fail(STDG_E_UNSUPPORTED, "trilinear elements take P^{-1} in a separate pass");
     P.list = g.d_list;
-    int rc = table[g.a](g.q, P, g.count, s);
+    P.qt = d_qt + g.a;
+    int rc = (g.affine ? affine : trilinear)[g.a](g.q, P, g.count, s);
     if (rc != STDG_OK) return rc;
   }
   return STDG_OK;
@@ -79,8 +86,9 @@ int launch_residual(const ApplyArgs& a) {
   }
   if (a.prec == STDG_FP64)
     return run_groups<double>(m, a.dt, mode, (const double*)x, (const double*)a.load, (double*)a.y, a.stream,
-                              affine_f64);
-  return run_groups<float>(m, a.dt, mode, (const float*)x, (const float*)a.load, (float*)a.y, a.stream, affine_f32);
+                              affine_f64, trilinear_f64, (const QTables<double>*)m->d_qt64);
+  return run_groups<float>(m, a.dt, mode, (const float*)x, (const float*)a.load, (float*)a.y, a.stream, affine_f32,
+                           trilinear_f32, (const QTables<float>*)m->d_qt32);
 }
 
 }  // namespace stdg

@@ -54,9 +54,9 @@ struct KCfg {
   static constexpr int NF = 4 * A2;                 // face items per face
   static constexpr int ND = A / 2;                  // odd offsets 1, 3, .. < A
   static constexpr int LVL = 6 * A3 + 24 * A2;      // staged level: E~', H~' then fluxes
-  template <typename T, int Q>
-  static constexpr int LC() {  // test levels staged per LDS pass (about 16 KB)
-    constexpr int c = 16384 / (LVL * (int)sizeof(T));
+  template <typename T, int Q, bool AFF = true>
+  static constexpr int LC() {  // test levels staged per LDS pass (about 16 KB; one for trilinear elements)
+    constexpr int c = AFF ? 16384 / (LVL * (int)sizeof(T)) : 1;
     return c < 1 ? 1 : (c > Q ? Q : c);
   }
   // neighbour blocks are staged through LDS a face at a time (4 tangential
@@ -64,11 +64,25 @@ struct KCfg {
   // fits in 24 KB; larger ones are gathered straight from global memory
   template <typename T, int Q>
   static constexpr bool stage() { return 4 * (Q + 1) * A3 * (int)sizeof(T) <= 24576; }
-  template <typename T, int Q>
+  // trilinear elements: Gauss rule of GQ = a + 1 points per direction for the
+  // mass; PP quadrature points per thread
+  static constexpr int GQ = A + 1, G2 = GQ * GQ, G3 = G2 * GQ;
+  static constexpr int PP = (G3 + NT - 1) / NT;
+  static constexpr int MASS_A = 3 * A * G2, MASS = MASS_A + 3 * G3;  // two sweep buffers
+  static constexpr int QTAB = GQ * A;                                // sqrt(w_g) L_j(x_g)
+  static constexpr int QTAB_PAD = (QTAB + 3) & ~3;
+  template <typename T, int Q, bool AFF>
+  static constexpr int main_elems() {
+    // staged contracted levels, or (aliased, used earlier) the staging
+    // buffers, or (aliased) the mass sweep buffers
+    constexpr int a = LC<T, Q, AFF>() * LVL, b = stage<T, Q>() ? 2 * 4 * (Q + 1) * A3 : 0;
+    constexpr int ab = a > b ? a : b;
+    return AFF ? ab : (ab > MASS ? ab : MASS);
+  }
+  template <typename T, int Q, bool AFF>
   static constexpr int lds_elems() {
-    // staged contracted levels, or (aliased, used earlier) the staging buffers
-    constexpr int a = LC<T, Q>() * LVL, b = stage<T, Q>() ? 2 * 4 * (Q + 1) * A3 : 0;
-    return a > b ? a : b;
+    // trilinear elements add the quadrature table and the metric at the points
+    return main_elems<T, Q, AFF>() + (AFF ? 0 : QTAB_PAD + 6 * G3);
   }
 };
 
@@ -80,6 +94,8 @@ struct KParams {
   const T* x;
   const T* load;
   T* y;
+  const double* verts;    // [ne][8][3] (trilinear elements)
+  const QTables<T>* qt;   // mass rule of this group's a (trilinear elements)
   T dt;
   int mode;  // kept for launch bookkeeping; the kernels take the mode as a template argument
   Tables<T> tab;
@@ -133,12 +149,157 @@ __device__ __forceinline__ int face_base(int alpha, int u, int v, int n) {
   return alpha == 0 ? n * u + n * n * v : (alpha == 1 ? u + n * n * v : u + n * v);
 }
 
-template <typename T, int A, int Q, int MODE>
-__global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T> P) {
+// Metric G = |J| DF^{-1} DF^{-T} of a trilinear map at the quadrature points
+// (index (m GQ + h) GQ + g, g along x-hat), into LDS as Gl[entry][point].  With DF columns d0, d1, d2 the rows of DF^{-1} are
+// (d1 x d2, d2 x d0, d0 x d1) / det, so G_ij = r_i . r_j / det.
+template <typename T, int A>
+__device__ __forceinline__ void trilinear_metric(const double* X, const QTables<T>* qt, int tid, T* __restrict__ Gl) {
+  using C = KCfg<A>;
+  // x(xi) = sum_S c_S prod_{d in S} xi_d over subsets S of the axes (bit d),
+  // c_S = sum_{V subset S} (-1)^{|S| - |V|} X_V  (vertex V = x-hat bit fastest)
+  T cs[8][3];
+#pragma unroll
+  for (int S = 0; S < 8; ++S)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int V = 0; V < 8; ++V)
+        if ((V & S) == V) v += ((__builtin_popcount(S ^ V) & 1) ? -1.0 : 1.0) * X[3 * V + c];
+      cs[S][c] = (T)v;
+    }
+#pragma unroll
+  for (int k = 0; k < C::PP; ++k) {
+    const int pt = tid + k * C::NT;
+    if (pt >= C::G3) break;
+    const T x1 = qt->x[pt % C::GQ], x2 = qt->x[(pt / C::GQ) % C::GQ], x3 = qt->x[pt / C::G2];
+    T d[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      d[0][c] = cs[1][c] + cs[3][c] * x2 + cs[5][c] * x3 + cs[7][c] * (x2 * x3);
+      d[1][c] = cs[2][c] + cs[3][c] * x1 + cs[6][c] * x3 + cs[7][c] * (x1 * x3);
+      d[2][c] = cs[4][c] + cs[5][c] * x1 + cs[6][c] * x2 + cs[7][c] * (x1 * x2);
+    }
+    T r[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+      r[i][0] = d[i1][1] * d[i2][2] - d[i1][2] * d[i2][1];
+      r[i][1] = d[i1][2] * d[i2][0] - d[i1][0] * d[i2][2];
+      r[i][2] = d[i1][0] * d[i2][1] - d[i1][1] * d[i2][0];
+    }
+    const T idet = T(1) / (d[0][0] * r[0][0] + d[0][1] * r[0][1] + d[0][2] * r[0][2]);
+    const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k6 = 0; k6 < 6; ++k6)
+      Gl[k6 * C::G3 + pt] = (r[ii[k6]][0] * r[jj[k6]][0] + r[ii[k6]][1] * r[jj[k6]][1] + r[ii[k6]][2] * r[jj[k6]][2]) * idet;
+  }
+}
+
+// Mass of a trilinear element applied to one field (3 components) of one
+// level, by sum factorisation over the GQ^3 Gauss rule:
+//   r_c(s) = kappa sum_g phi_s(x_g) w_g (G(x_g) u(x_g))_c,  u(x_g) = sum_t phi_t(x_g) u_t.
+// Bt = sqrt(w_g) L_j(x_g) in LDS (the weight split over both sweeps).  Sweeps
+// alternate between bufA (3 A GQ^2) and bufB (3 GQ^3); the caller must
+// synchronise before reusing the buffers for anything but another call.
+template <typename T, int A>
+__device__ __forceinline__ void trilinear_mass(T* __restrict__ bufA, T* __restrict__ bufB, const T* __restrict__ Bt,
+                                               const T* __restrict__ Gl, T kappa, const T (&u)[3], T (&r)[3],
+                                               int tid, bool pos_lane, uint32_t s) {
+  using C = KCfg<A>;
+  constexpr int A2 = C::A2, A3 = C::A3, GQ = C::GQ, G2 = C::G2, G3 = C::G3, NT = C::NT;
+  if (pos_lane) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bufA[c * A3 + s] = u[c];
+  }
+  __syncthreads();
+  // x-hat: [c][l][k][j] -> [c][l][k][g]
+  for (int o = tid; o < 3 * A2 * GQ; o += NT) {
+    const int g = o % GQ, row = o / GQ;
+    const T* src = bufA + row * A;
+    const T* b = Bt + g * A;
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < A; ++j) acc += b[j] * src[j];
+    bufB[o] = acc;
+  }
+  __syncthreads();
+  // y-hat: [c][l][k][g] -> [c][l][h][g]
+  for (int o = tid; o < 3 * A * G2; o += NT) {
+    const int g = o % GQ, h = (o / GQ) % GQ, row = o / G2;
+    const T* src = bufB + row * (A * GQ) + g;
+    const T* b = Bt + h * A;
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < A; ++k) acc += b[k] * src[k * GQ];
+    bufA[o] = acc;
+  }
+  __syncthreads();
+  // z-hat to the points, and the pointwise kappa G
+#pragma unroll
+  for (int kk = 0; kk < C::PP; ++kk) {
+    const int pt = tid + kk * NT;
+    if (pt < G3) {
+      const int m = pt / G2, hg = pt - m * G2;
+      const T* b = Bt + m * A;
+      T v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < A; ++l) acc += b[l] * bufA[(c * A + l) * G2 + hg];
+        v[c] = acc;
+      }
+      T G[6];
+#pragma unroll
+      for (int k6 = 0; k6 < 6; ++k6) G[k6] = Gl[k6 * G3 + pt];
+      bufB[0 * G3 + pt] = kappa * (G[0] * v[0] + G[3] * v[1] + G[4] * v[2]);
+      bufB[1 * G3 + pt] = kappa * (G[3] * v[0] + G[1] * v[1] + G[5] * v[2]);
+      bufB[2 * G3 + pt] = kappa * (G[4] * v[0] + G[5] * v[1] + G[2] * v[2]);
+    }
+  }
+  __syncthreads();
+  // back along z-hat: [c][m][h][g] -> [c][l][h][g]
+  for (int o = tid; o < 3 * A * G2; o += NT) {
+    const int hg = o % G2, l = (o / G2) % A, c = o / (A * G2);
+    const T* src = bufB + c * G3 + hg;
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < GQ; ++m) acc += Bt[m * A + l] * src[m * G2];
+    bufA[o] = acc;
+  }
+  __syncthreads();
+  // back along y-hat: [c][l][h][g] -> [c][l][k][g]
+  for (int o = tid; o < 3 * A2 * GQ; o += NT) {
+    const int g = o % GQ, k = (o / GQ) % A, row = o / (A * GQ);
+    const T* src = bufA + row * G2 + g;
+    T acc = T(0);
+#pragma unroll
+    for (int h = 0; h < GQ; ++h) acc += Bt[h * A + k] * src[h * GQ];
+    bufB[o] = acc;
+  }
+  __syncthreads();
+  // back along x-hat, at this thread's position s = (j, k, l)
+  {
+    const int j = (int)(s % A), kl = (int)(s / A);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T* src = bufB + (c * A2 + kl) * GQ;
+      T acc = T(0);
+#pragma unroll
+      for (int g = 0; g < GQ; ++g) acc += Bt[g * A + j] * src[g];
+      r[c] = acc;
+    }
+  }
+}
+
+template <typename T, int A, int Q, int MODE, bool AFF>
+__global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   using C = KCfg<A>;
   constexpr int A2 = C::A2, A3 = C::A3, NF = C::NF, ND = C::ND, LVL = C::LVL;
-  constexpr int LC = C::template LC<T, Q>();
+  constexpr int LC = C::template LC<T, Q, AFF>();
   constexpr bool resid = MODE == 1, pre = MODE == 2;  // operator / residual / operator with P^{-1}
+  static_assert(AFF || !pre, "trilinear elements take P^{-1} in a separate pass");
   constexpr int m0 = resid ? 0 : 1;                   // first trial level stored in x
   constexpr int NL = Q + 1 - m0;                      // trial levels stored per component
   constexpr int BLK = 6 * NL * A3 * (int)sizeof(T);   // bytes of one element block of x
@@ -365,6 +526,17 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
     }
   }
   const T winv = T(1) / w;
+
+  // trilinear elements: quadrature table and the metric at the points, in LDS
+  T* qB = sm + C::template main_elems<T, Q, AFF>();
+  T* Gl = qB + C::QTAB_PAD;
+  T keps = T(0), kmu = T(0);
+  if constexpr (!AFF) {
+    for (int k = tid; k < C::QTAB; k += C::NT) qB[k] = P.qt->B[k];
+    trilinear_metric<T, A>(P.verts + 24 * (int64_t)e, P.qt, tid, Gl);
+    keps = (T)P.metric[e].eps;
+    kmu = (T)P.metric[e].mu;
+  }
   // Dh[n][s_m] X(s_m -> n) = 2 rho_{s_m}^2 / w(s) * (w X)(s_m -> n)
 #pragma unroll
   for (int m = 0; m < 3; ++m) cf[m] = T(2 * (2 * sidx[m] + 1)) * winv;
@@ -383,6 +555,25 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
 
 #pragma unroll
   for (int i0 = 0; i0 < Q; i0 += LC) {
+    // trilinear elements: the mass terms of these levels, by quadrature
+    T mres[AFF ? 1 : LC][6];
+    if constexpr (!AFF) {
+#pragma unroll
+      for (int ii = 0; ii < LC; ++ii) {
+        const int i = i0 + ii;
+        if (i >= Q) break;
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          T u[3], r[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) u[c] = xr[3 * f + c][i + 1] - ((resid && i == 0) ? xr[3 * f + c][0] : T(0));
+          trilinear_mass<T, A>(sm, sm + C::MASS_A, qB, Gl, f == 0 ? keps : kmu, u, r, tid, pos_lane, s);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) mres[ii][3 * f + c] = r[c];
+        }
+      }
+      __syncthreads();  // the sweep buffers alias the staged levels
+    }
     // (a) contracted levels, scaled by w(s), into LDS
     if (pos_lane) {
 #pragma unroll
@@ -495,7 +686,9 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_affine_kernel(KParams<T>
             }
             // mass: the time-derivative factor is the shift delta_{m,i+1} - delta_{i0} delta_{m0}
             T mass;
-            if (pre) {
+            if constexpr (!AFF) {
+              mass = mres[ii][3 * f + c];
+            } else if (pre) {
               mass = xr[3 * f + c][i + 1];
             } else {
               const T* Mm = f == 0 ? Me : Mh;

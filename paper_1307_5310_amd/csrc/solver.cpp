@@ -2,7 +2,8 @@
 // B_h(U, V) = L(V) for every test function (Section 3, eq. weakform;
 // Section 4, eq. weakform_stabilized), by restarted GMRES preconditioned from
 // the right with P = the time-derivative terms (Section 5.4,
-// eq. preconditioner; block diagonal, applied exactly on affine elements).
+// eq. preconditioner; block diagonal, exact on affine elements, from the
+// metric at the element centre on trilinear ones).
 //
 // Every restart cycle starts from the true residual L - B U evaluated in
 // FP64.  Inner applies run in FP64 (the plain path) or in FP32 with FP64
@@ -113,7 +114,6 @@ extern "C" int stdg_slab_solve(const stdg_mesh* mesh, double t0, double dt, cons
   std::memset(info, 0, sizeof(*info));
 
   Mesh* m = const_cast<Mesh*>(&mesh->m);
-  if (m->n_nonaffine > 0) return fail(STDG_E_UNSUPPORTED, "stdg_slab_solve: trilinear elements not supported yet");
   hipStream_t s = (hipStream_t)stream;
   int rc = ensure_state_off(m);
   if (rc != STDG_OK) return rc;

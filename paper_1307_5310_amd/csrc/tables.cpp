@@ -7,11 +7,16 @@
 //   int L_i l_m' = delta_{m,i+1} - delta_{i0} delta_{m0}  (the mass factor is a
 //       shift, used directly by the kernels, no table);
 //   Dh[n][j] = int L_n L_j' = 2 sqrt((2n+1)(2j+1)) for n < j, j - n odd;
-//   traces L_j(0) = (-1)^j sqrt(2j+1), L_j(1) = sqrt(2j+1).
+//   traces L_j(0) = (-1)^j sqrt(2j+1), L_j(1) = sqrt(2j+1);
+// and the Gauss-Legendre mass rule of trilinear elements (n = p + 2 points).
 #include <cmath>
 #include <cstring>
 
 #include "internal.h"
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
 
 namespace stdg {
 
@@ -55,6 +60,70 @@ void fill_tables_f32(Tables<float>* t) {
     t->tr0[j] = (float)d.tr0[j];
     t->tr1[j] = (float)d.tr1[j];
   }
+}
+
+void gauss_rule01(int n, double* x, double* w) {
+  // roots of P_n on [-1, 1] from the Chebyshev-like initial guesses, refined
+  // by Newton's method; mapped to [0, 1] with weights halved
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double pm = n == 1 ? 1.0 : p0;
+      dp = n * (z * p1 - pm) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double pm = n == 1 ? 1.0 : p0;
+      dp = n * (z * p1 - pm) / (z * z - 1.0);
+    }
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+static double legendre01(int j, double xi) {
+  const double u = 2.0 * xi - 1.0;
+  double p0 = 1.0, p1 = u;
+  if (j == 0) return 1.0;
+  for (int k = 1; k < j; ++k) {
+    const double p2 = ((2.0 * k + 1.0) * u * p1 - k * p0) / (k + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  return std::sqrt(2.0 * j + 1.0) * p1;
+}
+
+void fill_qtables_f64(int a, QTables<double>* t) {
+  std::memset(t, 0, sizeof(*t));
+  const int n = a + 1;
+  double x[kMaxA + 1], w[kMaxA + 1];
+  gauss_rule01(n, x, w);
+  for (int g = 0; g < n; ++g) {
+    t->x[g] = x[g];
+    for (int j = 0; j < a; ++j) t->B[g * a + j] = std::sqrt(w[g]) * legendre01(j, x[g]);
+  }
+}
+
+void fill_qtables_f32(int a, QTables<float>* t) {
+  QTables<double> d;
+  fill_qtables_f64(a, &d);
+  for (int i = 0; i < (kMaxA + 1) * kMaxA; ++i) t->B[i] = (float)d.B[i];
+  for (int i = 0; i <= kMaxA; ++i) t->x[i] = (float)d.x[i];
 }
 
 }  // namespace stdg
