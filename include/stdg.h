@@ -62,7 +62,8 @@ typedef enum {
   STDG_E_DEVICE = -4,        /* HIP runtime error or missing GPU                */
   STDG_E_NOT_CONVERGED = -5, /* solver hit its iteration limit (info is filled) */
   STDG_E_NOT_READY = -6,     /* serving ticket not finished yet                 */
-  STDG_E_CAPACITY = -7       /* request larger than the HBM budget              */
+  STDG_E_CAPACITY = -7,      /* request larger than the HBM budget              */
+  STDG_E_CANCELLED = -8      /* serving request dropped while the server stopped */
 } stdg_status;
 
 typedef enum { STDG_FP64 = 0, STDG_FP32 = 1 } stdg_prec;
@@ -205,6 +206,78 @@ int stdg_slab_solve(const stdg_mesh* mesh, double t0, double dt, const double* l
 /* Discrete energy 1/2 int (eps E.E + mu H.H) of an FP64 state (eq. stability:energydef);
  * on trilinear elements with the mass rule of the residual (p + 2 Gauss points per direction). */
 int stdg_energy(const stdg_mesh* mesh, const double* state_dev, double* energy_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: independent PEC cavity solves (a mesh, an initial field, a current
+ * and a number of slabs each), marched slab by slab (Section 2.2, time slabs;
+ * each slab solved as stdg_slab_solve does) by one server thread per server.
+ *
+ * Admission: a request is admitted when a contiguous reservation of its
+ * device footprint (mesh tables, state, load, Krylov vectors; reported in
+ * stdg_result.device_bytes) fits in the server's HBM arena and fewer than
+ * max_active requests are in flight; otherwise it waits in FIFO order.
+ * Admitted requests run concurrently, each on its own stream: the server
+ * advances whichever request's last step has completed (one GMRES iteration,
+ * restart cycle or slab boundary at a time), so requests that arrive while
+ * others run join at the next step and their work overlaps on the device.
+ * Each request's arithmetic is independent of the others (own buffers, fixed
+ * reduction order): its result is bitwise the same alone and in a mix.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  size_t hbm_budget;     /* bytes of the server's device arena (0 = 16 GiB)        */
+  int32_t max_active;    /* requests in flight at once (0 = 16)                    */
+  int32_t inner_prec;    /* stdg_solve_opts fields, applied to every slab          */
+  int32_t restart;
+  int32_t max_iters;     /* per slab */
+  int32_t max_refine;
+  double rtol;
+  double inner_rtol;
+} stdg_serve_opts;
+
+typedef struct {
+  stdg_mesh_desc mesh;       /* host arrays, copied by stdg_serve_submit            */
+  double t0, dt;             /* start time and slab length (> 0)                    */
+  int32_t n_slabs;           /* >= 1                                                */
+  stdg_source source;        /* current density (kind 0 = none), load per slab      */
+  int32_t n_modes;           /* initial field: cavity-mode superposition, as        */
+  const int32_t* mnl;        /*   stdg_project_modes (affine meshes), or            */
+  const double* abc;
+  const double* init_state;  /*   an FP64 state (host, state layout) if not NULL    */
+} stdg_request;
+
+typedef struct {
+  int32_t status;            /* STDG_OK, STDG_E_NOT_CONVERGED (a slab missed rtol),
+                                STDG_E_CANCELLED, or the error that stopped it      */
+  int32_t slabs_done;
+  int64_t iters;             /* inner GMRES iterations over all slabs               */
+  double max_rel_res;        /* largest final relative residual over the slabs      */
+  double energy_start;       /* discrete energy at t0                               */
+  double energy_end;         /* ... at the end of the last slab done                */
+  double t_submit, t_admit, t_done;  /* seconds on the server clock                 */
+  int64_t state_size;        /* entries of the final state                          */
+  int64_t device_bytes;      /* reservation the request held                        */
+  double* state;             /* in: caller host buffer for the final state, or NULL */
+  int64_t state_capacity;    /* in: entries available at state                      */
+} stdg_result;
+
+/* Start a server on the context's device.  The server thread owns the
+ * context's device while it runs: do not use the same context from other
+ * threads until stdg_serve_stop returns. */
+int stdg_serve_start(stdg_ctx* ctx, const stdg_serve_opts* opts, stdg_server** out);
+/* Queue a request (thread-safe; every array is copied before return).
+ * STDG_E_CAPACITY if its footprint exceeds the whole arena, STDG_E_ARG on
+ * invalid sizes; mesh errors surface through stdg_serve_poll. */
+int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ticket);
+/* STDG_E_NOT_READY until the request has finished; then fills *out (copying
+ * the final state into out->state when out->state_capacity suffices, else
+ * STDG_E_ARG and the result is kept) and releases the ticket.  Thread-safe. */
+int stdg_serve_poll(stdg_server* server, uint64_t ticket, stdg_result* out);
+/* Seconds on the server clock (the clock of t_submit, t_admit, t_done). */
+double stdg_serve_clock(const stdg_server* server);
+/* Stop: waits for the device work in flight, drops requests still queued or
+ * running and results not yet polled, frees the arena; the handle is invalid
+ * afterwards. */
+int stdg_serve_stop(stdg_server* server);
 
 #ifdef __cplusplus
 }

@@ -11,14 +11,16 @@ import ctypes
 import numpy as np
 
 from ._lib import (StdgError, STDG_FP32, STDG_FP64, STDG_OPERATOR, STDG_RESIDUAL,
-                   STDG_OPERATOR_PRECOND, MeshDesc, MeshInfo, Source, SolveOpts, SolveInfo,
-                   lib, check, ptr, stream_handle, exported_symbols)
+                   STDG_OPERATOR_PRECOND, STDG_E_NOT_READY, MeshDesc, MeshInfo, Source, SolveOpts,
+                   SolveInfo, ServeOpts, Request, Result, lib, check, ptr, stream_handle,
+                   exported_symbols)
 
 __all__ = ["StdgError", "STDG_FP32", "STDG_FP64", "STDG_OPERATOR", "STDG_RESIDUAL",
            "STDG_OPERATOR_PRECOND", "stdg_version", "stdg_init", "stdg_finalize",
            "stdg_mesh_upload", "stdg_mesh_info", "stdg_mesh_offsets", "stdg_mesh_free",
            "stdg_residual_apply", "stdg_load_assemble", "stdg_project_modes",
-           "stdg_slab_solve", "stdg_energy", "exported_symbols"]
+           "stdg_slab_solve", "stdg_energy", "stdg_serve_start", "stdg_serve_submit",
+           "stdg_serve_poll", "stdg_serve_clock", "stdg_serve_stop", "exported_symbols"]
 
 
 def stdg_version():
@@ -35,7 +37,8 @@ def stdg_finalize(ctx):
     check(lib().stdg_finalize(ctx))
 
 
-def stdg_mesh_upload(ctx, vertices, hexes, p, q, eps, mu):
+def _mesh_desc(vertices, hexes, p, q, eps, mu):
+    """MeshDesc over contiguous copies; returns (desc, arrays kept alive)."""
     v = np.ascontiguousarray(vertices, dtype=np.float64)
     h = np.ascontiguousarray(hexes, dtype=np.int64)
     p = np.ascontiguousarray(p, dtype=np.int32)
@@ -44,6 +47,11 @@ def stdg_mesh_upload(ctx, vertices, hexes, p, q, eps, mu):
     mu = np.ascontiguousarray(mu, dtype=np.float64)
     d = MeshDesc(v.shape[0], v.ctypes.data, h.shape[0], h.ctypes.data, p.ctypes.data,
                  q.ctypes.data, eps.ctypes.data, mu.ctypes.data)
+    return d, (v, h, p, q, eps, mu)
+
+
+def stdg_mesh_upload(ctx, vertices, hexes, p, q, eps, mu):
+    d, _keep = _mesh_desc(vertices, hexes, p, q, eps, mu)
     out = ctypes.c_void_p()
     check(lib().stdg_mesh_upload(ctx, ctypes.byref(d), ctypes.byref(out)))
     return out
@@ -115,3 +123,57 @@ def stdg_energy(mesh, state, stream=None):
     out = ctypes.c_double()
     check(lib().stdg_energy(mesh, ptr(state), ctypes.byref(out), stream_handle(stream)))
     return out.value
+
+
+def stdg_serve_start(ctx, hbm_budget=0, max_active=0, inner_prec=STDG_FP32, restart=10, max_iters=500,
+                     max_refine=100, rtol=1e-10, inner_rtol=1e-4):
+    o = ServeOpts(int(hbm_budget), int(max_active), int(inner_prec), int(restart), int(max_iters),
+                  int(max_refine), float(rtol), float(inner_rtol))
+    h = ctypes.c_void_p()
+    check(lib().stdg_serve_start(ctx, ctypes.byref(o), ctypes.byref(h)))
+    return h
+
+
+def stdg_serve_submit(server, vertices, hexes, p, q, eps, mu, t0, dt, n_slabs, source=None, mnl=None,
+                      abc=None, init_state=None):
+    """Queue one request; every array is copied before return.  Returns the ticket."""
+    d, _keep = _mesh_desc(vertices, hexes, p, q, eps, mu)
+    r = Request()
+    r.mesh = d
+    r.t0, r.dt, r.n_slabs = float(t0), float(dt), int(n_slabs)
+    r.source = _source(source)
+    keep2 = []
+    if mnl is not None and len(mnl):
+        mnl = np.ascontiguousarray(mnl, dtype=np.int32).reshape(-1, 3)
+        abc = np.ascontiguousarray(abc, dtype=np.float64).reshape(-1, 3)
+        keep2 += [mnl, abc]
+        r.n_modes, r.mnl, r.abc = mnl.shape[0], mnl.ctypes.data, abc.ctypes.data
+    if init_state is not None:
+        init_state = np.ascontiguousarray(init_state, dtype=np.float64)
+        keep2.append(init_state)
+        r.init_state = init_state.ctypes.data
+    t = ctypes.c_uint64()
+    check(lib().stdg_serve_submit(server, ctypes.byref(r), ctypes.byref(t)))
+    return t.value
+
+
+def stdg_serve_poll(server, ticket, state_out=None):
+    """None while the request runs; then a dict of the result (the final state
+    is written into state_out, a float64 numpy array, when given)."""
+    res = Result()
+    if state_out is not None:
+        res.state = state_out.ctypes.data
+        res.state_capacity = state_out.size
+    st = lib().stdg_serve_poll(server, ctypes.c_uint64(int(ticket)), ctypes.byref(res))
+    if st == STDG_E_NOT_READY:
+        return None
+    check(st)
+    return {name: getattr(res, name) for name, _ in Result._fields_ if name not in ("state", "state_capacity")}
+
+
+def stdg_serve_clock(server):
+    return lib().stdg_serve_clock(server)
+
+
+def stdg_serve_stop(server):
+    check(lib().stdg_serve_stop(server))

@@ -19,9 +19,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstdg.so")
 
 STDG_OK = 0
+STDG_E_NOT_READY = -6
 STATUS_NAMES = {0: "STDG_OK", -1: "STDG_E_ARG", -2: "STDG_E_UNSUPPORTED", -3: "STDG_E_NOMEM",
                 -4: "STDG_E_DEVICE", -5: "STDG_E_NOT_CONVERGED", -6: "STDG_E_NOT_READY",
-                -7: "STDG_E_CAPACITY"}
+                -7: "STDG_E_CAPACITY", -8: "STDG_E_CANCELLED"}
 STDG_FP64, STDG_FP32 = 0, 1
 STDG_OPERATOR, STDG_RESIDUAL, STDG_OPERATOR_PRECOND = 0, 1, 2
 
@@ -68,6 +69,28 @@ class SolveInfo(ctypes.Structure):
                 ("energy_end", ctypes.c_double)]
 
 
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int32),
+                ("inner_prec", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("mesh", MeshDesc), ("t0", ctypes.c_double), ("dt", ctypes.c_double),
+                ("n_slabs", ctypes.c_int32), ("source", Source), ("n_modes", ctypes.c_int32),
+                ("mnl", ctypes.c_void_p), ("abc", ctypes.c_void_p), ("init_state", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slabs_done", ctypes.c_int32), ("iters", ctypes.c_int64),
+                ("max_rel_res", ctypes.c_double), ("energy_start", ctypes.c_double),
+                ("energy_end", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("state_size", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("state", ctypes.c_void_p), ("state_capacity", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -95,6 +118,11 @@ def lib():
             "stdg_slab_solve": ([vp, dbl, dbl, vp, ctypes.POINTER(SolveOpts), vp, vp,
                                  ctypes.POINTER(SolveInfo), vp], ctypes.c_int),
             "stdg_energy": ([vp, vp, ctypes.POINTER(dbl), vp], ctypes.c_int),
+            "stdg_serve_start": ([vp, ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)], ctypes.c_int),
+            "stdg_serve_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+            "stdg_serve_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(Result)], ctypes.c_int),
+            "stdg_serve_clock": ([vp], dbl),
+            "stdg_serve_stop": ([vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)

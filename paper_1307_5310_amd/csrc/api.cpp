@@ -25,6 +25,16 @@ int hip_fail(hipError_t e, const char* what) {
 int dev_alloc(Ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 256;
+  if (ctx->chunk) {
+    const size_t off = (ctx->chunk_off + 255) & ~(size_t)255;
+    if (off + bytes > ctx->chunk_size)
+      return fail(STDG_E_CAPACITY, "allocation of " + std::to_string(bytes) + " bytes exceeds the reservation (" +
+                                       std::to_string(off) + " of " + std::to_string(ctx->chunk_size) + " used)");
+    *p = ctx->chunk + off;
+    ctx->chunk_off = off + bytes;
+    ctx->used += bytes;
+    return STDG_OK;
+  }
   if (ctx->used + bytes > ctx->budget)
     return fail(STDG_E_CAPACITY, "allocation of " + std::to_string(bytes) + " bytes exceeds the HBM budget (" +
                                      std::to_string(ctx->used) + " of " + std::to_string(ctx->budget) + " used)");
@@ -40,7 +50,8 @@ int dev_alloc(Ctx* ctx, void** p, size_t bytes) {
 void dev_free(Ctx* ctx, void* p, size_t bytes) {
   if (!p) return;
   if (bytes == 0) bytes = 256;
-  (void)hipFree(p);
+  const bool in_chunk = ctx->chunk && (char*)p >= ctx->chunk && (char*)p < ctx->chunk + ctx->chunk_size;
+  if (!in_chunk) (void)hipFree(p);
   ctx->used = ctx->used >= bytes ? ctx->used - bytes : 0;
 }
 

@@ -87,6 +87,11 @@ struct Ctx {
   int device;
   size_t budget;
   size_t used;
+  // Optional device chunk that every allocation of this context is carved
+  // from (a serving request's reservation): bump allocation, 256-byte
+  // aligned; frees inside the chunk are no-ops, the owner returns it whole.
+  char* chunk = nullptr;
+  size_t chunk_size = 0, chunk_off = 0;
 };
 
 struct Mesh {

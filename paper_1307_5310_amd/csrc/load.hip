@@ -357,8 +357,11 @@ int stdg_project_modes(const stdg_mesh* mesh, int32_t n_modes, const int32_t* mn
   int32_t* d_mnl = nullptr;
   double* d_abc = nullptr;
   size_t nb = sizeof(int32_t) * 3 * (n_modes > 0 ? n_modes : 1), nd = sizeof(double) * 3 * (n_modes > 0 ? n_modes : 1);
-  STDG_HIP(hipMalloc(&d_mnl, nb));
-  STDG_HIP(hipMalloc(&d_abc, nd));
+  if ((rc = dev_alloc(m.ctx, (void**)&d_mnl, nb)) != STDG_OK) return rc;
+  if ((rc = dev_alloc(m.ctx, (void**)&d_abc, nd)) != STDG_OK) {
+    dev_free(m.ctx, d_mnl, nb);
+    return rc;
+  }
   if (n_modes > 0) {
     STDG_HIP(hipMemcpy(d_mnl, mnl, sizeof(int32_t) * 3 * n_modes, hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(d_abc, abc, sizeof(double) * 3 * n_modes, hipMemcpyHostToDevice));
@@ -376,8 +379,8 @@ int stdg_project_modes(const stdg_mesh* mesh, int32_t n_modes, const int32_t* mn
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "project kernel");
   STDG_HIP(hipStreamSynchronize((hipStream_t)stream));
-  STDG_HIP(hipFree(d_mnl));
-  STDG_HIP(hipFree(d_abc));
+  dev_free(m.ctx, d_mnl, nb);
+  dev_free(m.ctx, d_abc, nd);
   return STDG_OK;
 }
 
@@ -387,13 +390,16 @@ int stdg_energy(const stdg_mesh* mesh, const double* state_dev, double* energy_o
   int rc = ensure_state_off(&m);
   if (rc != STDG_OK) return rc;
   double* d_tmp = nullptr;
-  STDG_HIP(hipMalloc(&d_tmp, sizeof(double) * (m.ne + 1)));
+  const size_t nb = sizeof(double) * (m.ne + 1);
+  if ((rc = dev_alloc(m.ctx, (void**)&d_tmp, nb)) != STDG_OK) return rc;
   rc = energy_async(&m, state_dev, d_tmp, d_tmp + m.ne, (hipStream_t)stream);
-  if (rc != STDG_OK) return rc;
-  STDG_HIP(hipMemcpyAsync(energy_out, d_tmp + m.ne, sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream));
-  STDG_HIP(hipStreamSynchronize((hipStream_t)stream));
-  STDG_HIP(hipFree(d_tmp));
-  return STDG_OK;
+  if (rc == STDG_OK) {
+    hipError_t e = hipMemcpyAsync(energy_out, d_tmp + m.ne, sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) rc = hip_fail(e, "stdg_energy");
+  }
+  dev_free(m.ctx, d_tmp, nb);
+  return rc;
 }
 
 }  // extern "C"

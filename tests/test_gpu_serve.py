@@ -1,0 +1,183 @@
+"""GPU tests of the serving loop (stdg_serve_*): independent cavity solves
+marched slab by slab (Section 2.2), admitted by device footprint and run
+concurrently.
+
+* each request's result is bitwise the same alone, in a mix, and as the plain
+  stdg_slab_solve march of the same slabs;
+* a small request matches the oracle's direct slab solves to 1e-10;
+* admission waits for memory; errors stay per request and are reported
+  through the result; stop with work in flight returns."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import Lib, note, oracle_disc, rel_err
+
+pytestmark = pytest.mark.gpu
+
+OPTS = dict(inner_prec=1, rtol=1e-12, max_iters=3000, max_refine=300)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return Lib()
+
+
+def _small_stream(k, sizes=(4, 6), degrees=(2, 3), n_slabs=3):
+    return synth.serving_stream(n_requests=k, sizes=sizes, degrees=degrees, n_slabs=n_slabs)
+
+
+def _submit(stdg, srv, rq):
+    m = rq["mesh"]
+    return stdg.stdg_serve_submit(srv, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu, 0.0, rq["dt"], rq["n_slabs"],
+                                  source=None, mnl=rq["init"].mnl, abc=rq["init"].abc)
+
+
+def _wait(stdg, srv, tickets, sizes, timeout=120.0):
+    out = {}
+    t_end = time.time() + timeout
+    while len(out) < len(tickets):
+        assert time.time() < t_end, "serving requests did not finish in time"
+        for t, n in zip(tickets, sizes):
+            if t in out:
+                continue
+            st = np.zeros(n)
+            r = stdg.stdg_serve_poll(srv, t, st)
+            if r is not None:
+                r["state"] = st
+                out[t] = r
+        time.sleep(0.002)
+    return [out[t] for t in tickets]
+
+
+def _march(lib, rq):
+    """The same request through stdg_project_modes + stdg_slab_solve."""
+    stdg = lib.stdg
+    m = rq["mesh"]
+    mh = lib.upload(m)
+    info = stdg.stdg_mesh_info(mh)
+    st = lib.torch.zeros(info["state_size"], dtype=lib.torch.float64, device="cuda")
+    stdg.stdg_project_modes(mh, rq["init"].mnl, rq["init"].abc, st)
+    for n in range(rq["n_slabs"]):
+        r = stdg.stdg_slab_solve(mh, n * rq["dt"], rq["dt"], None, st, **OPTS)
+        assert r["status"] == 0
+    out = st.cpu().numpy()
+    stdg.stdg_mesh_free(mh)
+    return out
+
+
+def test_serve_matches_slab_solve_alone_and_in_mix(lib):
+    stdg = lib.stdg
+    reqs = _small_stream(10)
+    sizes = [r["mesh"].state_size() for r in reqs]
+    note("serve: one request alone")
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 30, max_active=4, **OPTS)
+    try:
+        alone = _wait(stdg, srv, [_submit(stdg, srv, reqs[3])], [sizes[3]])[0]
+        note("serve: ten requests in a mix")
+        tickets = [_submit(stdg, srv, r) for r in reqs]
+        mix = _wait(stdg, srv, tickets, sizes)
+    finally:
+        stdg.stdg_serve_stop(srv)
+    assert alone["status"] == 0 and alone["slabs_done"] == reqs[3]["n_slabs"]
+    for r in mix:
+        assert r["status"] == 0, r
+        assert abs(r["energy_end"] - r["energy_start"]) < 1e-10 * r["energy_start"]
+    assert np.array_equal(alone["state"], mix[3]["state"])
+    note("serve: plain march of request 3")
+    ref = _march(lib, reqs[3])
+    assert np.array_equal(ref, mix[3]["state"])
+
+
+def test_serve_matches_oracle(lib):
+    stdg = lib.stdg
+    rq = _small_stream(1, sizes=(4,), degrees=(2,), n_slabs=2)[0]
+    m = rq["mesh"]
+    d = oracle_disc(m)
+    from oracle import fields
+    s = fields.project(d, fields.mode_superposition(rq["init"].mnl, rq["init"].abc), 0.0)
+    for _ in range(rq["n_slabs"]):
+        s = d.level_state(d.solve_direct(s, rq["dt"]), 1)
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 28, **OPTS)
+    try:
+        r = _wait(stdg, srv, [_submit(stdg, srv, rq)], [m.state_size()])[0]
+    finally:
+        stdg.stdg_serve_stop(srv)
+    assert r["status"] == 0
+    assert rel_err(r["state"], s) < 1e-10
+
+
+def test_admission_waits_for_memory(lib):
+    stdg = lib.stdg
+    reqs = _small_stream(3, sizes=(6,), degrees=(3,), n_slabs=2)
+    sizes = [r["mesh"].state_size() for r in reqs]
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 30, **OPTS)
+    try:
+        one = _wait(stdg, srv, [_submit(stdg, srv, reqs[0])], sizes[:1])[0]
+    finally:
+        stdg.stdg_serve_stop(srv)
+    # an arena that holds one of these requests but not two
+    budget = int(one["device_bytes"] * 1.5)
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=budget, **OPTS)
+    try:
+        res = _wait(stdg, srv, [_submit(stdg, srv, r) for r in reqs], sizes)
+    finally:
+        stdg.stdg_serve_stop(srv)
+    for a, b in zip(res, res[1:]):
+        assert b["t_admit"] >= a["t_done"] - 1e-3
+    for r in res:
+        assert r["status"] == 0
+    assert np.array_equal(res[0]["state"], one["state"])
+
+
+def test_errors_stay_per_request(lib):
+    stdg = lib.stdg
+    good = _small_stream(1, sizes=(4,), degrees=(2,), n_slabs=2)[0]
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 26, **OPTS)
+    try:
+        # larger than the whole arena: refused at submit
+        big = synth.serving_stream(n_requests=1, sizes=(16,), degrees=(6,), n_slabs=1)[0]
+        with pytest.raises(stdg.StdgError) as ei:
+            _submit(stdg, srv, big)
+        assert ei.value.status == -7
+        # invalid degree: refused at submit
+        m = good["mesh"]
+        with pytest.raises(stdg.StdgError):
+            stdg.stdg_serve_submit(srv, m.vertices, m.hexes, np.full(m.n_elements, 12), m.q, m.eps, m.mu, 0.0,
+                                   good["dt"], 1)
+        # a face shared by three elements: the mesh build fails inside the server
+        bad_h = m.hexes.copy()
+        bad_h[1] = bad_h[0]
+        bad_h[2] = bad_h[0]
+        t_bad = stdg.stdg_serve_submit(srv, m.vertices, bad_h, m.p, m.q, m.eps, m.mu, 0.0, good["dt"], 1)
+        t_good = _submit(stdg, srv, good)
+        r_bad, r_good = _wait(stdg, srv, [t_bad, t_good], [m.state_size(), m.state_size()])
+    finally:
+        stdg.stdg_serve_stop(srv)
+    assert r_bad["status"] == -1 and r_bad["slabs_done"] == 0
+    assert r_good["status"] == 0 and r_good["slabs_done"] == 2
+
+
+def test_not_converged_is_reported(lib):
+    stdg = lib.stdg
+    rq = _small_stream(1, sizes=(4,), degrees=(2,), n_slabs=2)[0]
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 26, inner_prec=0, rtol=1e-14, max_iters=1)
+    try:
+        r = _wait(stdg, srv, [_submit(stdg, srv, rq)], [rq["mesh"].state_size()])[0]
+    finally:
+        stdg.stdg_serve_stop(srv)
+    assert r["status"] == -5 and r["slabs_done"] == 2 and 0 < r["max_rel_res"] < 1
+
+
+def test_stop_with_work_in_flight(lib):
+    stdg = lib.stdg
+    reqs = _small_stream(6, sizes=(6, 8), degrees=(3, 4), n_slabs=20)
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 30, max_active=2, **OPTS)
+    tickets = [_submit(stdg, srv, r) for r in reqs]
+    time.sleep(0.05)
+    t0 = time.time()
+    stdg.stdg_serve_stop(srv)
+    assert time.time() - t0 < 30
+    assert len(tickets) == 6
