@@ -47,6 +47,10 @@ def parse():
                     help="elements in the oracle's timed sample (0 = sized to ~15 s)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=256,
+                    help="requests of the Poisson serving stream (0 = skip the serving leg)")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-max-active", type=int, default=16)
     return ap.parse_args()
 
 
@@ -181,6 +185,13 @@ def main():
         except Exception as e:  # solver reported separately; the apply line still prints
             log("slab solve skipped: %s" % e)
 
+    serving = None
+    if args.serve_requests > 0:
+        log("serving stream: %d requests" % args.serve_requests)
+        serving = time_serving(stdg, ctx, args.serve_requests, args.serve_budget_gb, args.serve_max_active)
+        log("serving: %.2f solves/s, p50 %.3f s, p99 %.3f s" % (serving["solves_per_s"], serving["p50_latency_s"],
+                                                               serving["p99_latency_s"]))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline on a bounded sample")
@@ -216,9 +227,63 @@ def main():
     }
     if solve is not None:
         out["slab_solve"] = solve
+    if serving is not None:
+        out["serving"] = serving
     print(json.dumps(out), flush=True)
     stdg.stdg_mesh_free(mh)
     stdg.stdg_finalize(ctx)
+
+
+def time_serving(stdg, ctx, n_requests, budget_gb, max_active):
+    """The serving stream: independent PEC cavity solves (n^3, n in {4,..,16},
+    p in 2..6, q = p - 1, eps in {1,2,4} per element, 20 slabs, dt = h/(2p+1))
+    arriving as a Poisson process at 50 per second, submitted at their arrival
+    times; FP32 applies inside FP64 refinement to rtol 1e-10 per slab."""
+    import synth
+    reqs = synth.serving_stream(n_requests=n_requests)
+    dofs = [r["mesh"].trial_size() * r["n_slabs"] for r in reqs]
+    srv = stdg.stdg_serve_start(ctx, hbm_budget=int(budget_gb * (1 << 30)), max_active=max_active,
+                                inner_prec=stdg.STDG_FP32, rtol=1e-10, max_iters=3000, max_refine=300)
+    results = {}
+    try:
+        c0 = stdg.stdg_serve_clock(srv)
+        tickets = []
+        k = 0
+        last_log = 0.0
+        while len(results) < len(reqs):
+            now = stdg.stdg_serve_clock(srv) - c0
+            while k < len(reqs) and reqs[k]["arrival"] <= now:
+                m = reqs[k]["mesh"]
+                tickets.append(stdg.stdg_serve_submit(srv, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu, 0.0,
+                                                      reqs[k]["dt"], reqs[k]["n_slabs"], mnl=reqs[k]["init"].mnl,
+                                                      abc=reqs[k]["init"].abc))
+                k += 1
+            for i, t in enumerate(tickets):
+                if i not in results:
+                    r = stdg.stdg_serve_poll(srv, t)
+                    if r is not None:
+                        results[i] = r
+            if now - last_log > 5.0:
+                log("serving: %d submitted, %d done at %.1f s" % (k, len(results), now))
+                last_log = now
+            time.sleep(0.0005)
+    finally:
+        stdg.stdg_serve_stop(srv)
+    res = [results[i] for i in range(len(reqs))]
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    bad = [i for i, r in enumerate(res) if r["status"] != 0]
+    return {"requests": len(res), "rate_per_s": 50.0, "slabs_per_request": reqs[0]["n_slabs"],
+            "solves_per_s": round(len(res) / span, 3), "slab_solves_per_s": round(sum(r["slabs_done"] for r in res) / span, 2),
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "mean_latency_s": round(float(lat.mean()), 4), "span_s": round(span, 3),
+            "gdof_per_s_trial_x_slabs": round(sum(dofs) / span / 1e9, 3),
+            "iters_per_slab": round(sum(r["iters"] for r in res) / sum(r["slabs_done"] for r in res), 2),
+            "max_rel_res": max(r["max_rel_res"] for r in res), "failed": bad,
+            "hbm_budget_gb": budget_gb, "max_active": max_active,
+            "max_energy_drift": max(abs(r["energy_end"] - r["energy_start"]) / max(r["energy_start"], 1e-300)
+                                    for r in res)}
 
 
 def time_solves(stdg, torch, mh, m, cfg):
@@ -227,13 +292,15 @@ def time_solves(stdg, torch, mh, m, cfg):
     info = stdg.stdg_mesh_info(mh)
     modes = cfg["init"]
     res = {}
-    for name, inner in (("fp32_refine", stdg.STDG_FP32), ("fp64", stdg.STDG_FP64)):
+    for name, inner, krylov in (("fp32_refine", stdg.STDG_FP32, stdg.STDG_FP64),
+                                ("fp32_refine_fp32_basis", stdg.STDG_FP32, stdg.STDG_FP32),
+                                ("fp64", stdg.STDG_FP64, stdg.STDG_FP64)):
         state = torch.zeros(info["state_size"], dtype=torch.float64, device="cuda")
         stdg.stdg_project_modes(mh, modes.mnl, modes.abc, state)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, state, inner_prec=inner, rtol=1e-10,
-                                 max_iters=3000, max_refine=300)
+                                 max_iters=3000, max_refine=300, krylov_prec=krylov)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         res[name] = {"s_per_solve": round(el, 4), "solves_per_s": round(1.0 / el, 3), "iters": r["iters"],
@@ -241,6 +308,8 @@ def time_solves(stdg, torch, mh, m, cfg):
                      "energy_drift": (r["energy_end"] - r["energy_start"]) / max(r["energy_start"], 1e-300)}
         log("slab solve %s: %.3f s, %d iters" % (name, el, r["iters"]))
     res["speedup_fp32_refine"] = round(res["fp64"]["s_per_solve"] / res["fp32_refine"]["s_per_solve"], 3)
+    res["speedup_fp32_refine_fp32_basis"] = round(
+        res["fp64"]["s_per_solve"] / res["fp32_refine_fp32_basis"]["s_per_solve"], 3)
     return res
 
 

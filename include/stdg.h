@@ -184,6 +184,8 @@ typedef struct {
                           applies (one per restart cycle; default 100)           */
   double rtol;         /* stop when ||L - B U||_2 <= rtol ||L - B U_0||_2 (FP64)  */
   double inner_rtol;   /* relative tolerance of each inner GMRES (FP32 inner)    */
+  int32_t krylov_prec; /* storage of the Krylov basis: STDG_FP64 (default), or
+                          STDG_FP32 with FP32 inner applies (sums stay FP64)     */
 } stdg_solve_opts;
 
 typedef struct {
@@ -232,6 +234,7 @@ typedef struct {
   int32_t max_refine;
   double rtol;
   double inner_rtol;
+  int32_t krylov_prec;
 } stdg_serve_opts;
 
 typedef struct {

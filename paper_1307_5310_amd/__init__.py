@@ -106,9 +106,9 @@ def stdg_project_modes(mesh, mnl, abc, state, stream=None):
 
 
 def stdg_slab_solve(mesh, t0, dt, load, state, inner_prec=STDG_FP64, restart=10, max_iters=500,
-                    max_refine=100, rtol=1e-12, inner_rtol=1e-4, slab_U=None, stream=None):
+                    max_refine=100, rtol=1e-12, inner_rtol=1e-4, slab_U=None, stream=None, krylov_prec=STDG_FP64):
     o = SolveOpts(int(inner_prec), int(restart), int(max_iters), int(max_refine), float(rtol),
-                  float(inner_rtol))
+                  float(inner_rtol), int(krylov_prec))
     info = SolveInfo()
     st = lib().stdg_slab_solve(mesh, float(t0), float(dt), ptr(load), ctypes.byref(o), ptr(state),
                                ptr(slab_U), ctypes.byref(info), stream_handle(stream))
@@ -126,9 +126,9 @@ def stdg_energy(mesh, state, stream=None):
 
 
 def stdg_serve_start(ctx, hbm_budget=0, max_active=0, inner_prec=STDG_FP32, restart=10, max_iters=500,
-                     max_refine=100, rtol=1e-10, inner_rtol=1e-4):
+                     max_refine=100, rtol=1e-10, inner_rtol=1e-4, krylov_prec=STDG_FP64):
     o = ServeOpts(int(hbm_budget), int(max_active), int(inner_prec), int(restart), int(max_iters),
-                  int(max_refine), float(rtol), float(inner_rtol))
+                  int(max_refine), float(rtol), float(inner_rtol), int(krylov_prec))
     h = ctypes.c_void_p()
     check(lib().stdg_serve_start(ctx, ctypes.byref(o), ctypes.byref(h)))
     return h

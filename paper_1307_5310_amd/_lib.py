@@ -60,7 +60,8 @@ class Source(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("max_refine", ctypes.c_int32),
-                ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double)]
+                ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+                ("krylov_prec", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -73,7 +74,8 @@ class ServeOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("max_refine", ctypes.c_int32),
-                ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double)]
+                ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+                ("krylov_prec", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):

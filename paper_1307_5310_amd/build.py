@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstdg.so")
 
 HOST_SOURCES = ["api.cpp", "mesh.cpp", "tables.cpp", "solver.cpp", "serve.cpp"]
-HIP_SOURCES = ["residual.hip", "blas.hip", "load.hip"]
+HIP_SOURCES = ["residual.hip", "blas.hip", "krylov.hip", "load.hip"]
 SLICES = [(real, a, aff) for real in ("float", "double") for a in range(2, 10) for aff in (1, 0)]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

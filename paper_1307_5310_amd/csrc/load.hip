@@ -170,47 +170,83 @@ struct ProjParams {
   const double* abc;
 };
 
+// L2 projection on affine elements, sum factorised over the tensor Gauss rule
+// of a + 3 points per direction: the field is evaluated once per point (mapped
+// covariantly, times |J|) into shared memory, contracted one direction at a
+// time against w_g L_j(x_g), and the per-mode 3x3 mass G = |J| DF^{-1} DF^{-T}
+// is inverted at the end (the mass of an affine element is G (x) I).
+// Dynamic shared memory: 3 nx^3 + nx^2 a + nx a^2 doubles, nx = a + 3.
 __global__ void project_kernel(ProjParams P) {
+  extern __shared__ double sh[];
+  __shared__ double qx[kMaxA + 3], qw[kMaxA + 3], Bt[(kMaxA + 3) * kMaxA];
   const int e = blockIdx.x;
   const ElemInfo I = P.info[e];
-  const int a = I.a, a3 = a * a * a;
-  __shared__ double rxx[16], rxw[16];
-  const int nx = a + 3;
-  if (threadIdx.x == 0) gauss01(nx, rxx, rxw);
+  const int a = I.a, a2 = a * a, a3 = a2 * a;
+  const int nx = a + 3, nx2 = nx * nx, nx3 = nx2 * nx;
+  if (threadIdx.x == 0) gauss01(nx, qx, qw);
   __syncthreads();
+  for (int k = threadIdx.x; k < nx * a; k += blockDim.x) {
+    const int g = k / a, j = k - g * a;
+    Bt[k] = qw[g] * leg(j, qx[g]);
+  }
   const double* X = P.verts + 24 * e;
+  double F0[3], DF[3][3], Di[3][3];
+  trilinear(X, 0.5, 0.5, 0.5, F0, DF);
+  const double det = inv3(DF, Di);
+  double* F = sh;
+  double* T1 = sh + 3 * nx3;
+  double* T2 = T1 + nx2 * a;
+  for (int pt = threadIdx.x; pt < nx3; pt += blockDim.x) {
+    const int g1 = pt % nx, g2 = (pt / nx) % nx, g3 = pt / nx2;
+    double xp[3], DFp[3][3];
+    trilinear(X, qx[g1], qx[g2], qx[g3], xp, DFp);
+    double E[3] = {0.0, 0.0, 0.0};
+    for (int r = 0; r < P.n_modes; ++r) {
+      const double kx = M_PI * P.mnl[3 * r] * xp[0], ky = M_PI * P.mnl[3 * r + 1] * xp[1],
+                   kz = M_PI * P.mnl[3 * r + 2] * xp[2];
+      const double sx = sin(kx), cx = cos(kx), sy = sin(ky), cy = cos(ky), sz = sin(kz), cz = cos(kz);
+      E[0] += P.abc[3 * r] * cx * sy * sz;
+      E[1] += P.abc[3 * r + 1] * sx * cy * sz;
+      E[2] += P.abc[3 * r + 2] * sx * sy * cz;
+    }
+    // E . DF^{-T} e_c |J| = (DF^{-1} E)_c |J|
+    for (int c = 0; c < 3; ++c) F[c * nx3 + pt] = det * (Di[c][0] * E[0] + Di[c][1] * E[1] + Di[c][2] * E[2]);
+  }
+  __syncthreads();
   double* out = P.out + P.state_off[e];
+  for (int c = 0; c < 3; ++c) {
+    const double* Fc = F + c * nx3;
+    for (int o = threadIdx.x; o < nx2 * a; o += blockDim.x) {  // [g3][g2][j]
+      const int j = o % a, g23 = o / a;
+      double acc = 0.0;
+      for (int g1 = 0; g1 < nx; ++g1) acc += Bt[g1 * a + j] * Fc[g23 * nx + g1];
+      T1[o] = acc;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < nx * a2; o += blockDim.x) {  // [g3][k][j]
+      const int j = o % a, k = (o / a) % a, g3 = o / a2;
+      double acc = 0.0;
+      for (int g2 = 0; g2 < nx; ++g2) acc += Bt[g2 * a + k] * T1[(g3 * nx + g2) * a + j];
+      T2[o] = acc;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < a3; s += blockDim.x) {  // [l][k][j]
+      const int jk = s % a2, l = s / a2;
+      double acc = 0.0;
+      for (int g3 = 0; g3 < nx; ++g3) acc += Bt[g3 * a + l] * T2[g3 * a2 + jk];
+      out[(int64_t)c * a3 + s] = acc;
+    }
+    __syncthreads();
+  }
+  // c_s = G^{-1} b_s with G = |J| DF^{-1} DF^{-T}
+  double G[3][3], Gi[3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int d = 0; d < 3; ++d) G[c][d] = det * (Di[c][0] * Di[d][0] + Di[c][1] * Di[d][1] + Di[c][2] * Di[d][2]);
+  inv3(G, Gi);
   for (int s = threadIdx.x; s < a3; s += blockDim.x) {
-    const int sj = s % a, sk = (s / a) % a, sl = s / (a * a);
-    double b[3] = {0.0, 0.0, 0.0};
-    double G[3][3] = {{0}};
-    for (int gz = 0; gz < nx; ++gz)
-      for (int gy = 0; gy < nx; ++gy)
-        for (int gx = 0; gx < nx; ++gx) {
-          double F[3], DF[3][3], Di[3][3];
-          trilinear(X, rxx[gx], rxx[gy], rxx[gz], F, DF);
-          const double det = inv3(DF, Di);
-          const double phi = leg(sj, rxx[gx]) * leg(sk, rxx[gy]) * leg(sl, rxx[gz]);
-          double E[3] = {0.0, 0.0, 0.0};
-          for (int r = 0; r < P.n_modes; ++r) {
-            const double kx = M_PI * P.mnl[3 * r] * F[0], ky = M_PI * P.mnl[3 * r + 1] * F[1],
-                         kz = M_PI * P.mnl[3 * r + 2] * F[2];
-            E[0] += P.abc[3 * r] * cos(kx) * sin(ky) * sin(kz);
-            E[1] += P.abc[3 * r + 1] * sin(kx) * cos(ky) * sin(kz);
-            E[2] += P.abc[3 * r + 2] * sin(kx) * sin(ky) * cos(kz);
-          }
-          const double w = rxw[gx] * rxw[gy] * rxw[gz] * det;
-          for (int c = 0; c < 3; ++c) b[c] += w * phi * (Di[c][0] * E[0] + Di[c][1] * E[1] + Di[c][2] * E[2]);
-          // unit-coefficient metric |J| DF^{-1} DF^{-T} integrated over the element
-          for (int c = 0; c < 3; ++c)
-            for (int d = 0; d < 3; ++d)
-              G[c][d] += w * (Di[c][0] * Di[d][0] + Di[c][1] * Di[d][1] + Di[c][2] * Di[d][2]);
-        }
-    // affine elements: unit-coefficient mass = G (x) I, so c_s = G^{-1} b_s
-    double Gi[3][3];
-    inv3(G, Gi);
+    const double b0 = out[s], b1 = out[a3 + s], b2 = out[2 * a3 + s];
     for (int c = 0; c < 3; ++c) {
-      out[(int64_t)c * a3 + s] = Gi[c][0] * b[0] + Gi[c][1] * b[1] + Gi[c][2] * b[2];
+      out[(int64_t)c * a3 + s] = Gi[c][0] * b0 + Gi[c][1] * b1 + Gi[c][2] * b2;
       out[(int64_t)(3 + c) * a3 + s] = 0.0;
     }
   }
@@ -375,7 +411,9 @@ int stdg_project_modes(const stdg_mesh* mesh, int32_t n_modes, const int32_t* mn
   P.n_modes = n_modes;
   P.mnl = d_mnl;
   P.abc = d_abc;
-  hipLaunchKernelGGL(project_kernel, dim3((unsigned)m.ne), dim3(128), 0, (hipStream_t)stream, P);
+  const int amax = m.p_max + 1, nx = amax + 3;
+  const size_t shb = sizeof(double) * (3 * nx * nx * nx + nx * nx * amax + nx * amax * amax);
+  hipLaunchKernelGGL(project_kernel, dim3((unsigned)m.ne), dim3(256), shb, (hipStream_t)stream, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "project kernel");
   STDG_HIP(hipStreamSynchronize((hipStream_t)stream));

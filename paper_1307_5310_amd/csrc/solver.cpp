@@ -7,8 +7,10 @@
 //
 // Every restart cycle starts from the true residual L - B U evaluated in
 // FP64.  Inner applies run in FP64 (the plain path) or in FP32 with FP64
-// Krylov vectors and FP64 orthogonalisation (classical Gram-Schmidt applied
-// twice); with FP32 applies each cycle is one step of iterative refinement.
+// orthogonalisation (classical Gram-Schmidt applied twice, fused into three
+// passes over the basis, krylov.hip); with FP32 applies each cycle is one step
+// of iterative refinement.  The basis is stored in FP64, or optionally in FP32
+// (all sums still FP64).
 // The end-of-slab state is the l_1 block of the solution (continuity in time:
 // l_1(1) = 1, every other trial function vanishes at the slab end).
 #include <algorithm>
@@ -21,10 +23,12 @@
 namespace stdg {
 
 namespace {
-// pinned host scalars: h of the two Gram-Schmidt passes, ||w||^2, ||r||^2,
-// the energies, and the GMRES coefficients y on their way to the device
-constexpr int kH1 = 0, kH2 = kMaxBasis, kHN = 2 * kMaxBasis, kBeta = kHN + 1, kE0 = kHN + 2, kE1 = kHN + 3,
-              kY = kHN + 4, kHostScalars = kY + kMaxBasis;
+// device scalars (mirrored to pinned host memory after each step): h and c of
+// the two Gram-Schmidt passes, ||Vt_{j+1}||^2, ||r||^2, basis scales s_j, the
+// correction coefficients, and the energies
+constexpr int kH1 = 0, kC1 = kMaxBasis, kH2 = 2 * kMaxBasis, kC2 = 3 * kMaxBasis, kHN = 4 * kMaxBasis,
+              kBeta = kHN + 1, kE0 = kHN + 2, kE1 = kHN + 3, kMirror = kHN + 4,  // entries copied back
+              kS = kMirror, kY = kS + kMaxBasis + 1, kScalars = kY + kMaxBasis;
 
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 }  // namespace
@@ -32,8 +36,13 @@ size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 int slab_opts_from(const stdg_solve_opts* o, SlabOpts* out) {
   if (o->inner_prec != STDG_FP64 && o->inner_prec != STDG_FP32)
     return fail(STDG_E_ARG, "stdg_slab_solve: unknown inner precision");
+  if (o->krylov_prec != STDG_FP64 && o->krylov_prec != STDG_FP32)
+    return fail(STDG_E_ARG, "stdg_slab_solve: unknown Krylov basis precision");
+  if (o->krylov_prec == STDG_FP32 && o->inner_prec != STDG_FP32)
+    return fail(STDG_E_ARG, "stdg_slab_solve: an FP32 Krylov basis needs FP32 inner applies");
   SlabOpts r;
   r.f32 = o->inner_prec == STDG_FP32;
+  r.v32 = o->krylov_prec == STDG_FP32;
   r.restart = o->restart > 0 ? o->restart : 10;
   if (r.restart + 1 > kMaxBasis) return fail(STDG_E_ARG, "stdg_slab_solve: restart must be <= 31");
   r.max_iters = o->max_iters > 0 ? o->max_iters : 500;
@@ -46,10 +55,13 @@ int slab_opts_from(const stdg_solve_opts* o, SlabOpts* out) {
 
 size_t slab_solver_bytes(int64_t n, int64_t nt, int64_t ne, const SlabOpts& o) {
   const size_t n8 = round256(sizeof(double) * n), n4 = round256(sizeof(float) * n);
-  size_t b = round256(sizeof(double) * n * (o.restart + 1)) + 5 * n8 + round256(sizeof(double) * nt);
-  if (o.f32) b += 2 * n4;
-  b += round256(sizeof(double) * kDotBlocks * kMaxBasis) + round256(sizeof(double) * kMaxBasis) +
-       round256(sizeof(double) * (ne + 2));
+  const int64_t ld = (n + 63) / 64 * 64;
+  size_t b = round256((o.v32 ? sizeof(float) : sizeof(double)) * ld * (o.restart + 1)) + 4 * n8 +
+             round256(sizeof(double) * nt);
+  if (o.v32) b += n8;                 // residual before rounding into the basis
+  if (o.f32) b += (o.v32 ? 1 : 2) * n4;
+  b += round256(sizeof(double) * kMaxBasis * kMaxDotBlocks) + round256(sizeof(unsigned) * 4) +
+       round256(sizeof(double) * kScalars) + round256(sizeof(double) * (ne + 2));
   return b;
 }
 
@@ -60,25 +72,29 @@ int SlabSolver::init(Mesh* m, const SlabOpts& o, hipStream_t s) {
   int rc = ensure_state_off(m);
   if (rc != STDG_OK) return rc;
   n_ = m->unk_off.back();
+  ld_ = (n_ + 63) / 64 * 64;
   const int64_t nt = m->trial_off.back();
   const size_t n8 = sizeof(double) * n_, n4 = sizeof(float) * n_;
   Ctx* c = m->ctx;
-  if ((rc = dev_alloc(c, (void**)&V_, n8 * (o.restart + 1))) != STDG_OK) return rc;
+  if ((rc = dev_alloc(c, &V_, (o.v32 ? 4 : 8) * (size_t)ld_ * (o.restart + 1))) != STDG_OK) return rc;
   if ((rc = dev_alloc(c, (void**)&w_, n8)) != STDG_OK) return rc;
   if ((rc = dev_alloc(c, (void**)&x_, n8)) != STDG_OK) return rc;
-  if ((rc = dev_alloc(c, (void**)&r_, n8)) != STDG_OK) return rc;
   if ((rc = dev_alloc(c, (void**)&d_, n8)) != STDG_OK) return rc;
   if ((rc = dev_alloc(c, (void**)&pd_, n8)) != STDG_OK) return rc;
   if ((rc = dev_alloc(c, (void**)&U_, sizeof(double) * nt)) != STDG_OK) return rc;
+  if (o.v32 && (rc = dev_alloc(c, (void**)&r_, n8)) != STDG_OK) return rc;
   if (o.f32) {
-    if ((rc = dev_alloc(c, (void**)&v32_, n4)) != STDG_OK) return rc;
+    if (!o.v32 && (rc = dev_alloc(c, (void**)&v32_, n4)) != STDG_OK) return rc;
     if ((rc = dev_alloc(c, (void**)&w32_, n4)) != STDG_OK) return rc;
   }
-  if ((rc = dev_alloc(c, (void**)&partial_, sizeof(double) * kDotBlocks * kMaxBasis)) != STDG_OK) return rc;
-  if ((rc = dev_alloc(c, (void**)&hdev_, sizeof(double) * kMaxBasis)) != STDG_OK) return rc;
+  if ((rc = dev_alloc(c, (void**)&dw_.partial, sizeof(double) * kMaxBasis * kMaxDotBlocks)) != STDG_OK) return rc;
+  if ((rc = dev_alloc(c, (void**)&dw_.counter, sizeof(unsigned) * 4)) != STDG_OK) return rc;
+  if ((rc = dev_alloc(c, (void**)&hv_, sizeof(double) * kScalars)) != STDG_OK) return rc;
   if ((rc = dev_alloc(c, (void**)&etmp_, sizeof(double) * (m->ne + 2))) != STDG_OK) return rc;
-  STDG_HIP(hipHostMalloc((void**)&hb_, sizeof(double) * kHostScalars, hipHostMallocDefault));
-  std::memset(hb_, 0, sizeof(double) * kHostScalars);
+  STDG_HIP(hipMemsetAsync(dw_.counter, 0, sizeof(unsigned) * 4, s_));
+  STDG_HIP(hipMemsetAsync(hv_, 0, sizeof(double) * kScalars, s_));
+  STDG_HIP(hipHostMalloc((void**)&hb_, sizeof(double) * kScalars, hipHostMallocDefault));
+  std::memset(hb_, 0, sizeof(double) * kScalars);
   STDG_HIP(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
   return STDG_OK;
 }
@@ -87,36 +103,40 @@ void SlabSolver::release() {
   if (!m_) return;
   Ctx* c = m_->ctx;
   const size_t n8 = sizeof(double) * n_, n4 = sizeof(float) * n_;
-  dev_free(c, V_, n8 * (o_.restart + 1));
+  dev_free(c, V_, (o_.v32 ? 4 : 8) * (size_t)ld_ * (o_.restart + 1));
   dev_free(c, w_, n8);
   dev_free(c, x_, n8);
-  dev_free(c, r_, n8);
   dev_free(c, d_, n8);
   dev_free(c, pd_, n8);
   dev_free(c, U_, sizeof(double) * m_->trial_off.back());
+  dev_free(c, r_, n8);
   dev_free(c, v32_, n4);
   dev_free(c, w32_, n4);
-  dev_free(c, partial_, sizeof(double) * kDotBlocks * kMaxBasis);
-  dev_free(c, hdev_, sizeof(double) * kMaxBasis);
+  dev_free(c, dw_.partial, sizeof(double) * kMaxBasis * kMaxDotBlocks);
+  dev_free(c, dw_.counter, sizeof(unsigned) * 4);
+  dev_free(c, hv_, sizeof(double) * kScalars);
   dev_free(c, etmp_, sizeof(double) * (m_->ne + 2));
   if (hb_) (void)hipHostFree(hb_);
   if (ev_) (void)hipEventDestroy(ev_);
-  V_ = w_ = x_ = r_ = U_ = d_ = pd_ = partial_ = hdev_ = etmp_ = hb_ = nullptr;
+  V_ = nullptr;
+  w_ = x_ = r_ = U_ = d_ = pd_ = hv_ = etmp_ = hb_ = nullptr;
   v32_ = w32_ = nullptr;
+  dw_ = DotWork();
   ev_ = nullptr;
   m_ = nullptr;
   phase_ = kIdle;
 }
 
-// r = L - B U(x) in FP64, and ||r||^2 into the pinned scalars
+// r' = B U(x) - L in FP64 (into the first basis slot when the basis is FP64),
+// and ||r'||^2 into the scalars; the Krylov residual is r = -r'
 int SlabSolver::launch_true_residual() {
   int rc;
   if ((rc = layout_embed(m_, U_, x_, state_, s_)) != STDG_OK) return rc;
-  ApplyArgs a{m_, dt_, STDG_FP64, STDG_RESIDUAL, U_, load_, r_, s_};
+  double* res = o_.v32 ? r_ : (double*)basis(0);
+  ApplyArgs a{m_, dt_, STDG_FP64, STDG_RESIDUAL, U_, load_, res, s_};
   if ((rc = launch_residual(a)) != STDG_OK) return rc;
-  if ((rc = blas_scale(r_, r_, -1.0, n_, s_)) != STDG_OK) return rc;
-  if ((rc = blas_multi_dot(r_, n_, 1, r_, false, n_, partial_, hdev_, s_)) != STDG_OK) return rc;
-  STDG_HIP(hipMemcpyAsync(hb_ + kBeta, hdev_, sizeof(double), hipMemcpyDeviceToHost, s_));
+  if ((rc = vec_dot(res, res, n_, hv_ + kBeta, dw_, s_)) != STDG_OK) return rc;
+  STDG_HIP(hipMemcpyAsync(hb_, hv_, sizeof(double) * kMirror, hipMemcpyDeviceToHost, s_));
   return STDG_OK;
 }
 
@@ -130,8 +150,7 @@ int SlabSolver::begin(double dt, const double* load, double* state, double* slab
   rel_res = energy_start = energy_end = 0.0;
   converged_ = false;
   int rc;
-  if ((rc = energy_async(m_, state_, etmp_, etmp_ + m_->ne, s_)) != STDG_OK) return rc;
-  STDG_HIP(hipMemcpyAsync(hb_ + kE0, etmp_ + m_->ne, sizeof(double), hipMemcpyDeviceToHost, s_));
+  if ((rc = energy_async(m_, state_, etmp_, hv_ + kE0, s_)) != STDG_OK) return rc;
   if ((rc = layout_guess(m_, x_, state_, s_)) != STDG_OK) return rc;
   if ((rc = launch_true_residual()) != STDG_OK) return rc;
   STDG_HIP(hipEventRecord(ev_, s_));
@@ -139,10 +158,14 @@ int SlabSolver::begin(double dt, const double* load, double* state, double* slab
   return STDG_OK;
 }
 
+// GMRES on B P^{-1} z' = r' (z' = -z, r' = -r): V_0 = r' / beta, Vt_0 = r', s_0 = 1 / beta
 int SlabSolver::start_cycle() {
   ++cycles_;
   int rc;
-  if ((rc = blas_scale(V_, r_, 1.0 / beta_, n_, s_)) != STDG_OK) return rc;
+  if (o_.v32 && (rc = vec_store(basis(0), true, r_, n_, s_)) != STDG_OK) return rc;
+  hs_[0] = 1.0 / beta_;
+  hb_[kS] = hs_[0];
+  STDG_HIP(hipMemcpyAsync(hv_ + kS, hb_ + kS, sizeof(double), hipMemcpyHostToDevice, s_));
   for (int i = 0; i <= o_.restart; ++i) g_[i] = 0.0;
   g_[0] = beta_;
   const double target = o_.rtol * beta0_;
@@ -151,48 +174,55 @@ int SlabSolver::start_cycle() {
   return launch_iteration();
 }
 
+// one Arnoldi step on w~ = B P^{-1} Vt_j (the true w is s_j w~)
 int SlabSolver::launch_iteration() {
   int rc;
   const int j = j_;
-  double* Vj = V_ + (int64_t)j * n_;
   const void* wsrc;
   if (o_.f32) {
-    if ((rc = blas_to_f32(v32_, Vj, 1.0, n_, s_)) != STDG_OK) return rc;
-    ApplyArgs a{m_, dt_, STDG_FP32, STDG_OPERATOR_PRECOND, v32_, nullptr, w32_, s_};
+    const float* in = (const float*)basis(j);
+    if (!o_.v32) {
+      if ((rc = vec_store(v32_, true, (const double*)basis(j), n_, s_)) != STDG_OK) return rc;
+      in = v32_;
+    }
+    ApplyArgs a{m_, dt_, STDG_FP32, STDG_OPERATOR_PRECOND, in, nullptr, w32_, s_};
     if ((rc = launch_residual(a)) != STDG_OK) return rc;
     wsrc = w32_;
   } else {
-    ApplyArgs a{m_, dt_, STDG_FP64, STDG_OPERATOR_PRECOND, Vj, nullptr, w_, s_};
+    ApplyArgs a{m_, dt_, STDG_FP64, STDG_OPERATOR_PRECOND, basis(j), nullptr, w_, s_};
     if ((rc = launch_residual(a)) != STDG_OK) return rc;
     wsrc = w_;
   }
   ++iters;
-  // classical Gram-Schmidt, twice
-  if ((rc = blas_multi_dot(V_, n_, j + 1, wsrc, o_.f32, n_, partial_, hdev_, s_)) != STDG_OK) return rc;
-  if ((rc = blas_update(w_, wsrc, o_.f32, V_, n_, j + 1, hdev_, n_, s_)) != STDG_OK) return rc;
-  STDG_HIP(hipMemcpyAsync(hb_ + kH1, hdev_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s_));
-  if ((rc = blas_multi_dot(V_, n_, j + 1, w_, false, n_, partial_, hdev_, s_)) != STDG_OK) return rc;
-  if ((rc = blas_update(w_, w_, false, V_, n_, j + 1, hdev_, n_, s_)) != STDG_OK) return rc;
-  STDG_HIP(hipMemcpyAsync(hb_ + kH2, hdev_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s_));
-  if ((rc = blas_multi_dot(w_, n_, 1, w_, false, n_, partial_, hdev_, s_)) != STDG_OK) return rc;
-  STDG_HIP(hipMemcpyAsync(hb_ + kHN, hdev_, sizeof(double), hipMemcpyDeviceToHost, s_));
+  const bool v32 = o_.v32, w32 = o_.f32;
+  if ((rc = arnoldi_dot(V_, v32, ld_, j + 1, wsrc, w32, n_, hv_ + kS, hv_ + kH1, hv_ + kC1, dw_, s_)) != STDG_OK)
+    return rc;
+  if ((rc = arnoldi_update_dot(V_, v32, ld_, j + 1, wsrc, w32, hv_ + kC1, w_, n_, hv_ + kS, hv_ + kH2, hv_ + kC2,
+                               dw_, s_)) != STDG_OK)
+    return rc;
+  if ((rc = arnoldi_update_norm(V_, v32, ld_, j + 1, w_, hv_ + kC2, basis(j + 1), n_, hv_ + kHN, hv_ + kS + j + 1,
+                                dw_, s_)) != STDG_OK)
+    return rc;
+  STDG_HIP(hipMemcpyAsync(hb_, hv_, sizeof(double) * kMirror, hipMemcpyDeviceToHost, s_));
   STDG_HIP(hipEventRecord(ev_, s_));
   phase_ = kWaitIter;
   return STDG_OK;
 }
 
-// y = H^{-1} g, correction d = sum_j y_j V_j, x += P^{-1} d, then the true residual
+// y = H^{-1} g, correction d = -sum_j y_j V_j = -sum_j (y_j s_j) Vt_j (the sign
+// undoes r' = -r), x += P^{-1} d, then the true residual
 int SlabSolver::launch_cycle_end() {
   const int k = j_;
-  double* y = hb_ + kY;
+  double y[kMaxBasis];
   for (int i = k - 1; i >= 0; --i) {
     double t = g_[i];
     for (int l = i + 1; l < k; ++l) t -= H_[i * kMaxBasis + l] * y[l];
     y[i] = t / H_[i * kMaxBasis + i];
   }
+  for (int i = 0; i < k; ++i) hb_[kY + i] = -y[i] * hs_[i];
   int rc;
-  STDG_HIP(hipMemcpyAsync(hdev_, y, sizeof(double) * k, hipMemcpyHostToDevice, s_));
-  if ((rc = blas_lincomb(d_, false, V_, n_, k, hdev_, n_, s_)) != STDG_OK) return rc;
+  STDG_HIP(hipMemcpyAsync(hv_ + kY, hb_ + kY, sizeof(double) * k, hipMemcpyHostToDevice, s_));
+  if ((rc = basis_combine(d_, V_, o_.v32, ld_, k, hv_ + kY, n_, s_)) != STDG_OK) return rc;
   if ((rc = launch_precond_scale(m_, STDG_FP64, d_, pd_, s_)) != STDG_OK) return rc;
   if ((rc = blas_axpy(x_, pd_, 1.0, n_, s_)) != STDG_OK) return rc;
   if ((rc = launch_true_residual()) != STDG_OK) return rc;
@@ -205,8 +235,8 @@ int SlabSolver::launch_slab_end() {
   int rc;
   if (slabU_ && (rc = layout_embed(m_, slabU_, x_, state_, s_)) != STDG_OK) return rc;
   if ((rc = layout_level(m_, state_, x_, 1, s_)) != STDG_OK) return rc;
-  if ((rc = energy_async(m_, state_, etmp_, etmp_ + m_->ne, s_)) != STDG_OK) return rc;
-  STDG_HIP(hipMemcpyAsync(hb_ + kE1, etmp_ + m_->ne, sizeof(double), hipMemcpyDeviceToHost, s_));
+  if ((rc = energy_async(m_, state_, etmp_, hv_ + kE1, s_)) != STDG_OK) return rc;
+  STDG_HIP(hipMemcpyAsync(hb_, hv_, sizeof(double) * kMirror, hipMemcpyDeviceToHost, s_));
   STDG_HIP(hipEventRecord(ev_, s_));
   phase_ = kWaitEnd;
   return STDG_OK;
@@ -226,13 +256,14 @@ int SlabSolver::advance(bool* done) {
     }
     case kWaitIter: {
       const int j = j_;
+      const double sj = hs_[j];
       double hcol[kMaxBasis + 1];
-      const double hnext = std::sqrt(hb_[kHN]);
-      for (int i = 0; i <= j; ++i) hcol[i] = hb_[kH1 + i] + hb_[kH2 + i];
+      const double nrm = std::sqrt(hb_[kHN]);
+      for (int i = 0; i <= j; ++i) hcol[i] = sj * (hb_[kH1 + i] + hb_[kH2 + i]);
+      const double hnext = sj * nrm;
       hcol[j + 1] = hnext;
+      hs_[j + 1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
       if (!std::isfinite(hnext)) return fail(STDG_E_NOT_CONVERGED, "stdg_slab_solve: non-finite Krylov vector");
-      int rc;
-      if (hnext > 0.0 && (rc = blas_scale(V_ + (int64_t)(j + 1) * n_, w_, 1.0 / hnext, n_, s_)) != STDG_OK) return rc;
       // Givens rotations
       for (int i = 0; i < j; ++i) {
         const double t = cs_[i] * hcol[i] + sn_[i] * hcol[i + 1];

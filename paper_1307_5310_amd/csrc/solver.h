@@ -1,4 +1,5 @@
-// Slab-solver internals: device vector kernels and layout conversions.
+// Slab-solver internals: device vector kernels, layout conversions, the fused
+// Arnoldi kernels and the resumable GMRES state machine.
 #pragma once
 
 #include "internal.h"
@@ -6,17 +7,29 @@
 namespace stdg {
 
 constexpr int kMaxBasis = 32;   // restart + 1 <= 32
-constexpr int kDotBlocks = 1024;
+constexpr int kMaxDotBlocks = 1024;
 
-int blas_multi_dot(const double* V, int64_t ld, int k, const void* w, bool w_f32, int64_t n, double* partial,
-                   double* out, hipStream_t s);
-int blas_update(double* w, const void* src, bool src_f32, const double* V, int64_t ld, int k, const double* h,
-                int64_t n, hipStream_t s);
-int blas_scale(double* out, const double* in, double alpha, int64_t n, hipStream_t s);
-int blas_lincomb(void* out, bool out_f32, const double* V, int64_t ld, int k, const double* y, int64_t n,
-                 hipStream_t s);
+// Scratch of the deterministic reductions: kMaxBasis * kMaxDotBlocks partials
+// and a counter that must be zero before the first use (kernels leave it zero).
+struct DotWork {
+  double* partial = nullptr;
+  unsigned* counter = nullptr;
+};
+// Fused Arnoldi kernels (krylov.hip); V holds k basis vectors of length n
+// (leading dimension ld) in FP32 (v32) or FP64, w in FP32 (w32) or FP64.
+int arnoldi_dot(const void* V, bool v32, int64_t ld, int k, const void* w, bool w32, int64_t n, const double* s,
+                double* h, double* c, const DotWork& dw, hipStream_t st);
+int arnoldi_update_dot(const void* V, bool v32, int64_t ld, int k, const void* w, bool w32, const double* cin,
+                       double* wout, int64_t n, const double* s, double* h, double* c, const DotWork& dw,
+                       hipStream_t st);
+int arnoldi_update_norm(const void* V, bool v32, int64_t ld, int k, const double* w, const double* cin, void* vout,
+                        int64_t n, double* norm2, double* s_next, const DotWork& dw, hipStream_t st);
+int basis_combine(double* out, const void* V, bool v32, int64_t ld, int k, const double* coef, int64_t n,
+                  hipStream_t st);
+int vec_dot(const double* a, const double* b, int64_t n, double* out, const DotWork& dw, hipStream_t st);
+int vec_store(void* out, bool out32, const double* in, int64_t n, hipStream_t st);
+
 int blas_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
-int blas_to_f32(float* out, const double* in, double alpha, int64_t n, hipStream_t s);
 int layout_embed(const Mesh* m, double* U, const double* x, const double* st, hipStream_t s);
 int layout_level(const Mesh* m, double* st, const double* x, int lev, hipStream_t s);
 int layout_guess(const Mesh* m, double* x, const double* st, hipStream_t s);
@@ -26,6 +39,7 @@ int ensure_state_off(Mesh* m);
 // Options of one slab solve (validated copies of stdg_solve_opts).
 struct SlabOpts {
   bool f32 = false;
+  bool v32 = false;  // Krylov basis stored in FP32 (FP32 inner applies only)
   int restart = 10, max_iters = 500, max_refine = 100;
   double rtol = 1e-10, inner_rtol = 1e-4;
 };
@@ -68,12 +82,16 @@ class SlabSolver {
   hipEvent_t ev_ = nullptr;
   Phase phase_ = kIdle;
   int64_t n_ = 0;
+  void* basis(int j) const { return (char*)V_ + (size_t)j * (size_t)ld_ * (o_.v32 ? 4 : 8); }
+  int64_t ld_ = 0;  // basis leading dimension: n rounded up to a multiple of 64
   // device work vectors
-  double *V_ = nullptr, *w_ = nullptr, *x_ = nullptr, *r_ = nullptr, *U_ = nullptr, *d_ = nullptr, *pd_ = nullptr;
+  void* V_ = nullptr;  // restart + 1 unnormalised basis vectors (FP32 or FP64)
+  double *w_ = nullptr, *x_ = nullptr, *r_ = nullptr, *U_ = nullptr, *d_ = nullptr, *pd_ = nullptr;
   float *v32_ = nullptr, *w32_ = nullptr;
-  double *partial_ = nullptr, *hdev_ = nullptr, *etmp_ = nullptr;
-  // pinned host scalars: [0, kMaxBasis) h1, [kMaxBasis, 2k) h2, then norm2, beta2, e0, e1, and y
-  double* hb_ = nullptr;
+  DotWork dw_;
+  double *hv_ = nullptr, *etmp_ = nullptr;  // device scalars (layout kH1.. in solver.cpp)
+  double* hb_ = nullptr;                    // pinned host copy of the scalars
+  double hs_[kMaxBasis + 1];                // basis scales s_j on the host
   // slab state
   double dt_ = 0.0;
   const double* load_ = nullptr;

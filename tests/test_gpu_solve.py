@@ -50,8 +50,11 @@ def test_mode_superposition_projection(lib):
     lib.stdg.stdg_mesh_free(mh)
 
 
-@pytest.mark.parametrize("inner", [0, 1])
-def test_slab_solve_te101_cavity(lib, inner):
+SOLVE_PATHS = [(0, 0), (1, 0), (1, 1)]  # (inner applies, Krylov basis storage): FP64 = 0, FP32 = 1
+
+
+@pytest.mark.parametrize("inner,krylov", SOLVE_PATHS)
+def test_slab_solve_te101_cavity(lib, inner, krylov):
     cfg = synth.cavity_small()
     m = cfg["mesh"]
     d = oracle_disc(m)
@@ -60,9 +63,9 @@ def test_slab_solve_te101_cavity(lib, inner):
     mh = lib.upload(m)
     st = _state_dev(lib, s0)
     Ud = lib.torch.zeros(d.trial_off[-1], dtype=lib.torch.float64, device="cuda")
-    note("te101 solve inner=%d" % inner)
+    note("te101 solve inner=%d krylov=%d" % (inner, krylov))
     info = lib.stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, st, inner_prec=inner, rtol=1e-13,
-                                    max_iters=400, max_refine=40, slab_U=Ud)
+                                    max_iters=400, max_refine=40, slab_U=Ud, krylov_prec=krylov)
     assert info["status"] == 0, info
     assert rel_err(Ud.cpu().numpy(), U_ref) < 1e-10
     assert rel_err(st.cpu().numpy(), d.level_state(U_ref, 1)) < 1e-10
@@ -70,8 +73,8 @@ def test_slab_solve_te101_cavity(lib, inner):
     lib.stdg.stdg_mesh_free(mh)
 
 
-@pytest.mark.parametrize("inner", [0, 1])
-def test_slab_solve_mixed_degrees_with_source(lib, inner):
+@pytest.mark.parametrize("inner,krylov", SOLVE_PATHS)
+def test_slab_solve_mixed_degrees_with_source(lib, inner, krylov):
     v, h = synth.box_mesh((3, 2, 2))
     ne = h.shape[0]
     rng = np.random.default_rng(21)
@@ -92,9 +95,31 @@ def test_slab_solve_mixed_degrees_with_source(lib, inner):
     st = _state_dev(lib, s0)
     Ud = lib.torch.zeros(d.trial_off[-1], dtype=lib.torch.float64, device="cuda")
     info = lib.stdg.stdg_slab_solve(mh, t0, dt, Ld, st, inner_prec=inner, rtol=1e-13, max_iters=600,
-                                    max_refine=60, slab_U=Ud)
+                                    max_refine=60, slab_U=Ud, krylov_prec=krylov)
     assert info["status"] == 0, info
     assert rel_err(Ud.cpu().numpy(), U_ref) < 1e-10
+    lib.stdg.stdg_mesh_free(mh)
+
+
+def test_slab_solve_bitwise_repeatable_and_option_checks(lib):
+    cfg = synth.cavity_two_material(n=4, p=3, q=2)
+    m = cfg["mesh"]
+    mh = lib.upload(m)
+    info_m = lib.stdg.stdg_mesh_info(mh)
+    s0 = np.random.default_rng(3).standard_normal(info_m["state_size"])
+    outs = []
+    for _ in range(2):
+        st = lib.dev(s0, lib.torch.float64)
+        r = lib.stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, st, inner_prec=1, rtol=1e-12, max_iters=400,
+                                     max_refine=40)
+        assert r["status"] == 0
+        outs.append(st.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    st = lib.dev(s0, lib.torch.float64)
+    with pytest.raises(lib.stdg.StdgError):  # an FP32 basis needs FP32 applies
+        lib.stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, st, inner_prec=0, krylov_prec=1)
+    with pytest.raises(lib.stdg.StdgError):  # restart + 1 must fit the basis
+        lib.stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, st, inner_prec=0, restart=40)
     lib.stdg.stdg_mesh_free(mh)
 
 
@@ -126,8 +151,8 @@ def test_not_converged_reports_and_fills_info(lib):
     lib.stdg.stdg_mesh_free(mh)
 
 
-@pytest.mark.parametrize("inner", [1, 0])
-def test_two_material_32cubed_first_slab_properties(lib, inner):
+@pytest.mark.parametrize("inner,krylov", [(1, 0), (0, 0), (1, 1)])
+def test_two_material_32cubed_first_slab_properties(lib, inner, krylov):
     """Full-size 32^3 p = 4 q = 3 solve of the first slab: energy conserved and
     the oracle's residual on sampled elements of the GPU solution is small."""
     cfg = synth.cavity_two_material()
@@ -139,9 +164,10 @@ def test_two_material_32cubed_first_slab_properties(lib, inner):
     lib.stdg.stdg_project_modes(mh, modes.mnl, modes.abc, st)
     s0 = st.cpu().numpy()
     Ud = lib.torch.zeros(info_m["trial_size"], dtype=lib.torch.float64, device="cuda")
-    note("32^3 solve inner=%d" % inner)
-    info = lib.stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, st, inner_prec=inner, rtol=1e-10, slab_U=Ud)
-    note("32^3 solve inner=%d: %s" % (inner, info))
+    note("32^3 solve inner=%d krylov=%d" % (inner, krylov))
+    info = lib.stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, st, inner_prec=inner, rtol=1e-10, slab_U=Ud,
+                                    krylov_prec=krylov, max_iters=2000, max_refine=300)
+    note("32^3 solve inner=%d krylov=%d: %s" % (inner, krylov, info))
     assert info["status"] == 0
     assert abs(info["energy_end"] - info["energy_start"]) < 1e-9 * info["energy_start"]
     d = oracle_disc(m)
