@@ -51,6 +51,8 @@ def parse():
                     help="requests of the Poisson serving stream (0 = skip the serving leg)")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-max-active", type=int, default=16)
+    ap.add_argument("--serve-krylov", choices=("fp32", "fp64"), default="fp32",
+                    help="storage of the serving solver's Krylov basis (sums are FP64 either way)")
     return ap.parse_args()
 
 
@@ -188,7 +190,8 @@ def main():
     serving = None
     if args.serve_requests > 0:
         log("serving stream: %d requests" % args.serve_requests)
-        serving = time_serving(stdg, ctx, args.serve_requests, args.serve_budget_gb, args.serve_max_active)
+        serving = time_serving(stdg, ctx, args.serve_requests, args.serve_budget_gb, args.serve_max_active,
+                               args.serve_krylov)
         log("serving: %.2f solves/s, p50 %.3f s, p99 %.3f s" % (serving["solves_per_s"], serving["p50_latency_s"],
                                                                serving["p99_latency_s"]))
 
@@ -234,7 +237,7 @@ def main():
     stdg.stdg_finalize(ctx)
 
 
-def time_serving(stdg, ctx, n_requests, budget_gb, max_active):
+def time_serving(stdg, ctx, n_requests, budget_gb, max_active, krylov):
     """The serving stream: independent PEC cavity solves (n^3, n in {4,..,16},
     p in 2..6, q = p - 1, eps in {1,2,4} per element, 20 slabs, dt = h/(2p+1))
     arriving as a Poisson process at 50 per second, submitted at their arrival
@@ -243,7 +246,8 @@ def time_serving(stdg, ctx, n_requests, budget_gb, max_active):
     reqs = synth.serving_stream(n_requests=n_requests)
     dofs = [r["mesh"].trial_size() * r["n_slabs"] for r in reqs]
     srv = stdg.stdg_serve_start(ctx, hbm_budget=int(budget_gb * (1 << 30)), max_active=max_active,
-                                inner_prec=stdg.STDG_FP32, rtol=1e-10, max_iters=3000, max_refine=300)
+                                inner_prec=stdg.STDG_FP32, rtol=1e-10, max_iters=3000, max_refine=300,
+                                krylov_prec=stdg.STDG_FP32 if krylov == "fp32" else stdg.STDG_FP64)
     results = {}
     try:
         c0 = stdg.stdg_serve_clock(srv)
@@ -281,7 +285,7 @@ def time_serving(stdg, ctx, n_requests, budget_gb, max_active):
             "gdof_per_s_trial_x_slabs": round(sum(dofs) / span / 1e9, 3),
             "iters_per_slab": round(sum(r["iters"] for r in res) / sum(r["slabs_done"] for r in res), 2),
             "max_rel_res": max(r["max_rel_res"] for r in res), "failed": bad,
-            "hbm_budget_gb": budget_gb, "max_active": max_active,
+            "hbm_budget_gb": budget_gb, "max_active": max_active, "krylov_basis": krylov,
             "max_energy_drift": max(abs(r["energy_end"] - r["energy_start"]) / max(r["energy_start"], 1e-300)
                                     for r in res)}
 

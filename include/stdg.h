@@ -267,9 +267,11 @@ typedef struct {
  * context's device while it runs: do not use the same context from other
  * threads until stdg_serve_stop returns. */
 int stdg_serve_start(stdg_ctx* ctx, const stdg_serve_opts* opts, stdg_server** out);
-/* Queue a request (thread-safe; every array is copied before return).
- * STDG_E_CAPACITY if its footprint exceeds the whole arena, STDG_E_ARG on
- * invalid sizes; mesh errors surface through stdg_serve_poll. */
+/* Queue a request (thread-safe; every array is copied before return).  The
+ * mesh is validated and analysed during the call (faces, metric, kernel
+ * groups), so mesh errors are returned here (STDG_E_ARG, STDG_E_UNSUPPORTED);
+ * STDG_E_CAPACITY if the request's footprint exceeds the whole arena.  The
+ * request's latency clock (t_submit) starts on entry. */
 int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ticket);
 /* STDG_E_NOT_READY until the request has finished; then fills *out (copying
  * the final state into out->state when out->state_capacity suffices, else

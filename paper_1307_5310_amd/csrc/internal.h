@@ -80,7 +80,8 @@ void gauss_rule01(int n, double* x, double* w);
 struct Group {
   int a, q, affine;
   int64_t count;
-  int32_t* d_list;  // element ids, locality order
+  int32_t* d_list;           // element ids, locality order (device)
+  std::vector<int32_t> ids;  // the same on the host
 };
 
 struct Ctx {
@@ -95,7 +96,7 @@ struct Ctx {
 };
 
 struct Mesh {
-  Ctx* ctx;
+  Ctx* ctx = nullptr;
   int64_t ne, nv;
   int64_t n_int_faces, n_bnd_faces;
   std::vector<int32_t> p, q;
@@ -133,6 +134,15 @@ struct ApplyArgs {
 };
 int launch_residual(const ApplyArgs& a);
 int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s);
+
+// Mesh construction (mesh.cpp): host analysis (validation, faces, metric,
+// groups) and the device copies, separable so that a server can analyse a
+// request's mesh on the submitting thread.
+int build_mesh_host(const stdg_mesh_desc* d, Mesh* m);
+int upload_mesh(Ctx* ctx, Mesh* m);
+int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m);
+void release_mesh(Mesh* m);
+size_t mesh_device_bytes(const Mesh& m);
 
 // Allocation against the context budget.
 int dev_alloc(Ctx* ctx, void** p, size_t bytes);

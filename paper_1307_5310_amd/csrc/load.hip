@@ -100,62 +100,88 @@ __device__ double inv3(const double A[3][3], double B[3][3]) {
   return det;
 }
 
-__device__ void source_at(const stdg_source& s, const double x[3], double t, double J[3]) {
-  if (s.kind != 1) {
-    J[0] = J[1] = J[2] = 0.0;
-    return;
-  }
-  const double dx = x[0] - s.center[0], dy = x[1] - s.center[1], dz = x[2] - s.center[2];
-  const double r2 = dx * dx + dy * dy + dz * dz;
-  const double tt = t - s.t0;
-  const double g = s.amp * exp(-r2 / (2.0 * s.sigma_x * s.sigma_x)) * sin(2.0 * M_PI * s.f0 * tt) *
-                   exp(-tt * tt / (2.0 * s.sigma_t * s.sigma_t));
-  J[0] = g * s.dir[0];
-  J[1] = g * s.dir[1];
-  J[2] = g * s.dir[2];
-}
 
-// One block per element; thread per output (c, s): accumulate over the tensor
-// rule the space-time integral against L_i(tau) for all test levels i.
+// Space-time separable current J(x, t) = dir amp g(x) h(t) (stdg_source kind 1):
+//   L_E[c, i, s] = T_i S_c(s),  T_i = dt sum_t w_t L_i(tau_t) h(t0 + tau_t dt),
+//   S_c(s) = amp sum_g w_g phi_s(x_g) g(F(x_g)) |J| (DF^{-1} dir)_c,
+// with Gauss rules of q + 3 points in time and p + 3 per space direction; S is
+// sum factorised like the projection (point values in shared memory, then one
+// direction at a time).  Dynamic shared memory: 3 nx^3 + nx^2 a + nx a^2
+// doubles, nx = a + 2.
 __global__ void load_kernel(LoadParams P) {
+  extern __shared__ double sh[];
+  __shared__ double qx[kMaxA + 2], qw[kMaxA + 2], Bt[(kMaxA + 2) * kMaxA], tx[kMaxQ + 3], tw[kMaxQ + 3], Ti[kMaxQ];
   const int e = blockIdx.x;
   const ElemInfo I = P.info[e];
-  const int a = I.a, q = I.q, a3 = a * a * a;
-  __shared__ double rxx[16], rxw[16], rtx[16], rtw[16];
-  const int nx = a + 2, nt = q + 3;
+  const int a = I.a, q = I.q, a2 = a * a, a3 = a2 * a;
+  double* out = P.out + I.unk_off;
+  if (P.src.kind != 1) {
+    for (int idx = threadIdx.x; idx < 6 * q * a3; idx += blockDim.x) out[idx] = 0.0;
+    return;
+  }
+  const int nx = a + 2, nx2 = nx * nx, nx3 = nx2 * nx, nt = q + 3;
   if (threadIdx.x == 0) {
-    gauss01(nx, rxx, rxw);
-    gauss01(nt, rtx, rtw);
+    gauss01(nx, qx, qw);
+    gauss01(nt, tx, tw);
   }
   __syncthreads();
-  const double* X = P.verts + 24 * e;
-  double* out = P.out + I.unk_off;
-  for (int idx = threadIdx.x; idx < 3 * a3; idx += blockDim.x) {
-    const int c = idx / a3, s = idx - c * a3;
-    const int sj = s % a, sk = (s / a) % a, sl = s / (a * a);
-    double acc[kMaxQ];
-    for (int i = 0; i < kMaxQ; ++i) acc[i] = 0.0;
-    for (int gz = 0; gz < nx; ++gz)
-      for (int gy = 0; gy < nx; ++gy)
-        for (int gx = 0; gx < nx; ++gx) {
-          double F[3], DF[3][3], Di[3][3];
-          trilinear(X, rxx[gx], rxx[gy], rxx[gz], F, DF);
-          const double det = inv3(DF, Di);
-          const double phi = leg(sj, rxx[gx]) * leg(sk, rxx[gy]) * leg(sl, rxx[gz]);
-          const double wsp = rxw[gx] * rxw[gy] * rxw[gz] * det * phi;
-          for (int gt = 0; gt < nt; ++gt) {
-            double J[3];
-            source_at(P.src, F, P.t0 + rtx[gt] * P.dt, J);
-            // J . DF^{-T} e_c = (DF^{-1} J)_c
-            const double jc = Di[c][0] * J[0] + Di[c][1] * J[1] + Di[c][2] * J[2];
-            const double base = P.dt * rtw[gt] * wsp * jc;
-            for (int i = 0; i < q; ++i) acc[i] += base * leg(i, rtx[gt]);
-          }
-        }
-    for (int i = 0; i < q; ++i) {
-      out[((int64_t)c * q + i) * a3 + s] = acc[i];          // E part
-      out[((int64_t)(3 + c) * q + i) * a3 + s] = 0.0;       // H part: g = 0
+  const stdg_source& S = P.src;
+  if ((int)threadIdx.x < q) {
+    const int i = threadIdx.x;
+    double v = 0.0;
+    for (int g = 0; g < nt; ++g) {
+      const double tt = P.t0 + tx[g] * P.dt - S.t0;
+      const double h = sin(2.0 * M_PI * S.f0 * tt) * exp(-tt * tt / (2.0 * S.sigma_t * S.sigma_t));
+      v += tw[g] * leg(i, tx[g]) * h;
     }
+    Ti[i] = P.dt * v;
+  }
+  for (int k = threadIdx.x; k < nx * a; k += blockDim.x) {
+    const int g = k / a, j = k - g * a;
+    Bt[k] = qw[g] * leg(j, qx[g]);
+  }
+  const double* X = P.verts + 24 * e;
+  double* F = sh;
+  double* T1 = sh + 3 * nx3;
+  double* T2 = T1 + nx2 * a;
+  for (int pt = threadIdx.x; pt < nx3; pt += blockDim.x) {
+    const int g1 = pt % nx, g2 = (pt / nx) % nx, g3 = pt / nx2;
+    double xp[3], DF[3][3], Di[3][3];
+    trilinear(X, qx[g1], qx[g2], qx[g3], xp, DF);
+    const double det = inv3(DF, Di);
+    const double dx = xp[0] - S.center[0], dy = xp[1] - S.center[1], dz = xp[2] - S.center[2];
+    const double gsp = S.amp * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * S.sigma_x * S.sigma_x)) * det;
+    // J . DF^{-T} e_c = (DF^{-1} J)_c
+    for (int c = 0; c < 3; ++c)
+      F[c * nx3 + pt] = gsp * (Di[c][0] * S.dir[0] + Di[c][1] * S.dir[1] + Di[c][2] * S.dir[2]);
+  }
+  __syncthreads();
+  for (int c = 0; c < 3; ++c) {
+    const double* Fc = F + c * nx3;
+    for (int o = threadIdx.x; o < nx2 * a; o += blockDim.x) {  // [g3][g2][j]
+      const int j = o % a, g23 = o / a;
+      double acc = 0.0;
+      for (int g1 = 0; g1 < nx; ++g1) acc += Bt[g1 * a + j] * Fc[g23 * nx + g1];
+      T1[o] = acc;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < nx * a2; o += blockDim.x) {  // [g3][k][j]
+      const int j = o % a, k = (o / a) % a, g3 = o / a2;
+      double acc = 0.0;
+      for (int g2 = 0; g2 < nx; ++g2) acc += Bt[g2 * a + k] * T1[(g3 * nx + g2) * a + j];
+      T2[o] = acc;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < a3; s += blockDim.x) {  // [l][k][j]
+      const int jk = s % a2, l = s / a2;
+      double acc = 0.0;
+      for (int g3 = 0; g3 < nx; ++g3) acc += Bt[g3 * a + l] * T2[g3 * a2 + jk];
+      for (int i = 0; i < q; ++i) {
+        out[((int64_t)c * q + i) * a3 + s] = Ti[i] * acc;      // E part
+        out[((int64_t)(3 + c) * q + i) * a3 + s] = 0.0;        // H part: g = 0
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -376,7 +402,9 @@ int stdg_load_assemble(const stdg_mesh* mesh, const stdg_source* src, double t0,
   P.src = *src;
   P.t0 = t0;
   P.dt = dt;
-  hipLaunchKernelGGL(load_kernel, dim3((unsigned)m.ne), dim3(128), 0, (hipStream_t)stream, P);
+  const int amax = m.p_max + 1, nx = amax + 2;
+  const size_t shb = sizeof(double) * (3 * nx * nx * nx + nx * nx * amax + nx * amax * amax);
+  hipLaunchKernelGGL(load_kernel, dim3((unsigned)m.ne), dim3(256), shb, (hipStream_t)stream, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "load kernel");
   return STDG_OK;

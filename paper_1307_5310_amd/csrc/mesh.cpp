@@ -97,9 +97,8 @@ uint64_t spread3(uint64_t v) {
 
 }  // namespace
 
-int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m) {
+int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
   const int64_t ne = d->n_elements, nv = d->n_vertices;
-  m->ctx = ctx;
   m->ne = ne;
   m->nv = nv;
   m->p.assign(d->p, d->p + ne);
@@ -261,7 +260,35 @@ int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m) {
   }
   m->p_max = *std::max_element(m->p.begin(), m->p.end());
   m->q_max = *std::max_element(m->q.begin(), m->q.end());
+  m->groups.clear();
+  for (auto& kv : gm) {
+    auto& lst = kv.second;
+    std::sort(lst.begin(), lst.end());
+    Group g;
+    g.a = std::get<0>(kv.first);
+    g.q = std::get<1>(kv.first);
+    g.affine = std::get<2>(kv.first);
+    g.count = (int64_t)lst.size();
+    g.d_list = nullptr;
+    g.ids.resize(lst.size());
+    for (size_t i = 0; i < lst.size(); ++i) g.ids[i] = lst[i].second;
+    m->groups.push_back(std::move(g));
+  }
+  return STDG_OK;
+}
 
+size_t mesh_device_bytes(const Mesh& m) {
+  auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t b = r256(sizeof(ElemInfo) * m.ne) + r256(sizeof(ElemMetric) * m.ne) + r256(sizeof(double) * 24 * m.ne) +
+             r256(sizeof(QTables<double>) * (kMaxA + 1)) + r256(sizeof(QTables<float>) * (kMaxA + 1)) +
+             r256(sizeof(int64_t) * (m.ne + 1));
+  for (const Group& g : m.groups) b += r256(sizeof(int32_t) * g.count);
+  return b;
+}
+
+int upload_mesh(Ctx* ctx, Mesh* m) {
+  const int64_t ne = m->ne;
+  m->ctx = ctx;
   // device copies
   size_t bytes_info = sizeof(ElemInfo) * ne, bytes_metric = sizeof(ElemMetric) * ne;
   size_t bytes_verts = sizeof(double) * 24 * ne;
@@ -287,22 +314,19 @@ int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m) {
     STDG_HIP(hipMemcpy(m->d_qt64, q64.data(), b64, hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d_qt32, q32.data(), b32, hipMemcpyHostToDevice));
   }
-  for (auto& kv : gm) {
-    auto& lst = kv.second;
-    std::sort(lst.begin(), lst.end());
-    std::vector<int32_t> ids(lst.size());
-    for (size_t i = 0; i < lst.size(); ++i) ids[i] = lst[i].second;
-    Group g;
-    g.a = std::get<0>(kv.first);
-    g.q = std::get<1>(kv.first);
-    g.affine = std::get<2>(kv.first);
-    g.count = (int64_t)ids.size();
-    if ((rc = dev_alloc(ctx, (void**)&g.d_list, sizeof(int32_t) * ids.size())) != STDG_OK) return rc;
-    m->device_bytes += sizeof(int32_t) * ids.size();
-    STDG_HIP(hipMemcpy(g.d_list, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice));
-    m->groups.push_back(g);
+  for (Group& g : m->groups) {
+    if ((rc = dev_alloc(ctx, (void**)&g.d_list, sizeof(int32_t) * g.count)) != STDG_OK) return rc;
+    m->device_bytes += sizeof(int32_t) * g.count;
+    STDG_HIP(hipMemcpy(g.d_list, g.ids.data(), sizeof(int32_t) * g.count, hipMemcpyHostToDevice));
   }
   return STDG_OK;
+}
+
+int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m) {
+  m->ctx = ctx;
+  int rc = build_mesh_host(d, m);
+  if (rc != STDG_OK) return rc;
+  return upload_mesh(ctx, m);
 }
 
 void release_mesh(Mesh* m) {
@@ -314,7 +338,7 @@ void release_mesh(Mesh* m) {
   if (m->d_qt32) dev_free(ctx, m->d_qt32, sizeof(QTables<float>) * (kMaxA + 1));
   m->d_qt64 = m->d_qt32 = nullptr;
   for (auto& g : m->groups)
-    if (g.d_list) dev_free(ctx, g.d_list, sizeof(int32_t) * g.count);
+    if (g.d_list && ctx) dev_free(ctx, g.d_list, sizeof(int32_t) * g.count);
   if (m->d_scratch) dev_free(ctx, m->d_scratch, m->scratch_bytes);
   if (m->d_state_off) dev_free(ctx, m->d_state_off, sizeof(int64_t) * (m->ne + 1));
   m->d_state_off = nullptr;

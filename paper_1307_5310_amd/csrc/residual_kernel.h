@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
     constexpr int CH = NL * A3;                     // entries per component block
     constexpr int KC = (CH + C::NT - 1) / C::NT;    // loads per thread per block
     constexpr int GBC0 = 96 / (4 * KC * WORDS);
-    constexpr int GBC = GBC0 < 1 ? 1 : (GBC0 > 6 ? 6 : GBC0);
+    constexpr int GBC = GBC0 < 1 ? 1 : (GBC0 > 3 ? 3 : GBC0);  // at most 3 faces in flight: fewer VGPRs, more waves
     int nstaged = 0;  // staged faces so far (uniform): buffers strictly alternate
 #pragma unroll
     for (int g0 = 0; g0 < 6; g0 += GBC) {

@@ -32,20 +32,17 @@ extern "C" int stdg_load_assemble(const stdg_mesh* mesh, const stdg_source* src,
 
 namespace stdg {
 
-int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m);
-void release_mesh(Mesh* m);
-
 namespace {
 
 using Clock = std::chrono::steady_clock;
 
 struct Request {
   uint64_t ticket = 0;
-  std::vector<double> vertices, eps, mu, init;
-  std::vector<int64_t> hexes;
-  std::vector<int32_t> p, q, mnl;
+  stdg_mesh* mesh = nullptr;  // analysed on the submitting thread, uploaded at admission
+  std::vector<double> init;
+  std::vector<int32_t> mnl;
   std::vector<double> abc;
-  int64_t ne = 0, nv = 0;
+  int64_t ne = 0;
   double t0 = 0.0, dt = 0.0;
   int n_slabs = 0;
   stdg_source src{};
@@ -149,20 +146,15 @@ namespace {
 
 size_t footprint_of(const Request& r, const SlabOpts& so) {
   auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const int64_t ne = r.ne;
-  size_t b = 0;
-  // mesh tables: info, metric, vertices, state offsets, quadrature tables, one list per group
-  b += r256(sizeof(ElemInfo) * ne) + r256(sizeof(ElemMetric) * ne) + r256(sizeof(double) * 24 * ne) +
-       r256(sizeof(int64_t) * (ne + 1));
-  b += r256(sizeof(QTables<double>) * (kMaxA + 1)) + r256(sizeof(QTables<float>) * (kMaxA + 1));
-  b += r256(sizeof(int32_t) * ne) + 256 * 2 * kMaxA * kMaxQ;
+  const Mesh& m = r.mesh->m;
+  size_t b = mesh_device_bytes(m);
   // preconditioner scratch of meshes with a non-diagonal metric (FP32 then FP64)
-  b += r256(sizeof(float) * r.n_unk) + r256(sizeof(double) * r.n_unk);
+  if (m.n_diag != m.ne) b += r256(sizeof(float) * r.n_unk) + r256(sizeof(double) * r.n_unk);
   // state, load, projection inputs
-  b += r256(sizeof(double) * r.n_state) + (r.src.kind ? r256(sizeof(double) * r.n_unk) : 0) + 2 * 256 +
-       r256(sizeof(double) * 3 * (r.mnl.size() / 3 + 1));
-  b += slab_solver_bytes(r.n_unk, r.n_trial, ne, so);
-  return b + 65536;
+  b += r256(sizeof(double) * r.n_state) + (r.src.kind ? r256(sizeof(double) * r.n_unk) : 0) +
+       2 * r256(sizeof(double) * 3 * (r.mnl.size() / 3 + 1));
+  b += slab_solver_bytes(r.n_unk, r.n_trial, r.ne, so);
+  return b + 16384;  // alignment of the individual allocations
 }
 
 }  // namespace
@@ -181,23 +173,9 @@ int Server::start(Active* a) {
   a->out.res.state_size = r->n_state;
   STDG_HIP(hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking));
   STDG_HIP(hipEventCreateWithFlags(&a->done_ev, hipEventDisableTiming));
-  a->mesh = new (std::nothrow) stdg_mesh;
-  if (!a->mesh) return fail(STDG_E_NOMEM, "serve: host allocation failed");
-  stdg_mesh_desc d;
-  d.n_vertices = r->nv;
-  d.vertices = r->vertices.data();
-  d.n_elements = r->ne;
-  d.hexes = r->hexes.data();
-  d.p = r->p.data();
-  d.q = r->q.data();
-  d.eps = r->eps.data();
-  d.mu = r->mu.data();
-  int rc;
-  try {
-    rc = build_mesh(&a->ctx, &d, &a->mesh->m);
-  } catch (const std::bad_alloc&) {
-    rc = fail(STDG_E_NOMEM, "serve: host allocation failed");
-  }
+  a->mesh = r->mesh;
+  r->mesh = nullptr;
+  int rc = upload_mesh(&a->ctx, &a->mesh->m);
   if (rc != STDG_OK) return rc;
   Mesh& m = a->mesh->m;
   if ((rc = dev_alloc(&a->ctx, (void**)&a->state, sizeof(double) * r->n_state)) != STDG_OK) return rc;
@@ -273,6 +251,10 @@ void Server::retire(Active* a, int status) {
     std::lock_guard<std::mutex> lk(mu);
     finished[a->rq->ticket] = std::move(a->out);
   }
+  if (a->rq->mesh) {
+    release_mesh(&a->rq->mesh->m);
+    delete a->rq->mesh;
+  }
   delete a->rq;
   delete a;
 }
@@ -327,7 +309,7 @@ void Server::run() {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait_for(lk, std::chrono::milliseconds(2), [&] { return stop.load() || !pending.empty(); });
       } else {
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        std::this_thread::yield();
       }
     }
   }
@@ -336,6 +318,7 @@ void Server::run() {
   std::lock_guard<std::mutex> lk(mu);
   for (Request* r : pending) {
     finished[r->ticket].res.status = STDG_E_CANCELLED;
+    delete r->mesh;
     delete r;
   }
   pending.clear();
@@ -390,6 +373,7 @@ int stdg_serve_start(stdg_ctx* ctx, const stdg_serve_opts* opts, stdg_server** o
 int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ticket) {
   if (!server || !req || !ticket) return fail(STDG_E_ARG, "stdg_serve_submit: NULL argument");
   Server& S = server->s;
+  const double t_in = S.now();
   const stdg_mesh_desc& d = req->mesh;
   if (d.n_elements <= 0 || d.n_vertices <= 0 || !d.vertices || !d.hexes || !d.p || !d.q || !d.eps || !d.mu)
     return fail(STDG_E_ARG, "stdg_serve_submit: empty mesh or NULL array");
@@ -400,33 +384,30 @@ int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ti
     return fail(STDG_E_ARG, "stdg_serve_submit: invalid mode list");
   Request* r = new (std::nothrow) Request;
   if (!r) return fail(STDG_E_NOMEM, "stdg_serve_submit: host allocation failed");
+  int rc;
   try {
-    r->ne = d.n_elements;
-    r->nv = d.n_vertices;
-    r->vertices.assign(d.vertices, d.vertices + 3 * d.n_vertices);
-    r->hexes.assign(d.hexes, d.hexes + 8 * d.n_elements);
-    r->p.assign(d.p, d.p + d.n_elements);
-    r->q.assign(d.q, d.q + d.n_elements);
-    r->eps.assign(d.eps, d.eps + d.n_elements);
-    r->mu.assign(d.mu, d.mu + d.n_elements);
-    for (int64_t e = 0; e < r->ne; ++e) {
-      if (r->p[e] < 1 || r->p[e] > kMaxA - 1 || r->q[e] < 1 || r->q[e] > kMaxQ) {
-        delete r;
-        return fail(STDG_E_ARG, "stdg_serve_submit: degree out of range");
+    r->mesh = new stdg_mesh;
+    rc = build_mesh_host(&d, &r->mesh->m);
+    if (rc == STDG_OK) {
+      const Mesh& m = r->mesh->m;
+      r->ne = m.ne;
+      r->n_unk = m.unk_off.back();
+      r->n_trial = m.trial_off.back();
+      r->n_state = m.state_off.back();
+      if (req->n_modes > 0) {
+        if (m.n_nonaffine > 0) rc = fail(STDG_E_UNSUPPORTED, "stdg_serve_submit: mode projection needs affine elements");
+        r->mnl.assign(req->mnl, req->mnl + 3 * req->n_modes);
+        r->abc.assign(req->abc, req->abc + 3 * req->n_modes);
       }
-      const int64_t a3 = (int64_t)(r->p[e] + 1) * (r->p[e] + 1) * (r->p[e] + 1);
-      r->n_unk += 6 * r->q[e] * a3;
-      r->n_trial += 6 * (r->q[e] + 1) * a3;
-      r->n_state += 6 * a3;
+      if (req->init_state) r->init.assign(req->init_state, req->init_state + r->n_state);
     }
-    if (req->n_modes > 0) {
-      r->mnl.assign(req->mnl, req->mnl + 3 * req->n_modes);
-      r->abc.assign(req->abc, req->abc + 3 * req->n_modes);
-    }
-    if (req->init_state) r->init.assign(req->init_state, req->init_state + r->n_state);
   } catch (const std::bad_alloc&) {
+    rc = fail(STDG_E_NOMEM, "stdg_serve_submit: host allocation failed");
+  }
+  if (rc != STDG_OK) {
+    delete r->mesh;
     delete r;
-    return fail(STDG_E_NOMEM, "stdg_serve_submit: host allocation failed");
+    return rc;
   }
   r->t0 = req->t0;
   r->dt = req->dt;
@@ -435,6 +416,7 @@ int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ti
   r->footprint = footprint_of(*r, S.so);
   if (r->footprint > S.arena_size) {
     const size_t fp = r->footprint;
+    delete r->mesh;
     delete r;
     return fail(STDG_E_CAPACITY, "stdg_serve_submit: request needs " + std::to_string(fp) +
                                      " device bytes, the arena holds " + std::to_string(S.arena_size));
@@ -442,7 +424,7 @@ int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ti
   {
     std::lock_guard<std::mutex> lk(S.mu);
     r->ticket = S.next_ticket++;
-    r->t_submit = S.now();
+    r->t_submit = t_in;
     S.known[r->ticket] = true;
     S.pending.push_back(r);
     *ticket = r->ticket;

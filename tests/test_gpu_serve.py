@@ -5,8 +5,9 @@ concurrently.
 * each request's result is bitwise the same alone, in a mix, and as the plain
   stdg_slab_solve march of the same slabs;
 * a small request matches the oracle's direct slab solves to 1e-10;
-* admission waits for memory; errors stay per request and are reported
-  through the result; stop with work in flight returns."""
+* admission waits for memory; invalid requests are refused at submit, a
+  failing request reports through its result without disturbing the others;
+  stop with work in flight returns."""
 import time
 
 import numpy as np
@@ -52,7 +53,7 @@ def _wait(stdg, srv, tickets, sizes, timeout=120.0):
     return [out[t] for t in tickets]
 
 
-def _march(lib, rq):
+def _march(lib, rq, **opts):
     """The same request through stdg_project_modes + stdg_slab_solve."""
     stdg = lib.stdg
     m = rq["mesh"]
@@ -61,19 +62,21 @@ def _march(lib, rq):
     st = lib.torch.zeros(info["state_size"], dtype=lib.torch.float64, device="cuda")
     stdg.stdg_project_modes(mh, rq["init"].mnl, rq["init"].abc, st)
     for n in range(rq["n_slabs"]):
-        r = stdg.stdg_slab_solve(mh, n * rq["dt"], rq["dt"], None, st, **OPTS)
+        r = stdg.stdg_slab_solve(mh, n * rq["dt"], rq["dt"], None, st, **opts)
         assert r["status"] == 0
     out = st.cpu().numpy()
     stdg.stdg_mesh_free(mh)
     return out
 
 
-def test_serve_matches_slab_solve_alone_and_in_mix(lib):
+@pytest.mark.parametrize("krylov", [0, 1])
+def test_serve_matches_slab_solve_alone_and_in_mix(lib, krylov):
     stdg = lib.stdg
+    opts = dict(OPTS, krylov_prec=krylov)
     reqs = _small_stream(10)
     sizes = [r["mesh"].state_size() for r in reqs]
     note("serve: one request alone")
-    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 30, max_active=4, **OPTS)
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 30, max_active=4, **opts)
     try:
         alone = _wait(stdg, srv, [_submit(stdg, srv, reqs[3])], [sizes[3]])[0]
         note("serve: ten requests in a mix")
@@ -87,7 +90,7 @@ def test_serve_matches_slab_solve_alone_and_in_mix(lib):
         assert abs(r["energy_end"] - r["energy_start"]) < 1e-10 * r["energy_start"]
     assert np.array_equal(alone["state"], mix[3]["state"])
     note("serve: plain march of request 3")
-    ref = _march(lib, reqs[3])
+    ref = _march(lib, reqs[3], **opts)
     assert np.array_equal(ref, mix[3]["state"])
 
 
@@ -147,11 +150,16 @@ def test_errors_stay_per_request(lib):
         with pytest.raises(stdg.StdgError):
             stdg.stdg_serve_submit(srv, m.vertices, m.hexes, np.full(m.n_elements, 12), m.q, m.eps, m.mu, 0.0,
                                    good["dt"], 1)
-        # a face shared by three elements: the mesh build fails inside the server
+        # a face shared by three elements: the mesh analysis refuses it at submit
         bad_h = m.hexes.copy()
         bad_h[1] = bad_h[0]
         bad_h[2] = bad_h[0]
-        t_bad = stdg.stdg_serve_submit(srv, m.vertices, bad_h, m.p, m.q, m.eps, m.mu, 0.0, good["dt"], 1)
+        with pytest.raises(stdg.StdgError) as ei:
+            stdg.stdg_serve_submit(srv, m.vertices, bad_h, m.p, m.q, m.eps, m.mu, 0.0, good["dt"], 1)
+        assert ei.value.status == -1
+        # a request whose slab fails inside the server (non-finite initial state)
+        t_bad = stdg.stdg_serve_submit(srv, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu, 0.0, good["dt"], 2,
+                                       init_state=np.full(m.state_size(), np.nan))
         t_good = _submit(stdg, srv, good)
         r_bad, r_good = _wait(stdg, srv, [t_bad, t_good], [m.state_size(), m.state_size()])
     finally:
