@@ -47,6 +47,8 @@ def parse():
                     help="elements in the oracle's timed sample (0 = sized to ~15 s)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-graded", action="store_true", help="skip the graded trilinear 24^3 leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the 48^3 p=6 q=4 leg")
     ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the Poisson serving stream (0 = skip the serving leg)")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
@@ -187,6 +189,14 @@ def main():
         except Exception as e:  # solver reported separately; the apply line still prints
             log("slab solve skipped: %s" % e)
 
+    graded = large = None
+    if not args.no_graded:
+        log("graded trilinear 24^3")
+        graded = time_graded(stdg, torch, ctx, 20, 5)
+    if not args.no_large:
+        log("large cavity 48^3 p=6 q=4")
+        large = time_large(stdg, torch, ctx, 10, 3)
+
     serving = None
     if args.serve_requests > 0:
         log("serving stream: %d requests" % args.serve_requests)
@@ -230,6 +240,10 @@ def main():
     }
     if solve is not None:
         out["slab_solve"] = solve
+    if graded is not None:
+        out["graded_trilinear"] = graded
+    if large is not None:
+        out["large_cavity"] = large
     if serving is not None:
         out["serving"] = serving
     print(json.dumps(out), flush=True)
@@ -288,6 +302,110 @@ def time_serving(stdg, ctx, n_requests, budget_gb, max_active, krylov):
             "hbm_budget_gb": budget_gb, "max_active": max_active, "krylov_basis": krylov,
             "max_energy_drift": max(abs(r["energy_end"] - r["energy_start"]) / max(r["energy_start"], 1e-300)
                                     for r in res)}
+
+
+def _time_mode(stdg, torch, mh, dt, prec, mode, x, y, steps, warmup):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        stdg.stdg_residual_apply(mh, dt, prec, mode, x, None, y, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        stdg.stdg_residual_apply(mh, dt, prec, mode, x, None, y, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _slab_with_source(stdg, torch, mh, info, cfg, inner, krylov):
+    """One slab from a zero field driven by the workload's current, from the
+    middle of its time window (load assembly included in the time)."""
+    src = cfg["source"]
+    t0 = src.t0 - cfg["dt"]
+    state = torch.zeros(info["state_size"], dtype=torch.float64, device="cuda")
+    load = torch.zeros(info["unknown_size"], dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    stdg.stdg_load_assemble(mh, src, t0, cfg["dt"], load)
+    r = stdg.stdg_slab_solve(mh, t0, cfg["dt"], load, state, inner_prec=inner, krylov_prec=krylov, rtol=1e-10,
+                             max_iters=4000, max_refine=400)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    return {"s_per_slab": round(el, 4), "iters": r["iters"], "rel_res": r["rel_res"], "status": r["status"],
+            "energy_end": r["energy_end"]}
+
+
+def time_graded(stdg, torch, ctx, steps, warmup):
+    """Graded trilinear 24^3 mesh (p = 3..6 by ring, q = p - 2, interior
+    vertices perturbed by 10% of h): the operator apply (quadrature mass) and
+    one source-driven slab."""
+    import synth
+    cfg = synth.graded_nonaffine()
+    m = cfg["mesh"]
+    mh = stdg.stdg_mesh_upload(ctx, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu)
+    info = stdg.stdg_mesh_info(mh)
+    a = m.p.astype(np.int64) + 1
+    q = m.q.astype(np.int64)
+    G = a + 1
+    trial = int((6 * (q + 1) * a ** 3).sum())
+    mass_qp = 2 * q * (3 * 2 * 2 * (a ** 3 * G + a ** 2 * G ** 2 + a * G ** 3) + 15 * G ** 3) + 80 * G ** 3
+    flops = float((174 * q * a ** 3 + 24 * q * a ** 2 * (a ** 2 // 4) - 6 * q * a ** 3 + mass_qp).sum())
+    out = {"workload": cfg["name"] + ", eps = mu = 1, dt = %g" % cfg["dt"], "elements": m.n_elements,
+           "trial_dof": trial}
+    nu = info["unknown_size"]
+    x64 = torch.from_numpy(synth.random_vector(nu, 0)).cuda()
+    for name, prec, x in (("fp32", stdg.STDG_FP32, x64.float()), ("fp64", stdg.STDG_FP64, x64)):
+        y = torch.empty_like(x)
+        ms = _time_mode(stdg, torch, mh, cfg["dt"], prec, stdg.STDG_OPERATOR, x, y, steps, warmup)
+        ms_pre = _time_mode(stdg, torch, mh, cfg["dt"], prec, stdg.STDG_OPERATOR_PRECOND, x, y, steps, warmup)
+        sz = 4 if prec == stdg.STDG_FP32 else 8
+        bytes_ = float((12 * q * a ** 3).sum() * sz)
+        peak_tf = 157.3 if prec == stdg.STDG_FP32 else 78.6
+        out[name] = {"operator_ms": round(ms, 5), "gdof_per_s": round(trial / (ms * 1e-3) / 1e9, 2),
+                     "precond_operator_ms": round(ms_pre, 5),
+                     "hbm_frac": round(bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "compute_frac": round(flops / (ms * 1e-3) / 1e12 / peak_tf, 4),
+                     "algorithmic_bytes": bytes_, "algorithmic_flops": flops}
+        log("graded %s: operator %.3f ms (%.1f GDoF/s)" % (name, ms, trial / (ms * 1e-3) / 1e9))
+    out["slab_fp32_refine_fp32_basis"] = _slab_with_source(stdg, torch, mh, info, cfg, stdg.STDG_FP32, stdg.STDG_FP32)
+    out["slab_fp64"] = _slab_with_source(stdg, torch, mh, info, cfg, stdg.STDG_FP64, stdg.STDG_FP64)
+    stdg.stdg_mesh_free(mh)
+    return out
+
+
+def time_large(stdg, torch, ctx, steps, warmup):
+    """48^3 affine cavity, p = 6, q = 4 (1.14e9 trial DoF), eps ~ U[1, 4]:
+    the preconditioned operator apply and one source-driven slab."""
+    import synth
+    cfg = synth.large_cavity()
+    m = cfg["mesh"]
+    t = time.perf_counter()
+    mh = stdg.stdg_mesh_upload(ctx, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu)
+    log("large: mesh upload %.1f s" % (time.perf_counter() - t))
+    info = stdg.stdg_mesh_info(mh)
+    a, q, ne = 7, 4, m.n_elements
+    trial = 6 * (q + 1) * a ** 3 * ne
+    out = {"workload": cfg["name"] + ", eps ~ U[1,4], dt = h/13", "elements": ne, "trial_dof": trial}
+    nu = info["unknown_size"]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    x64 = torch.randn(nu, dtype=torch.float64, device="cuda", generator=g)
+    for name, prec, x in (("fp32", stdg.STDG_FP32, x64.float()), ("fp64", stdg.STDG_FP64, x64)):
+        y = torch.empty_like(x)
+        ms = _time_mode(stdg, torch, mh, cfg["dt"], prec, stdg.STDG_OPERATOR_PRECOND, x, y, steps, warmup)
+        sz = 4 if prec == stdg.STDG_FP32 else 8
+        bytes_ = 12 * q * a ** 3 * sz * ne
+        out[name] = {"apply_ms": round(ms, 4), "gdof_per_s": round(trial / (ms * 1e-3) / 1e9, 2),
+                     "hbm_frac": round(bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log("large %s: apply %.3f ms (%.1f GDoF/s)" % (name, ms, trial / (ms * 1e-3) / 1e9))
+        del y
+    del x64
+    torch.cuda.empty_cache()
+    out["slab_fp32_refine_fp32_basis"] = _slab_with_source(stdg, torch, mh, info, cfg, stdg.STDG_FP32, stdg.STDG_FP32)
+    log("large: one slab %.2f s" % out["slab_fp32_refine_fp32_basis"]["s_per_slab"])
+    stdg.stdg_mesh_free(mh)
+    return out
 
 
 def time_solves(stdg, torch, mh, m, cfg):

@@ -116,6 +116,11 @@ struct Mesh {
   // mass rules of trilinear elements, indexed by a (QTables<double>, QTables<float>)
   void* d_qt64 = nullptr;
   void* d_qt32 = nullptr;
+  // side streams for applies over several kernel groups (created on first use):
+  // the groups run concurrently, forked from and joined back into the caller's stream
+  static constexpr int kAux = 4;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kAux] = {};
   // scratch for preconditioned applies on non-diagonal meshes (lazily sized)
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;

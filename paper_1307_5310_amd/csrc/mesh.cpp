@@ -331,6 +331,14 @@ int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m) {
 
 void release_mesh(Mesh* m) {
   Ctx* ctx = m->ctx;
+  for (int k = 0; k < Mesh::kAux; ++k) {
+    if (m->aux[k]) (void)hipStreamDestroy(m->aux[k]);
+    if (m->join_ev[k]) (void)hipEventDestroy(m->join_ev[k]);
+    m->aux[k] = nullptr;
+    m->join_ev[k] = nullptr;
+  }
+  if (m->fork_ev) (void)hipEventDestroy(m->fork_ev);
+  m->fork_ev = nullptr;
   if (m->d_info) dev_free(ctx, m->d_info, sizeof(ElemInfo) * m->ne);
   if (m->d_metric) dev_free(ctx, m->d_metric, sizeof(ElemMetric) * m->ne);
   if (m->d_verts) dev_free(ctx, m->d_verts, sizeof(double) * 24 * m->ne);

@@ -1,4 +1,7 @@
 // Dispatch of the residual kernels over the (a, q, affine) groups of a mesh.
+#include <algorithm>
+#include <vector>
+
 #include "residual_kernel.h"
 
 namespace stdg {
@@ -25,6 +28,19 @@ static Launcher<float> trilinear_f32[kMaxA + 1] = STDG_TABLE(trilinear_, float);
 static Launcher<double> trilinear_f64[kMaxA + 1] = STDG_TABLE(trilinear_, double);
 #undef STDG_TABLE
 
+static int ensure_aux(Mesh* m) {
+  if (m->fork_ev) return STDG_OK;
+  for (int k = 0; k < Mesh::kAux; ++k) {
+    STDG_HIP(hipStreamCreateWithFlags(&m->aux[k], hipStreamNonBlocking));
+    STDG_HIP(hipEventCreateWithFlags(&m->join_ev[k], hipEventDisableTiming));
+  }
+  STDG_HIP(hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming));
+  return STDG_OK;
+}
+
+// Launch every (a, q, affine) group; with several groups they run on side
+// streams, largest first, forked from and joined back into s (the groups
+// write disjoint outputs, so the result does not depend on their order).
 template <typename T>
 static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* load, T* y, hipStream_t s,
                       Launcher<T>* affine, Launcher<T>* trilinear, const QTables<T>* d_qt) {
@@ -38,14 +54,34 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
   P.dt = (T)dt;
   P.mode = mode;
   if constexpr (sizeof(T) == 8) fill_tables_f64(&P.tab); else fill_tables_f32(&P.tab);
+  std::vector<const Group*> order;
   for (const Group& g : m->groups) {
     if (g.count == 0) continue;
     if (!g.affine && mode == STDG_OPERATOR_PRECOND)
       return fail(STDG_E_UNSUPPORTED, "trilinear elements take P^{-1} in a separate pass");
+    order.push_back(&g);
+  }
+  auto work = [](const Group* g) { return g->count * (int64_t)g->q * g->a * g->a * g->a * (g->affine ? 1 : 3); };
+  std::stable_sort(order.begin(), order.end(), [&](const Group* l, const Group* r) { return work(l) > work(r); });
+  const bool fork = order.size() > 1;
+  if (fork) {
+    int rc = ensure_aux(const_cast<Mesh*>(m));
+    if (rc != STDG_OK) return rc;
+    STDG_HIP(hipEventRecord(m->fork_ev, s));
+    for (int k = 0; k < Mesh::kAux && k < (int)order.size(); ++k) STDG_HIP(hipStreamWaitEvent(m->aux[k], m->fork_ev, 0));
+  }
+  for (size_t i = 0; i < order.size(); ++i) {
+    const Group& g = *order[i];
     P.list = g.d_list;
     P.qt = d_qt + g.a;
-    int rc = (g.affine ? affine : trilinear)[g.a](g.q, P, g.count, s);
+    int rc = (g.affine ? affine : trilinear)[g.a](g.q, P, g.count, fork ? m->aux[i % Mesh::kAux] : s);
     if (rc != STDG_OK) return rc;
+  }
+  if (fork) {
+    for (int k = 0; k < Mesh::kAux && k < (int)order.size(); ++k) {
+      STDG_HIP(hipEventRecord(m->join_ev[k], m->aux[k]));
+      STDG_HIP(hipStreamWaitEvent(s, m->join_ev[k], 0));
+    }
   }
   return STDG_OK;
 }

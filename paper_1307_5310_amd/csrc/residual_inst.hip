@@ -24,25 +24,26 @@
 
 namespace stdg {
 
-template <int QQ>
+template <int QQ, int MODE>
 static constexpr size_t shmem_bytes() {
-  return sizeof(STDG_REAL) * KCfg<STDG_A>::template lds_elems<STDG_REAL, QQ, (bool)STDG_AFF>();
+  return sizeof(STDG_REAL) * KCfg<STDG_A>::template lds_elems<STDG_REAL, QQ, (bool)STDG_AFF, MODE>();
 }
 
 template <int QQ>
 static int launch_q(const KParams<STDG_REAL>& P, dim3 grid, dim3 block, hipStream_t stream) {
   switch (P.mode) {
     case 0:
-      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 0, (bool)STDG_AFF>), grid, block, shmem_bytes<QQ>(),
+      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 0, (bool)STDG_AFF>), grid, block, (shmem_bytes<QQ, 0>()),
                          stream, P);
       break;
     case 1:
-      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 1, (bool)STDG_AFF>), grid, block, shmem_bytes<QQ>(),
+      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 1, (bool)STDG_AFF>), grid, block, (shmem_bytes<QQ, 1>()),
                          stream, P);
       break;
     default:
 #if STDG_AFF
-      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 2, true>), grid, block, shmem_bytes<QQ>(), stream, P);
+      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 2, true>), grid, block, (shmem_bytes<QQ, 2>()), stream,
+                         P);
       break;
 #else
       return fail(STDG_E_UNSUPPORTED, "trilinear elements take P^{-1} in a separate pass");

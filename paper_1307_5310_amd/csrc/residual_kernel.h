@@ -60,29 +60,32 @@ struct KCfg {
     return c < 1 ? 1 : (c > Q ? Q : c);
   }
   // neighbour blocks are staged through LDS a face at a time (4 tangential
-  // component blocks of up to q + 1 levels, double-buffered) when one face
-  // fits in 24 KB; larger ones are gathered straight from global memory
+  // component blocks of the stored levels, double-buffered) when a face of
+  // q + 1 levels fits in 24 KB; larger ones are gathered straight from global
+  // memory (measured faster there, e.g. FP32 with p = 6, q = 4)
   template <typename T, int Q>
   static constexpr bool stage() { return 4 * (Q + 1) * A3 * (int)sizeof(T) <= 24576; }
+  static constexpr int levels(int Q, int MODE) { return MODE == 1 ? Q + 1 : Q; }  // stored trial levels
   // trilinear elements: Gauss rule of GQ = a + 1 points per direction for the
   // mass; PP quadrature points per thread
   static constexpr int GQ = A + 1, G2 = GQ * GQ, G3 = G2 * GQ;
   static constexpr int PP = (G3 + NT - 1) / NT;
-  static constexpr int MASS_A = 3 * A * G2, MASS = MASS_A + 3 * G3;  // two sweep buffers
+  static constexpr int MASS_A = 6 * A * G2, MASS = MASS_A + 6 * G3;  // two sweep buffers, both fields
   static constexpr int QTAB = GQ * A;                                // sqrt(w_g) L_j(x_g)
   static constexpr int QTAB_PAD = (QTAB + 3) & ~3;
-  template <typename T, int Q, bool AFF>
+  template <typename T, int Q, bool AFF, int MODE>
   static constexpr int main_elems() {
     // staged contracted levels, or (aliased, used earlier) the staging
     // buffers, or (aliased) the mass sweep buffers
-    constexpr int a = LC<T, Q, AFF>() * LVL, b = stage<T, Q>() ? 2 * 4 * (Q + 1) * A3 : 0;
+    constexpr int NL = levels(Q, MODE);
+    constexpr int a = LC<T, Q, AFF>() * LVL, b = stage<T, Q>() ? 2 * 4 * NL * A3 : 0;
     constexpr int ab = a > b ? a : b;
     return AFF ? ab : (ab > MASS ? ab : MASS);
   }
-  template <typename T, int Q, bool AFF>
+  template <typename T, int Q, bool AFF, int MODE>
   static constexpr int lds_elems() {
     // trilinear elements add the quadrature table and the metric at the points
-    return main_elems<T, Q, AFF>() + (AFF ? 0 : QTAB_PAD + 6 * G3);
+    return main_elems<T, Q, AFF, MODE>() + (AFF ? 0 : QTAB_PAD + 6 * G3);
   }
 };
 
@@ -196,25 +199,27 @@ __device__ __forceinline__ void trilinear_metric(const double* X, const QTables<
   }
 }
 
-// Mass of a trilinear element applied to one field (3 components) of one
-// level, by sum factorisation over the GQ^3 Gauss rule:
-//   r_c(s) = kappa sum_g phi_s(x_g) w_g (G(x_g) u(x_g))_c,  u(x_g) = sum_t phi_t(x_g) u_t.
+// Mass of a trilinear element applied to both fields (6 components: E with
+// eps, H with mu) of one level, by sum factorisation over the GQ^3 Gauss rule:
+//   r_fc(s) = kappa_f sum_g phi_s(x_g) w_g (G(x_g) u_f(x_g))_c,
+//   u_f(x_g) = sum_t phi_t(x_g) u_f,t.
 // Bt = sqrt(w_g) L_j(x_g) in LDS (the weight split over both sweeps).  Sweeps
-// alternate between bufA (3 A GQ^2) and bufB (3 GQ^3); the caller must
+// alternate between bufA (6 A GQ^2) and bufB (6 GQ^3); the caller must
 // synchronise before reusing the buffers for anything but another call.
 template <typename T, int A>
 __device__ __forceinline__ void trilinear_mass(T* __restrict__ bufA, T* __restrict__ bufB, const T* __restrict__ Bt,
-                                               const T* __restrict__ Gl, T kappa, const T (&u)[3], T (&r)[3],
+                                               const T* __restrict__ Gl, T keps, T kmu, const T (&u)[6], T (&r)[6],
                                                int tid, bool pos_lane, uint32_t s) {
   using C = KCfg<A>;
   constexpr int A2 = C::A2, A3 = C::A3, GQ = C::GQ, G2 = C::G2, G3 = C::G3, NT = C::NT;
+  constexpr int NC = 6;
   if (pos_lane) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) bufA[c * A3 + s] = u[c];
+    for (int c = 0; c < NC; ++c) bufA[c * A3 + s] = u[c];
   }
   __syncthreads();
   // x-hat: [c][l][k][j] -> [c][l][k][g]
-  for (int o = tid; o < 3 * A2 * GQ; o += NT) {
+  for (int o = tid; o < NC * A2 * GQ; o += NT) {
     const int g = o % GQ, row = o / GQ;
     const T* src = bufA + row * A;
     const T* b = Bt + g * A;
@@ -225,7 +230,7 @@ __device__ __forceinline__ void trilinear_mass(T* __restrict__ bufA, T* __restri
   }
   __syncthreads();
   // y-hat: [c][l][k][g] -> [c][l][h][g]
-  for (int o = tid; o < 3 * A * G2; o += NT) {
+  for (int o = tid; o < NC * A * G2; o += NT) {
     const int g = o % GQ, h = (o / GQ) % GQ, row = o / G2;
     const T* src = bufB + row * (A * GQ) + g;
     const T* b = Bt + h * A;
@@ -235,32 +240,36 @@ __device__ __forceinline__ void trilinear_mass(T* __restrict__ bufA, T* __restri
     bufA[o] = acc;
   }
   __syncthreads();
-  // z-hat to the points, and the pointwise kappa G
+  // z-hat to the points, and the pointwise kappa G, for both fields
 #pragma unroll
   for (int kk = 0; kk < C::PP; ++kk) {
     const int pt = tid + kk * NT;
     if (pt < G3) {
       const int m = pt / G2, hg = pt - m * G2;
       const T* b = Bt + m * A;
-      T v[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T acc = T(0);
-#pragma unroll
-        for (int l = 0; l < A; ++l) acc += b[l] * bufA[(c * A + l) * G2 + hg];
-        v[c] = acc;
-      }
       T G[6];
 #pragma unroll
       for (int k6 = 0; k6 < 6; ++k6) G[k6] = Gl[k6 * G3 + pt];
-      bufB[0 * G3 + pt] = kappa * (G[0] * v[0] + G[3] * v[1] + G[4] * v[2]);
-      bufB[1 * G3 + pt] = kappa * (G[3] * v[0] + G[1] * v[1] + G[5] * v[2]);
-      bufB[2 * G3 + pt] = kappa * (G[4] * v[0] + G[5] * v[1] + G[2] * v[2]);
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        T v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T acc = T(0);
+#pragma unroll
+          for (int l = 0; l < A; ++l) acc += b[l] * bufA[((3 * f + c) * A + l) * G2 + hg];
+          v[c] = acc;
+        }
+        const T kap = f == 0 ? keps : kmu;
+        bufB[(3 * f + 0) * G3 + pt] = kap * (G[0] * v[0] + G[3] * v[1] + G[4] * v[2]);
+        bufB[(3 * f + 1) * G3 + pt] = kap * (G[3] * v[0] + G[1] * v[1] + G[5] * v[2]);
+        bufB[(3 * f + 2) * G3 + pt] = kap * (G[4] * v[0] + G[5] * v[1] + G[2] * v[2]);
+      }
     }
   }
   __syncthreads();
   // back along z-hat: [c][m][h][g] -> [c][l][h][g]
-  for (int o = tid; o < 3 * A * G2; o += NT) {
+  for (int o = tid; o < NC * A * G2; o += NT) {
     const int hg = o % G2, l = (o / G2) % A, c = o / (A * G2);
     const T* src = bufB + c * G3 + hg;
     T acc = T(0);
@@ -270,7 +279,7 @@ __device__ __forceinline__ void trilinear_mass(T* __restrict__ bufA, T* __restri
   }
   __syncthreads();
   // back along y-hat: [c][l][h][g] -> [c][l][k][g]
-  for (int o = tid; o < 3 * A2 * GQ; o += NT) {
+  for (int o = tid; o < NC * A2 * GQ; o += NT) {
     const int g = o % GQ, k = (o / GQ) % A, row = o / (A * GQ);
     const T* src = bufA + row * G2 + g;
     T acc = T(0);
@@ -283,7 +292,7 @@ __device__ __forceinline__ void trilinear_mass(T* __restrict__ bufA, T* __restri
   {
     const int j = (int)(s % A), kl = (int)(s / A);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NC; ++c) {
       const T* src = bufB + (c * A2 + kl) * GQ;
       T acc = T(0);
 #pragma unroll
@@ -528,7 +537,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   const T winv = T(1) / w;
 
   // trilinear elements: quadrature table and the metric at the points, in LDS
-  T* qB = sm + C::template main_elems<T, Q, AFF>();
+  T* qB = sm + C::template main_elems<T, Q, AFF, MODE>();
   T* Gl = qB + C::QTAB_PAD;
   T keps = T(0), kmu = T(0);
   if constexpr (!AFF) {
@@ -562,15 +571,12 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
       for (int ii = 0; ii < LC; ++ii) {
         const int i = i0 + ii;
         if (i >= Q) break;
+        T u[6], r[6];
 #pragma unroll
-        for (int f = 0; f < 2; ++f) {
-          T u[3], r[3];
+        for (int c = 0; c < 6; ++c) u[c] = xr[c][i + 1] - ((resid && i == 0) ? xr[c][0] : T(0));
+        trilinear_mass<T, A>(sm, sm + C::MASS_A, qB, Gl, keps, kmu, u, r, tid, pos_lane, s);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) u[c] = xr[3 * f + c][i + 1] - ((resid && i == 0) ? xr[3 * f + c][0] : T(0));
-          trilinear_mass<T, A>(sm, sm + C::MASS_A, qB, Gl, f == 0 ? keps : kmu, u, r, tid, pos_lane, s);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) mres[ii][3 * f + c] = r[c];
-        }
+        for (int c = 0; c < 6; ++c) mres[ii][c] = r[c];
       }
       __syncthreads();  // the sweep buffers alias the staged levels
     }
