@@ -186,6 +186,11 @@ typedef struct {
   double inner_rtol;   /* relative tolerance of each inner GMRES (FP32 inner)    */
   int32_t krylov_prec; /* storage of the Krylov basis: STDG_FP64 (default), or
                           STDG_FP32 with FP32 inner applies (sums stay FP64)     */
+  double eta_tol;      /* inexact solve (Section 5.3): > 0 also stops once this
+                          slab's term of the iteration-error bound eta_it^2
+                          (eq. a_posteriori:iteration) is <= eta_tol^2; 0 = off  */
+  double eta_t_final;  /* t_N of that bound (final time, slabs from t = 0), > 0
+                          when eta_tol > 0                                       */
 } stdg_solve_opts;
 
 typedef struct {
@@ -194,6 +199,8 @@ typedef struct {
   double rel_res;       /* final ||L - B U|| / ||L - B U_0|| in FP64             */
   double energy_start;  /* discrete energy (eq. stability:energydef) at t0      */
   double energy_end;    /* ... at t0 + dt                                       */
+  double eta2;          /* with eta_tol: this slab's term of eta_it^2 at the final
+                           iterate (sum the terms over slabs for eta_it^2)       */
 } stdg_solve_info;
 
 /* state_dev (FP64 state layout) holds the fields at t0 on entry and at t0 + dt
@@ -204,6 +211,14 @@ typedef struct {
 int stdg_slab_solve(const stdg_mesh* mesh, double t0, double dt, const double* load_dev,
                     const stdg_solve_opts* opts, double* state_dev, double* slab_U_dev,
                     stdg_solve_info* info, void* stream);
+
+/* Dual norms of a residual-layout FP64 vector r (e.g. from STDG_RESIDUAL) in
+ * W_h' with the L2(I_n; L2(Omega)) norm (Section 5.3: the Riesz representor is
+ * an L2 projection): norms_out[0] = ||r_E||^2, norms_out[1] = ||r_H||^2.  Exact
+ * on affine elements; trilinear elements use the mass with the metric at the
+ * element centre.  Synchronises `stream`. */
+int stdg_residual_dual_norm(const stdg_mesh* mesh, double dt, const double* r_dev, double* norms_out,
+                            void* stream);
 
 /* Discrete energy 1/2 int (eps E.E + mu H.H) of an FP64 state (eq. stability:energydef);
  * on trilinear elements with the mass rule of the residual (p + 2 Gauss points per direction). */

@@ -406,6 +406,40 @@ class Discretisation:
             out[self.unk_off[e]:self.unk_off[e + 1]] = res.ravel()
         return out
 
+    # -- inexact solve: dual norm of the residual and the iteration-error bound --
+    def dual_norms(self, R, dt, elements=None):
+        """(||R_E||^2, ||R_H||^2) in the dual of the test space W_h with the
+        L2(I_n; L2(Omega)) norm (Section 5.3): the Riesz representor of a
+        residual-layout vector R [f][c][i][s] solves (dt M_K) z_i = R_i per
+        element and test level (test functions orthonormal in time on [0, 1],
+        dx dt = dt dx dtau), M_K the unit-coefficient element mass; the norm is
+        R . z."""
+        out = np.zeros(2)
+        for e in (range(self.ne) if elements is None else elements):
+            e = int(e)
+            a = int(self.a[e])
+            a3 = a ** 3
+            qe = int(self.q[e])
+            key = ("M1", a, self.nq(e), tuple(np.round((self.X(e) - self.X(e)[0]).ravel(), 14)))
+            if key not in self._cache:
+                self._cache[key] = mass_matrix(self.X(e), a, 1.0, self.nq(e))
+            M = self._cache[key]
+            blk = R[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, qe, a3)
+            for f in range(2):
+                rhs = blk[f].transpose(0, 2, 1).reshape(3 * a3, qe)
+                z = np.linalg.solve(M, rhs) / dt
+                out[f] += float(np.sum(rhs * z))
+        return out
+
+    def eta_it_term(self, R, dt, t_final):
+        """One slab's contribution to eta_it^2 (eq. a_posteriori:iteration,
+        taken as printed): 4 [(2 t_N / eps_min + dt^2 / (2 t_N eps_min)) ||R_E||^2
+        + (2 t_N / mu_min + dt^2 / (2 t_N mu_min)) ||R_H||^2]."""
+        rE, rH = self.dual_norms(R, dt)
+        em, mm = float(np.min(self.eps)), float(np.min(self.mu))
+        return 4.0 * ((2 * t_final / em + dt ** 2 / (2 * t_final * em)) * rE +
+                      (2 * t_final / mm + dt ** 2 / (2 * t_final * mm)) * rH)
+
     # -- energy (eq. stability:energydef) -------------------------------------
     def energy(self, state):
         """1/2 int (eps E.E + mu H.H) of a state [field][comp][s] per element."""

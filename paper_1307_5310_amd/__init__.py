@@ -19,7 +19,7 @@ __all__ = ["StdgError", "STDG_FP32", "STDG_FP64", "STDG_OPERATOR", "STDG_RESIDUA
            "STDG_OPERATOR_PRECOND", "stdg_version", "stdg_init", "stdg_finalize",
            "stdg_mesh_upload", "stdg_mesh_info", "stdg_mesh_offsets", "stdg_mesh_free",
            "stdg_residual_apply", "stdg_load_assemble", "stdg_project_modes",
-           "stdg_slab_solve", "stdg_energy", "stdg_serve_start", "stdg_serve_submit",
+           "stdg_slab_solve", "stdg_energy", "stdg_residual_dual_norm", "stdg_serve_start", "stdg_serve_submit",
            "stdg_serve_poll", "stdg_serve_clock", "stdg_serve_stop", "exported_symbols"]
 
 
@@ -106,9 +106,10 @@ def stdg_project_modes(mesh, mnl, abc, state, stream=None):
 
 
 def stdg_slab_solve(mesh, t0, dt, load, state, inner_prec=STDG_FP64, restart=10, max_iters=500,
-                    max_refine=100, rtol=1e-12, inner_rtol=1e-4, slab_U=None, stream=None, krylov_prec=STDG_FP64):
+                    max_refine=100, rtol=1e-12, inner_rtol=1e-4, slab_U=None, stream=None, krylov_prec=STDG_FP64,
+                    eta_tol=0.0, eta_t_final=0.0):
     o = SolveOpts(int(inner_prec), int(restart), int(max_iters), int(max_refine), float(rtol),
-                  float(inner_rtol), int(krylov_prec))
+                  float(inner_rtol), int(krylov_prec), float(eta_tol), float(eta_t_final))
     info = SolveInfo()
     st = lib().stdg_slab_solve(mesh, float(t0), float(dt), ptr(load), ctypes.byref(o), ptr(state),
                                ptr(slab_U), ctypes.byref(info), stream_handle(stream))
@@ -117,6 +118,12 @@ def stdg_slab_solve(mesh, t0, dt, load, state, inner_prec=STDG_FP64, restart=10,
     if st not in (0, -5):
         check(st)
     return res
+
+
+def stdg_residual_dual_norm(mesh, dt, r, stream=None):
+    out = (ctypes.c_double * 2)()
+    check(lib().stdg_residual_dual_norm(mesh, float(dt), ptr(r), out, stream_handle(stream)))
+    return out[0], out[1]
 
 
 def stdg_energy(mesh, state, stream=None):

@@ -61,13 +61,14 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("krylov_prec", ctypes.c_int32)]
+                ("krylov_prec", ctypes.c_int32), ("eta_tol", ctypes.c_double),
+                ("eta_t_final", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("refinements", ctypes.c_int32),
                 ("rel_res", ctypes.c_double), ("energy_start", ctypes.c_double),
-                ("energy_end", ctypes.c_double)]
+                ("energy_end", ctypes.c_double), ("eta2", ctypes.c_double)]
 
 
 class ServeOpts(ctypes.Structure):
@@ -120,6 +121,7 @@ def lib():
             "stdg_slab_solve": ([vp, dbl, dbl, vp, ctypes.POINTER(SolveOpts), vp, vp,
                                  ctypes.POINTER(SolveInfo), vp], ctypes.c_int),
             "stdg_energy": ([vp, vp, ctypes.POINTER(dbl), vp], ctypes.c_int),
+            "stdg_residual_dual_norm": ([vp, dbl, vp, ctypes.POINTER(dbl), vp], ctypes.c_int),
             "stdg_serve_start": ([vp, ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)], ctypes.c_int),
             "stdg_serve_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
             "stdg_serve_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(Result)], ctypes.c_int),

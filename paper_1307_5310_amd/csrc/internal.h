@@ -106,6 +106,9 @@ struct Mesh {
   std::vector<double> verts;   // [ne][8][3] element vertex coordinates
   std::vector<Group> groups;
   int n_affine, n_nonaffine, n_diag;
+  // materials and metric bounds for the iteration-error bound: min eps, min mu,
+  // and max over elements of 1 / lambda_min(|J| DF^{-1} DF^{-T}) (centre metric)
+  double eps_min = 0.0, mu_min = 0.0, inv_gmin = 0.0;
   int p_max, q_max;
   // device copies
   ElemInfo* d_info = nullptr;

@@ -347,6 +347,69 @@ __global__ void energy_kernel(const ElemInfo* info, const ElemMetric* metric, co
   if (threadIdx.x == 0) partial[e] = 0.5 * red[0];
 }
 
+// Riesz representor of a residual-layout vector per element: sum over levels
+// and spatial modes of R_f . (G^{-1} R_f) with the unit-coefficient metric
+// (exact mass inverse on affine elements; the centre metric on trilinear ones).
+// partial[2 e + f] for the fields f = E, H (divided by dt by the caller).
+__global__ void dual_norm_kernel(const ElemInfo* info, const ElemMetric* metric, int64_t ne, const double* R,
+                                 double* partial) {
+  const int64_t e = blockIdx.x;
+  if (e >= ne) return;
+  const ElemInfo I = info[e];
+  const int per = I.q * I.a * I.a * I.a;
+  const double* mm = metric[e].m;
+  const double kap[2] = {metric[e].eps, metric[e].mu};
+  __shared__ double red[2][256];
+  double acc[2] = {0.0, 0.0};
+  for (int idx = threadIdx.x; idx < per; idx += blockDim.x) {
+    for (int f = 0; f < 2; ++f) {
+      const double* Mi = mm + 12 + 6 * f;
+      const double* rb = R + I.unk_off + (int64_t)3 * f * per + idx;
+      const double r0 = rb[0], r1 = rb[per], r2 = rb[2 * per];
+      acc[f] += kap[f] * (Mi[0] * r0 * r0 + Mi[1] * r1 * r1 + Mi[2] * r2 * r2 +
+                          2.0 * (Mi[3] * r0 * r1 + Mi[4] * r0 * r2 + Mi[5] * r1 * r2));
+    }
+  }
+  red[0][threadIdx.x] = acc[0];
+  red[1][threadIdx.x] = acc[1];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * e] = red[0][0];
+    partial[2 * e + 1] = red[1][0];
+  }
+}
+
+// out[f] = scale * sum_e partial[2 e + f], f = 0, 1, in a fixed order
+__global__ void sum2_kernel(const double* v, int64_t n, double scale, double* out) {
+  __shared__ double red[2][512];
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    a0 += v[2 * i];
+    a1 += v[2 * i + 1];
+  }
+  red[0][threadIdx.x] = a0;
+  red[1][threadIdx.x] = a1;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = scale * red[0][0];
+    out[1] = scale * red[1][0];
+  }
+}
+
 // fixed-order sum of n values by one block (deterministic)
 __global__ void sum_kernel(const double* v, int64_t n, double* out) {
   __shared__ double red[1024];
@@ -369,6 +432,15 @@ int energy_async(const Mesh* m, const double* state, double* d_partial, double* 
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1024), 0, s, d_partial, m->ne, d_out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "energy kernels");
+  return STDG_OK;
+}
+
+int dual_norms_async(const Mesh* m, double dt, const double* R, double* d_partial, double* d_out, hipStream_t s) {
+  hipLaunchKernelGGL(dual_norm_kernel, dim3((unsigned)m->ne), dim3(256), 0, s, m->d_info, m->d_metric, m->ne, R,
+                     d_partial);
+  hipLaunchKernelGGL(sum2_kernel, dim3(1), dim3(512), 0, s, d_partial, m->ne, 1.0 / dt, d_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "dual norm kernels");
   return STDG_OK;
 }
 
@@ -448,6 +520,26 @@ int stdg_project_modes(const stdg_mesh* mesh, int32_t n_modes, const int32_t* mn
   dev_free(m.ctx, d_mnl, nb);
   dev_free(m.ctx, d_abc, nd);
   return STDG_OK;
+}
+
+int stdg_residual_dual_norm(const stdg_mesh* mesh, double dt, const double* r_dev, double* norms_out,
+                            void* stream) {
+  if (!mesh || !r_dev || !norms_out) return fail(STDG_E_ARG, "stdg_residual_dual_norm: NULL argument");
+  if (!(dt > 0.0)) return fail(STDG_E_ARG, "stdg_residual_dual_norm: dt must be > 0");
+  Mesh& m = const_cast<stdg_mesh*>(mesh)->m;
+  double* d_tmp = nullptr;
+  const size_t nb = sizeof(double) * (2 * m.ne + 2);
+  int rc;
+  if ((rc = dev_alloc(m.ctx, (void**)&d_tmp, nb)) != STDG_OK) return rc;
+  rc = dual_norms_async(&m, dt, r_dev, d_tmp, d_tmp + 2 * m.ne, (hipStream_t)stream);
+  if (rc == STDG_OK) {
+    hipError_t e = hipMemcpyAsync(norms_out, d_tmp + 2 * m.ne, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) rc = hip_fail(e, "stdg_residual_dual_norm");
+  }
+  dev_free(m.ctx, d_tmp, nb);
+  return rc;
 }
 
 int stdg_energy(const stdg_mesh* mesh, const double* state_dev, double* energy_out, void* stream) {

@@ -11,6 +11,10 @@
 
 #include "internal.h"
 
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
 namespace stdg {
 
 namespace {
@@ -75,6 +79,22 @@ void metric_of(const double DF[3][3], double G[6], double* det) {
     }
   G[0] = M[0][0]; G[1] = M[1][1]; G[2] = M[2][2];
   G[3] = M[0][1]; G[4] = M[0][2]; G[5] = M[1][2];
+}
+
+// smallest eigenvalue of a symmetric 3x3 (packed xx yy zz xy xz yz), by the
+// trigonometric solution of the characteristic cubic
+double sym_lambda_min(const double G[6]) {
+  const double p1 = G[3] * G[3] + G[4] * G[4] + G[5] * G[5];
+  const double q = (G[0] + G[1] + G[2]) / 3.0;
+  if (p1 == 0.0) return std::min(G[0], std::min(G[1], G[2]));
+  const double p2 = (G[0] - q) * (G[0] - q) + (G[1] - q) * (G[1] - q) + (G[2] - q) * (G[2] - q) + 2.0 * p1;
+  const double p = std::sqrt(p2 / 6.0);
+  const double B[6] = {(G[0] - q) / p, (G[1] - q) / p, (G[2] - q) / p, G[3] / p, G[4] / p, G[5] / p};
+  const double detB = B[0] * (B[1] * B[2] - B[5] * B[5]) - B[3] * (B[3] * B[2] - B[5] * B[4]) +
+                      B[4] * (B[3] * B[5] - B[1] * B[4]);
+  const double r = std::max(-1.0, std::min(1.0, detB / 2.0));
+  const double phi = std::acos(r) / 3.0;
+  return q + 2.0 * p * std::cos(phi + 2.0 * M_PI / 3.0);
 }
 
 void sym_inverse(const double G[6], double out[6]) {
@@ -227,6 +247,9 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     }
     sym_inverse(M.m, M.m + 12);
     sym_inverse(M.m + 6, M.m + 18);
+    m->inv_gmin = std::max(m->inv_gmin, 1.0 / sym_lambda_min(G));
+    m->eps_min = e == 0 ? d->eps[e] : std::min(m->eps_min, d->eps[e]);
+    m->mu_min = e == 0 ? d->mu[e] : std::min(m->mu_min, d->mu[e]);
     bool diag = affine && std::fabs(G[3]) <= 1e-13 * (G[0] + G[1] + G[2]) &&
                 std::fabs(G[4]) <= 1e-13 * (G[0] + G[1] + G[2]) && std::fabs(G[5]) <= 1e-13 * (G[0] + G[1] + G[2]);
     if (diag) {

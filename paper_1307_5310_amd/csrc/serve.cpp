@@ -341,7 +341,8 @@ int stdg_serve_start(stdg_ctx* ctx, const stdg_serve_opts* opts, stdg_server** o
   if (opts) o = *opts;
   if (o.hbm_budget == 0) o.hbm_budget = (size_t)16 << 30;
   if (o.max_active <= 0) o.max_active = 16;
-  stdg_solve_opts so{o.inner_prec, o.restart, o.max_iters, o.max_refine, o.rtol, o.inner_rtol, o.krylov_prec};
+  stdg_solve_opts so{o.inner_prec, o.restart, o.max_iters, o.max_refine, o.rtol, o.inner_rtol, o.krylov_prec, 0.0,
+                     0.0};
   SlabOpts sop;
   int rc = slab_opts_from(&so, &sop);
   if (rc != STDG_OK) return rc;

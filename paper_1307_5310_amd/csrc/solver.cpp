@@ -27,7 +27,8 @@ namespace {
 // the two Gram-Schmidt passes, ||Vt_{j+1}||^2, ||r||^2, basis scales s_j, the
 // correction coefficients, and the energies
 constexpr int kH1 = 0, kC1 = kMaxBasis, kH2 = 2 * kMaxBasis, kC2 = 3 * kMaxBasis, kHN = 4 * kMaxBasis,
-              kBeta = kHN + 1, kE0 = kHN + 2, kE1 = kHN + 3, kMirror = kHN + 4,  // entries copied back
+              kBeta = kHN + 1, kE0 = kHN + 2, kE1 = kHN + 3, kDE = kHN + 4, kDH = kHN + 5,
+              kMirror = kHN + 6,  // entries copied back
               kS = kMirror, kY = kS + kMaxBasis + 1, kScalars = kY + kMaxBasis;
 
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -49,6 +50,10 @@ int slab_opts_from(const stdg_solve_opts* o, SlabOpts* out) {
   r.max_refine = o->max_refine > 0 ? o->max_refine : 100;
   r.rtol = o->rtol > 0 ? o->rtol : 1e-10;
   r.inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-4;
+  if (o->eta_tol < 0.0 || (o->eta_tol > 0.0 && !(o->eta_t_final > 0.0)))
+    return fail(STDG_E_ARG, "stdg_slab_solve: eta_tol needs eta_t_final > 0");
+  r.eta_tol = o->eta_tol;
+  r.eta_t_final = o->eta_t_final;
   *out = r;
   return STDG_OK;
 }
@@ -61,7 +66,7 @@ size_t slab_solver_bytes(int64_t n, int64_t nt, int64_t ne, const SlabOpts& o) {
   if (o.v32) b += n8;                 // residual before rounding into the basis
   if (o.f32) b += (o.v32 ? 1 : 2) * n4;
   b += round256(sizeof(double) * kMaxBasis * kMaxDotBlocks) + round256(sizeof(unsigned) * 4) +
-       round256(sizeof(double) * kScalars) + round256(sizeof(double) * (ne + 2));
+       round256(sizeof(double) * kScalars) + round256(sizeof(double) * (2 * ne + 4));
   return b;
 }
 
@@ -90,7 +95,7 @@ int SlabSolver::init(Mesh* m, const SlabOpts& o, hipStream_t s) {
   if ((rc = dev_alloc(c, (void**)&dw_.partial, sizeof(double) * kMaxBasis * kMaxDotBlocks)) != STDG_OK) return rc;
   if ((rc = dev_alloc(c, (void**)&dw_.counter, sizeof(unsigned) * 4)) != STDG_OK) return rc;
   if ((rc = dev_alloc(c, (void**)&hv_, sizeof(double) * kScalars)) != STDG_OK) return rc;
-  if ((rc = dev_alloc(c, (void**)&etmp_, sizeof(double) * (m->ne + 2))) != STDG_OK) return rc;
+  if ((rc = dev_alloc(c, (void**)&etmp_, sizeof(double) * (2 * m->ne + 4))) != STDG_OK) return rc;
   STDG_HIP(hipMemsetAsync(dw_.counter, 0, sizeof(unsigned) * 4, s_));
   STDG_HIP(hipMemsetAsync(hv_, 0, sizeof(double) * kScalars, s_));
   STDG_HIP(hipHostMalloc((void**)&hb_, sizeof(double) * kScalars, hipHostMallocDefault));
@@ -115,7 +120,7 @@ void SlabSolver::release() {
   dev_free(c, dw_.partial, sizeof(double) * kMaxBasis * kMaxDotBlocks);
   dev_free(c, dw_.counter, sizeof(unsigned) * 4);
   dev_free(c, hv_, sizeof(double) * kScalars);
-  dev_free(c, etmp_, sizeof(double) * (m_->ne + 2));
+  dev_free(c, etmp_, sizeof(double) * (2 * m_->ne + 4));
   if (hb_) (void)hipHostFree(hb_);
   if (ev_) (void)hipEventDestroy(ev_);
   V_ = nullptr;
@@ -136,8 +141,18 @@ int SlabSolver::launch_true_residual() {
   ApplyArgs a{m_, dt_, STDG_FP64, STDG_RESIDUAL, U_, load_, res, s_};
   if ((rc = launch_residual(a)) != STDG_OK) return rc;
   if ((rc = vec_dot(res, res, n_, hv_ + kBeta, dw_, s_)) != STDG_OK) return rc;
+  if (o_.eta_tol > 0.0 && (rc = dual_norms_async(m_, dt_, res, etmp_, hv_ + kDE, s_)) != STDG_OK) return rc;
   STDG_HIP(hipMemcpyAsync(hb_, hv_, sizeof(double) * kMirror, hipMemcpyDeviceToHost, s_));
   return STDG_OK;
+}
+
+// the slab's term of the iteration-error bound (eq. a_posteriori:iteration, as printed):
+// 4 [(2 t_N / eps_min + dt^2 / (2 t_N eps_min)) ||R_E||^2 + (same with mu) ||R_H||^2]
+double SlabSolver::eta_term() const {
+  const double tN = o_.eta_t_final, dt = dt_;
+  const double cE = 2.0 * tN / m_->eps_min + dt * dt / (2.0 * tN * m_->eps_min);
+  const double cH = 2.0 * tN / m_->mu_min + dt * dt / (2.0 * tN * m_->mu_min);
+  return 4.0 * (cE * hb_[kDE] + cH * hb_[kDH]);
 }
 
 int SlabSolver::begin(double dt, const double* load, double* state, double* slab_U) {
@@ -147,7 +162,7 @@ int SlabSolver::begin(double dt, const double* load, double* state, double* slab
   slabU_ = slab_U;
   status = STDG_OK;
   iters = refinements = cycles_ = 0;
-  rel_res = energy_start = energy_end = 0.0;
+  rel_res = energy_start = energy_end = eta2 = 0.0;
   converged_ = false;
   int rc;
   if ((rc = energy_async(m_, state_, etmp_, hv_ + kE0, s_)) != STDG_OK) return rc;
@@ -170,6 +185,14 @@ int SlabSolver::start_cycle() {
   g_[0] = beta_;
   const double target = o_.rtol * beta0_;
   inner_target_ = o_.f32 ? std::max(o_.inner_rtol * beta_, target) : target;
+  if (o_.eta_tol > 0.0) {
+    // ||R||_{W'}^2 <= ||R||_2^2 max_K 1 / (dt lambda_min(G_K)): a Euclidean residual
+    // below this keeps the slab's eta term below eta_tol^2 (checked exactly at the cycle end)
+    const double tN = o_.eta_t_final, dt = dt_;
+    const double cmax = std::max(2.0 * tN / m_->eps_min + dt * dt / (2.0 * tN * m_->eps_min),
+                                 2.0 * tN / m_->mu_min + dt * dt / (2.0 * tN * m_->mu_min));
+    inner_target_ = std::max(inner_target_, o_.eta_tol / std::sqrt(4.0 * cmax * m_->inv_gmin / dt));
+  }
   j_ = 0;
   return launch_iteration();
 }
@@ -251,6 +274,10 @@ int SlabSolver::advance(bool* done) {
       refinements = 1;
       if (!std::isfinite(beta0_)) return fail(STDG_E_ARG, "stdg_slab_solve: non-finite initial residual");
       converged_ = beta0_ == 0.0;
+      if (o_.eta_tol > 0.0) {
+        eta2 = eta_term();
+        converged_ = converged_ || eta2 <= o_.eta_tol * o_.eta_tol;
+      }
       if (converged_ || iters >= o_.max_iters) return launch_slab_end();
       return start_cycle();
     }
@@ -286,6 +313,10 @@ int SlabSolver::advance(bool* done) {
       beta_ = std::sqrt(hb_[kBeta]);
       refinements += 1;
       converged_ = beta_ <= o_.rtol * beta0_;
+      if (o_.eta_tol > 0.0) {
+        eta2 = eta_term();
+        converged_ = converged_ || eta2 <= o_.eta_tol * o_.eta_tol;
+      }
       if (converged_ || iters >= o_.max_iters || (o_.f32 && cycles_ >= o_.max_refine)) return launch_slab_end();
       return start_cycle();
     }
@@ -335,6 +366,7 @@ extern "C" int stdg_slab_solve(const stdg_mesh* mesh, double t0, double dt, cons
   info->rel_res = S.rel_res;
   info->energy_start = S.energy_start;
   info->energy_end = S.energy_end;
+  info->eta2 = S.eta2;
   if (rc == STDG_OK && S.status != STDG_OK)
     rc = fail(S.status, "stdg_slab_solve: relative residual " + std::to_string(S.rel_res) + " after " +
                             std::to_string(S.iters) + " iterations");

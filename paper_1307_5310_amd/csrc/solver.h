@@ -34,6 +34,8 @@ int layout_embed(const Mesh* m, double* U, const double* x, const double* st, hi
 int layout_level(const Mesh* m, double* st, const double* x, int lev, hipStream_t s);
 int layout_guess(const Mesh* m, double* x, const double* st, hipStream_t s);
 int energy_async(const Mesh* m, const double* state, double* d_partial, double* d_out, hipStream_t s);
+// (||R_E||^2, ||R_H||^2) in W_h' of a residual-layout FP64 vector; d_partial holds 2 ne doubles
+int dual_norms_async(const Mesh* m, double dt, const double* R, double* d_partial, double* d_out, hipStream_t s);
 int ensure_state_off(Mesh* m);
 
 // Options of one slab solve (validated copies of stdg_solve_opts).
@@ -42,6 +44,7 @@ struct SlabOpts {
   bool v32 = false;  // Krylov basis stored in FP32 (FP32 inner applies only)
   int restart = 10, max_iters = 500, max_refine = 100;
   double rtol = 1e-10, inner_rtol = 1e-4;
+  double eta_tol = 0.0, eta_t_final = 0.0;  // inexact solve: stop once eta_it^2 of the slab <= eta_tol^2
 };
 int slab_opts_from(const stdg_solve_opts* o, SlabOpts* out);
 
@@ -67,6 +70,7 @@ class SlabSolver {
   int status = 0;  // STDG_OK or STDG_E_NOT_CONVERGED
   int iters = 0, refinements = 0;
   double rel_res = 0.0, energy_start = 0.0, energy_end = 0.0;
+  double eta2 = 0.0;  // the slab's term of eta_it^2 at the final iterate (inexact solve only)
 
  private:
   enum Phase { kIdle, kWaitStart, kWaitIter, kWaitCycle, kWaitEnd };
@@ -98,6 +102,7 @@ class SlabSolver {
   double* state_ = nullptr;
   double* slabU_ = nullptr;
   double beta0_ = 0.0, beta_ = 0.0, inner_target_ = 0.0;
+  double eta_term() const;  // eta_it^2 term of the residual in the scalars
   int cycles_ = 0, j_ = 0;
   bool converged_ = false;
   double H_[kMaxBasis * kMaxBasis], cs_[kMaxBasis], sn_[kMaxBasis], g_[kMaxBasis + 1];
