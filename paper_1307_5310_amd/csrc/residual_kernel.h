@@ -59,12 +59,12 @@ struct KCfg {
     constexpr int c = AFF ? 16384 / (LVL * (int)sizeof(T)) : 1;
     return c < 1 ? 1 : (c > Q ? Q : c);
   }
-  // neighbour blocks are staged through LDS a face at a time (4 tangential
-  // component blocks of the stored levels, double-buffered) when a face of
-  // q + 1 levels fits in 24 KB; larger ones are gathered straight from global
-  // memory (measured faster there, e.g. FP32 with p = 6, q = 4)
+  // FP32 neighbour blocks are staged through LDS a face at a time (4
+  // tangential component blocks of the stored levels, double-buffered) when a
+  // face of q + 1 levels fits in 24 KB; FP64 blocks and larger faces are
+  // gathered straight from global memory (measured faster there)
   template <typename T, int Q>
-  static constexpr bool stage() { return 4 * (Q + 1) * A3 * (int)sizeof(T) <= 24576; }
+  static constexpr bool stage() { return sizeof(T) == 4 && 4 * (Q + 1) * A3 * (int)sizeof(T) <= 24576; }
   static constexpr int levels(int Q, int MODE) { return MODE == 1 ? Q + 1 : Q; }  // stored trial levels
   // trilinear elements: Gauss rule of GQ = a + 1 points per direction for the
   // mass; PP quadrature points per thread
