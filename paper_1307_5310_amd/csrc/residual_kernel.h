@@ -308,6 +308,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   constexpr int A2 = C::A2, A3 = C::A3, NF = C::NF, ND = C::ND, LVL = C::LVL;
   constexpr int LC = C::template LC<T, Q, AFF>();
   constexpr bool resid = MODE == 1, pre = MODE == 2;  // operator / residual / operator with P^{-1}
+  constexpr bool kSelectCurl = sizeof(T) == 4 && A >= 7;
   static_assert(AFF || !pre, "trilinear elements take P^{-1} in a separate pass");
   constexpr int m0 = resid ? 0 : 1;                   // first trial level stored in x
   constexpr int NL = Q + 1 - m0;                      // trial levels stored per component
@@ -667,7 +668,17 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
 #pragma unroll
             for (int dd = 0; dd < ND; ++dd) {
               const int d = 2 * dd + 1;
-              if (f == 0) {
+              if constexpr (kSelectCurl) {
+                // selects instead of 0/1 factors: fewer live registers (measured
+                // faster for FP32 with p >= 6, slower elsewhere)
+                if (f == 0) {
+                  p1 += sidx[c1] >= d ? X2[-d * stride[c1]] : T(0);
+                  p2 += sidx[c2] >= d ? X1[-d * stride[c2]] : T(0);
+                } else {
+                  p1 += sidx[c1] + d < A ? X2[d * stride[c1]] : T(0);
+                  p2 += sidx[c2] + d < A ? X1[d * stride[c2]] : T(0);
+                }
+              } else if (f == 0) {
                 p1 += mE[c1][dd] * X2[-d * stride[c1]];
                 p2 += mE[c2][dd] * X1[-d * stride[c2]];
               } else {
