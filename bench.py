@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--serve-max-active", type=int, default=16)
     ap.add_argument("--serve-krylov", choices=("fp32", "fp64"), default="fp32",
                     help="storage of the serving solver's Krylov basis (sums are FP64 either way)")
+    ap.add_argument("--serve-eta-rel", type=float, default=1e-3,
+                    help="also run the stream with inexact solves, eta_it <= this * sqrt(2 E(0)) per "
+                         "request (0 = skip)")
     return ap.parse_args()
 
 
@@ -206,6 +209,13 @@ def main():
                                args.serve_krylov)
         log("serving: %.2f solves/s, p50 %.3f s, p99 %.3f s" % (serving["solves_per_s"], serving["p50_latency_s"],
                                                                serving["p99_latency_s"]))
+        if args.serve_eta_rel > 0:
+            log("serving stream, inexact solves")
+            serving["inexact"] = time_serving(stdg, ctx, args.serve_requests, args.serve_budget_gb,
+                                              args.serve_max_active, args.serve_krylov, args.serve_eta_rel)
+            log("serving inexact: %.2f solves/s, p50 %.3f s, p99 %.3f s" % (
+                serving["inexact"]["solves_per_s"], serving["inexact"]["p50_latency_s"],
+                serving["inexact"]["p99_latency_s"]))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -253,7 +263,7 @@ def main():
     stdg.stdg_finalize(ctx)
 
 
-def time_serving(stdg, ctx, n_requests, budget_gb, max_active, krylov):
+def time_serving(stdg, ctx, n_requests, budget_gb, max_active, krylov, eta_rel=0.0):
     """The serving stream: independent PEC cavity solves (n^3, n in {4,..,16},
     p in 2..6, q = p - 1, eps in {1,2,4} per element, 20 slabs, dt = h/(2p+1))
     arriving as a Poisson process at 50 per second, submitted at their arrival
@@ -263,7 +273,8 @@ def time_serving(stdg, ctx, n_requests, budget_gb, max_active, krylov):
     dofs = [r["mesh"].trial_size() * r["n_slabs"] for r in reqs]
     srv = stdg.stdg_serve_start(ctx, hbm_budget=int(budget_gb * (1 << 30)), max_active=max_active,
                                 inner_prec=stdg.STDG_FP32, rtol=1e-10, max_iters=3000, max_refine=300,
-                                krylov_prec=stdg.STDG_FP32 if krylov == "fp32" else stdg.STDG_FP64)
+                                krylov_prec=stdg.STDG_FP32 if krylov == "fp32" else stdg.STDG_FP64,
+                                eta_rel=eta_rel)
     results = {}
     try:
         c0 = stdg.stdg_serve_clock(srv)
@@ -302,6 +313,9 @@ def time_serving(stdg, ctx, n_requests, budget_gb, max_active, krylov):
             "iters_per_slab": round(sum(r["iters"] for r in res) / sum(r["slabs_done"] for r in res), 2),
             "max_rel_res": max(r["max_rel_res"] for r in res), "failed": bad,
             "hbm_budget_gb": budget_gb, "max_active": max_active, "krylov_basis": krylov,
+            "stop": ("eta_it <= %g sqrt(2 E(0)) per request" % eta_rel) if eta_rel > 0 else "rtol 1e-10 per slab",
+            "max_eta_it_rel": (max(r["eta_it"] / np.sqrt(2 * r["energy_start"]) for r in res if r["energy_start"] > 0)
+                               if eta_rel > 0 else None),
             "max_energy_drift": max(abs(r["energy_end"] - r["energy_start"]) / max(r["energy_start"], 1e-300)
                                     for r in res)}
 
@@ -449,6 +463,25 @@ def time_solves(stdg, torch, mh, m, cfg):
                                              "iters": r["iters"], "eta_it_term": float(np.sqrt(r["eta2"])),
                                              "eta_tol": float(eta_tol), "rel_res": r["rel_res"]}
     log("slab solve inexact: %.3f s, %d iters" % (el, r["iters"]))
+    # the whole 64-slab march of the workload with the inexact solve
+    state = torch.zeros(info["state_size"], dtype=torch.float64, device="cuda")
+    stdg.stdg_project_modes(mh, modes.mnl, modes.abc, state)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eta2, iters = 0.0, 0
+    for n in range(n_slabs):
+        r = stdg.stdg_slab_solve(mh, n * cfg["dt"], cfg["dt"], None, state, inner_prec=stdg.STDG_FP32, rtol=1e-10,
+                                 max_iters=3000, max_refine=300, krylov_prec=stdg.STDG_FP32, eta_tol=eta_tol,
+                                 eta_t_final=n_slabs * cfg["dt"])
+        eta2 += r["eta2"]
+        iters += r["iters"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res["march_inexact_64_slabs"] = {"s": round(el, 3), "slab_solves_per_s": round(n_slabs / el, 2),
+                                     "iters_per_slab": round(iters / n_slabs, 2),
+                                     "eta_it_rel": float(np.sqrt(eta2) / np.sqrt(2.0 * e0)),
+                                     "energy_drift": (r["energy_end"] - e0) / e0}
+    log("64-slab inexact march: %.2f s (%.1f slab solves/s)" % (el, n_slabs / el))
     res["speedup_fp32_refine"] = round(res["fp64"]["s_per_solve"] / res["fp32_refine"]["s_per_solve"], 3)
     res["speedup_fp32_refine_fp32_basis"] = round(
         res["fp64"]["s_per_solve"] / res["fp32_refine_fp32_basis"]["s_per_solve"], 3)

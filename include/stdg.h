@@ -250,6 +250,11 @@ typedef struct {
   double rtol;
   double inner_rtol;
   int32_t krylov_prec;
+  double eta_rel;        /* > 0: inexact solves (Section 5.3): each request stops a
+                            slab once its term of eta_it^2 (t_N = n_slabs dt) is
+                            <= (eta_rel sqrt(2 E(t0)))^2 / n_slabs, so that
+                            eta_it <= eta_rel sqrt(2 E(t0)) over the request;
+                            0 = solve every slab to rtol                         */
 } stdg_serve_opts;
 
 typedef struct {
@@ -274,6 +279,7 @@ typedef struct {
   double t_submit, t_admit, t_done;  /* seconds on the server clock                 */
   int64_t state_size;        /* entries of the final state                          */
   int64_t device_bytes;      /* reservation the request held                        */
+  double eta_it;             /* with eta_rel: the accumulated iteration-error bound */
   double* state;             /* in: caller host buffer for the final state, or NULL */
   int64_t state_capacity;    /* in: entries available at state                      */
 } stdg_result;

@@ -76,7 +76,7 @@ class ServeOpts(ctypes.Structure):
                 ("inner_prec", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("krylov_prec", ctypes.c_int32)]
+                ("krylov_prec", ctypes.c_int32), ("eta_rel", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):
@@ -91,6 +91,7 @@ class Result(ctypes.Structure):
                 ("energy_end", ctypes.c_double), ("t_submit", ctypes.c_double),
                 ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
                 ("state_size", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("eta_it", ctypes.c_double),
                 ("state", ctypes.c_void_p), ("state_capacity", ctypes.c_int64)]
 
 

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -29,6 +30,7 @@ extern "C" int stdg_project_modes(const stdg_mesh* mesh, int32_t n_modes, const 
                                   double* state_dev, void* stream);
 extern "C" int stdg_load_assemble(const stdg_mesh* mesh, const stdg_source* src, double t0, double dt,
                                   double* load_dev, void* stream);
+extern "C" int stdg_energy(const stdg_mesh* mesh, const double* state_dev, double* energy_out, void* stream);
 
 namespace stdg {
 
@@ -69,6 +71,7 @@ struct Active {
   int slab = 0;
   bool finishing = false;
   hipEvent_t done_ev = nullptr;
+  double eta2 = 0.0;  // accumulated iteration-error bound (inexact solves)
   Finished out;
 };
 
@@ -154,6 +157,7 @@ size_t footprint_of(const Request& r, const SlabOpts& so) {
   b += r256(sizeof(double) * r.n_state) + (r.src.kind ? r256(sizeof(double) * r.n_unk) : 0) +
        2 * r256(sizeof(double) * 3 * (r.mnl.size() / 3 + 1));
   b += slab_solver_bytes(r.n_unk, r.n_trial, r.ne, so);
+  b += r256(sizeof(double) * (r.ne + 1));  // energy of the initial field (inexact solves)
   return b + 16384;  // alignment of the individual allocations
 }
 
@@ -190,7 +194,16 @@ int Server::start(Active* a) {
                                  a->stream)) != STDG_OK)
       return rc;
   }
-  if ((rc = a->solver.init(&m, so, a->stream)) != STDG_OK) return rc;
+  SlabOpts ro = so;
+  if (opts.eta_rel > 0.0) {
+    // per-slab budget of the iteration-error bound, relative to the initial energy
+    double e0 = 0.0;
+    if ((rc = stdg_energy(a->mesh, a->state, &e0, a->stream)) != STDG_OK) return rc;
+    ro.eta_t_final = r->n_slabs * r->dt;
+    ro.eta_tol = opts.eta_rel * std::sqrt(2.0 * e0) / std::sqrt((double)r->n_slabs);
+    if (!(ro.eta_tol > 0.0)) ro.eta_tol = 0.0;  // zero field: solve to rtol
+  }
+  if ((rc = a->solver.init(&m, ro, a->stream)) != STDG_OK) return rc;
   a->solver_ready = true;
   return start_slab(a);
 }
@@ -220,6 +233,8 @@ int Server::step(Active* a, bool* finished_now) {
   res.energy_end = a->solver.energy_end;
   res.iters += a->solver.iters;
   res.max_rel_res = std::max(res.max_rel_res, a->solver.rel_res);
+  a->eta2 += a->solver.eta2;
+  res.eta_it = std::sqrt(a->eta2);
   if (a->solver.status != STDG_OK) res.status = a->solver.status;
   res.slabs_done = ++a->slab;
   if (a->slab < a->rq->n_slabs) return start_slab(a);
@@ -341,6 +356,7 @@ int stdg_serve_start(stdg_ctx* ctx, const stdg_serve_opts* opts, stdg_server** o
   if (opts) o = *opts;
   if (o.hbm_budget == 0) o.hbm_budget = (size_t)16 << 30;
   if (o.max_active <= 0) o.max_active = 16;
+  if (o.eta_rel < 0.0) return fail(STDG_E_ARG, "stdg_serve_start: eta_rel must be >= 0");
   stdg_solve_opts so{o.inner_prec, o.restart, o.max_iters, o.max_refine, o.rtol, o.inner_rtol, o.krylov_prec, 0.0,
                      0.0};
   SlabOpts sop;

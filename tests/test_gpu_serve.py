@@ -189,3 +189,35 @@ def test_stop_with_work_in_flight(lib):
     stdg.stdg_serve_stop(srv)
     assert time.time() - t0 < 30
     assert len(tickets) == 6
+
+
+def test_inexact_serving_within_eta(lib):
+    """Requests solved inexactly (Section 5.3): each stops its slabs at a share
+    of the iteration-error budget; the accumulated eta_it is within the budget,
+    the true error against the oracle's exact march is below it, and the
+    result is the same alone and in a mix."""
+    stdg = lib.stdg
+    from oracle import fields
+    reqs = _small_stream(4, sizes=(2,), degrees=(2, 3), n_slabs=3)
+    sizes = [r["mesh"].state_size() for r in reqs]
+    eta_rel = 1e-3
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 30, eta_rel=eta_rel, **OPTS)
+    try:
+        alone = _wait(stdg, srv, [_submit(stdg, srv, reqs[1])], [sizes[1]])[0]
+        mix = _wait(stdg, srv, [_submit(stdg, srv, r) for r in reqs], sizes)
+    finally:
+        stdg.stdg_serve_stop(srv)
+    assert np.array_equal(alone["state"], mix[1]["state"])
+    rq = reqs[1]
+    d = oracle_disc(rq["mesh"])
+    s = fields.project(d, fields.mode_superposition(rq["init"].mnl, rq["init"].abc), 0.0)
+    budget = eta_rel * np.sqrt(2 * d.energy(s))
+    for n in range(rq["n_slabs"]):
+        note("inexact serving: oracle slab %d" % n)
+        s = d.level_state(d.solve_direct(s, rq["dt"]), 1)
+    r = mix[1]
+    err = np.sqrt(2 * d.energy(r["state"] - s))
+    note("inexact serving: error %.3e, eta_it %.3e, budget %.3e, iters %d" % (err, r["eta_it"], budget, r["iters"]))
+    assert r["status"] == 0
+    assert r["eta_it"] <= budget * (1 + 1e-12)
+    assert err <= r["eta_it"]
