@@ -13,8 +13,9 @@ integrated in physical space-time with
 * neighbour traces at the same physical points, found by Newton inversion of
   the neighbour's map; faces are matched by physical centroid;
 * the average / tangential-jump operators of Section 2.4 and the terms of
-  C_h (eq. bilinearform:C) and S_h (eq. bilinearform:S) as written, with the
-  temporal L2 projection pi-tilde computed by quadrature;
+  C_h (eq. bilinearform:C), S_h (eq. bilinearform:S) and the dissipative D_h
+  (the remark after Section 4) as written, with the temporal L2 projection
+  pi-tilde computed by quadrature;
 * its own Legendre evaluation by the three-term recurrence.
 
 Only tiny meshes are feasible (dense matrices, many quadrature points).
@@ -144,10 +145,10 @@ def _face_param(face, uv):
     return xh, tang
 
 
-def assemble(vertices, hexes, p, q, eps, mu, dt, nvol_extra=2, nface_extra=2, nt=None):
-    """Dense slab matrix B[test dof, trial dof] of B_h = C_h + S_h by physical
-    quadrature.  Row layout per element [field][c][i][s]; column layout per
-    element [field][d][m][t] (m = 0..q)."""
+def assemble(vertices, hexes, p, q, eps, mu, dt, nvol_extra=2, nface_extra=2, nt=None, c_diss=0.0):
+    """Dense slab matrix B[test dof, trial dof] of B_h = C_h + S_h (+ D_h for
+    c_diss > 0) by physical quadrature.  Row layout per element [field][c][i][s];
+    column layout per element [field][d][m][t] (m = 0..q)."""
     vertices = np.asarray(vertices, dtype=np.float64)
     hexes = np.asarray(hexes)
     ne = hexes.shape[0]
@@ -249,6 +250,10 @@ def assemble(vertices, hexes, p, q, eps, mu, dt, nvol_extra=2, nface_extra=2, nt
                 Rb = np.einsum("p,pbk,pak->ab", wS, np.cross(n1[:, None, :], v1), v1)  # int (n x u) . w
                 put(e, 0, e, 1, Nt, Pb)
                 put(e, 1, e, 0, Nt, -Rb)
+                if c_diss > 0.0:
+                    # D_h on the PEC face: (alpha_E [E]_T, [v]_T), [u]_T = n x u, g = 0
+                    aE = c_diss / np.sqrt(mu[e] / eps[e])
+                    put(e, 0, e, 0, Nt, aE * np.einsum("p,pak,pbk->ab", wS, n1xv1, n1xv1))
                 continue
             elk = els[k]
             xh2 = elk.invert(x)
@@ -267,4 +272,12 @@ def assemble(vertices, hexes, p, q, eps, mu, dt, nvol_extra=2, nface_extra=2, nt
                 # H-row: -([E]_T, {w}) - 1/2 (({E}, [dw]_T) + ([E]_T, {dw}))
                 put(e, 1, kk, 0, Nt, -Ql)
                 put(e, 1, kk, 0, Nd, -0.5 * (Pl + Ql))
+                if c_diss > 0.0:
+                    # D_h: (alpha [U]_T, [pi v]_T): the time-projected test function
+                    # pi L_i = L_i + (pi L_i - L_i) gives the N + Nd time factors
+                    aE = c_diss / (0.5 * (np.sqrt(mu[e] / eps[e]) + np.sqrt(mu[k] / eps[k])))
+                    aH = c_diss / (0.5 * (np.sqrt(eps[e] / mu[e]) + np.sqrt(eps[k] / mu[k])))
+                    J = np.einsum("p,pak,pbk->ab", wS, n1xv1, np.cross(nl[:, None, :], ul))  # int (n1 x v1) . (n_l x u_l)
+                    put(e, 0, kk, 0, Nt + Nd, aE * J)
+                    put(e, 1, kk, 1, Nt + Nd, aH * J)
     return B

@@ -7,6 +7,8 @@ Everything follows the slab bilinear form of the paper:
               + sum_f ({H}, [v]_T)_f - sum_f ([E]_T, {w})_f          (Section 2.5, eq. bilinearform:C)
   S_h(U, V) = stabilisation of eq. bilinearform:S (Section 4.1)
   B_h = C_h + S_h                                                    (eq. weakform_stabilized)
+  D_h(U, V) = dissipative upwind-type face terms (remark closing Section 4),
+              added to B_h when c_diss > 0
   R_h(V) = B_h(U_h, V) - L(V),  L(V) = (J, v) - (n x g, w)_{F_b}      (Section 5, eq. residual)
 
 with centred fluxes ({v} = v and [v]_T = n x v on boundary faces; g = 0 here:
@@ -31,6 +33,10 @@ Readings where the paper is silent or garbled (each pinned by a test):
 * mass quadrature: n_q = p + 2 Gauss points per direction (exact on affine
   elements); the same rule is used by the library.
 * load quadrature: p + 3 points per space direction, q + 3 in time.
+* D_h: the projection on interior faces acts on the test function (rows
+  i >= min(q_K, q_K') vanish for own and neighbour trial), the trial jump is
+  not projected; on PEC faces nothing is projected and g = 0; {.} of the
+  impedances is the plain mean of the two sides, on PEC faces the element's own.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -170,6 +176,42 @@ def face_matrices(a, face, a_other=None, neighbour=False):
     return FE.reshape(3 * n3, 3 * m3), FH.reshape(3 * n3, 3 * m3)
 
 
+def dissipation_matrices(X, a, face, Xo=None, ao=None, nq=None):
+    """Face matrices of the dissipative stabilisation (the upwind-type remark
+    after Section 4): with covariant basis functions u = DF^{-T} e_c phi_s,
+      Dself[(c,s),(d,t)] = int_f (n x u_(c,s)) . (n x u_(d,t)) dS      (K's own trial)
+      Dnb[(c,s),(d,t)]   = int_f (n x u_(c,s)) . (n x u'_(d,t)) dS     (neighbour trial)
+    in physical space on local face (alpha, side) of K, n the unit normal,
+    u' the neighbour's basis of degree ao on its opposite face at the same
+    physical points (conforming, canonical orientation).  The face rule has
+    max(a, ao) + 2 Gauss points per direction unless nq is given: exact on
+    affine elements, a quadrature of the rational integrand on trilinear ones."""
+    alpha, side = divmod(face, 2)
+    tang = [d for d in range(3) if d != alpha]
+    n = (max(a, ao or a) + 2) if nq is None else nq
+    pts, w = face_points(face, n)
+    DF = jacobian(X, pts)                                   # [P, 3, 3], DF[:, :, m] = dx / dxhat_m
+    nv = np.cross(DF[:, :, tang[0]], DF[:, :, tang[1]])
+    dS = np.linalg.norm(nv, axis=1)
+    nrm = nv / dS[:, None] * (2.0 * side - 1.0) * np.sign(np.einsum("pi,pi->p", nv, DF[:, :, alpha]))[:, None]
+    wS = w * dS
+
+    def nx_basis(Xe, ae, fpts):
+        Dinv = np.linalg.inv(jacobian(Xe, fpts))            # rows: DF^{-1}; DF^{-T} e_c = Dinv[c, :]
+        Phi, _ = basis_at(ae, fpts)
+        vecs = np.cross(nrm[:, None, :], Dinv)              # [P, c, 3]: n x DF^{-T} e_c
+        return np.einsum("pck,ps->pcsk", vecs, Phi).reshape(len(fpts), 3 * ae ** 3, 3)
+
+    A = nx_basis(X, a, pts)
+    Dself = np.einsum("p,pak,pbk->ab", wS, A, A)
+    if Xo is None:
+        return Dself, None
+    pts_o, _ = face_points(opposite(face), n)
+    B = nx_basis(Xo, ao, pts_o)
+    Dnb = np.einsum("p,pak,pbk->ab", wS, A, B)
+    return Dself, Dnb
+
+
 # ----------------------------------------------------------------------------
 # discretisation of one mesh
 # ----------------------------------------------------------------------------
@@ -184,7 +226,7 @@ class Discretisation:
       state        : per element [field][comp][s]   (fields at one time)
     with s = j + a (k + a l), j the x-hat index."""
 
-    def __init__(self, vertices, hexes, p, q, eps, mu, mass_nq=None):
+    def __init__(self, vertices, hexes, p, q, eps, mu, mass_nq=None, c_diss=0.0):
         self.vertices = np.asarray(vertices, dtype=np.float64)
         self.hexes = np.asarray(hexes, dtype=np.int64)
         self.p = np.asarray(p, dtype=np.int64)
@@ -197,6 +239,7 @@ class Discretisation:
         if not canon.all():
             raise ValueError("only conforming faces in canonical orientation are supported")
         self.mass_nq = mass_nq
+        self.c_diss = float(c_diss)  # dissipative stabilisation D_h, c >= 0 (0 = off)
         a3 = self.a ** 3
         self.trial_size = 6 * (self.q + 1) * a3
         self.unk_size = 6 * self.q * a3
@@ -283,6 +326,43 @@ class Discretisation:
             FE, FH = self.face(a, f, ak, neighbour=True)
             out.append((k, dt * Nc, 0.5 * FE, 0, 1))
             out.append((k, dt * Nc, -0.5 * FH, 1, 0))
+        if self.c_diss > 0.0:
+            out += self.dissipation_blocks(e, dt)
+        return out
+
+    def dissipation_blocks(self, e, dt):
+        """D_h (the dissipative remark after Section 4): on interior faces
+        (alpha_E [E]_T, [pi v]_T) + (alpha_H [H]_T, [pi w]_T), the test function
+        projected in time onto the common test space (levels i < min(q, q'),
+        so rows i >= min(q, q') vanish for own and neighbour trial alike); on
+        PEC faces (alpha_E [E]_T, [v]_T) with g = 0.  alpha_E = c / {sqrt(mu/eps)},
+        alpha_H = c / {sqrt(eps/mu)}."""
+        qe = int(self.q[e])
+        a = int(self.a[e])
+        Xe = self.X(e)
+        out = []
+        ze, zh = np.sqrt(self.mu[e] / self.eps[e]), np.sqrt(self.eps[e] / self.mu[e])
+        for f in range(6):
+            k = int(self.nb[e, f])
+            if k < 0:
+                _, N = self.tables(qe, qe)
+                Ds, _ = dissipation_matrices(Xe, a, f, nq=self.mass_nq)
+                out.append((e, dt * N, (self.c_diss / ze) * Ds, 0, 0))
+                continue
+            qk, ak = int(self.q[k]), int(self.a[k])
+            r = min(qe, qk)
+            aE = self.c_diss / (0.5 * (ze + np.sqrt(self.mu[k] / self.eps[k])))
+            aH = self.c_diss / (0.5 * (zh + np.sqrt(self.eps[k] / self.mu[k])))
+            Ds, Dn = dissipation_matrices(Xe, a, f, self.X(k), ak, nq=self.mass_nq)
+            _, Ns = self.tables(qe, qe)
+            _, Nk = self.tables(qe, qk)
+            Ns, Nk = Ns.copy(), Nk.copy()
+            Ns[r:, :] = 0.0
+            Nk[r:, :] = 0.0
+            out.append((e, dt * Ns, aE * Ds, 0, 0))
+            out.append((e, dt * Ns, aH * Ds, 1, 1))
+            out.append((k, dt * Nk, -aE * Dn, 0, 0))
+            out.append((k, dt * Nk, -aH * Dn, 1, 1))
         return out
 
     # -- layout helpers ---------------------------------------------------------
