@@ -134,6 +134,22 @@ int stdg_mesh_offsets(const stdg_mesh* mesh, int64_t* trial_off, int64_t* unknow
                       int64_t* state_off);
 int stdg_mesh_free(stdg_mesh* mesh);
 
+/* Dissipative upwind-type stabilisation D_h (the remark closing Section 4):
+ * from this call on, every residual apply and slab solve on `mesh` uses
+ * B_h + D_h with
+ *   D_h(U, V) = sum_{interior f} (alpha_E [E]_T, [pi v]_T)_f + (alpha_H [H]_T, [pi w]_T)_f
+ *             + sum_{PEC f} (alpha_E [E]_T, [v]_T)_f,
+ *   alpha_E = c / {sqrt(mu/eps)}, alpha_H = c / {sqrt(eps/mu)}  ({.}: mean of the
+ *   two sides, the element's own value on PEC faces; g = 0),
+ * pi the temporal projection onto the common test space of the two elements
+ * (the same truncation as S_h).  The energy then drops by the dissipation of
+ * the slab instead of being conserved.  c = 0 switches it off (the device
+ * coefficients are freed).  Needs affine elements (constant face metric):
+ * STDG_E_UNSUPPORTED if the mesh has trilinear ones and c > 0; STDG_E_ARG for
+ * c < 0 or non-finite.  Synchronous (host to device copy of 192 bytes per
+ * element); not to be called while work on the mesh is in flight. */
+int stdg_mesh_set_dissipation(stdg_mesh* mesh, double c);
+
 /* The hot path: the matrix-free space-time residual of one slab (Section 5,
  * eq. residual; evaluation of Section 5.2: mass, curl and flux terms).
  * Affine elements use their constant metric; trilinear elements integrate the

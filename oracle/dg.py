@@ -203,12 +203,13 @@ def dissipation_matrices(X, a, face, Xo=None, ao=None, nq=None):
         return np.einsum("pck,ps->pcsk", vecs, Phi).reshape(len(fpts), 3 * ae ** 3, 3)
 
     A = nx_basis(X, a, pts)
-    Dself = np.einsum("p,pak,pbk->ab", wS, A, A)
+    Aw = A * wS[:, None, None]
+    Dself = np.tensordot(Aw, A, axes=([0, 2], [0, 2]))      # sum_p,k w A[p,a,k] A[p,b,k]
     if Xo is None:
         return Dself, None
     pts_o, _ = face_points(opposite(face), n)
     B = nx_basis(Xo, ao, pts_o)
-    Dnb = np.einsum("p,pak,pbk->ab", wS, A, B)
+    Dnb = np.tensordot(Aw, B, axes=([0, 2], [0, 2]))
     return Dself, Dnb
 
 
@@ -342,18 +343,29 @@ class Discretisation:
         Xe = self.X(e)
         out = []
         ze, zh = np.sqrt(self.mu[e] / self.eps[e]), np.sqrt(self.eps[e] / self.mu[e])
+
+        def face_mats(f, k):
+            # cached by the shape of the pair (translation invariant)
+            Xk = None if k < 0 else self.X(k)
+            ak = None if k < 0 else int(self.a[k])
+            key = ("D", a, ak, f, tuple(np.round((Xe - Xe[0]).ravel(), 14)),
+                   None if Xk is None else tuple(np.round((Xk - Xe[0]).ravel(), 14)))
+            if key not in self._cache:
+                self._cache[key] = dissipation_matrices(Xe, a, f, Xk, ak, nq=self.mass_nq)
+            return self._cache[key]
+
         for f in range(6):
             k = int(self.nb[e, f])
             if k < 0:
                 _, N = self.tables(qe, qe)
-                Ds, _ = dissipation_matrices(Xe, a, f, nq=self.mass_nq)
+                Ds, _ = face_mats(f, -1)
                 out.append((e, dt * N, (self.c_diss / ze) * Ds, 0, 0))
                 continue
             qk, ak = int(self.q[k]), int(self.a[k])
             r = min(qe, qk)
             aE = self.c_diss / (0.5 * (ze + np.sqrt(self.mu[k] / self.eps[k])))
             aH = self.c_diss / (0.5 * (zh + np.sqrt(self.eps[k] / self.mu[k])))
-            Ds, Dn = dissipation_matrices(Xe, a, f, self.X(k), ak, nq=self.mass_nq)
+            Ds, Dn = face_mats(f, k)
             _, Ns = self.tables(qe, qe)
             _, Nk = self.tables(qe, qk)
             Ns, Nk = Ns.copy(), Nk.copy()

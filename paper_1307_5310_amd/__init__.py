@@ -17,7 +17,7 @@ from ._lib import (StdgError, STDG_FP32, STDG_FP64, STDG_OPERATOR, STDG_RESIDUAL
 
 __all__ = ["StdgError", "STDG_FP32", "STDG_FP64", "STDG_OPERATOR", "STDG_RESIDUAL",
            "STDG_OPERATOR_PRECOND", "stdg_version", "stdg_init", "stdg_finalize",
-           "stdg_mesh_upload", "stdg_mesh_info", "stdg_mesh_offsets", "stdg_mesh_free",
+           "stdg_mesh_upload", "stdg_mesh_info", "stdg_mesh_offsets", "stdg_mesh_free", "stdg_mesh_set_dissipation",
            "stdg_residual_apply", "stdg_load_assemble", "stdg_project_modes",
            "stdg_slab_solve", "stdg_energy", "stdg_residual_dual_norm", "stdg_serve_start", "stdg_serve_submit",
            "stdg_serve_poll", "stdg_serve_clock", "stdg_serve_stop", "exported_symbols"]
@@ -72,6 +72,10 @@ def stdg_mesh_offsets(mesh):
 
 def stdg_mesh_free(mesh):
     check(lib().stdg_mesh_free(mesh))
+
+
+def stdg_mesh_set_dissipation(mesh, c):
+    check(lib().stdg_mesh_set_dissipation(mesh, float(c)))
 
 
 def stdg_residual_apply(mesh, dt, prec, mode, x, load, y, stream=None):

@@ -116,6 +116,7 @@ def lib():
             "stdg_mesh_info": ([vp, ctypes.POINTER(MeshInfo)], ctypes.c_int),
             "stdg_mesh_offsets": ([vp, vp, vp, vp], ctypes.c_int),
             "stdg_mesh_free": ([vp], ctypes.c_int),
+            "stdg_mesh_set_dissipation": ([vp, dbl], ctypes.c_int),
             "stdg_residual_apply": ([vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
             "stdg_load_assemble": ([vp, ctypes.POINTER(Source), dbl, dbl, vp, vp], ctypes.c_int),
             "stdg_project_modes": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),

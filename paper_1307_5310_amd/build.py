@@ -2,8 +2,8 @@
 
 Every call recompiles every source (objects go to ``_build/`` next to this
 file; the library is ``libstdg.so`` in this package directory).  The residual
-kernels are compiled once per (precision, a = p + 1, affine or trilinear) slice so the slices build
-in parallel.
+kernels are compiled once per (precision, a = p + 1, affine or trilinear, with or
+without the dissipative face terms) slice so the slices build in parallel.
 """
 import os
 import shutil
@@ -18,7 +18,9 @@ LIB = os.path.join(HERE, "libstdg.so")
 
 HOST_SOURCES = ["api.cpp", "mesh.cpp", "tables.cpp", "solver.cpp", "serve.cpp"]
 HIP_SOURCES = ["residual.hip", "blas.hip", "krylov.hip", "load.hip"]
-SLICES = [(real, a, aff) for real in ("float", "double") for a in range(2, 10) for aff in (1, 0)]
+# (precision, a, affine, dissipative): the dissipative variants exist for affine elements only
+SLICES = [(real, a, aff, 0) for real in ("float", "double") for a in range(2, 10) for aff in (1, 0)] + \
+         [(real, a, 1, 1) for real in ("float", "double") for a in range(2, 10)]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -52,10 +54,10 @@ def build(jobs=None, verbose=False):
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmds.append([hipcc] + COMMON + lang + ["-c", path, "-o", obj])
         objs.append(obj)
-    for real, a, aff in SLICES:
-        obj = os.path.join(BUILD, "residual_%s_a%d_%s.o" % (real, a, "aff" if aff else "tri"))
+    for real, a, aff, diss in SLICES:
+        obj = os.path.join(BUILD, "residual_%s_a%d_%s%s.o" % (real, a, "aff" if aff else "tri", "_diss" if diss else ""))
         cmds.append([hipcc] + COMMON + ["-x", "hip", "-DSTDG_REAL=%s" % real, "-DSTDG_A=%d" % a,
-                                        "-DSTDG_AFF=%d" % aff,
+                                        "-DSTDG_AFF=%d" % aff, "-DSTDG_DISS=%d" % diss,
                                         "-c", os.path.join(CSRC, "residual_inst.hip"), "-o", obj])
         objs.append(obj)
     jobs = jobs or min(16, os.cpu_count() or 4)

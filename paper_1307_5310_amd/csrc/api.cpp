@@ -153,6 +153,12 @@ int stdg_mesh_offsets(const stdg_mesh* mesh, int64_t* trial_off, int64_t* unknow
   return STDG_OK;
 }
 
+int stdg_mesh_set_dissipation(stdg_mesh* mesh, double c) {
+  if (!mesh) return fail(STDG_E_ARG, "stdg_mesh_set_dissipation: mesh is NULL");
+  STDG_HIP(hipSetDevice(mesh->m.ctx->device));
+  return stdg::set_dissipation(&mesh->m, c);
+}
+
 int stdg_mesh_free(stdg_mesh* mesh) {
   if (!mesh) return fail(STDG_E_ARG, "stdg_mesh_free: mesh is NULL");
   release_mesh(&mesh->m);

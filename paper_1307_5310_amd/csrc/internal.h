@@ -127,6 +127,14 @@ struct Mesh {
   // scratch for preconditioned applies on non-diagonal meshes (lazily sized)
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;
+  // dissipative stabilisation D_h (c = 0: off): per element kDissWords doubles,
+  //   [g]      alpha_E of face g        [6 + g]  alpha_H of face g (0 on PEC faces)
+  //   [12 + 3 alpha + (0, 1, 2)] = K_aa, K_bb, K_ab of the faces normal to alpha,
+  // K = |t_a x t_b| g^{-1} the face metric of the tangent vectors t_a, t_b along
+  // the axes (alpha + 1) % 3, (alpha + 2) % 3 (constant on affine elements)
+  static constexpr int kDissWords = 24;
+  double c_diss = 0.0;
+  double* d_diss = nullptr;
 };
 
 // Kernel launchers (residual.hip).
@@ -151,6 +159,7 @@ int upload_mesh(Ctx* ctx, Mesh* m);
 int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m);
 void release_mesh(Mesh* m);
 size_t mesh_device_bytes(const Mesh& m);
+int set_dissipation(Mesh* m, double c);
 
 // Allocation against the context budget.
 int dev_alloc(Ctx* ctx, void** p, size_t bytes);

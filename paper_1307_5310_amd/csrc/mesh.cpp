@@ -345,6 +345,69 @@ int upload_mesh(Ctx* ctx, Mesh* m) {
   return STDG_OK;
 }
 
+// Coefficients of D_h (the dissipative remark closing Section 4) for affine
+// meshes: alpha_E = c / {sqrt(mu / eps)}, alpha_H = c / {sqrt(eps / mu)} per face
+// (the mean of both sides, the element's own value on PEC faces, where only the
+// E term exists), and per axis the face metric K that turns the physical
+// integral of (n x v) . (n x u) into sum K_cd v_c u_d over the reference face.
+int set_dissipation(Mesh* m, double c) {
+  if (!(c >= 0.0) || !std::isfinite(c)) return fail(STDG_E_ARG, "dissipation coefficient must be finite and >= 0");
+  if (c > 0.0 && m->n_nonaffine > 0)
+    return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation needs affine elements (constant face metric)");
+  const size_t bytes = sizeof(double) * Mesh::kDissWords * m->ne;
+  if (c == 0.0) {
+    if (m->d_diss) {
+      dev_free(m->ctx, m->d_diss, bytes);
+      m->device_bytes -= bytes;
+    }
+    m->d_diss = nullptr;
+    m->c_diss = 0.0;
+    return STDG_OK;
+  }
+  std::vector<double> h((size_t)Mesh::kDissWords * m->ne, 0.0);
+  for (int64_t e = 0; e < m->ne; ++e) {
+    double* o = h.data() + (size_t)Mesh::kDissWords * e;
+    const ElemMetric& M = m->metric[e];
+    const double ze = std::sqrt(M.mu / M.eps), zh = std::sqrt(M.eps / M.mu);
+    for (int g = 0; g < 6; ++g) {
+      const int k = m->info[e].nb[g];
+      if (k < 0) {
+        o[g] = c / ze;
+        o[6 + g] = 0.0;
+      } else {
+        const ElemMetric& N = m->metric[k];
+        o[g] = c / (0.5 * (ze + std::sqrt(N.mu / N.eps)));
+        o[6 + g] = c / (0.5 * (zh + std::sqrt(N.eps / N.mu)));
+      }
+    }
+    const double* X = m->verts.data() + 24 * e;
+    double d[3][3];  // d[axis] = dF / dx-hat_axis (constant)
+    for (int ax = 0; ax < 3; ++ax)
+      for (int k = 0; k < 3; ++k) d[ax][k] = X[3 * (1 << ax) + k] - X[k];
+    for (int al = 0; al < 3; ++al) {
+      const double* ta = d[(al + 1) % 3];
+      const double* tb = d[(al + 2) % 3];
+      const double aa = ta[0] * ta[0] + ta[1] * ta[1] + ta[2] * ta[2];
+      const double bb = tb[0] * tb[0] + tb[1] * tb[1] + tb[2] * tb[2];
+      const double ab = ta[0] * tb[0] + ta[1] * tb[1] + ta[2] * tb[2];
+      const double cx = ta[1] * tb[2] - ta[2] * tb[1], cy = ta[2] * tb[0] - ta[0] * tb[2],
+                   cz = ta[0] * tb[1] - ta[1] * tb[0];
+      const double area = std::sqrt(cx * cx + cy * cy + cz * cz);
+      o[12 + 3 * al + 0] = bb / area;
+      o[12 + 3 * al + 1] = aa / area;
+      o[12 + 3 * al + 2] = -ab / area;
+    }
+  }
+  if (!m->d_diss) {
+    int rc = dev_alloc(m->ctx, (void**)&m->d_diss, bytes);
+    if (rc != STDG_OK) return rc;
+    m->device_bytes += bytes;
+  }
+  STDG_HIP(hipMemcpy(m->d_diss, h.data(), bytes, hipMemcpyHostToDevice));
+  m->c_diss = c;
+  return STDG_OK;
+}
+
 int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m) {
   m->ctx = ctx;
   int rc = build_mesh_host(d, m);
@@ -372,6 +435,9 @@ void release_mesh(Mesh* m) {
     if (g.d_list && ctx) dev_free(ctx, g.d_list, sizeof(int32_t) * g.count);
   if (m->d_scratch) dev_free(ctx, m->d_scratch, m->scratch_bytes);
   if (m->d_state_off) dev_free(ctx, m->d_state_off, sizeof(int64_t) * (m->ne + 1));
+  if (m->d_diss) dev_free(ctx, m->d_diss, sizeof(double) * Mesh::kDissWords * m->ne);
+  m->d_diss = nullptr;
+  m->c_diss = 0.0;
   m->d_state_off = nullptr;
   m->d_info = nullptr;
   m->d_metric = nullptr;

@@ -13,6 +13,8 @@ STDG_DECL_ALL(affine_, float)
 STDG_DECL_ALL(affine_, double)
 STDG_DECL_ALL(trilinear_, float)
 STDG_DECL_ALL(trilinear_, double)
+STDG_DECL_ALL(affine_diss_, float)
+STDG_DECL_ALL(affine_diss_, double)
 #undef STDG_DECL_ALL
 #undef STDG_DECL
 
@@ -26,6 +28,8 @@ static Launcher<float> affine_f32[kMaxA + 1] = STDG_TABLE(affine_, float);
 static Launcher<double> affine_f64[kMaxA + 1] = STDG_TABLE(affine_, double);
 static Launcher<float> trilinear_f32[kMaxA + 1] = STDG_TABLE(trilinear_, float);
 static Launcher<double> trilinear_f64[kMaxA + 1] = STDG_TABLE(trilinear_, double);
+static Launcher<float> affine_diss_f32[kMaxA + 1] = STDG_TABLE(affine_diss_, float);
+static Launcher<double> affine_diss_f64[kMaxA + 1] = STDG_TABLE(affine_diss_, double);
 #undef STDG_TABLE
 
 static int ensure_aux(Mesh* m) {
@@ -51,6 +55,7 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
   P.load = load;
   P.y = y;
   P.verts = m->d_verts;
+  P.diss = m->d_diss;
   P.dt = (T)dt;
   P.mode = mode;
   if constexpr (sizeof(T) == 8) fill_tables_f64(&P.tab); else fill_tables_f32(&P.tab);
@@ -59,6 +64,8 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
     if (g.count == 0) continue;
     if (!g.affine && mode == STDG_OPERATOR_PRECOND)
       return fail(STDG_E_UNSUPPORTED, "trilinear elements take P^{-1} in a separate pass");
+    if (!g.affine && m->d_diss)
+      return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation needs affine elements");
     order.push_back(&g);
   }
   auto work = [](const Group* g) { return g->count * (int64_t)g->q * g->a * g->a * g->a * (g->affine ? 1 : 3); };
@@ -120,11 +127,12 @@ int launch_residual(const ApplyArgs& a) {
     x = mm->d_scratch;
     mode = STDG_OPERATOR;
   }
+  const bool diss = m->d_diss != nullptr;
   if (a.prec == STDG_FP64)
     return run_groups<double>(m, a.dt, mode, (const double*)x, (const double*)a.load, (double*)a.y, a.stream,
-                              affine_f64, trilinear_f64, (const QTables<double>*)m->d_qt64);
-  return run_groups<float>(m, a.dt, mode, (const float*)x, (const float*)a.load, (float*)a.y, a.stream, affine_f32,
-                           trilinear_f32, (const QTables<float>*)m->d_qt32);
+                              diss ? affine_diss_f64 : affine_f64, trilinear_f64, (const QTables<double>*)m->d_qt64);
+  return run_groups<float>(m, a.dt, mode, (const float*)x, (const float*)a.load, (float*)a.y, a.stream,
+                           diss ? affine_diss_f32 : affine_f32, trilinear_f32, (const QTables<float>*)m->d_qt32);
 }
 
 }  // namespace stdg

@@ -1,7 +1,8 @@
 // One (precision, a, element kind) slice of the residual kernels: instantiates
 // q = 1..6 and exposes a launcher.  Compiled once per (STDG_REAL, STDG_A,
-// STDG_AFF) by the build; STDG_AFF = 1 for affine elements (constant metric),
-// 0 for trilinear ones (mass by quadrature, no fused P^{-1}).
+// STDG_AFF, STDG_DISS) by the build; STDG_AFF = 1 for affine elements (constant
+// metric), 0 for trilinear ones (mass by quadrature, no fused P^{-1});
+// STDG_DISS = 1 adds the dissipative face terms (affine elements only).
 #include "residual_kernel.h"
 
 #ifndef STDG_A
@@ -14,9 +15,18 @@
 #error "STDG_AFF must be defined"
 #endif
 
+#ifndef STDG_DISS
+#define STDG_DISS 0
+#endif
+#if STDG_DISS && !STDG_AFF
+#error "the dissipative kernels are built for affine elements only"
+#endif
+
 #define STDG_CAT2(a, b) a##b
 #define STDG_CAT(a, b) STDG_CAT2(a, b)
-#if STDG_AFF
+#if STDG_DISS
+#define STDG_KIND affine_diss_
+#elif STDG_AFF
 #define STDG_KIND affine_
 #else
 #define STDG_KIND trilinear_
@@ -26,23 +36,23 @@ namespace stdg {
 
 template <int QQ, int MODE>
 static constexpr size_t shmem_bytes() {
-  return sizeof(STDG_REAL) * KCfg<STDG_A>::template lds_elems<STDG_REAL, QQ, (bool)STDG_AFF, MODE>();
+  return sizeof(STDG_REAL) * KCfg<STDG_A>::template lds_elems<STDG_REAL, QQ, (bool)STDG_AFF, MODE, (bool)STDG_DISS>();
 }
 
 template <int QQ>
 static int launch_q(const KParams<STDG_REAL>& P, dim3 grid, dim3 block, hipStream_t stream) {
   switch (P.mode) {
     case 0:
-      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 0, (bool)STDG_AFF>), grid, block, (shmem_bytes<QQ, 0>()),
+      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 0, (bool)STDG_AFF, (bool)STDG_DISS>), grid, block, (shmem_bytes<QQ, 0>()),
                          stream, P);
       break;
     case 1:
-      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 1, (bool)STDG_AFF>), grid, block, (shmem_bytes<QQ, 1>()),
+      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 1, (bool)STDG_AFF, (bool)STDG_DISS>), grid, block, (shmem_bytes<QQ, 1>()),
                          stream, P);
       break;
     default:
 #if STDG_AFF
-      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 2, true>), grid, block, (shmem_bytes<QQ, 2>()), stream,
+      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 2, true, (bool)STDG_DISS>), grid, block, (shmem_bytes<QQ, 2>()), stream,
                          P);
       break;
 #else

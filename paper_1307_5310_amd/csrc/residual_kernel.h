@@ -27,6 +27,16 @@
 //   R_H[c] -= sigma eps(c,d,alpha) L_{s_alpha}(side) G_d,  d = 3 - c - alpha.
 // Faces with different p couple only the tangential modes < min(a, a').
 //
+// Dissipative stabilisation D_h (the remark closing Section 4), affine
+// elements only (DISS kernels): with the time-contracted tangential jumps
+// J_c = T_self(U_c) - T_nb(U_c) (T_self alone on PEC faces; zero on interior
+// faces for i >= min(q, q'), where the projected test function vanishes)
+//   R_E[c] += alpha_E L_{s_alpha}(side) sum_d K_cd J_d(E),
+//   R_H[c] += alpha_H L_{s_alpha}(side) sum_d K_cd J_d(H)   (interior faces only)
+// over the four faces whose normal is not c; K = |t_a x t_b| g^{-1} is the
+// constant metric of the face, so the physical (n x v) . (n x u) becomes
+// sum K_cd v_c u_d for covariant reference components.
+//
 // Work layout: NT = a^3 rounded up to a multiple of 64 threads per element.
 // Thread s owns spatial position s: all 6 components and all time levels in
 // registers, so the time contraction, the mass term, the loads and the stores
@@ -53,10 +63,12 @@ struct KCfg {
   static constexpr int NT = ((A3 + 63) / 64) * 64;  // one spatial position per thread
   static constexpr int NF = 4 * A2;                 // face items per face
   static constexpr int ND = A / 2;                  // odd offsets 1, 3, .. < A
-  static constexpr int LVL = 6 * A3 + 24 * A2;      // staged level: E~', H~' then fluxes
-  template <typename T, int Q, bool AFF = true>
+  // staged level: E~', H~' then the fluxes (and with D_h the tangential jumps)
+  static constexpr int lvl(bool diss) { return 6 * A3 + (diss ? 48 : 24) * A2; }
+  static constexpr int LVL = lvl(false);
+  template <typename T, int Q, bool AFF = true, bool DISS = false>
   static constexpr int LC() {  // test levels staged per LDS pass (about 16 KB; one for trilinear elements)
-    constexpr int c = AFF ? 16384 / (LVL * (int)sizeof(T)) : 1;
+    constexpr int c = AFF ? 16384 / (lvl(DISS) * (int)sizeof(T)) : 1;
     return c < 1 ? 1 : (c > Q ? Q : c);
   }
   // FP32 neighbour blocks are staged through LDS a face at a time (4
@@ -73,19 +85,19 @@ struct KCfg {
   static constexpr int MASS_A = 6 * A * G2, MASS = MASS_A + 6 * G3;  // two sweep buffers, both fields
   static constexpr int QTAB = GQ * A;                                // sqrt(w_g) L_j(x_g)
   static constexpr int QTAB_PAD = (QTAB + 3) & ~3;
-  template <typename T, int Q, bool AFF, int MODE>
+  template <typename T, int Q, bool AFF, int MODE, bool DISS = false>
   static constexpr int main_elems() {
     // staged contracted levels, or (aliased, used earlier) the staging
     // buffers, or (aliased) the mass sweep buffers
     constexpr int NL = levels(Q, MODE);
-    constexpr int a = LC<T, Q, AFF>() * LVL, b = stage<T, Q>() ? 2 * 4 * NL * A3 : 0;
+    constexpr int a = LC<T, Q, AFF, DISS>() * lvl(DISS), b = stage<T, Q>() ? 2 * 4 * NL * A3 : 0;
     constexpr int ab = a > b ? a : b;
     return AFF ? ab : (ab > MASS ? ab : MASS);
   }
-  template <typename T, int Q, bool AFF, int MODE>
+  template <typename T, int Q, bool AFF, int MODE, bool DISS = false>
   static constexpr int lds_elems() {
     // trilinear elements add the quadrature table and the metric at the points
-    return main_elems<T, Q, AFF, MODE>() + (AFF ? 0 : QTAB_PAD + 6 * G3);
+    return main_elems<T, Q, AFF, MODE, DISS>() + (AFF ? 0 : QTAB_PAD + 6 * G3);
   }
 };
 
@@ -99,6 +111,7 @@ struct KParams {
   T* y;
   const double* verts;    // [ne][8][3] (trilinear elements)
   const QTables<T>* qt;   // mass rule of this group's a (trilinear elements)
+  const double* diss;     // D_h coefficients per element (dissipative kernels)
   T dt;
   int mode;  // kept for launch bookkeeping; the kernels take the mode as a template argument
   Tables<T> tab;
@@ -302,11 +315,12 @@ __device__ __forceinline__ void trilinear_mass(T* __restrict__ bufA, T* __restri
   }
 }
 
-template <typename T, int A, int Q, int MODE, bool AFF>
+template <typename T, int A, int Q, int MODE, bool AFF, bool DISS = false>
 __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   using C = KCfg<A>;
-  constexpr int A2 = C::A2, A3 = C::A3, NF = C::NF, ND = C::ND, LVL = C::LVL;
-  constexpr int LC = C::template LC<T, Q, AFF>();
+  constexpr int A2 = C::A2, A3 = C::A3, NF = C::NF, ND = C::ND, LVL = C::lvl(DISS);
+  constexpr int LC = C::template LC<T, Q, AFF, DISS>();
+  static_assert(AFF || !DISS, "the dissipative terms need the constant face metric of affine elements");
   constexpr bool resid = MODE == 1, pre = MODE == 2;  // operator / residual / operator with P^{-1}
   constexpr bool kSelectCurl = sizeof(T) == 4 && A >= 7;
   static_assert(AFF || !pre, "trilinear elements take P^{-1} in a separate pass");
@@ -538,7 +552,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   const T winv = T(1) / w;
 
   // trilinear elements: quadrature table and the metric at the points, in LDS
-  T* qB = sm + C::template main_elems<T, Q, AFF, MODE>();
+  T* qB = sm + C::template main_elems<T, Q, AFF, MODE, DISS>();
   T* Gl = qB + C::QTAB_PAD;
   T keps = T(0), kmu = T(0);
   if constexpr (!AFF) {
@@ -554,6 +568,21 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   const T iuv = T(1) / (dsqrt<T>(T(2 * fu + 1)) * dsqrt<T>(T(2 * fv + 1)));
   const int tgt[3] = {sidx[1] + A * sidx[2], sidx[0] + A * sidx[2], sidx[0] + A * sidx[1]};
   constexpr int stride[3] = {1, A, A2};
+
+  // D_h coefficients (uniform): alpha_E, alpha_H per face, face metric per axis
+  T dE[6], dH[6], Kx[3][3];
+  if constexpr (DISS) {
+    const double* dc = P.diss + (int64_t)Mesh::kDissWords * e;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+      dE[g] = (T)dc[g];
+      dH[g] = (T)dc[6 + g];
+    }
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Kx[al][k] = (T)dc[12 + 3 * al + k];
+  }
 
   const T dt = P.dt;
   const bool has_load = resid && P.load != nullptr;
@@ -642,6 +671,14 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
             T val = (tf == 0 ? -ws : ws) * iuv * (side ? s1 : s0);  // G = -w T(E), F = w T(H)
             if (has) val += T(0.5) * acc[g][i];
             sm[ii * LVL + 6 * A3 + (g * 4 + tc) * A2 + t] = val;
+            if constexpr (DISS) {
+              // tangential jump own - neighbour of this component; on interior
+              // faces rows i >= min(q, q') vanish (D_h tests with the function
+              // projected onto the common temporal test space)
+              const T own = iuv * (side ? s1 : s0);
+              const T jmp = !has ? own : (i < nb_q[g] ? own - acc[g][i] : T(0));
+              sm[ii * LVL + 6 * A3 + 24 * A2 + (g * 4 + tc) * A2 + t] = jmp;
+            }
           }
         }
       }
@@ -717,7 +754,27 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
               }
               mass = symget(Mm, c, 0) * v0 + symget(Mm, c, 1) * v1 + symget(Mm, c, 2) * v2;
             }
-            T out = mass + dt * (cu + lift);
+            // D_h: sum over the four faces whose normal is not c of
+            // alpha_f L_{s_alpha}(side) (K jump)_c, jumps of field f itself
+            T dl = T(0);
+            if constexpr (DISS) {
+              const T* Dl = Fl + 24 * A2;
+              const T* al = f == 0 ? dE : dH;
+#pragma unroll
+              for (int wv = 0; wv < 2; ++wv) {
+                const int alpha = wv == 0 ? c1 : c2;
+                const int ka = c == (alpha + 1) % 3 ? 0 : 1;  // slot of component c on faces normal to alpha
+                const int sd = 2 * f + ka, sx = 2 * f + 1 - ka;
+                const T kd = Kx[alpha][ka], ko = Kx[alpha][2];
+                const T* d0 = Dl + (2 * alpha) * 4 * A2 + tgt[alpha];
+                const T* d1 = Dl + (2 * alpha + 1) * 4 * A2 + tgt[alpha];
+                const T j0 = kd * d0[sd * A2] + ko * d0[sx * A2];
+                const T j1 = kd * d1[sd * A2] + ko * d1[sx * A2];
+                // L_l(1) = rho_l, L_l(0) = (-1)^l rho_l
+                dl += rsm[alpha] * (al[2 * alpha + 1] * j1 + sg[alpha] * al[2 * alpha] * j0);
+              }
+            }
+            T out = mass + dt * (cu + lift + dl);
             const uint32_t o = so + (uint32_t)((((3 * f + c) * Q + i) * A3) * (int)sizeof(T));
             if (has_load) out -= buf_load<T>(lrs, o);
             buf_store<T>(out, yrs, o);
