@@ -49,6 +49,7 @@ def parse():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-graded", action="store_true", help="skip the graded trilinear 24^3 leg")
     ap.add_argument("--no-large", action="store_true", help="skip the 48^3 p=6 q=4 leg")
+    ap.add_argument("--no-diss", action="store_true", help="skip the dissipative (D_h, c = 1) leg")
     ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the Poisson serving stream (0 = skip the serving leg)")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
@@ -78,10 +79,10 @@ def time_applies(stdg, torch, mh, dt, prec, mode, x, y, steps, warmup):
     return wall, per
 
 
-def measured_traffic(prec):
-    """HBM bytes per launch of the timed kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current kernel
-    source (else None)."""
+def measured_traffic(prec, variant=""):
+    """HBM bytes per launch of the timed kernel (variant "dissipative_": the
+    kernel with D_h) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, if it was taken on the current kernel source (else None)."""
     import hashlib
     h = hashlib.sha256()
     for f in ("residual_kernel.h", "residual_inst.hip"):
@@ -93,7 +94,7 @@ def measured_traffic(prec):
     text = open(path).read()
     if ("sha256[:16] (residual_kernel.h + residual_inst.hip): " + h.hexdigest()[:16]) not in text:
         return None
-    key = "traffic_bytes_%s = " % ("fp32" if prec == 1 else "fp64")
+    key = "traffic_bytes_%s%s = " % (variant, "fp32" if prec == 1 else "fp64")
     for line in text.splitlines():
         if line.startswith(key):
             return float(line[len(key):])
@@ -194,6 +195,12 @@ def main():
         except Exception as e:  # solver reported separately; the apply line still prints
             log("slab solve skipped: %s" % e)
 
+    diss = None
+    if not args.no_diss:
+        log("dissipative stabilisation D_h, c = 1")
+        diss = time_dissipative(stdg, torch, mh, cfg, args, (("fp32", stdg.STDG_FP32, x32, y32),
+                                                            ("fp64", stdg.STDG_FP64, x64, y64)))
+
     graded = large = None
     if not args.no_graded:
         log("graded trilinear 24^3")
@@ -246,12 +253,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(1) if (args.n, args.p, args.q) == (32, 4, 3) else None,
-                     "kernel": "residual_kernel<float,5,3,2,true>", "kernel_ms": round(k32, 5),
+                     "kernel": "residual_kernel<float,5,3,2,true,false>", "kernel_ms": round(k32, 5),
                      "algorithmic_bytes": bytes32},
         "cpu_baseline": cpu,
     }
     if solve is not None:
         out["slab_solve"] = solve
+    if diss is not None:
+        out["dissipative"] = diss
     if graded is not None:
         out["graded_trilinear"] = graded
     if large is not None:
@@ -350,6 +359,52 @@ def _slab_with_source(stdg, torch, mh, info, cfg, inner, krylov):
     el = time.perf_counter() - t
     return {"s_per_slab": round(el, 4), "iters": r["iters"], "rel_res": r["rel_res"], "status": r["status"],
             "energy_end": r["energy_end"]}
+
+
+def time_dissipative(stdg, torch, mh, cfg, args, vecs, c=1.0):
+    """The headline workload with the dissipative stabilisation D_h switched on
+    (c = 1): the preconditioned apply in both precisions next to the plain one
+    (timed the same way, back to back), and one slab solve (FP32 applies with
+    FP64 refinement, FP32 basis) from the projected modes with its energy loss."""
+    a, q = args.p + 1, args.q
+    ne = cfg["mesh"].n_elements
+    trial = 6 * (q + 1) * a ** 3 * ne
+    dt = cfg["dt"]
+    mode = stdg.STDG_OPERATOR_PRECOND
+    out = {"c": c}
+    plain = {name: _time_mode(stdg, torch, mh, dt, prec, mode, x, y, args.steps, args.warmup)
+             for name, prec, x, y in vecs}
+    stdg.stdg_mesh_set_dissipation(mh, c)
+    try:
+        for name, prec, x, y in vecs:
+            ms = _time_mode(stdg, torch, mh, dt, prec, mode, x, y, args.steps, args.warmup)
+            sz = 4 if prec == stdg.STDG_FP32 else 8
+            bytes_ = (12 * q * a ** 3 + 24) * sz * ne  # + the 24 face coefficients per element
+            out[name] = {"apply_ms": round(ms, 5), "plain_apply_ms": round(plain[name], 5),
+                         "over_plain": round(ms / plain[name], 3),
+                         "gdof_per_s": round(trial / (ms * 1e-3) / 1e9, 2),
+                         "hbm_frac": round(bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "algorithmic_bytes": bytes_,
+                         "traffic": measured_traffic(prec, "dissipative_")
+                         if (args.n, args.p, args.q) == (32, 4, 3) else None}
+            log("dissipative %s: apply %.3f ms (plain %.3f ms)" % (name, ms, plain[name]))
+        info = stdg.stdg_mesh_info(mh)
+        modes = cfg["init"]
+        state = torch.zeros(info["state_size"], dtype=torch.float64, device="cuda")
+        stdg.stdg_project_modes(mh, modes.mnl, modes.abc, state)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = stdg.stdg_slab_solve(mh, 0.0, dt, None, state, inner_prec=stdg.STDG_FP32, rtol=1e-10, max_iters=3000,
+                                 max_refine=300, krylov_prec=stdg.STDG_FP32)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["slab_fp32_refine_fp32_basis"] = {
+            "s_per_solve": round(el, 4), "iters": r["iters"], "rel_res": r["rel_res"], "status": r["status"],
+            "energy_loss_rel": (r["energy_start"] - r["energy_end"]) / max(r["energy_start"], 1e-300)}
+        log("dissipative slab solve: %.3f s, %d iters" % (el, r["iters"]))
+    finally:
+        stdg.stdg_mesh_set_dissipation(mh, 0.0)
+    return out
 
 
 def time_graded(stdg, torch, ctx, steps, warmup):

@@ -146,8 +146,9 @@ int stdg_mesh_free(stdg_mesh* mesh);
  * the slab instead of being conserved.  c = 0 switches it off (the device
  * coefficients are freed).  Needs affine elements (constant face metric):
  * STDG_E_UNSUPPORTED if the mesh has trilinear ones and c > 0; STDG_E_ARG for
- * c < 0 or non-finite.  Synchronous (host to device copy of 192 bytes per
- * element); not to be called while work on the mesh is in flight. */
+ * c < 0 or non-finite.  Synchronous (host to device copy of 288 bytes per
+ * element: the coefficients in FP64 and FP32); not to be called while work on
+ * the mesh is in flight. */
 int stdg_mesh_set_dissipation(stdg_mesh* mesh, double c);
 
 /* The hot path: the matrix-free space-time residual of one slab (Section 5,

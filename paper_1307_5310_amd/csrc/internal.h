@@ -134,7 +134,8 @@ struct Mesh {
   // the axes (alpha + 1) % 3, (alpha + 2) % 3 (constant on affine elements)
   static constexpr int kDissWords = 24;
   double c_diss = 0.0;
-  double* d_diss = nullptr;
+  double* d_diss = nullptr;   // FP64 copy (FP64 kernels)
+  float* d_diss32 = nullptr;  // FP32 copy (FP32 kernels)
 };
 
 // Kernel launchers (residual.hip).

@@ -354,13 +354,15 @@ int set_dissipation(Mesh* m, double c) {
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(STDG_E_ARG, "dissipation coefficient must be finite and >= 0");
   if (c > 0.0 && m->n_nonaffine > 0)
     return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation needs affine elements (constant face metric)");
-  const size_t bytes = sizeof(double) * Mesh::kDissWords * m->ne;
+  const size_t bytes = sizeof(double) * Mesh::kDissWords * m->ne, bytes32 = sizeof(float) * Mesh::kDissWords * m->ne;
   if (c == 0.0) {
     if (m->d_diss) {
       dev_free(m->ctx, m->d_diss, bytes);
-      m->device_bytes -= bytes;
+      dev_free(m->ctx, m->d_diss32, bytes32);
+      m->device_bytes -= bytes + bytes32;
     }
     m->d_diss = nullptr;
+    m->d_diss32 = nullptr;
     m->c_diss = 0.0;
     return STDG_OK;
   }
@@ -401,9 +403,17 @@ int set_dissipation(Mesh* m, double c) {
   if (!m->d_diss) {
     int rc = dev_alloc(m->ctx, (void**)&m->d_diss, bytes);
     if (rc != STDG_OK) return rc;
-    m->device_bytes += bytes;
+    rc = dev_alloc(m->ctx, (void**)&m->d_diss32, bytes32);
+    if (rc != STDG_OK) {
+      dev_free(m->ctx, m->d_diss, bytes);
+      m->d_diss = nullptr;
+      return rc;
+    }
+    m->device_bytes += bytes + bytes32;
   }
+  std::vector<float> h32(h.begin(), h.end());
   STDG_HIP(hipMemcpy(m->d_diss, h.data(), bytes, hipMemcpyHostToDevice));
+  STDG_HIP(hipMemcpy(m->d_diss32, h32.data(), bytes32, hipMemcpyHostToDevice));
   m->c_diss = c;
   return STDG_OK;
 }
@@ -436,7 +446,9 @@ void release_mesh(Mesh* m) {
   if (m->d_scratch) dev_free(ctx, m->d_scratch, m->scratch_bytes);
   if (m->d_state_off) dev_free(ctx, m->d_state_off, sizeof(int64_t) * (m->ne + 1));
   if (m->d_diss) dev_free(ctx, m->d_diss, sizeof(double) * Mesh::kDissWords * m->ne);
+  if (m->d_diss32) dev_free(ctx, m->d_diss32, sizeof(float) * Mesh::kDissWords * m->ne);
   m->d_diss = nullptr;
+  m->d_diss32 = nullptr;
   m->c_diss = 0.0;
   m->d_state_off = nullptr;
   m->d_info = nullptr;

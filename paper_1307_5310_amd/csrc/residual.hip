@@ -55,7 +55,7 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
   P.load = load;
   P.y = y;
   P.verts = m->d_verts;
-  P.diss = m->d_diss;
+  if constexpr (sizeof(T) == 8) P.diss = m->d_diss; else P.diss = m->d_diss32;
   P.dt = (T)dt;
   P.mode = mode;
   if constexpr (sizeof(T) == 8) fill_tables_f64(&P.tab); else fill_tables_f32(&P.tab);

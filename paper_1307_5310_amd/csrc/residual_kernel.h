@@ -67,8 +67,10 @@ struct KCfg {
   static constexpr int lvl(bool diss) { return 6 * A3 + (diss ? 48 : 24) * A2; }
   static constexpr int LVL = lvl(false);
   template <typename T, int Q, bool AFF = true, bool DISS = false>
-  static constexpr int LC() {  // test levels staged per LDS pass (about 16 KB; one for trilinear elements)
-    constexpr int c = AFF ? 16384 / (lvl(DISS) * (int)sizeof(T)) : 1;
+  static constexpr int LC() {
+    // test levels staged per LDS pass: about 16 KB (24 KB with the D_h jumps,
+    // which keeps p = 4, q = 3 in one FP32 pass); one for trilinear elements
+    constexpr int c = AFF ? (DISS ? 24576 : 16384) / (lvl(DISS) * (int)sizeof(T)) : 1;
     return c < 1 ? 1 : (c > Q ? Q : c);
   }
   // FP32 neighbour blocks are staged through LDS a face at a time (4
@@ -111,7 +113,7 @@ struct KParams {
   T* y;
   const double* verts;    // [ne][8][3] (trilinear elements)
   const QTables<T>* qt;   // mass rule of this group's a (trilinear elements)
-  const double* diss;     // D_h coefficients per element (dissipative kernels)
+  const T* diss;          // D_h coefficients per element (dissipative kernels)
   T dt;
   int mode;  // kept for launch bookkeeping; the kernels take the mode as a template argument
   Tables<T> tab;
@@ -569,19 +571,14 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   const int tgt[3] = {sidx[1] + A * sidx[2], sidx[0] + A * sidx[2], sidx[0] + A * sidx[1]};
   constexpr int stride[3] = {1, A, A2};
 
-  // D_h coefficients (uniform): alpha_E, alpha_H per face, face metric per axis
-  T dE[6], dH[6], Kx[3][3];
+  // D_h coefficients (uniform, loaded once; read at their use they would be
+  // reloaded after every output store): alpha_E, alpha_H per face, face metric
+  // per axis
+  T dc[DISS ? Mesh::kDissWords : 1];
   if constexpr (DISS) {
-    const double* dc = P.diss + (int64_t)Mesh::kDissWords * e;
+    const T* src = P.diss + (int64_t)Mesh::kDissWords * e;
 #pragma unroll
-    for (int g = 0; g < 6; ++g) {
-      dE[g] = (T)dc[g];
-      dH[g] = (T)dc[6 + g];
-    }
-#pragma unroll
-    for (int al = 0; al < 3; ++al)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) Kx[al][k] = (T)dc[12 + 3 * al + k];
+    for (int k = 0; k < 21; ++k) dc[k] = src[k];
   }
 
   const T dt = P.dt;
@@ -759,13 +756,13 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
             T dl = T(0);
             if constexpr (DISS) {
               const T* Dl = Fl + 24 * A2;
-              const T* al = f == 0 ? dE : dH;
+              const T* al = dc + 6 * f;
 #pragma unroll
               for (int wv = 0; wv < 2; ++wv) {
                 const int alpha = wv == 0 ? c1 : c2;
                 const int ka = c == (alpha + 1) % 3 ? 0 : 1;  // slot of component c on faces normal to alpha
                 const int sd = 2 * f + ka, sx = 2 * f + 1 - ka;
-                const T kd = Kx[alpha][ka], ko = Kx[alpha][2];
+                const T kd = dc[12 + 3 * alpha + ka], ko = dc[12 + 3 * alpha + 2];
                 const T* d0 = Dl + (2 * alpha) * 4 * A2 + tgt[alpha];
                 const T* d1 = Dl + (2 * alpha + 1) * 4 * A2 + tgt[alpha];
                 const T j0 = kd * d0[sd * A2] + ko * d0[sx * A2];
