@@ -43,7 +43,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import basis
-from .geometry import face_topology, jacobian, map_point
+from .geometry import face_map, face_topology, jacobian, map_point
 
 LEVI = np.zeros((3, 3, 3))
 LEVI[0, 1, 2] = LEVI[1, 2, 0] = LEVI[2, 0, 1] = 1.0
@@ -176,14 +176,58 @@ def face_matrices(a, face, a_other=None, neighbour=False):
     return FE.reshape(3 * n3, 3 * m3), FH.reshape(3 * n3, 3 * m3)
 
 
-def dissipation_matrices(X, a, face, Xo=None, ao=None, nq=None):
+def face_matrices_oriented(a, face, ao, face_o, A, b):
+    """The neighbour face matrices of ``face_matrices`` for a neighbour met in
+    any orientation: its basis is evaluated on its own face ``face_o`` at the
+    points (u', v') = A (u, v) + b matched to K's face points, and its
+    covariant reference components are carried into K's frame along the
+    face, E-hat_{tau_i} = sum_j A[j, i] E-hat'_{tau'_j} (chain rule for the
+    tangent vectors of the shared face; the normal components do not enter
+    the fluxes).  Geometry-free like the canonical case; exact quadrature."""
+    alpha, side = divmod(face, 2)
+    tang = [d for d in range(3) if d != alpha]
+    alpha_o, side_o = divmod(face_o, 2)
+    tang_o = [d for d in range(3) if d != alpha_o]
+    n = max(a, ao) + 1
+    pts, w = face_points(face, n)
+    Phi, _ = basis_at(a, pts)
+    uv = pts[:, tang]
+    uvo = uv @ A.T + b[None, :]
+    pts_o = np.zeros_like(pts)
+    pts_o[:, alpha_o] = float(side_o)
+    pts_o[:, tang_o[0]] = uvo[:, 0]
+    pts_o[:, tang_o[1]] = uvo[:, 1]
+    Psi, _ = basis_at(ao, pts_o)
+    Cmap = np.zeros((3, 3))                      # K-frame component d <- neighbour component d'
+    for i in range(2):
+        for j in range(2):
+            Cmap[tang[i], tang_o[j]] = A[j, i]
+    nhat = (2.0 * side - 1.0) * EYE3[alpha]
+    Sface = (Phi * w[:, None]).T @ Psi
+    n3, m3 = a ** 3, ao ** 3
+    FE = np.zeros((3, n3, 3, m3))
+    FH = np.zeros((3, n3, 3, m3))
+    for c in range(3):
+        for d in range(3):
+            ed_x_n = np.cross(EYE3[d], nhat)[c]
+            n_x_ed = np.cross(nhat, EYE3[d])[c]
+            for dp in range(3):
+                if Cmap[d, dp] == 0.0:
+                    continue
+                FE[c, :, dp, :] += Cmap[d, dp] * ed_x_n * Sface
+                FH[c, :, dp, :] -= Cmap[d, dp] * n_x_ed * Sface
+    return FE.reshape(3 * n3, 3 * m3), FH.reshape(3 * n3, 3 * m3)
+
+
+def dissipation_matrices(X, a, face, Xo=None, ao=None, nq=None, face_o=None, fmap=None):
     """Face matrices of the dissipative stabilisation (the upwind-type remark
     after Section 4): with covariant basis functions u = DF^{-T} e_c phi_s,
       Dself[(c,s),(d,t)] = int_f (n x u_(c,s)) . (n x u_(d,t)) dS      (K's own trial)
       Dnb[(c,s),(d,t)]   = int_f (n x u_(c,s)) . (n x u'_(d,t)) dS     (neighbour trial)
     in physical space on local face (alpha, side) of K, n the unit normal,
-    u' the neighbour's basis of degree ao on its opposite face at the same
-    physical points (conforming, canonical orientation).  The face rule has
+    u' the neighbour's basis of degree ao on its face at the same physical
+    points (its opposite face at the same tangential coordinates, or face_o
+    through the face map fmap = (A, b) for other orientations).  The face rule has
     max(a, ao) + 2 Gauss points per direction unless nq is given: exact on
     affine elements, a quadrature of the rational integrand on trilinear ones."""
     alpha, side = divmod(face, 2)
@@ -207,7 +251,17 @@ def dissipation_matrices(X, a, face, Xo=None, ao=None, nq=None):
     Dself = np.tensordot(Aw, A, axes=([0, 2], [0, 2]))      # sum_p,k w A[p,a,k] A[p,b,k]
     if Xo is None:
         return Dself, None
-    pts_o, _ = face_points(opposite(face), n)
+    if fmap is None:
+        pts_o, _ = face_points(opposite(face), n)
+    else:
+        Am, bm = fmap
+        alpha_o, side_o = divmod(face_o, 2)
+        tang_o = [d for d in range(3) if d != alpha_o]
+        uvo = pts[:, tang] @ Am.T + bm[None, :]
+        pts_o = np.zeros_like(pts)
+        pts_o[:, alpha_o] = float(side_o)
+        pts_o[:, tang_o[0]] = uvo[:, 0]
+        pts_o[:, tang_o[1]] = uvo[:, 1]
     B = nx_basis(Xo, ao, pts_o)
     Dnb = np.tensordot(Aw, B, axes=([0, 2], [0, 2]))
     return Dself, Dnb
@@ -236,9 +290,13 @@ class Discretisation:
         self.eps = np.asarray(eps, dtype=np.float64)
         self.mu = np.asarray(mu, dtype=np.float64)
         self.ne = self.hexes.shape[0]
-        self.nb, self.nbf, canon = face_topology(self.hexes)
-        if not canon.all():
-            raise ValueError("only conforming faces in canonical orientation are supported")
+        self.nb, self.nbf, self.canon = face_topology(self.hexes)
+        # face maps of the interior faces met in another orientation
+        self.fmap = {}
+        for e in range(self.hexes.shape[0]):
+            for f in range(6):
+                if self.nb[e, f] >= 0 and not self.canon[e, f]:
+                    self.fmap[(e, f)] = face_map(self.hexes[e], f, self.hexes[self.nb[e, f]], int(self.nbf[e, f]))
         self.mass_nq = mass_nq
         self.c_diss = float(c_diss)  # dissipative stabilisation D_h, c >= 0 (0 = off)
         a3 = self.a ** 3
@@ -324,7 +382,14 @@ class Discretisation:
             _, Nc = self.tables(qe, qk)
             Nc = Nc.copy()
             Nc[min(qe, qk):, :] = 0.0            # S_h: neighbour coupling only on common test modes
-            FE, FH = self.face(a, f, ak, neighbour=True)
+            if (e, f) in self.fmap:
+                A, b = self.fmap[(e, f)]
+                key = ("FO", a, f, ak, int(self.nbf[e, f]), tuple(A.ravel()), tuple(b))
+                if key not in self._cache:
+                    self._cache[key] = face_matrices_oriented(a, f, ak, int(self.nbf[e, f]), A, b)
+                FE, FH = self._cache[key]
+            else:
+                FE, FH = self.face(a, f, ak, neighbour=True)
             out.append((k, dt * Nc, 0.5 * FE, 0, 1))
             out.append((k, dt * Nc, -0.5 * FH, 1, 0))
         if self.c_diss > 0.0:
@@ -348,10 +413,14 @@ class Discretisation:
             # cached by the shape of the pair (translation invariant)
             Xk = None if k < 0 else self.X(k)
             ak = None if k < 0 else int(self.a[k])
+            fm = self.fmap.get((e, f))
             key = ("D", a, ak, f, tuple(np.round((Xe - Xe[0]).ravel(), 14)),
-                   None if Xk is None else tuple(np.round((Xk - Xe[0]).ravel(), 14)))
+                   None if Xk is None else tuple(np.round((Xk - Xe[0]).ravel(), 14)),
+                   None if fm is None else (int(self.nbf[e, f]), tuple(fm[0].ravel()), tuple(fm[1])))
             if key not in self._cache:
-                self._cache[key] = dissipation_matrices(Xe, a, f, Xk, ak, nq=self.mass_nq)
+                self._cache[key] = dissipation_matrices(Xe, a, f, Xk, ak, nq=self.mass_nq,
+                                                        face_o=None if fm is None else int(self.nbf[e, f]),
+                                                        fmap=fm)
             return self._cache[key]
 
         for f in range(6):

@@ -105,6 +105,27 @@ def face_topology(hexes):
     return nb, nbf, canonical
 
 
+def face_map(hexrow, face, hexrow_o, face_o):
+    """Map between the reference coordinates of a shared face: (u', v') =
+    A (u, v) + b takes the tangential coordinates (u, v) of local face `face`
+    of one element (the two remaining axes in increasing order) to those of
+    local face `face_o` of its neighbour, found from the shared vertex ids.
+    On a conforming face it is a symmetry of the unit square (A a signed
+    permutation); canonical orientation is A = I, b = 0."""
+    mine = face_vertices(hexrow, face)
+    theirs = face_vertices(hexrow_o, face_o)
+    corner = {}
+    for j, g in enumerate(theirs):
+        corner[g] = np.array([j & 1, j >> 1], dtype=np.int64)
+    p00, p10, p01 = corner[mine[0]], corner[mine[1]], corner[mine[2]]
+    A = np.stack([p10 - p00, p01 - p00], axis=1)
+    b = p00.copy()
+    if sorted(np.abs(A).sum(axis=0).tolist()) != [1, 1] or abs(round(np.linalg.det(A))) != 1 or \
+            not np.array_equal(A @ np.array([1, 1]) + b, corner[mine[3]]):
+        raise ValueError("faces do not match as quadrilaterals")
+    return A, b
+
+
 def is_affine(X, tol=1e-12):
     """True when the trilinear map is affine (the hexahedron is a parallelepiped)."""
     x0 = X[0]

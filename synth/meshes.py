@@ -112,3 +112,39 @@ def affine_transform(vertices, A, b=(0.0, 0.0, 0.0)):
 def centroids(vertices, hexes):
     """Arithmetic mean of the 8 vertices of every element."""
     return vertices[hexes].mean(axis=1)
+
+
+def cube_rotations():
+    """The 24 proper rotations of the reference cube as permutations of its 8
+    corners: perm[v_new] = v_old, i.e. relabelling an element's vertices with
+    hexes[e] = hexes[e][perm] turns it without inverting it (each rotation is
+    a signed permutation of the centred axes with determinant +1)."""
+    import itertools
+    out = []
+    for axes in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            R = np.zeros((3, 3), dtype=np.int64)
+            for i in range(3):
+                R[i, axes[i]] = signs[i]
+            if round(np.linalg.det(R)) != 1:
+                continue
+            perm = []
+            for v in range(8):
+                s_new = np.array([2 * ((v >> d) & 1) - 1 for d in range(3)])
+                s_old = R @ s_new
+                perm.append(int(sum(((s_old[d] + 1) // 2) << d for d in range(3))))
+            out.append(perm)
+    return out
+
+
+def reorient(hexes, seed, frac=1.0):
+    """Relabel the vertices of a random fraction of the elements by random
+    cube rotations (seeded): the same physical mesh with faces met in every
+    orientation (axes swapped and reversed between neighbours)."""
+    rots = cube_rotations()
+    rng = np.random.default_rng(seed)
+    out = np.array(hexes, dtype=np.int64, copy=True)
+    for e in range(out.shape[0]):
+        if rng.random() < frac:
+            out[e] = out[e][rots[rng.integers(len(rots))]]
+    return out
