@@ -120,13 +120,15 @@ typedef struct {
   int64_t device_bytes;      /* device memory held by the mesh                  */
 } stdg_mesh_info_t;
 
-/* Build faces and neighbours (matching sorted vertex ids), check that every
- * interior face is conforming with canonical orientation (neighbour across
- * face (alpha, side) touches it with its face (alpha, 1 - side) and the same
- * vertex order; else STDG_E_UNSUPPORTED), classify elements as affine
- * (parallelepiped) or trilinear, group them by (p, q, affine), compute offsets
- * and copy everything to the device.  Faces on exactly one element are PEC
- * boundary faces. */
+/* Build faces and neighbours (matching sorted vertex ids), find how each
+ * neighbour meets the face (its local face and the symmetry of the square
+ * between the two faces' reference coordinates: any hex orientation is
+ * accepted; STDG_E_ARG if the shared vertices do not match as a
+ * quadrilateral), classify elements as affine (parallelepiped) or trilinear,
+ * group them by (p, q, affine), compute offsets and copy everything to the
+ * device.  Faces on exactly one element are PEC boundary faces (a face that
+ * is only partly shared, as at a hanging node, is therefore not supported:
+ * conforming meshes only). */
 int stdg_mesh_upload(stdg_ctx* ctx, const stdg_mesh_desc* desc, stdg_mesh** out);
 int stdg_mesh_info(const stdg_mesh* mesh, stdg_mesh_info_t* out);
 /* Host copies of the element offsets (n_elements + 1 entries each, any may be NULL). */

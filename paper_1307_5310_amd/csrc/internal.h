@@ -29,15 +29,26 @@ int hip_fail(hipError_t e, const char* what);
 enum : int32_t {
   kAffine = 1,        // parallelepiped: constant metric
   kDiagMass = 2,      // metric diagonal (axis-aligned box)
+  kPermuted = 4,      // some neighbour meets this element in another orientation
   kBoundaryBase = 8,  // bit 3 + f: face f is a PEC boundary face
 };
+
+// Orientation of interior face f as seen from its element (byte orient[f]):
+//   bits 0-2  the neighbour's local face f' (axis f' / 2, side f' % 2)
+//   bit 3     swap: our face coordinate u runs along the neighbour's v', v along u'
+//   bit 4     the neighbour coordinate matched with our u runs from 1 to 0
+//   bit 5     the same for our v
+// (u, v) are the two tangential reference axes of a face in increasing order.
+// Canonical orientation is f' = f ^ 1 with bits 3-5 clear.
+enum : uint8_t { kOrientSwap = 8, kOrientFlipU = 16, kOrientFlipV = 32 };
 
 // Per-element record read by the kernels (64 bytes).
 struct ElemInfo {
   int32_t a, q, flags, pad;
   int64_t trial_off, unk_off;
   int32_t nb[6];
-  int32_t pad2[2];
+  uint8_t orient[6];
+  uint8_t pad2[2];
 };
 static_assert(sizeof(ElemInfo) == 64, "ElemInfo layout");
 

@@ -1,4 +1,4 @@
-// Mesh builder: faces and neighbours, orientation check, affine detection,
+// Mesh builder: faces, neighbours and their orientations, affine detection,
 // metric coefficients, (p, q, affine) groups in locality order, offsets, and
 // the device copies (Section 2.2-2.4 of the paper: hexahedral triangulation,
 // covariant element maps, interior / boundary faces).
@@ -36,6 +36,42 @@ std::array<int, 4> face_local_vertices(int face) {
       out[n++] = b[0] + 2 * b[1] + 4 * b[2];
     }
   return out;
+}
+
+// Orientation byte (see ElemInfo) of face `face` of element `h` against face
+// `face_o` of its neighbour `ho`, from the vertex ids: corner (bu, bv) of our
+// face is matched with corner (bu', bv') of theirs; the match must be a
+// symmetry of the square.  Returns false if it is not.
+bool face_orientation(const int64_t* h, int face, const int64_t* ho, int face_o, uint8_t* out) {
+  auto lv = face_local_vertices(face), lo = face_local_vertices(face_o);
+  int cu[4], cv[4];
+  for (int k = 0; k < 4; ++k) {
+    int j = -1;
+    for (int l = 0; l < 4; ++l)
+      if (ho[lo[l]] == h[lv[k]]) j = l;
+    if (j < 0) return false;
+    cu[k] = j & 1;
+    cv[k] = j >> 1;
+  }
+  // corner k = bu + 2 bv of our face sits at (cu[k], cv[k]) on theirs
+  const bool swap = cu[1] == cu[0];  // moving along our u changes their v'
+  int flip_u, flip_v;
+  if (!swap) {
+    flip_u = cu[0];
+    flip_v = cv[0];
+  } else {
+    flip_u = cv[0];
+    flip_v = cu[0];
+  }
+  // check all four corners against the map
+  for (int k = 0; k < 4; ++k) {
+    const int bu = k & 1, bv = k >> 1;
+    const int ou = swap ? (bv ^ flip_v) : (bu ^ flip_u);
+    const int ov = swap ? (bu ^ flip_u) : (bv ^ flip_v);
+    if (cu[k] != ou || cv[k] != ov) return false;
+  }
+  *out = (uint8_t)(face_o | (swap ? kOrientSwap : 0) | (flip_u ? kOrientFlipU : 0) | (flip_v ? kOrientFlipV : 0));
+  return true;
 }
 
 struct FaceRec {
@@ -183,18 +219,18 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     } else if (j - i == 2) {
       const FaceRec &A = faces[i], &B = faces[i + 1];
       if (A.elem == B.elem) return fail(STDG_E_ARG, "element touches itself across a face");
-      bool ok = (A.face / 2 == B.face / 2) && (A.face % 2 != B.face % 2);
-      if (ok) {
-        auto la = face_local_vertices(A.face), lb = face_local_vertices(B.face);
-        for (int k = 0; k < 4; ++k)
-          if (d->hexes[8 * A.elem + la[k]] != d->hexes[8 * B.elem + lb[k]]) ok = false;
-      }
-      if (!ok)
-        return fail(STDG_E_UNSUPPORTED, "face between elements " + std::to_string(A.elem) + " and " +
-                                            std::to_string(B.elem) + " is not in canonical orientation");
       if (A.elem > INT32_MAX || B.elem > INT32_MAX) return fail(STDG_E_ARG, "too many elements");
+      uint8_t oa, ob;
+      if (!face_orientation(d->hexes + 8 * A.elem, A.face, d->hexes + 8 * B.elem, B.face, &oa) ||
+          !face_orientation(d->hexes + 8 * B.elem, B.face, d->hexes + 8 * A.elem, A.face, &ob))
+        return fail(STDG_E_ARG, "face between elements " + std::to_string(A.elem) + " and " +
+                                    std::to_string(B.elem) + " does not match as a quadrilateral");
       m->info[A.elem].nb[A.face] = (int32_t)B.elem;
       m->info[B.elem].nb[B.face] = (int32_t)A.elem;
+      m->info[A.elem].orient[A.face] = oa;
+      m->info[B.elem].orient[B.face] = ob;
+      if (oa != (uint8_t)(A.face ^ 1)) m->info[A.elem].flags |= kPermuted;
+      if (ob != (uint8_t)(B.face ^ 1)) m->info[B.elem].flags |= kPermuted;
       ++m->n_int_faces;
     } else {
       return fail(STDG_E_ARG, "non-manifold face shared by more than two elements");

@@ -26,6 +26,10 @@
 //   R_E[c] += sigma eps(c,d,alpha) L_{s_alpha}(side) F_d
 //   R_H[c] -= sigma eps(c,d,alpha) L_{s_alpha}(side) G_d,  d = 3 - c - alpha.
 // Faces with different p couple only the tangential modes < min(a, a').
+// A neighbour met in another orientation (its face f' and a symmetry of the
+// square between the face coordinates) is read on its own face, with its
+// covariant tangential components and face modes carried into this
+// element's frame by the signed permutation of the face map.
 //
 // Dissipative stabilisation D_h (the remark closing Section 4), affine
 // elements only (DISS kernels): with the time-contracted tangential jumps
@@ -347,7 +351,8 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   // neighbour table, uniform per block
   int nb_id[6], nb_a[6], nb_q[6];
   const T* nb_x[6];
-  bool fast = true;
+  // neighbours met in another orientation take the general face path
+  bool fast = (Ip->flags & kPermuted) == 0;
 #pragma unroll
   for (int g = 0; g < 6; ++g) {
     nb_id[g] = Ip->nb[g];
@@ -491,28 +496,43 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
       }
     }
   } else if (face_lane) {
-    // different degrees around this element: p-truncated coupling, and S_h
-    // drops the neighbour term on test levels i >= min(q, q')
+    // different degrees or orientations around this element: p-truncated
+    // coupling, S_h drops the neighbour term on test levels i >= min(q, q'),
+    // and a neighbour met in another orientation is read on its own face f'
+    // with its tangential axes mapped to ours: the covariant component along
+    // our axis is +-the neighbour's along the matched axis (minus where the
+    // axis runs reversed), and mode j along a reversed axis takes (-1)^j
+    // (L_j(1 - x) = (-1)^j L_j(x)).
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
-      const int alpha = g >> 1, side = g & 1;
+      const int alpha = g >> 1;
       if (nb_id[g] < 0) continue;
       const int c = (alpha + 1 + (tc & 1)) % 3;
-      const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
+      const int code = Ip->orient[g];
+      const int go = code & 7, ao = go >> 1, so = go & 1;
+      const bool swp = (code & kOrientSwap) != 0, flu = (code & kOrientFlipU) != 0, flv = (code & kOrientFlipV) != 0;
+      const int tu = alpha == 0 ? 1 : 0;                      // our u axis (v is the other one)
+      const int tuo = ao == 0 ? 1 : 0, tvo = ao == 2 ? 1 : 2;  // the neighbour's u', v' axes
+      const bool on_u = c == tu;
+      const int cn = on_u ? (swp ? tvo : tuo) : (swp ? tuo : tvo);
+      const int mu = swp ? fv : fu, mv = swp ? fu : fv;      // the neighbour's mode along u', v'
+      const bool neg = (on_u ? flu : flv) ^ (((flu ? fu : 0) + (flv ? fv : 0)) & 1);
+      const T scale = (pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + cn] : T(1)) * (neg ? T(-1) : T(1));
       const int na = nb_a[g], nq = nb_q[g];
       if (fu >= na || fv >= na) continue;
       const int na3 = na * na * na;
-      const int ns = face_stride(alpha, na);
+      const int ns = face_stride(ao, na);
       const int nnlev = resid ? nq + 1 : nq;
-      const T* xb = nb_x[g] + (int64_t)(3 * tf + c) * nnlev * na3 + face_base(alpha, fu, fv, na);
+      const T* xb = nb_x[g] + (int64_t)(3 * tf + cn) * nnlev * na3 + face_base(ao, mu, mv, na);
 #pragma unroll
       for (int mp = 0; mp <= kMaxQ; ++mp) {
         if (mp < m0 || mp > nq) continue;
         const T* xl = xb + (int64_t)(mp - m0) * na3;
         T tr = T(0);
+        // trace on the neighbour's face at side so: L_l(so)
         for (int l = 0; l < na; ++l) {
           const T rho = dsqrt<T>(T(2 * l + 1));
-          tr += ((side && (l & 1)) ? -rho : rho) * xl[l * ns];
+          tr += ((so == 0 && (l & 1)) ? -rho : rho) * xl[l * ns];
         }
         tr *= scale;
 #pragma unroll
