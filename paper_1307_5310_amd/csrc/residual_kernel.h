@@ -57,6 +57,8 @@
 // below its position and the H-test reads E components above it.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace stdg {
@@ -169,6 +171,33 @@ __device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc
 __host__ __device__ constexpr int face_stride(int alpha, int n) { return alpha == 0 ? 1 : (alpha == 1 ? n : n * n); }
 __device__ __forceinline__ int face_base(int alpha, int u, int v, int n) {
   return alpha == 0 ? n * u + n * n * v : (alpha == 1 ? u + n * n * v : u + n * v);
+}
+
+// How the neighbour across face (alpha, side) is read for this element's
+// tangential component c and face mode (fu, fv) (u, v: the two tangential
+// axes in increasing order), from the face's orientation byte: the
+// neighbour's face axis and side, its component along the axis matched with
+// ours, its mode along its (u', v') axes, and the sign: minus where the
+// matched axis runs reversed (covariant components follow the tangent
+// vector) times (-1)^j for mode j along each reversed axis (L_j(1 - x) =
+// (-1)^j L_j(x)).
+struct FaceMap {
+  int ax, so, cn, mu, mv;
+  bool neg;
+};
+__device__ __forceinline__ FaceMap map_face(int alpha, int code, int c, int fu, int fv) {
+  FaceMap m;
+  m.ax = (code & 7) >> 1;
+  m.so = code & 1;
+  const bool swp = (code & kOrientSwap) != 0, flu = (code & kOrientFlipU) != 0, flv = (code & kOrientFlipV) != 0;
+  const int tu = alpha == 0 ? 1 : 0;                          // our u axis (v is the other one)
+  const int tuo = m.ax == 0 ? 1 : 0, tvo = m.ax == 2 ? 1 : 2;  // the neighbour's u', v' axes
+  const bool on_u = c == tu;
+  m.cn = on_u ? (swp ? tvo : tuo) : (swp ? tuo : tvo);
+  m.mu = swp ? fv : fu;
+  m.mv = swp ? fu : fv;
+  m.neg = (on_u ? flu : flv) ^ ((((flu ? fu : 0) + (flv ? fv : 0)) & 1) != 0);
+  return m;
 }
 
 // Metric G = |J| DF^{-1} DF^{-T} of a trilinear map at the quadrature points
@@ -351,8 +380,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   // neighbour table, uniform per block
   int nb_id[6], nb_a[6], nb_q[6];
   const T* nb_x[6];
-  // neighbours met in another orientation take the general face path
-  bool fast = (Ip->flags & kPermuted) == 0;
+  bool fast = true;
 #pragma unroll
   for (int g = 0; g < 6; ++g) {
     nb_id[g] = Ip->nb[g];
@@ -397,7 +425,12 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) acc[g][i] = T(0);
 
-  if (fast && C::template stage<T, Q>()) {
+  // The two uniform-degree paths come in two forms: elements whose
+  // neighbours all meet them in canonical orientation (compile-time face
+  // axes, strides and components), and elements with a permuted face, whose
+  // neighbours are read on their own face f' through the face map.
+  auto staged = [&](auto perm_tag) __attribute__((always_inline)) {
+    constexpr bool PERM = decltype(perm_tag)::value;
     // Neighbour blocks are read with unit-stride (coalesced) loads - thread
     // tid takes entries tid, tid + NT, ... of each tangential component block -
     // for a batch of GB faces at once, then passed face by face through a
@@ -415,12 +448,13 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
         const int g = g0 + gg;
         if (g >= 6) break;
         if (nb_id[g] < 0) continue;
-        const int alpha = g >> 1;
+        // the neighbour's tangential blocks on its own face axis
+        const int ax = PERM ? ((Ip->orient[g] & 7) >> 1) : (g >> 1);
         const __amdgpu_buffer_rsrc_t rsrc =
             __builtin_amdgcn_make_buffer_rsrc((void*)nb_x[g], (short)0, BLK, 0x00020000);
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
-          const int fc = 3 * (q4 >> 1) + (alpha + 1 + (q4 & 1)) % 3;
+          const int fc = 3 * (q4 >> 1) + (ax + 1 + (q4 & 1)) % 3;
 #pragma unroll
           for (int k = 0; k < KC; ++k)
             nbv[gg][q4][k] = buf_load<T>(rsrc, (uint32_t)((fc * CH + k * C::NT) * (int)sizeof(T)) +
@@ -443,7 +477,8 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
             if (CH % C::NT == 0 || p < CH) stg[q4 * CH + p] = nbv[gg][q4][k];
           }
         __syncthreads();
-        if (face_lane) {
+        if (!face_lane) continue;
+        if constexpr (!PERM) {
           const int c = (alpha + 1 + (tc & 1)) % 3;
           const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
           const int ns = face_stride(alpha, A);
@@ -460,41 +495,70 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
             for (int i = 0; i < Q; ++i)
               if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
           }
+        } else {
+          // the neighbour's face f' at the mapped mode, matched component and sign
+          const FaceMap fm = map_face(alpha, Ip->orient[g], (alpha + 1 + (tc & 1)) % 3, fu, fv);
+          const int slot = 2 * tf + (fm.cn == (fm.ax + 1) % 3 ? 0 : 1);
+          const T scale = (pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + fm.cn] : T(1)) * (fm.neg ? T(-1) : T(1));
+          const int ns = face_stride(fm.ax, A);
+          const T* src = stg + slot * CH + face_base(fm.ax, fm.mu, fm.mv, A);
+#pragma unroll
+          for (int ml = 0; ml < NL; ++ml) {
+            const int mp = ml + m0;
+            T tr = T(0);
+#pragma unroll
+            for (int l = 0; l < A; ++l) tr += (fm.so ? P.tab.tr1[l] : P.tab.tr0[l]) * src[ml * A3 + l * ns];
+            tr *= scale;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+              if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
+          }
         }
       }
     }
     __syncthreads();  // staging area is reused for the contracted levels
-  } else if (fast) {
-    // faces too large to stage: gather each face item straight from global
-    // memory (one buffer descriptor per face, compile-time immediates)
+  };
+  // faces too large to stage: gather each face item straight from global
+  // memory (one buffer descriptor per face, compile-time immediates)
+  auto gathered = [&](auto perm_tag) __attribute__((always_inline)) {
+    constexpr bool PERM = decltype(perm_tag)::value;
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
       if (nb_id[g] < 0) continue;
       const int alpha = g >> 1, side = g & 1;
       const int c = (alpha + 1 + (tc & 1)) % 3;
-      const int ns = face_stride(alpha, A);
+      // canonical: the neighbour's face (alpha, 1 - side), same component and mode
+      FaceMap fm{alpha, 1 - side, c, fu, fv, false};
+      if constexpr (PERM) fm = map_face(alpha, Ip->orient[g], c, fu, fv);
+      const int ns = face_stride(fm.ax, A);
       const __amdgpu_buffer_rsrc_t rsrc =
           __builtin_amdgcn_make_buffer_rsrc((void*)nb_x[g], (short)0, BLK, 0x00020000);
-      const uint32_t lo = (uint32_t)(((3 * tf + c) * NL * A3 + face_base(alpha, fu, fv, A)) * (int)sizeof(T));
+      const uint32_t lo = (uint32_t)(((3 * tf + fm.cn) * NL * A3 + face_base(fm.ax, fm.mu, fm.mv, A)) * (int)sizeof(T));
       T vals[NL][A];
 #pragma unroll
       for (int ml = 0; ml < NL; ++ml)
 #pragma unroll
         for (int l = 0; l < A; ++l) vals[ml][l] = buf_load<T>(rsrc, lo + (uint32_t)((ml * A3 + l * ns) * (int)sizeof(T)));
       if (!face_lane) continue;
-      const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
+      const T scale = (pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + fm.cn] : T(1)) * (fm.neg ? T(-1) : T(1));
 #pragma unroll
       for (int ml = 0; ml < NL; ++ml) {
         const int mp = ml + m0;
         T tr = T(0);
 #pragma unroll
-        for (int l = 0; l < A; ++l) tr += (side ? P.tab.tr0[l] : P.tab.tr1[l]) * vals[ml][l];
+        for (int l = 0; l < A; ++l) tr += (fm.so ? P.tab.tr1[l] : P.tab.tr0[l]) * vals[ml][l];
         tr *= scale;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
           if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
       }
     }
+  };
+  const bool permuted = (Ip->flags & kPermuted) != 0;
+  if (fast && C::template stage<T, Q>()) {
+    if (permuted) staged(std::true_type{}); else staged(std::false_type{});
+  } else if (fast) {
+    if (permuted) gathered(std::true_type{}); else gathered(std::false_type{});
   } else if (face_lane) {
     // different degrees or orientations around this element: p-truncated
     // coupling, S_h drops the neighbour term on test levels i >= min(q, q'),
@@ -508,22 +572,15 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
       const int alpha = g >> 1;
       if (nb_id[g] < 0) continue;
       const int c = (alpha + 1 + (tc & 1)) % 3;
-      const int code = Ip->orient[g];
-      const int go = code & 7, ao = go >> 1, so = go & 1;
-      const bool swp = (code & kOrientSwap) != 0, flu = (code & kOrientFlipU) != 0, flv = (code & kOrientFlipV) != 0;
-      const int tu = alpha == 0 ? 1 : 0;                      // our u axis (v is the other one)
-      const int tuo = ao == 0 ? 1 : 0, tvo = ao == 2 ? 1 : 2;  // the neighbour's u', v' axes
-      const bool on_u = c == tu;
-      const int cn = on_u ? (swp ? tvo : tuo) : (swp ? tuo : tvo);
-      const int mu = swp ? fv : fu, mv = swp ? fu : fv;      // the neighbour's mode along u', v'
-      const bool neg = (on_u ? flu : flv) ^ (((flu ? fu : 0) + (flv ? fv : 0)) & 1);
-      const T scale = (pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + cn] : T(1)) * (neg ? T(-1) : T(1));
+      const FaceMap fm = map_face(alpha, Ip->orient[g], c, fu, fv);
+      const int so = fm.so;
+      const T scale = (pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + fm.cn] : T(1)) * (fm.neg ? T(-1) : T(1));
       const int na = nb_a[g], nq = nb_q[g];
       if (fu >= na || fv >= na) continue;
       const int na3 = na * na * na;
-      const int ns = face_stride(ao, na);
+      const int ns = face_stride(fm.ax, na);
       const int nnlev = resid ? nq + 1 : nq;
-      const T* xb = nb_x[g] + (int64_t)(3 * tf + cn) * nnlev * na3 + face_base(ao, mu, mv, na);
+      const T* xb = nb_x[g] + (int64_t)(3 * tf + fm.cn) * nnlev * na3 + face_base(fm.ax, fm.mu, fm.mv, na);
 #pragma unroll
       for (int mp = 0; mp <= kMaxQ; ++mp) {
         if (mp < m0 || mp > nq) continue;
