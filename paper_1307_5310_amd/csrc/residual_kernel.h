@@ -57,8 +57,6 @@
 // below its position and the H-test reads E components above it.
 #pragma once
 
-#include <type_traits>
-
 #include "internal.h"
 
 namespace stdg {
@@ -429,8 +427,17 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   // neighbours all meet them in canonical orientation (compile-time face
   // axes, strides and components), and elements with a permuted face, whose
   // neighbours are read on their own face f' through the face map.
-  auto staged = [&](auto perm_tag) __attribute__((always_inline)) {
-    constexpr bool PERM = decltype(perm_tag)::value;
+  // The two uniform-degree paths come in two forms: elements whose
+  // neighbours all meet them in canonical orientation (compile-time face
+  // axes, strides and components), and, for affine kernels, elements with a
+  // permuted face, whose neighbours are read on their own face f' through
+  // the face map.  Trilinear kernels send permuted elements down the general
+  // path.  (Written out rather than as one generic lambda: the lambda form
+  // cost the trilinear kernels up to 57 VGPRs and an occupancy step.)
+  const bool permuted = (Ip->flags & kPermuted) != 0;
+  if (!AFF && permuted) fast = false;
+  const bool fast_perm = AFF && fast && permuted;
+  if (fast && !fast_perm && C::template stage<T, Q>()) {
     // Neighbour blocks are read with unit-stride (coalesced) loads - thread
     // tid takes entries tid, tid + NT, ... of each tangential component block -
     // for a batch of GB faces at once, then passed face by face through a
@@ -449,7 +456,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
         if (g >= 6) break;
         if (nb_id[g] < 0) continue;
         // the neighbour's tangential blocks on its own face axis
-        const int ax = PERM ? ((Ip->orient[g] & 7) >> 1) : (g >> 1);
+        const int ax = g >> 1;
         const __amdgpu_buffer_rsrc_t rsrc =
             __builtin_amdgcn_make_buffer_rsrc((void*)nb_x[g], (short)0, BLK, 0x00020000);
 #pragma unroll
@@ -478,7 +485,6 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
           }
         __syncthreads();
         if (!face_lane) continue;
-        if constexpr (!PERM) {
           const int c = (alpha + 1 + (tc & 1)) % 3;
           const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
           const int ns = face_stride(alpha, A);
@@ -495,7 +501,57 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
             for (int i = 0; i < Q; ++i)
               if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
           }
-        } else {
+      }
+    }
+    __syncthreads();  // staging area is reused for the contracted levels
+  } else if (fast_perm && C::template stage<T, Q>()) {
+    // Neighbour blocks are read with unit-stride (coalesced) loads - thread
+    // tid takes entries tid, tid + NT, ... of each tangential component block -
+    // for a batch of GB faces at once, then passed face by face through a
+    // double-buffered LDS staging area where the face lanes reduce them.
+    constexpr int CH = NL * A3;                     // entries per component block
+    constexpr int KC = (CH + C::NT - 1) / C::NT;    // loads per thread per block
+    constexpr int GBC0 = 96 / (4 * KC * WORDS);
+    constexpr int GBC = GBC0 < 1 ? 1 : (GBC0 > 3 ? 3 : GBC0);  // at most 3 faces in flight: fewer VGPRs, more waves
+    int nstaged = 0;  // staged faces so far (uniform): buffers strictly alternate
+#pragma unroll
+    for (int g0 = 0; g0 < 6; g0 += GBC) {
+      T nbv[GBC][4][KC];
+#pragma unroll
+      for (int gg = 0; gg < GBC; ++gg) {
+        const int g = g0 + gg;
+        if (g >= 6) break;
+        if (nb_id[g] < 0) continue;
+        // the neighbour's tangential blocks on its own face axis
+        const int ax = (Ip->orient[g] & 7) >> 1;
+        const __amdgpu_buffer_rsrc_t rsrc =
+            __builtin_amdgcn_make_buffer_rsrc((void*)nb_x[g], (short)0, BLK, 0x00020000);
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int fc = 3 * (q4 >> 1) + (ax + 1 + (q4 & 1)) % 3;
+#pragma unroll
+          for (int k = 0; k < KC; ++k)
+            nbv[gg][q4][k] = buf_load<T>(rsrc, (uint32_t)((fc * CH + k * C::NT) * (int)sizeof(T)) +
+                                                   (uint32_t)tid * (uint32_t)sizeof(T));
+        }
+      }
+#pragma unroll
+      for (int gg = 0; gg < GBC; ++gg) {
+        const int g = g0 + gg;
+        if (g >= 6) break;
+        if (nb_id[g] < 0) continue;
+        const int alpha = g >> 1, side = g & 1;
+        T* stg = sm + (nstaged & 1) * (4 * CH);
+        ++nstaged;
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+          for (int k = 0; k < KC; ++k) {
+            const int p = tid + k * C::NT;
+            if (CH % C::NT == 0 || p < CH) stg[q4 * CH + p] = nbv[gg][q4][k];
+          }
+        __syncthreads();
+        if (!face_lane) continue;
           // the neighbour's face f' at the mapped mode, matched component and sign
           const FaceMap fm = map_face(alpha, Ip->orient[g], (alpha + 1 + (tc & 1)) % 3, fu, fv);
           const int slot = 2 * tf + (fm.cn == (fm.ax + 1) % 3 ? 0 : 1);
@@ -513,15 +569,12 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
             for (int i = 0; i < Q; ++i)
               if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
           }
-        }
       }
     }
     __syncthreads();  // staging area is reused for the contracted levels
-  };
-  // faces too large to stage: gather each face item straight from global
-  // memory (one buffer descriptor per face, compile-time immediates)
-  auto gathered = [&](auto perm_tag) __attribute__((always_inline)) {
-    constexpr bool PERM = decltype(perm_tag)::value;
+  } else if (fast && !fast_perm) {
+    // faces too large to stage: gather each face item straight from global
+    // memory (one buffer descriptor per face, compile-time immediates)
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
       if (nb_id[g] < 0) continue;
@@ -529,7 +582,6 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
       const int c = (alpha + 1 + (tc & 1)) % 3;
       // canonical: the neighbour's face (alpha, 1 - side), same component and mode
       FaceMap fm{alpha, 1 - side, c, fu, fv, false};
-      if constexpr (PERM) fm = map_face(alpha, Ip->orient[g], c, fu, fv);
       const int ns = face_stride(fm.ax, A);
       const __amdgpu_buffer_rsrc_t rsrc =
           __builtin_amdgcn_make_buffer_rsrc((void*)nb_x[g], (short)0, BLK, 0x00020000);
@@ -553,27 +605,49 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
           if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
       }
     }
-  };
-  const bool permuted = (Ip->flags & kPermuted) != 0;
-  if (fast && C::template stage<T, Q>()) {
-    if (permuted) staged(std::true_type{}); else staged(std::false_type{});
-  } else if (fast) {
-    if (permuted) gathered(std::true_type{}); else gathered(std::false_type{});
+  } else if (fast_perm) {
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+      if (nb_id[g] < 0) continue;
+      const int alpha = g >> 1, side = g & 1;
+      const int c = (alpha + 1 + (tc & 1)) % 3;
+      // canonical: the neighbour's face (alpha, 1 - side), same component and mode
+      FaceMap fm{alpha, 1 - side, c, fu, fv, false};
+      fm = map_face(alpha, Ip->orient[g], c, fu, fv);
+      const int ns = face_stride(fm.ax, A);
+      const __amdgpu_buffer_rsrc_t rsrc =
+          __builtin_amdgcn_make_buffer_rsrc((void*)nb_x[g], (short)0, BLK, 0x00020000);
+      const uint32_t lo = (uint32_t)(((3 * tf + fm.cn) * NL * A3 + face_base(fm.ax, fm.mu, fm.mv, A)) * (int)sizeof(T));
+      T vals[NL][A];
+#pragma unroll
+      for (int ml = 0; ml < NL; ++ml)
+#pragma unroll
+        for (int l = 0; l < A; ++l) vals[ml][l] = buf_load<T>(rsrc, lo + (uint32_t)((ml * A3 + l * ns) * (int)sizeof(T)));
+      if (!face_lane) continue;
+      const T scale = (pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + fm.cn] : T(1)) * (fm.neg ? T(-1) : T(1));
+#pragma unroll
+      for (int ml = 0; ml < NL; ++ml) {
+        const int mp = ml + m0;
+        T tr = T(0);
+#pragma unroll
+        for (int l = 0; l < A; ++l) tr += (fm.so ? P.tab.tr1[l] : P.tab.tr0[l]) * vals[ml][l];
+        tr *= scale;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
+      }
+    }
   } else if (face_lane) {
     // different degrees or orientations around this element: p-truncated
     // coupling, S_h drops the neighbour term on test levels i >= min(q, q'),
     // and a neighbour met in another orientation is read on its own face f'
-    // with its tangential axes mapped to ours: the covariant component along
-    // our axis is +-the neighbour's along the matched axis (minus where the
-    // axis runs reversed), and mode j along a reversed axis takes (-1)^j
-    // (L_j(1 - x) = (-1)^j L_j(x)).
+    // through the face map (strides are run-time here anyway: na varies)
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
       const int alpha = g >> 1;
       if (nb_id[g] < 0) continue;
       const int c = (alpha + 1 + (tc & 1)) % 3;
       const FaceMap fm = map_face(alpha, Ip->orient[g], c, fu, fv);
-      const int so = fm.so;
       const T scale = (pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + fm.cn] : T(1)) * (fm.neg ? T(-1) : T(1));
       const int na = nb_a[g], nq = nb_q[g];
       if (fu >= na || fv >= na) continue;
@@ -586,10 +660,10 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
         if (mp < m0 || mp > nq) continue;
         const T* xl = xb + (int64_t)(mp - m0) * na3;
         T tr = T(0);
-        // trace on the neighbour's face at side so: L_l(so)
+        // trace on the neighbour's face at its side: L_l(side')
         for (int l = 0; l < na; ++l) {
           const T rho = dsqrt<T>(T(2 * l + 1));
-          tr += ((so == 0 && (l & 1)) ? -rho : rho) * xl[l * ns];
+          tr += ((fm.so == 0 && (l & 1)) ? -rho : rho) * xl[l * ns];
         }
         tr *= scale;
 #pragma unroll
