@@ -285,6 +285,8 @@ typedef struct {
   const int32_t* mnl;        /*   stdg_project_modes (affine meshes), or            */
   const double* abc;
   const double* init_state;  /*   an FP64 state (host, state layout) if not NULL    */
+  double c_diss;             /* >= 0: dissipative stabilisation D_h with this c, as  */
+                             /*   stdg_mesh_set_dissipation (affine meshes; 0 = off) */
 } stdg_request;
 
 typedef struct {

@@ -82,7 +82,8 @@ class ServeOpts(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("mesh", MeshDesc), ("t0", ctypes.c_double), ("dt", ctypes.c_double),
                 ("n_slabs", ctypes.c_int32), ("source", Source), ("n_modes", ctypes.c_int32),
-                ("mnl", ctypes.c_void_p), ("abc", ctypes.c_void_p), ("init_state", ctypes.c_void_p)]
+                ("mnl", ctypes.c_void_p), ("abc", ctypes.c_void_p), ("init_state", ctypes.c_void_p),
+                ("c_diss", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):

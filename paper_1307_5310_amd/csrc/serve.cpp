@@ -48,6 +48,7 @@ struct Request {
   double t0 = 0.0, dt = 0.0;
   int n_slabs = 0;
   stdg_source src{};
+  double c_diss = 0.0;
   int64_t n_unk = 0, n_trial = 0, n_state = 0;
   size_t footprint = 0;
   double t_submit = 0.0;
@@ -158,6 +159,8 @@ size_t footprint_of(const Request& r, const SlabOpts& so) {
        2 * r256(sizeof(double) * 3 * (r.mnl.size() / 3 + 1));
   b += slab_solver_bytes(r.n_unk, r.n_trial, r.ne, so);
   b += r256(sizeof(double) * (r.ne + 1));  // energy of the initial field (inexact solves)
+  if (r.c_diss > 0.0)  // D_h coefficients, FP64 and FP32
+    b += r256(sizeof(double) * Mesh::kDissWords * r.ne) + r256(sizeof(float) * Mesh::kDissWords * r.ne);
   return b + 16384;  // alignment of the individual allocations
 }
 
@@ -182,6 +185,7 @@ int Server::start(Active* a) {
   int rc = upload_mesh(&a->ctx, &a->mesh->m);
   if (rc != STDG_OK) return rc;
   Mesh& m = a->mesh->m;
+  if (r->c_diss > 0.0 && (rc = set_dissipation(&m, r->c_diss)) != STDG_OK) return rc;
   if ((rc = dev_alloc(&a->ctx, (void**)&a->state, sizeof(double) * r->n_state)) != STDG_OK) return rc;
   if (r->src.kind && (rc = dev_alloc(&a->ctx, (void**)&a->load, sizeof(double) * r->n_unk)) != STDG_OK) return rc;
   if (!r->init.empty()) {
@@ -399,6 +403,8 @@ int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ti
   if (req->source.kind != 0 && req->source.kind != 1) return fail(STDG_E_ARG, "stdg_serve_submit: unknown source kind");
   if (req->n_modes < 0 || (req->n_modes > 0 && (!req->mnl || !req->abc)))
     return fail(STDG_E_ARG, "stdg_serve_submit: invalid mode list");
+  if (!(req->c_diss >= 0.0) || !std::isfinite(req->c_diss))
+    return fail(STDG_E_ARG, "stdg_serve_submit: c_diss must be finite and >= 0");
   Request* r = new (std::nothrow) Request;
   if (!r) return fail(STDG_E_NOMEM, "stdg_serve_submit: host allocation failed");
   int rc;
@@ -417,6 +423,8 @@ int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ti
         r->abc.assign(req->abc, req->abc + 3 * req->n_modes);
       }
       if (req->init_state) r->init.assign(req->init_state, req->init_state + r->n_state);
+      if (req->c_diss > 0.0 && m.n_nonaffine > 0)
+        rc = fail(STDG_E_UNSUPPORTED, "stdg_serve_submit: dissipative stabilisation needs affine elements");
     }
   } catch (const std::bad_alloc&) {
     rc = fail(STDG_E_NOMEM, "stdg_serve_submit: host allocation failed");
@@ -430,6 +438,7 @@ int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ti
   r->dt = req->dt;
   r->n_slabs = req->n_slabs;
   r->src = req->source;
+  r->c_diss = req->c_diss;
   r->footprint = footprint_of(*r, S.so);
   if (r->footprint > S.arena_size) {
     const size_t fp = r->footprint;

@@ -221,3 +221,39 @@ def test_inexact_serving_within_eta(lib):
     assert r["status"] == 0
     assert r["eta_it"] <= budget * (1 + 1e-12)
     assert err <= r["eta_it"]
+
+
+def test_serving_with_dissipation(lib):
+    """A request with the dissipative stabilisation D_h (remark closing
+    Section 4): bitwise the plain march with stdg_mesh_set_dissipation, the
+    energy drops, and a trilinear mesh is refused at submit."""
+    stdg = lib.stdg
+    rq = _small_stream(1, sizes=(4,), degrees=(3,), n_slabs=3)[0]
+    m = rq["mesh"]
+    c = 0.6
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 28, **OPTS)
+    try:
+        t = stdg.stdg_serve_submit(srv, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu, 0.0, rq["dt"], rq["n_slabs"],
+                                   mnl=rq["init"].mnl, abc=rq["init"].abc, c_diss=c)
+        r = _wait(stdg, srv, [t], [m.state_size()])[0]
+        v, h = synth.box_mesh((2, 2, 2))
+        v = synth.perturb_interior(v, (2, 2, 2), 0.1, seed=3)
+        with pytest.raises(stdg.StdgError) as ei:
+            stdg.stdg_serve_submit(srv, v, h, np.full(8, 2), np.full(8, 1), np.ones(8), np.ones(8), 0.0, 0.05, 1,
+                                   init_state=np.ones(8 * 6 * 27), c_diss=c)
+        assert ei.value.status == -2
+    finally:
+        stdg.stdg_serve_stop(srv)
+    assert r["status"] == 0
+    assert r["energy_end"] < r["energy_start"]
+    mh = lib.upload(m)
+    try:
+        stdg.stdg_mesh_set_dissipation(mh, c)
+        st = lib.torch.zeros(m.state_size(), dtype=lib.torch.float64, device="cuda")
+        stdg.stdg_project_modes(mh, rq["init"].mnl, rq["init"].abc, st)
+        for n in range(rq["n_slabs"]):
+            assert stdg.stdg_slab_solve(mh, n * rq["dt"], rq["dt"], None, st, **OPTS)["status"] == 0
+        ref = st.cpu().numpy()
+    finally:
+        stdg.stdg_mesh_free(mh)
+    assert np.array_equal(ref, r["state"])
