@@ -238,6 +238,36 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     i = j;
   }
 
+  // conformity: on a conforming mesh the boundary faces close up, every edge
+  // of a boundary face lies on an even number (>= 2) of boundary faces; a face
+  // only partly shared (a hanging node) leaves its edges on one boundary face
+  {
+    std::vector<std::pair<int64_t, int64_t>> edges;
+    edges.reserve(4 * (size_t)m->n_bnd_faces);
+    for (int64_t e = 0; e < ne; ++e)
+      for (int f = 0; f < 6; ++f) {
+        if (m->info[e].nb[f] >= 0) continue;
+        auto lv = face_local_vertices(f);
+        // corners in cyclic order around the face: (0,0), (1,0), (1,1), (0,1)
+        const int64_t c[4] = {d->hexes[8 * e + lv[0]], d->hexes[8 * e + lv[1]], d->hexes[8 * e + lv[3]],
+                              d->hexes[8 * e + lv[2]]};
+        for (int k = 0; k < 4; ++k) {
+          int64_t a = c[k], b = c[(k + 1) % 4];
+          edges.push_back({std::min(a, b), std::max(a, b)});
+        }
+      }
+    std::sort(edges.begin(), edges.end());
+    for (size_t i = 0; i < edges.size();) {
+      size_t j = i + 1;
+      while (j < edges.size() && edges[j] == edges[i]) ++j;
+      if ((j - i) % 2 != 0)
+        return fail(STDG_E_UNSUPPORTED, "nonconforming mesh: boundary edge (" + std::to_string(edges[i].first) +
+                                            ", " + std::to_string(edges[i].second) +
+                                            ") does not close up (a face only partly shared, e.g. a hanging node)");
+      i = j;
+    }
+  }
+
   // geometry
   m->metric.assign(ne, ElemMetric{});
   m->verts.assign(ne * 24, 0.0);
