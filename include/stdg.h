@@ -126,9 +126,9 @@ typedef struct {
  * accepted; STDG_E_ARG if the shared vertices do not match as a
  * quadrilateral), classify elements as affine (parallelepiped) or trilinear,
  * group them by (p, q, affine), compute offsets and copy everything to the
- * device.  Faces on exactly one element are PEC boundary faces; the boundary
- * faces must close up (every edge on an even number of them), which refuses
- * faces that are only partly shared, as at hanging nodes, with
+ * device.  Faces on exactly one element are PEC boundary faces; a face split
+ * among smaller elements (2:1 refinement with hanging vertices, found by the
+ * smaller faces' centroids at its quarter points) is refused with
  * STDG_E_UNSUPPORTED: conforming meshes only. */
 int stdg_mesh_upload(stdg_ctx* ctx, const stdg_mesh_desc* desc, stdg_mesh** out);
 int stdg_mesh_info(const stdg_mesh* mesh, stdg_mesh_info_t* out);

@@ -238,34 +238,58 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     i = j;
   }
 
-  // conformity: on a conforming mesh the boundary faces close up, every edge
-  // of a boundary face lies on an even number (>= 2) of boundary faces; a face
-  // only partly shared (a hanging node) leaves its edges on one boundary face
+  // conformity: a face only partly shared (2:1 refinement, hanging vertices)
+  // leaves the coarse face and the four fine faces unmatched, so they would be
+  // taken for walls.  Such a coarse face has the centroids of the fine faces
+  // at its quarter points: look every boundary face's quarter points up among
+  // the boundary-face centroids (spatial hash, tolerance 1e-9 of the mesh size).
   {
-    std::vector<std::pair<int64_t, int64_t>> edges;
-    edges.reserve(4 * (size_t)m->n_bnd_faces);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < nv; ++v)
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = std::min(lo[c], d->vertices[3 * v + c]);
+        hi[c] = std::max(hi[c], d->vertices[3 * v + c]);
+      }
+    const double diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                  (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    const double tol = 1e-9 * (diag > 0 ? diag : 1.0);
+    auto point = [&](int64_t e, int f, double u, double w, double out[3]) {
+      auto lv = face_local_vertices(f);  // corners (0,0), (1,0), (0,1), (1,1)
+      const double wt[4] = {(1 - u) * (1 - w), u * (1 - w), (1 - u) * w, u * w};
+      for (int c = 0; c < 3; ++c) {
+        out[c] = 0.0;
+        for (int k = 0; k < 4; ++k) out[c] += wt[k] * d->vertices[3 * d->hexes[8 * e + lv[k]] + c];
+      }
+    };
+    auto cell = [&](const double x[3], int c) { return (int64_t)std::floor((x[c] - lo[c]) / (4 * tol)); };
+    std::map<std::array<int64_t, 3>, std::vector<std::array<double, 3>>> grid;
     for (int64_t e = 0; e < ne; ++e)
       for (int f = 0; f < 6; ++f) {
         if (m->info[e].nb[f] >= 0) continue;
-        auto lv = face_local_vertices(f);
-        // corners in cyclic order around the face: (0,0), (1,0), (1,1), (0,1)
-        const int64_t c[4] = {d->hexes[8 * e + lv[0]], d->hexes[8 * e + lv[1]], d->hexes[8 * e + lv[3]],
-                              d->hexes[8 * e + lv[2]]};
+        double x[3];
+        point(e, f, 0.5, 0.5, x);
+        grid[{cell(x, 0), cell(x, 1), cell(x, 2)}].push_back({x[0], x[1], x[2]});
+      }
+    for (int64_t e = 0; e < ne; ++e)
+      for (int f = 0; f < 6; ++f) {
+        if (m->info[e].nb[f] >= 0) continue;
         for (int k = 0; k < 4; ++k) {
-          int64_t a = c[k], b = c[(k + 1) % 4];
-          edges.push_back({std::min(a, b), std::max(a, b)});
+          double x[3];
+          point(e, f, (k & 1) ? 0.75 : 0.25, (k & 2) ? 0.75 : 0.25, x);
+          const int64_t c0 = cell(x, 0), c1 = cell(x, 1), c2 = cell(x, 2);
+          for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dx = -1; dx <= 1; ++dx) {
+                auto it = grid.find({c0 + dx, c1 + dy, c2 + dz});
+                if (it == grid.end()) continue;
+                for (const auto& y : it->second)
+                  if (std::fabs(y[0] - x[0]) <= tol && std::fabs(y[1] - x[1]) <= tol && std::fabs(y[2] - x[2]) <= tol)
+                    return fail(STDG_E_UNSUPPORTED, "nonconforming mesh: face " + std::to_string(f) + " of element " +
+                                                        std::to_string(e) +
+                                                        " is split among smaller elements (hanging vertices)");
+              }
         }
       }
-    std::sort(edges.begin(), edges.end());
-    for (size_t i = 0; i < edges.size();) {
-      size_t j = i + 1;
-      while (j < edges.size() && edges[j] == edges[i]) ++j;
-      if ((j - i) % 2 != 0)
-        return fail(STDG_E_UNSUPPORTED, "nonconforming mesh: boundary edge (" + std::to_string(edges[i].first) +
-                                            ", " + std::to_string(edges[i].second) +
-                                            ") does not close up (a face only partly shared, e.g. a hanging node)");
-      i = j;
-    }
   }
 
   // geometry
