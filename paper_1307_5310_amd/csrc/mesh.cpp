@@ -153,6 +153,52 @@ uint64_t spread3(uint64_t v) {
 
 }  // namespace
 
+// Work-list order of a mesh with a single kernel group and small element
+// blocks: columns of 8 x 8 elements (on the lattice of the median element
+// size) swept along z, the columns in snake order and each swept opposite to
+// the previous one.  A neighbour then lies at most 64 elements back or ahead
+// in the list, so while one XCD's L2 (4 MiB) holds several such layers of
+// FP32 blocks nearly every neighbour block read is an L2 hit (Morton order
+// leaves about an eighth of the neighbour pairs far apart).  Measured on the
+// 32^3 p = 4 q = 3 cavity: -5% apply time; no gain for blocks of p = 6 q = 4,
+// a loss for several groups (which run concurrently and interleave in
+// space): those keep the Morton order.  Returns false where it does not apply.
+bool column_order(const Mesh* m, const std::vector<std::array<double, 3>>& cen, const double lo[3],
+                  std::vector<std::pair<uint64_t, int32_t>>& lst) {
+  const int64_t ne = m->ne;
+  const int64_t a = m->p[0] + 1;
+  const double block = 24.0 * m->q[0] * (double)(a * a * a);  // FP32 bytes of an element's unknowns
+  if (4.0 * 1048576.0 / block < 6.0 * 64.0) return false;
+  const int64_t T = 8;
+  double h[3];
+  for (int c = 0; c < 3; ++c) {
+    std::vector<double> ext(ne);
+    for (int64_t e = 0; e < ne; ++e) {
+      double a = 1e300, b = -1e300;
+      for (int v = 0; v < 8; ++v) {
+        a = std::min(a, m->verts[24 * e + 3 * v + c]);
+        b = std::max(b, m->verts[24 * e + 3 * v + c]);
+      }
+      ext[e] = b - a;
+    }
+    std::nth_element(ext.begin(), ext.begin() + ne / 2, ext.end());
+    h[c] = ext[ne / 2] > 0 ? ext[ne / 2] : 1.0;
+  }
+  auto cell = [&](int64_t e, int c) {
+    return (int64_t)std::max(0.0, std::min(1048575.0, std::floor((cen[e][c] - lo[c]) / h[c] + 0.5)));
+  };
+  int64_t ntx = 1;
+  for (int64_t e = 0; e < ne; ++e) ntx = std::max(ntx, cell(e, 0) / T + 1);
+  for (auto& kv : lst) {
+    const int64_t e = kv.second, ix = cell(e, 0), iy = cell(e, 1), iz = cell(e, 2);
+    const int64_t tx = ix / T, ty = iy / T;
+    const int64_t tile = ty * ntx + ((ty & 1) ? ntx - 1 - tx : tx);
+    const int64_t zz = (tile & 1) ? 1048575 - iz : iz;
+    kv.first = ((uint64_t)tile << 40) | ((uint64_t)zz << 20) | (uint64_t)((iy % T) * T + (ix % T));
+  }
+  return true;
+}
+
 int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
   const int64_t ne = d->n_elements, nv = d->n_vertices;
   m->ne = ne;
@@ -371,6 +417,7 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     auto key = std::make_tuple(m->p[e] + 1, m->q[e], (m->info[e].flags & kAffine) ? 1 : 0);
     gm[key].push_back({code, (int32_t)e});
   }
+  if (gm.size() == 1) (void)column_order(m, cen, lo, gm.begin()->second);
   m->p_max = *std::max_element(m->p.begin(), m->p.end());
   m->q_max = *std::max_element(m->q.begin(), m->q.end());
   m->groups.clear();
