@@ -227,7 +227,12 @@ typedef struct {
  * on return (the l_1 block, i.e. continuity in time between slabs).
  * load_dev: residual-layout FP64 load of this slab, or NULL (J = 0).
  * slab_U_dev: optional FP64 full-trial output of the slab solution (NULL = none).
- * Synchronises `stream`.  STDG_E_NOT_CONVERGED still fills *info and state. */
+ * Synchronises `stream`.  STDG_E_NOT_CONVERGED still fills *info and state.
+ * The solver's device memory (Krylov basis and work vectors, counted against
+ * the context budget) is allocated on the first call and kept on the mesh for
+ * the next ones (a march of slabs allocates once); it is reallocated when the
+ * precisions or the restart length change and freed by stdg_mesh_free.  A call
+ * made while another thread solves on the same mesh uses memory of its own. */
 int stdg_slab_solve(const stdg_mesh* mesh, double t0, double dt, const double* load_dev,
                     const stdg_solve_opts* opts, double* state_dev, double* slab_U_dev,
                     stdg_solve_info* info, void* stream);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -106,6 +107,8 @@ struct Ctx {
   size_t chunk_size = 0, chunk_off = 0;
 };
 
+class SlabSolver;
+
 struct Mesh {
   Ctx* ctx = nullptr;
   int64_t ne, nv;
@@ -143,6 +146,11 @@ struct Mesh {
   //   [12 + 3 alpha + (0, 1, 2)] = K_aa, K_bb, K_ab of the faces normal to alpha,
   // K = |t_a x t_b| g^{-1} the face metric of the tangent vectors t_a, t_b along
   // the axes (alpha + 1) % 3, (alpha + 2) % 3 (constant on affine elements)
+  // the slab solver of stdg_slab_solve, kept between calls (its Krylov basis
+  // and work vectors stay allocated: a march of slabs allocates once); a call
+  // that finds it busy (another thread) uses a solver of its own
+  SlabSolver* solver = nullptr;
+  std::atomic<bool> solver_busy{false};
   static constexpr int kDissWords = 24;
   double c_diss = 0.0;
   double* d_diss = nullptr;   // FP64 copy (FP64 kernels)
@@ -172,6 +180,7 @@ int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m);
 void release_mesh(Mesh* m);
 size_t mesh_device_bytes(const Mesh& m);
 int set_dissipation(Mesh* m, double c);
+void release_cached_solver(Mesh* m);  // solver.cpp
 
 // Allocation against the context budget.
 int dev_alloc(Ctx* ctx, void** p, size_t bytes);

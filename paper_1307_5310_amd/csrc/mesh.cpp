@@ -374,6 +374,20 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     double G[6], det;
     metric_of(DF, G, &det);
     if (!(det > 0.0)) return fail(STDG_E_ARG, "element " + std::to_string(e) + " is inverted or degenerate");
+    // the trilinear map's Jacobian at each corner is the matrix of the three
+    // edges leaving it (oriented along the reference axes): all must be > 0
+    for (int v = 0; v < 8; ++v) {
+      double J[3][3];
+      for (int ax = 0; ax < 3; ++ax) {
+        const int w = v ^ (1 << ax);
+        const double sgn = ((v >> ax) & 1) ? -1.0 : 1.0;
+        for (int c = 0; c < 3; ++c) J[c][ax] = sgn * (X[w][c] - X[v][c]);
+      }
+      const double dj = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                        J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      if (!(dj > 0.0))
+        return fail(STDG_E_ARG, "element " + std::to_string(e) + " is inverted or folded at corner " + std::to_string(v));
+    }
     ElemMetric& M = m->metric[e];
     M.eps = d->eps[e];
     M.mu = d->mu[e];
@@ -403,6 +417,26 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
       hi[c] = std::max(hi[c], cen[e][c]);
     }
   }
+
+  // neighbours must lie across the face: the neighbour's centroid on the
+  // outer side of the face (refuses coincident or folded elements)
+  for (int64_t e = 0; e < ne; ++e)
+    for (int f = 0; f < 6; ++f) {
+      const int32_t k = m->info[e].nb[f];
+      if (k < 0) continue;
+      auto lv = face_local_vertices(f);
+      double fc[3] = {0, 0, 0};
+      for (int t = 0; t < 4; ++t)
+        for (int c = 0; c < 3; ++c) fc[c] += 0.25 * m->verts[24 * e + 3 * lv[t] + c];
+      double out = 0.0, ref = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        out += (cen[k][c] - fc[c]) * (fc[c] - cen[e][c]);
+        ref += (fc[c] - cen[e][c]) * (fc[c] - cen[e][c]);
+      }
+      if (!(out > 1e-12 * ref))
+        return fail(STDG_E_ARG, "elements " + std::to_string(e) + " and " + std::to_string(k) +
+                                    " share a face but do not lie on its two sides");
+    }
 
   // groups in Morton order of the element centroids
   std::map<std::tuple<int, int, int>, std::vector<std::pair<uint64_t, int32_t>>> gm;
@@ -564,6 +598,7 @@ int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m) {
 
 void release_mesh(Mesh* m) {
   Ctx* ctx = m->ctx;
+  release_cached_solver(m);
   for (int k = 0; k < Mesh::kAux; ++k) {
     if (m->aux[k]) (void)hipStreamDestroy(m->aux[k]);
     if (m->join_ev[k]) (void)hipEventDestroy(m->join_ev[k]);

@@ -18,6 +18,8 @@
 #include <cstring>
 #include <string>
 
+#include <new>
+
 #include "solver.h"
 
 namespace stdg {
@@ -130,6 +132,22 @@ void SlabSolver::release() {
   ev_ = nullptr;
   m_ = nullptr;
   phase_ = kIdle;
+}
+
+int SlabSolver::rebind(const SlabOpts& o, hipStream_t s) {
+  o_ = o;
+  s_ = s;
+  phase_ = kIdle;
+  STDG_HIP(hipMemsetAsync(dw_.counter, 0, sizeof(unsigned) * 4, s_));
+  STDG_HIP(hipMemsetAsync(hv_, 0, sizeof(double) * kScalars, s_));
+  return STDG_OK;
+}
+
+void release_cached_solver(Mesh* m) {
+  if (!m->solver) return;
+  m->solver->release();
+  delete m->solver;
+  m->solver = nullptr;
 }
 
 // r' = B U(x) - L in FP64 (into the first basis slot when the basis is FP64),
@@ -349,28 +367,54 @@ extern "C" int stdg_slab_solve(const stdg_mesh* mesh, double t0, double dt, cons
   std::memset(info, 0, sizeof(*info));
   Mesh* m = const_cast<Mesh*>(&mesh->m);
   hipStream_t s = (hipStream_t)stream;
-  SlabSolver S;
-  rc = S.init(m, o, s);
-  if (rc == STDG_OK) rc = S.begin(dt, load_dev, state_dev, slab_U_dev);
+  // the mesh's cached solver (allocated on the first call, kept until the
+  // mesh is freed or the precisions / restart change), or a private one if
+  // another thread holds it
+  SlabSolver own;
+  SlabSolver* S = &own;
+  bool expected = false;
+  const bool cached = m->solver_busy.compare_exchange_strong(expected, true);
+  if (cached) {
+    if (m->solver && !m->solver->compatible(o)) release_cached_solver(m);
+    if (m->solver) {
+      rc = m->solver->rebind(o, s);
+    } else {
+      m->solver = new (std::nothrow) SlabSolver;
+      rc = m->solver ? m->solver->init(m, o, s) : fail(STDG_E_NOMEM, "stdg_slab_solve: host allocation failed");
+      if (rc != STDG_OK) release_cached_solver(m);
+    }
+    S = m->solver;
+  } else {
+    rc = own.init(m, o, s);
+  }
+  if (rc == STDG_OK) rc = S->begin(dt, load_dev, state_dev, slab_U_dev);
   bool done = false;
   while (rc == STDG_OK && !done) {
-    hipError_t e = hipEventSynchronize(S.event());
+    hipError_t e = hipEventSynchronize(S->event());
     if (e != hipSuccess) {
       rc = hip_fail(e, "stdg_slab_solve: waiting for the device");
       break;
     }
-    rc = S.advance(&done);
+    rc = S->advance(&done);
   }
-  info->iters = S.iters;
-  info->refinements = S.refinements;
-  info->rel_res = S.rel_res;
-  info->energy_start = S.energy_start;
-  info->energy_end = S.energy_end;
-  info->eta2 = S.eta2;
-  if (rc == STDG_OK && S.status != STDG_OK)
-    rc = fail(S.status, "stdg_slab_solve: relative residual " + std::to_string(S.rel_res) + " after " +
-                            std::to_string(S.iters) + " iterations");
+  if (S) {
+    info->iters = S->iters;
+    info->refinements = S->refinements;
+    info->rel_res = S->rel_res;
+    info->energy_start = S->energy_start;
+    info->energy_end = S->energy_end;
+    info->eta2 = S->eta2;
+    if (rc == STDG_OK && S->status != STDG_OK)
+      rc = fail(S->status, "stdg_slab_solve: relative residual " + std::to_string(S->rel_res) + " after " +
+                               std::to_string(S->iters) + " iterations");
+  }
   (void)hipStreamSynchronize(s);
-  S.release();
+  if (cached) {
+    // a solver left mid-step by an error is not reused
+    if (rc != STDG_OK && rc != STDG_E_NOT_CONVERGED) release_cached_solver(m);
+    m->solver_busy.store(false);
+  } else {
+    own.release();
+  }
   return rc;
 }

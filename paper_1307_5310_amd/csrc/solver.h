@@ -60,6 +60,10 @@ class SlabSolver {
  public:
   int init(Mesh* m, const SlabOpts& o, hipStream_t s);
   void release();
+  // reuse for another solve: same allocation (precisions, restart), new
+  // tolerances and stream
+  bool compatible(const SlabOpts& o) const { return o.f32 == o_.f32 && o.v32 == o_.v32 && o.restart == o_.restart; }
+  int rebind(const SlabOpts& o, hipStream_t s);
   // start a slab: state (FP64, device) at its start, load may be NULL
   int begin(double dt, const double* load, double* state, double* slab_U);
   hipEvent_t event() const { return ev_; }

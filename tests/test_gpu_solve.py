@@ -187,3 +187,28 @@ def test_two_material_32cubed_first_slab_properties(lib, inner, krylov):
     den = np.sqrt(sum(np.sum(v ** 2) for v in r0.values()))
     assert num / den < 1e-8, num / den
     lib.stdg.stdg_mesh_free(mh)
+
+
+def test_resume_from_saved_state_is_bitwise(lib):
+    # the method is one-step (each slab starts from the previous end state):
+    # saving the FP64 state after two slabs and resuming on a fresh mesh
+    # handle gives bitwise the same third slab as the uninterrupted march
+    cfg = synth.cavity_two_material(n=3, p=3, q=2)
+    m = cfg["mesh"]
+    modes = cfg["init"]
+    opts = dict(inner_prec=1, rtol=1e-12, max_iters=2000, max_refine=200, krylov_prec=1)
+    mh = lib.upload(m)
+    st = lib.torch.zeros(m.state_size(), dtype=lib.torch.float64, device="cuda")
+    lib.stdg.stdg_project_modes(mh, modes.mnl, modes.abc, st)
+    saved = None
+    for n in range(3):
+        if n == 2:
+            saved = st.cpu().numpy().copy()
+        assert lib.stdg.stdg_slab_solve(mh, n * cfg["dt"], cfg["dt"], None, st, **opts)["status"] == 0
+    straight = st.cpu().numpy()
+    lib.stdg.stdg_mesh_free(mh)
+    mh = lib.upload(m)
+    st2 = _state_dev(lib, saved)
+    assert lib.stdg.stdg_slab_solve(mh, 2 * cfg["dt"], cfg["dt"], None, st2, **opts)["status"] == 0
+    lib.stdg.stdg_mesh_free(mh)
+    assert np.array_equal(st2.cpu().numpy(), straight)
