@@ -10,6 +10,11 @@ import ctypes
 
 import numpy as np
 
+try:
+    import torch
+except ImportError:  # pragma: no cover - the binding needs torch only for device tensors
+    torch = None
+
 from ._lib import (StdgError, STDG_FP32, STDG_FP64, STDG_OPERATOR, STDG_RESIDUAL,
                    STDG_OPERATOR_PRECOND, STDG_E_NOT_READY, MeshDesc, MeshInfo, Source, SolveOpts,
                    SolveInfo, ServeOpts, Request, Result, lib, check, ptr, stream_handle,
@@ -70,7 +75,43 @@ def stdg_mesh_offsets(mesh):
     return t, u, s
 
 
+_SIZES = {}
+
+
+def _sizes(mesh):
+    """(unknown, trial, state) sizes of a mesh handle, cached per handle."""
+    key = mesh.value if isinstance(mesh, ctypes.c_void_p) else int(mesh)
+    got = _SIZES.get(key)
+    if got is None:
+        info = stdg_mesh_info(mesh)
+        got = _SIZES[key] = (info["unknown_size"], info["trial_size"], info["state_size"])
+    return got
+
+
+def _dev(t, n, dtype, name, optional=False):
+    """Check a device vector before its address crosses the ABI: a contiguous
+    CUDA tensor of the expected dtype holding at least n elements (the kernels
+    index by the mesh's offsets and trust the caller for the extent)."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError("%s is required" % name)
+    if isinstance(t, int):
+        return  # a raw device address: the caller vouches for it
+    if torch is None or not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor on the GPU (or a raw device address)" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must live on the GPU" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if t.numel() < n:
+        raise ValueError("%s holds %d elements, the mesh needs %d" % (name, t.numel(), n))
+
+
 def stdg_mesh_free(mesh):
+    _SIZES.pop(mesh.value if isinstance(mesh, ctypes.c_void_p) else int(mesh), None)
     check(lib().stdg_mesh_free(mesh))
 
 
@@ -79,6 +120,12 @@ def stdg_mesh_set_dissipation(mesh, c):
 
 
 def stdg_residual_apply(mesh, dt, prec, mode, x, load, y, stream=None):
+    if torch is not None and mesh:
+        nu, nt, _ = _sizes(mesh)
+        dtype = torch.float64 if int(prec) == STDG_FP64 else torch.float32
+        _dev(x, nt if int(mode) == STDG_RESIDUAL else nu, dtype, "x")
+        _dev(load, nu, dtype, "load", optional=True)
+        _dev(y, nu, dtype, "y")
     check(lib().stdg_residual_apply(mesh, float(dt), int(prec), int(mode), ptr(x), ptr(load),
                                     ptr(y), stream_handle(stream)))
 
@@ -97,6 +144,8 @@ def _source(src):
 
 
 def stdg_load_assemble(mesh, src, t0, dt, load, stream=None):
+    if torch is not None and mesh:
+        _dev(load, _sizes(mesh)[0], torch.float64, "load")
     s = _source(src)
     check(lib().stdg_load_assemble(mesh, ctypes.byref(s), float(t0), float(dt), ptr(load),
                                    stream_handle(stream)))
@@ -105,6 +154,8 @@ def stdg_load_assemble(mesh, src, t0, dt, load, stream=None):
 def stdg_project_modes(mesh, mnl, abc, state, stream=None):
     mnl = np.ascontiguousarray(mnl, dtype=np.int32).reshape(-1, 3)
     abc = np.ascontiguousarray(abc, dtype=np.float64).reshape(-1, 3)
+    if torch is not None and mesh:
+        _dev(state, _sizes(mesh)[2], torch.float64, "state")
     check(lib().stdg_project_modes(mesh, mnl.shape[0], mnl.ctypes.data, abc.ctypes.data,
                                    ptr(state), stream_handle(stream)))
 
@@ -115,6 +166,11 @@ def stdg_slab_solve(mesh, t0, dt, load, state, inner_prec=STDG_FP64, restart=10,
     o = SolveOpts(int(inner_prec), int(restart), int(max_iters), int(max_refine), float(rtol),
                   float(inner_rtol), int(krylov_prec), float(eta_tol), float(eta_t_final))
     info = SolveInfo()
+    if torch is not None and mesh:
+        nu, nt, ns = _sizes(mesh)
+        _dev(load, nu, torch.float64, "load", optional=True)
+        _dev(state, ns, torch.float64, "state")
+        _dev(slab_U, nt, torch.float64, "slab_U", optional=True)
     st = lib().stdg_slab_solve(mesh, float(t0), float(dt), ptr(load), ctypes.byref(o), ptr(state),
                                ptr(slab_U), ctypes.byref(info), stream_handle(stream))
     res = {name: getattr(info, name) for name, _ in SolveInfo._fields_}
@@ -126,12 +182,16 @@ def stdg_slab_solve(mesh, t0, dt, load, state, inner_prec=STDG_FP64, restart=10,
 
 def stdg_residual_dual_norm(mesh, dt, r, stream=None):
     out = (ctypes.c_double * 2)()
+    if torch is not None and mesh:
+        _dev(r, _sizes(mesh)[0], torch.float64, "r")
     check(lib().stdg_residual_dual_norm(mesh, float(dt), ptr(r), out, stream_handle(stream)))
     return out[0], out[1]
 
 
 def stdg_energy(mesh, state, stream=None):
     out = ctypes.c_double()
+    if torch is not None and mesh:
+        _dev(state, _sizes(mesh)[2], torch.float64, "state")
     check(lib().stdg_energy(mesh, ptr(state), ctypes.byref(out), stream_handle(stream)))
     return out.value
 

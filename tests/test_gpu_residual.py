@@ -148,3 +148,29 @@ def test_two_material_32cubed_sampled(lib, prec):
         note("32^3 prec=%d mode=%d rel err %.3e" % (prec, mode, rel_err(got, ref)))
         assert rel_err(got, ref) < TOL[prec]
     stdg.stdg_mesh_free(mh)
+
+
+def test_binding_checks_device_buffers(lib):
+    # the binding refuses vectors of the wrong size, dtype or device before
+    # their addresses reach the kernels
+    stdg, t = lib.stdg, lib.torch
+    cfg = synth.cavity_small()
+    mh = lib.upload(cfg["mesh"])
+    try:
+        info = stdg.stdg_mesh_info(mh)
+        nu, nt = info["unknown_size"], info["trial_size"]
+        x = t.zeros(nu, dtype=t.float64, device="cuda")
+        y = t.zeros(nu, dtype=t.float64, device="cuda")
+        bad = [(t.zeros(nu - 1, dtype=t.float64, device="cuda"), y, stdg.STDG_OPERATOR),
+               (x, t.zeros(nu, dtype=t.float32, device="cuda"), stdg.STDG_OPERATOR),
+               (x.cpu(), y, stdg.STDG_OPERATOR),
+               (x, y, stdg.STDG_RESIDUAL)]          # RESIDUAL reads the full trial vector
+        for xx, yy, mode in bad:
+            with pytest.raises(ValueError):
+                stdg.stdg_residual_apply(mh, 0.1, stdg.STDG_FP64, mode, xx, None, yy)
+        stdg.stdg_residual_apply(mh, 0.1, stdg.STDG_FP64, stdg.STDG_RESIDUAL,
+                                 t.zeros(nt, dtype=t.float64, device="cuda"), None, y)
+        with pytest.raises(ValueError):
+            stdg.stdg_energy(mh, t.zeros(info["state_size"] - 6, dtype=t.float64, device="cuda"))
+    finally:
+        stdg.stdg_mesh_free(mh)
