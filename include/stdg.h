@@ -211,6 +211,12 @@ typedef struct {
                           (eq. a_posteriori:iteration) is <= eta_tol^2; 0 = off  */
   double eta_t_final;  /* t_N of that bound (final time, slabs from t = 0), > 0
                           when eta_tol > 0                                       */
+  int32_t use_graph;   /* 1: replay each Arnoldi iteration (apply, CGS2 passes,
+                          scalar copy) as a captured HIP graph, one per basis
+                          index, kept with the mesh's solver (meshes with one
+                          kernel group; captured on the second use of an index,
+                          recaptured when dt changes); results are bitwise those
+                          of the direct launches.  0 = direct launches          */
 } stdg_solve_opts;
 
 typedef struct {
@@ -280,6 +286,7 @@ typedef struct {
                             <= (eta_rel sqrt(2 E(t0)))^2 / n_slabs, so that
                             eta_it <= eta_rel sqrt(2 E(t0)) over the request;
                             0 = solve every slab to rtol                         */
+  int32_t use_graph;     /* as stdg_solve_opts.use_graph, for every request      */
 } stdg_serve_opts;
 
 typedef struct {

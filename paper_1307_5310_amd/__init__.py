@@ -162,9 +162,9 @@ def stdg_project_modes(mesh, mnl, abc, state, stream=None):
 
 def stdg_slab_solve(mesh, t0, dt, load, state, inner_prec=STDG_FP64, restart=10, max_iters=500,
                     max_refine=100, rtol=1e-12, inner_rtol=1e-4, slab_U=None, stream=None, krylov_prec=STDG_FP64,
-                    eta_tol=0.0, eta_t_final=0.0):
+                    eta_tol=0.0, eta_t_final=0.0, use_graph=False):
     o = SolveOpts(int(inner_prec), int(restart), int(max_iters), int(max_refine), float(rtol),
-                  float(inner_rtol), int(krylov_prec), float(eta_tol), float(eta_t_final))
+                  float(inner_rtol), int(krylov_prec), float(eta_tol), float(eta_t_final), int(bool(use_graph)))
     info = SolveInfo()
     if torch is not None and mesh:
         nu, nt, ns = _sizes(mesh)
@@ -197,9 +197,11 @@ def stdg_energy(mesh, state, stream=None):
 
 
 def stdg_serve_start(ctx, hbm_budget=0, max_active=0, inner_prec=STDG_FP32, restart=10, max_iters=500,
-                     max_refine=100, rtol=1e-10, inner_rtol=1e-4, krylov_prec=STDG_FP64, eta_rel=0.0):
+                     max_refine=100, rtol=1e-10, inner_rtol=1e-4, krylov_prec=STDG_FP64, eta_rel=0.0,
+                     use_graph=False):
     o = ServeOpts(int(hbm_budget), int(max_active), int(inner_prec), int(restart), int(max_iters),
-                  int(max_refine), float(rtol), float(inner_rtol), int(krylov_prec), float(eta_rel))
+                  int(max_refine), float(rtol), float(inner_rtol), int(krylov_prec), float(eta_rel),
+                  int(bool(use_graph)))
     h = ctypes.c_void_p()
     check(lib().stdg_serve_start(ctx, ctypes.byref(o), ctypes.byref(h)))
     return h

@@ -62,7 +62,7 @@ class SolveOpts(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
                 ("krylov_prec", ctypes.c_int32), ("eta_tol", ctypes.c_double),
-                ("eta_t_final", ctypes.c_double)]
+                ("eta_t_final", ctypes.c_double), ("use_graph", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -76,7 +76,8 @@ class ServeOpts(ctypes.Structure):
                 ("inner_prec", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("krylov_prec", ctypes.c_int32), ("eta_rel", ctypes.c_double)]
+                ("krylov_prec", ctypes.c_int32), ("eta_rel", ctypes.c_double),
+                ("use_graph", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):

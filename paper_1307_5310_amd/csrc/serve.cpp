@@ -362,7 +362,7 @@ int stdg_serve_start(stdg_ctx* ctx, const stdg_serve_opts* opts, stdg_server** o
   if (o.max_active <= 0) o.max_active = 16;
   if (o.eta_rel < 0.0) return fail(STDG_E_ARG, "stdg_serve_start: eta_rel must be >= 0");
   stdg_solve_opts so{o.inner_prec, o.restart, o.max_iters, o.max_refine, o.rtol, o.inner_rtol, o.krylov_prec, 0.0,
-                     0.0};
+                     0.0, o.use_graph};
   SlabOpts sop;
   int rc = slab_opts_from(&so, &sop);
   if (rc != STDG_OK) return rc;

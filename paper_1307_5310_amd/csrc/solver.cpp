@@ -56,6 +56,7 @@ int slab_opts_from(const stdg_solve_opts* o, SlabOpts* out) {
     return fail(STDG_E_ARG, "stdg_slab_solve: eta_tol needs eta_t_final > 0");
   r.eta_tol = o->eta_tol;
   r.eta_t_final = o->eta_t_final;
+  r.use_graph = o->use_graph != 0;
   *out = r;
   return STDG_OK;
 }
@@ -106,8 +107,19 @@ int SlabSolver::init(Mesh* m, const SlabOpts& o, hipStream_t s) {
   return STDG_OK;
 }
 
+void SlabSolver::drop_graphs() {
+  for (int j = 0; j < kMaxBasis; ++j) {
+    if (gexec_[j]) (void)hipGraphExecDestroy(gexec_[j]);
+    gexec_[j] = nullptr;
+    seen_[j] = false;
+  }
+}
+
 void SlabSolver::release() {
   if (!m_) return;
+  drop_graphs();
+  if (cap_) (void)hipStreamDestroy(cap_);
+  cap_ = nullptr;
   Ctx* c = m_->ctx;
   const size_t n8 = sizeof(double) * n_, n4 = sizeof(float) * n_;
   dev_free(c, V_, (o_.v32 ? 4 : 8) * (size_t)ld_ * (o_.restart + 1));
@@ -216,9 +228,12 @@ int SlabSolver::start_cycle() {
 }
 
 // one Arnoldi step on w~ = B P^{-1} Vt_j (the true w is s_j w~)
-int SlabSolver::launch_iteration() {
+// One Arnoldi iteration with basis index j: the preconditioned apply of V_j,
+// the CGS2 passes producing V_{j+1}, the copy of the new scalars to the host.
+// Every argument is a fixed device address of this solver (or dt), so the
+// sequence can be captured once per j and replayed.
+int SlabSolver::enqueue_iteration(int j) {
   int rc;
-  const int j = j_;
   const void* wsrc;
   if (o_.f32) {
     const float* in = (const float*)basis(j);
@@ -234,7 +249,6 @@ int SlabSolver::launch_iteration() {
     if ((rc = launch_residual(a)) != STDG_OK) return rc;
     wsrc = w_;
   }
-  ++iters;
   const bool v32 = o_.v32, w32 = o_.f32;
   if ((rc = arnoldi_dot(V_, v32, ld_, j + 1, wsrc, w32, n_, hv_ + kS, hv_ + kH1, hv_ + kC1, dw_, s_)) != STDG_OK)
     return rc;
@@ -245,6 +259,48 @@ int SlabSolver::launch_iteration() {
                                 dw_, s_)) != STDG_OK)
     return rc;
   STDG_HIP(hipMemcpyAsync(hb_, hv_, sizeof(double) * kMirror, hipMemcpyDeviceToHost, s_));
+  return STDG_OK;
+}
+
+int SlabSolver::launch_iteration() {
+  int rc;
+  const int j = j_;
+  // graphs for meshes with one kernel group (no side-stream fork); the first
+  // use of an index runs directly (it also sizes any lazily allocated scratch)
+  const bool graph = o_.use_graph && m_->groups.size() == 1;
+  if (graph && graph_dt_ != dt_) {
+    drop_graphs();
+    graph_dt_ = dt_;
+  }
+  if (graph && seen_[j]) {
+    if (!gexec_[j]) {
+      // captured on a stream of the solver's own, launched on the caller's
+      if (!cap_) STDG_HIP(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      const hipStream_t caller = s_;
+      STDG_HIP(hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal));
+      s_ = cap_;
+      rc = enqueue_iteration(j);
+      s_ = caller;
+      hipError_t e = hipStreamEndCapture(cap_, &g);
+      if (rc != STDG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(e, "slab solver: capturing an Arnoldi iteration");
+      e = hipGraphInstantiate(&gexec_[j], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        gexec_[j] = nullptr;
+        return hip_fail(e, "slab solver: instantiating an Arnoldi iteration");
+      }
+    }
+    STDG_HIP(hipGraphLaunch(gexec_[j], s_));
+  } else {
+    if ((rc = enqueue_iteration(j)) != STDG_OK) return rc;
+    seen_[j] = true;
+  }
+  ++iters;
   STDG_HIP(hipEventRecord(ev_, s_));
   phase_ = kWaitIter;
   return STDG_OK;

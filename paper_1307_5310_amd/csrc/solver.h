@@ -45,6 +45,7 @@ struct SlabOpts {
   int restart = 10, max_iters = 500, max_refine = 100;
   double rtol = 1e-10, inner_rtol = 1e-4;
   double eta_tol = 0.0, eta_t_final = 0.0;  // inexact solve: stop once eta_it^2 of the slab <= eta_tol^2
+  bool use_graph = false;                    // replay Arnoldi iterations as captured HIP graphs
 };
 int slab_opts_from(const stdg_solve_opts* o, SlabOpts* out);
 
@@ -96,6 +97,13 @@ class SlabSolver {
   void* V_ = nullptr;  // restart + 1 unnormalised basis vectors (FP32 or FP64)
   double *w_ = nullptr, *x_ = nullptr, *r_ = nullptr, *U_ = nullptr, *d_ = nullptr, *pd_ = nullptr;
   float *v32_ = nullptr, *w32_ = nullptr;
+  // captured Arnoldi iterations, one per basis index j (valid for graph_dt_)
+  int enqueue_iteration(int j);
+  void drop_graphs();
+  hipGraphExec_t gexec_[kMaxBasis] = {};
+  hipStream_t cap_ = nullptr;  // capture stream (the caller's may be the null stream, which cannot capture)
+  bool seen_[kMaxBasis] = {};
+  double graph_dt_ = 0.0;
   DotWork dw_;
   double *hv_ = nullptr, *etmp_ = nullptr;  // device scalars (layout kH1.. in solver.cpp)
   double* hb_ = nullptr;                    // pinned host copy of the scalars

@@ -69,14 +69,14 @@ def _march(lib, rq, **opts):
     return out
 
 
-@pytest.mark.parametrize("krylov", [0, 1])
-def test_serve_matches_slab_solve_alone_and_in_mix(lib, krylov):
+@pytest.mark.parametrize("krylov,graph", [(0, False), (1, False), (1, True)])
+def test_serve_matches_slab_solve_alone_and_in_mix(lib, krylov, graph):
     stdg = lib.stdg
     opts = dict(OPTS, krylov_prec=krylov)
     reqs = _small_stream(10)
     sizes = [r["mesh"].state_size() for r in reqs]
     note("serve: one request alone")
-    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 30, max_active=4, **opts)
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 30, max_active=4, use_graph=graph, **opts)
     try:
         alone = _wait(stdg, srv, [_submit(stdg, srv, reqs[3])], [sizes[3]])[0]
         note("serve: ten requests in a mix")

@@ -212,3 +212,38 @@ def test_resume_from_saved_state_is_bitwise(lib):
     assert lib.stdg.stdg_slab_solve(mh, 2 * cfg["dt"], cfg["dt"], None, st2, **opts)["status"] == 0
     lib.stdg.stdg_mesh_free(mh)
     assert np.array_equal(st2.cpu().numpy(), straight)
+
+
+@pytest.mark.parametrize("inner,krylov", [(0, 0), (1, 1)])
+def test_graph_replay_is_bitwise(lib, inner, krylov):
+    """Arnoldi iterations replayed as captured HIP graphs give bitwise the
+    direct launches' result, over a march whose graphs are replayed many
+    times with eager work between them, across a change of dt (recapture) and
+    on a sheared mesh (preconditioner pre-pass with its scratch)."""
+    for shear in (False, True):
+        cfg = synth.cavity_two_material(n=4, p=3, q=2)
+        m = cfg["mesh"]
+        if shear:
+            m = synth.Mesh(synth.affine_transform(m.vertices, np.array([[1.0, 0.2, 0.0], [0.0, 1.0, 0.1],
+                                                                          [0.1, 0.0, 1.0]])),
+                           m.hexes, m.p, m.q, m.eps, m.mu, shape=m.shape)
+        modes = cfg["init"]
+        opts = dict(inner_prec=inner, krylov_prec=krylov, rtol=1e-12, max_iters=3000, max_refine=300)
+        out = []
+        for graph in (False, True):
+            mh = lib.upload(m)
+            st = lib.torch.zeros(m.state_size(), dtype=lib.torch.float64, device="cuda")
+            if shear:
+                st.copy_(lib.torch.from_numpy(synth.random_vector(m.state_size(), 5)))
+            else:
+                lib.stdg.stdg_project_modes(mh, modes.mnl, modes.abc, st)
+            iters = 0
+            for n, dt in enumerate((0.01, 0.01, 0.01, 0.02, 0.02)):
+                note("graph=%d shear=%d slab %d" % (graph, shear, n))
+                r = lib.stdg.stdg_slab_solve(mh, 0.0, dt, None, st, use_graph=graph, **opts)
+                assert r["status"] == 0
+                iters += r["iters"]
+            out.append((st.cpu().numpy(), iters))
+            lib.stdg.stdg_mesh_free(mh)
+        assert out[0][1] == out[1][1] and out[0][1] > 20
+        assert np.array_equal(out[0][0], out[1][0])
