@@ -156,6 +156,10 @@ def main():
     log("workload %s: %d elements, %.1f M trial DoF" % (cfg["name"], ne, trial_dof / 1e6))
     ctx = stdg.stdg_init(0, 0)
     mh = stdg.stdg_mesh_upload(ctx, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu)
+    # element order of the kernels' work lists: the library's autotuner (timed
+    # here, outside the timed region)
+    order = stdg.stdg_mesh_autotune(mh, stdg.STDG_FP32, dt, reps=10)
+    log("autotuned work-list order: %s" % ("Morton" if order == 0 else "columns of %d" % order))
     info = stdg.stdg_mesh_info(mh)
     nu = info["unknown_size"]
     x64 = torch.from_numpy(synth.random_vector(nu, 0)).cuda()
@@ -256,7 +260,8 @@ def main():
         "config": {"workload": "PEC cavity %d^3 affine hex, p=%d q=%d, eps 1|4 split at x=0.5, dt=%g; "
                                "preconditioned operator apply on N(0,1) coefficients (seed 0)"
                                % (args.n, args.p, args.q, dt),
-                   "elements": ne, "trial_dof": trial_dof, "unknowns": nu},
+                   "elements": ne, "trial_dof": trial_dof, "unknowns": nu,
+                   "work_order": "Morton" if order == 0 else "columns of %d" % order},
         "fp64": {"value": round(gdofs64, 2), "unit": "GDoF/s", "ms_per_step": round(ms64, 5),
                  "kernel_ms": round(k64, 5),
                  "hbm_frac": round(bytes64 / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},

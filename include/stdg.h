@@ -118,6 +118,8 @@ typedef struct {
   int32_t n_affine, n_nonaffine, n_diagonal_mass;
   int32_t p_max, q_max;
   int64_t device_bytes;      /* device memory held by the mesh                  */
+  int32_t work_order;        /* element order of the kernels' work lists: 0 =
+                                Morton, T >= 2 = columns of T x T elements      */
 } stdg_mesh_info_t;
 
 /* Build faces and neighbours (matching sorted vertex ids), find how each
@@ -136,6 +138,21 @@ int stdg_mesh_info(const stdg_mesh* mesh, stdg_mesh_info_t* out);
 int stdg_mesh_offsets(const stdg_mesh* mesh, int64_t* trial_off, int64_t* unknown_off,
                       int64_t* state_off);
 int stdg_mesh_free(stdg_mesh* mesh);
+
+/* Order in which the residual kernels visit the elements of each (p, q,
+ * affine) group: 0 = Morton order of the centroids; T in 2..64 = columns of
+ * T x T elements swept along the third axis (neighbour blocks stay in L2).
+ * The upload picks columns of 8 for single-group meshes with small element
+ * blocks, else Morton.  Results do not depend on the order (each output reads
+ * only its element and its face neighbours).  STDG_E_ARG for other values. */
+int stdg_mesh_set_order(stdg_mesh* mesh, int32_t order);
+/* Autotuner: time `reps` preconditioned operator applies (precision prec,
+ * scratch vectors allocated and freed inside the call) for each candidate
+ * order (Morton, columns of 4, 8, 16), keep the fastest and return it in
+ * *order_out.  Synchronises `stream`.  Callers that cache the choice (the
+ * Python binding keys a JSON file on the mesh's shape) apply it later with
+ * stdg_mesh_set_order. */
+int stdg_mesh_autotune(stdg_mesh* mesh, int prec, double dt, int32_t reps, int32_t* order_out, void* stream);
 
 /* Dissipative upwind-type stabilisation D_h (the remark closing Section 4):
  * from this call on, every residual apply and slab solve on `mesh` uses

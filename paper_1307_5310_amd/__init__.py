@@ -23,6 +23,7 @@ from ._lib import (StdgError, STDG_FP32, STDG_FP64, STDG_OPERATOR, STDG_RESIDUAL
 __all__ = ["StdgError", "STDG_FP32", "STDG_FP64", "STDG_OPERATOR", "STDG_RESIDUAL",
            "STDG_OPERATOR_PRECOND", "stdg_version", "stdg_init", "stdg_finalize",
            "stdg_mesh_upload", "stdg_mesh_info", "stdg_mesh_offsets", "stdg_mesh_free", "stdg_mesh_set_dissipation",
+           "stdg_mesh_set_order", "stdg_mesh_autotune",
            "stdg_residual_apply", "stdg_load_assemble", "stdg_project_modes",
            "stdg_slab_solve", "stdg_energy", "stdg_residual_dual_norm", "stdg_serve_start", "stdg_serve_submit",
            "stdg_serve_poll", "stdg_serve_clock", "stdg_serve_stop", "exported_symbols"]
@@ -117,6 +118,45 @@ def stdg_mesh_free(mesh):
 
 def stdg_mesh_set_dissipation(mesh, c):
     check(lib().stdg_mesh_set_dissipation(mesh, float(c)))
+
+
+def stdg_mesh_set_order(mesh, order):
+    check(lib().stdg_mesh_set_order(mesh, int(order)))
+
+
+def _tune_key(mesh, prec):
+    i = stdg_mesh_info(mesh)
+    return "ne=%d,groups=%d,affine=%d,nonaffine=%d,diag=%d,pmax=%d,qmax=%d,unk=%d,prec=%d" % (
+        i["n_elements"], i["n_groups"], i["n_affine"], i["n_nonaffine"], i["n_diagonal_mass"], i["p_max"],
+        i["q_max"], i["unknown_size"], int(prec))
+
+
+def stdg_mesh_autotune(mesh, prec=STDG_FP32, dt=0.01, reps=10, cache=None, stream=None):
+    """Pick the kernels' element order for this mesh by timing (C ABI
+    stdg_mesh_autotune) and return it.  With a cache file (argument, or the
+    STDG_TUNE_CACHE environment variable) a choice stored for a mesh of the
+    same shape is applied without timing, and new choices are stored."""
+    import json
+    import os
+    path = cache or os.environ.get("STDG_TUNE_CACHE")
+    key = _tune_key(mesh, prec)
+    table = {}
+    if path and os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+        if key in table:
+            stdg_mesh_set_order(mesh, table[key])
+            return int(table[key])
+    out = ctypes.c_int32()
+    check(lib().stdg_mesh_autotune(mesh, int(prec), float(dt), int(reps), ctypes.byref(out),
+                                   stream_handle(stream)))
+    if path:
+        table[key] = int(out.value)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return int(out.value)
 
 
 def stdg_residual_apply(mesh, dt, prec, mode, x, load, y, stream=None):

@@ -47,7 +47,8 @@ class MeshInfo(ctypes.Structure):
                 ("state_size", ctypes.c_int64), ("n_groups", ctypes.c_int32),
                 ("n_affine", ctypes.c_int32), ("n_nonaffine", ctypes.c_int32),
                 ("n_diagonal_mass", ctypes.c_int32), ("p_max", ctypes.c_int32),
-                ("q_max", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("q_max", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("work_order", ctypes.c_int32)]
 
 
 class Source(ctypes.Structure):
@@ -119,6 +120,8 @@ def lib():
             "stdg_mesh_offsets": ([vp, vp, vp, vp], ctypes.c_int),
             "stdg_mesh_free": ([vp], ctypes.c_int),
             "stdg_mesh_set_dissipation": ([vp, dbl], ctypes.c_int),
+            "stdg_mesh_set_order": ([vp, i32], ctypes.c_int),
+            "stdg_mesh_autotune": ([vp, ctypes.c_int, dbl, i32, ctypes.POINTER(i32), vp], ctypes.c_int),
             "stdg_residual_apply": ([vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
             "stdg_load_assemble": ([vp, ctypes.POINTER(Source), dbl, dbl, vp, vp], ctypes.c_int),
             "stdg_project_modes": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),

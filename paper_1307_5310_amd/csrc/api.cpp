@@ -140,6 +140,7 @@ int stdg_mesh_info(const stdg_mesh* mesh, stdg_mesh_info_t* out) {
   out->p_max = m.p_max;
   out->q_max = m.q_max;
   out->device_bytes = (int64_t)m.device_bytes;
+  out->work_order = m.work_order;
   return STDG_OK;
 }
 
@@ -150,6 +151,60 @@ int stdg_mesh_offsets(const stdg_mesh* mesh, int64_t* trial_off, int64_t* unknow
   if (trial_off) std::memcpy(trial_off, m.trial_off.data(), n);
   if (unknown_off) std::memcpy(unknown_off, m.unk_off.data(), n);
   if (state_off) std::memcpy(state_off, m.state_off.data(), n);
+  return STDG_OK;
+}
+
+int stdg_mesh_set_order(stdg_mesh* mesh, int32_t order) {
+  if (!mesh) return fail(STDG_E_ARG, "stdg_mesh_set_order: mesh is NULL");
+  return stdg::set_work_order(&mesh->m, order);
+}
+
+int stdg_mesh_autotune(stdg_mesh* mesh, int prec, double dt, int32_t reps, int32_t* order_out, void* stream) {
+  if (!mesh || !order_out) return fail(STDG_E_ARG, "stdg_mesh_autotune: NULL argument");
+  if (prec != STDG_FP64 && prec != STDG_FP32) return fail(STDG_E_ARG, "stdg_mesh_autotune: unknown precision");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(STDG_E_ARG, "stdg_mesh_autotune: dt must be finite and > 0");
+  if (reps < 1) reps = 10;
+  Mesh* m = &mesh->m;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = (size_t)m->unk_off.back() * (prec == STDG_FP64 ? 8 : 4);
+  void *x = nullptr, *y = nullptr;
+  int rc = dev_alloc(m->ctx, &x, bytes);
+  if (rc == STDG_OK) rc = dev_alloc(m->ctx, &y, bytes);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int candidates[4] = {0, 4, 8, 16};
+  int best = m->work_order;
+  float best_ms = 0.0f;
+  if (rc == STDG_OK && hipEventCreate(&e0) != hipSuccess) rc = fail(STDG_E_DEVICE, "stdg_mesh_autotune: event");
+  if (rc == STDG_OK && hipEventCreate(&e1) != hipSuccess) rc = fail(STDG_E_DEVICE, "stdg_mesh_autotune: event");
+  if (rc == STDG_OK && hipMemsetAsync(x, 0, bytes, s) != hipSuccess) rc = fail(STDG_E_DEVICE, "stdg_mesh_autotune: memset");
+  for (int k = 0; k < 4 && rc == STDG_OK; ++k) {
+    if ((rc = set_work_order(m, candidates[k])) != STDG_OK) break;
+    ApplyArgs a{m, dt, prec, STDG_OPERATOR_PRECOND, x, nullptr, y, s};
+    for (int w = 0; w < 2 && rc == STDG_OK; ++w) rc = launch_residual(a);
+    if (rc != STDG_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(STDG_E_DEVICE, "stdg_mesh_autotune: event"); break; }
+    for (int r = 0; r < reps && rc == STDG_OK; ++r) rc = launch_residual(a);
+    if (rc != STDG_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = fail(STDG_E_DEVICE, "stdg_mesh_autotune: timing");
+      break;
+    }
+    if (k == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = candidates[k];
+    }
+  }
+  if (s) (void)hipStreamSynchronize(s); else (void)hipDeviceSynchronize();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (x) dev_free(m->ctx, x, bytes);
+  if (y) dev_free(m->ctx, y, bytes);
+  const int rc2 = set_work_order(m, best);
+  if (rc != STDG_OK) return rc;
+  if (rc2 != STDG_OK) return rc2;
+  *order_out = best;
   return STDG_OK;
 }
 

@@ -120,6 +120,7 @@ struct Mesh {
   std::vector<double> verts;   // [ne][8][3] element vertex coordinates
   std::vector<Group> groups;
   int n_affine, n_nonaffine, n_diag;
+  int work_order = 0;  // work-list order of the groups: 0 Morton, T >= 2 columns of T x T
   // materials and metric bounds for the iteration-error bound: min eps, min mu,
   // and max over elements of 1 / lambda_min(|J| DF^{-1} DF^{-T}) (centre metric)
   double eps_min = 0.0, mu_min = 0.0, inv_gmin = 0.0;
@@ -180,6 +181,8 @@ int build_mesh(Ctx* ctx, const stdg_mesh_desc* d, Mesh* m);
 void release_mesh(Mesh* m);
 size_t mesh_device_bytes(const Mesh& m);
 int set_dissipation(Mesh* m, double c);
+int default_work_order(const Mesh& m);
+int set_work_order(Mesh* m, int order);  // host lists, and the device lists once uploaded
 void release_cached_solver(Mesh* m);  // solver.cpp
 
 // Allocation against the context budget.

@@ -6,6 +6,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <tuple>
 
@@ -153,50 +154,89 @@ uint64_t spread3(uint64_t v) {
 
 }  // namespace
 
-// Work-list order of a mesh with a single kernel group and small element
-// blocks: columns of 8 x 8 elements (on the lattice of the median element
+// Work-list orders of the kernel groups.  Morton (order 0): the elements of
+// a group sorted along the Morton curve of their centroids.  Columns (order
+// T >= 2): columns of T x T elements (on the lattice of the median element
 // size) swept along z, the columns in snake order and each swept opposite to
-// the previous one.  A neighbour then lies at most 64 elements back or ahead
-// in the list, so while one XCD's L2 (4 MiB) holds several such layers of
-// FP32 blocks nearly every neighbour block read is an L2 hit (Morton order
-// leaves about an eighth of the neighbour pairs far apart).  Measured on the
-// 32^3 p = 4 q = 3 cavity: -5% apply time; no gain for blocks of p = 6 q = 4,
-// a loss for several groups (which run concurrently and interleave in
-// space): those keep the Morton order.  Returns false where it does not apply.
-bool column_order(const Mesh* m, const std::vector<std::array<double, 3>>& cen, const double lo[3],
-                  std::vector<std::pair<uint64_t, int32_t>>& lst) {
+// the previous one, so a neighbour lies at most T^2 elements back or ahead in
+// the list; while one XCD's L2 (4 MiB) holds several such layers of element
+// blocks nearly every neighbour block read is an L2 hit (Morton order leaves
+// about an eighth of the neighbour pairs far apart).  Measured on the 32^3
+// p = 4 q = 3 cavity: columns of 8, -5% apply time; no gain for blocks of
+// p = 6 q = 4, a loss for several groups (which run concurrently and
+// interleave in space).  default_work_order encodes that; stdg_mesh_autotune
+// measures instead.
+int default_work_order(const Mesh& m) {
+  if (m.groups.size() != 1) return 0;
+  const int64_t a = m.p[0] + 1;
+  const double block = 24.0 * m.q[0] * (double)(a * a * a);  // FP32 bytes of an element's unknowns
+  return 4.0 * 1048576.0 / block >= 6.0 * 64.0 ? 8 : 0;
+}
+
+int set_work_order(Mesh* m, int order) {
+  if (order != 0 && (order < 2 || order > 64)) return fail(STDG_E_ARG, "work order must be 0 (Morton) or 2..64");
   const int64_t ne = m->ne;
-  const int64_t a = m->p[0] + 1;
-  const double block = 24.0 * m->q[0] * (double)(a * a * a);  // FP32 bytes of an element's unknowns
-  if (4.0 * 1048576.0 / block < 6.0 * 64.0) return false;
-  const int64_t T = 8;
-  double h[3];
-  for (int c = 0; c < 3; ++c) {
-    std::vector<double> ext(ne);
-    for (int64_t e = 0; e < ne; ++e) {
-      double a = 1e300, b = -1e300;
-      for (int v = 0; v < 8; ++v) {
-        a = std::min(a, m->verts[24 * e + 3 * v + c]);
-        b = std::max(b, m->verts[24 * e + 3 * v + c]);
-      }
-      ext[e] = b - a;
+  std::vector<std::array<double, 3>> cen(ne);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t e = 0; e < ne; ++e)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int v = 0; v < 8; ++v) s += m->verts[24 * e + 3 * v + c];
+      cen[e][c] = s / 8.0;
+      lo[c] = std::min(lo[c], cen[e][c]);
+      hi[c] = std::max(hi[c], cen[e][c]);
     }
-    std::nth_element(ext.begin(), ext.begin() + ne / 2, ext.end());
-    h[c] = ext[ne / 2] > 0 ? ext[ne / 2] : 1.0;
-  }
+  std::function<uint64_t(int64_t)> key;
+  double h[3] = {1.0, 1.0, 1.0};
+  int64_t ntx = 1;
+  const int64_t T = order;
   auto cell = [&](int64_t e, int c) {
     return (int64_t)std::max(0.0, std::min(1048575.0, std::floor((cen[e][c] - lo[c]) / h[c] + 0.5)));
   };
-  int64_t ntx = 1;
-  for (int64_t e = 0; e < ne; ++e) ntx = std::max(ntx, cell(e, 0) / T + 1);
-  for (auto& kv : lst) {
-    const int64_t e = kv.second, ix = cell(e, 0), iy = cell(e, 1), iz = cell(e, 2);
-    const int64_t tx = ix / T, ty = iy / T;
-    const int64_t tile = ty * ntx + ((ty & 1) ? ntx - 1 - tx : tx);
-    const int64_t zz = (tile & 1) ? 1048575 - iz : iz;
-    kv.first = ((uint64_t)tile << 40) | ((uint64_t)zz << 20) | (uint64_t)((iy % T) * T + (ix % T));
+  if (order == 0) {
+    key = [&](int64_t e) {
+      uint64_t code = 0;
+      for (int c = 0; c < 3; ++c) {
+        const double span = hi[c] - lo[c];
+        const double t = span > 0 ? (cen[e][c] - lo[c]) / span : 0.0;
+        const uint64_t iv = (uint64_t)std::min(1048575.0, std::max(0.0, std::floor(t * 1048575.0)));
+        code |= spread3(iv) << c;
+      }
+      return code;
+    };
+  } else {
+    for (int c = 0; c < 3; ++c) {
+      std::vector<double> ext(ne);
+      for (int64_t e = 0; e < ne; ++e) {
+        double a = 1e300, b = -1e300;
+        for (int v = 0; v < 8; ++v) {
+          a = std::min(a, m->verts[24 * e + 3 * v + c]);
+          b = std::max(b, m->verts[24 * e + 3 * v + c]);
+        }
+        ext[e] = b - a;
+      }
+      std::nth_element(ext.begin(), ext.begin() + ne / 2, ext.end());
+      h[c] = ext[ne / 2] > 0 ? ext[ne / 2] : 1.0;
+    }
+    for (int64_t e = 0; e < ne; ++e) ntx = std::max(ntx, cell(e, 0) / T + 1);
+    key = [&](int64_t e) {
+      const int64_t ix = cell(e, 0), iy = cell(e, 1), iz = cell(e, 2);
+      const int64_t tx = ix / T, ty = iy / T;
+      const int64_t tile = ty * ntx + ((ty & 1) ? ntx - 1 - tx : tx);
+      const int64_t zz = (tile & 1) ? 1048575 - iz : iz;
+      return ((uint64_t)tile << 40) | ((uint64_t)zz << 20) | (uint64_t)((iy % T) * T + (ix % T));
+    };
   }
-  return true;
+  for (Group& g : m->groups) {
+    std::vector<std::pair<uint64_t, int32_t>> lst(g.ids.size());
+    for (size_t i = 0; i < g.ids.size(); ++i) lst[i] = {key(g.ids[i]), g.ids[i]};
+    std::sort(lst.begin(), lst.end());
+    for (size_t i = 0; i < lst.size(); ++i) g.ids[i] = lst[i].second;
+    if (g.d_list)
+      STDG_HIP(hipMemcpy(g.d_list, g.ids.data(), sizeof(int32_t) * g.count, hipMemcpyHostToDevice));
+  }
+  m->work_order = order;
+  return STDG_OK;
 }
 
 int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
@@ -438,20 +478,12 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
                                     " share a face but do not lie on its two sides");
     }
 
-  // groups in Morton order of the element centroids
+  // kernel groups by (a, q, affine); their work-list order is set below
   std::map<std::tuple<int, int, int>, std::vector<std::pair<uint64_t, int32_t>>> gm;
   for (int64_t e = 0; e < ne; ++e) {
-    uint64_t code = 0;
-    for (int c = 0; c < 3; ++c) {
-      double span = hi[c] - lo[c];
-      double t = span > 0 ? (cen[e][c] - lo[c]) / span : 0.0;
-      uint64_t iv = (uint64_t)std::min(1048575.0, std::max(0.0, std::floor(t * 1048575.0)));
-      code |= spread3(iv) << c;
-    }
     auto key = std::make_tuple(m->p[e] + 1, m->q[e], (m->info[e].flags & kAffine) ? 1 : 0);
-    gm[key].push_back({code, (int32_t)e});
+    gm[key].push_back({0, (int32_t)e});
   }
-  if (gm.size() == 1) (void)column_order(m, cen, lo, gm.begin()->second);
   m->p_max = *std::max_element(m->p.begin(), m->p.end());
   m->q_max = *std::max_element(m->q.begin(), m->q.end());
   m->groups.clear();
@@ -468,7 +500,7 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     for (size_t i = 0; i < lst.size(); ++i) g.ids[i] = lst[i].second;
     m->groups.push_back(std::move(g));
   }
-  return STDG_OK;
+  return set_work_order(m, default_work_order(*m));
 }
 
 size_t mesh_device_bytes(const Mesh& m) {

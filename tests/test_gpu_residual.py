@@ -174,3 +174,36 @@ def test_binding_checks_device_buffers(lib):
             stdg.stdg_energy(mh, t.zeros(info["state_size"] - 6, dtype=t.float64, device="cuda"))
     finally:
         stdg.stdg_mesh_free(mh)
+
+
+def test_work_order_and_autotune(lib, tmp_path):
+    # every element order gives bitwise the same apply; the autotuner returns
+    # one of its candidates, stores it in the cache and reuses it
+    stdg = lib.stdg
+    cfg = synth.cavity_two_material(n=8, p=3, q=2)
+    m = cfg["mesh"]
+    mh = lib.upload(m)
+    try:
+        assert stdg.stdg_mesh_info(mh)["work_order"] == 8
+        x = synth.random_vector(m.unknown_size(), 9)
+        ref = {}
+        for order in (0, 4, 8, 16, 3):
+            stdg.stdg_mesh_set_order(mh, order)
+            assert stdg.stdg_mesh_info(mh)["work_order"] == order
+            for prec in (0, 1):
+                y = lib.apply(mh, cfg["dt"], prec, stdg.STDG_OPERATOR_PRECOND, x)
+                ref.setdefault(prec, y)
+                assert np.array_equal(y, ref[prec])
+        with pytest.raises(stdg.StdgError):
+            stdg.stdg_mesh_set_order(mh, 1)
+        cache = str(tmp_path / "tune.json")
+        got = stdg.stdg_mesh_autotune(mh, stdg.STDG_FP32, cfg["dt"], reps=5, cache=cache)
+        assert got in (0, 4, 8, 16) and stdg.stdg_mesh_info(mh)["work_order"] == got
+        import json
+        table = json.load(open(cache))
+        assert list(table.values()) == [got]
+        stdg.stdg_mesh_set_order(mh, 0 if got else 4)
+        assert stdg.stdg_mesh_autotune(mh, stdg.STDG_FP32, cfg["dt"], cache=cache) == got
+        assert stdg.stdg_mesh_info(mh)["work_order"] == got
+    finally:
+        stdg.stdg_mesh_free(mh)
