@@ -144,12 +144,15 @@ int stdg_mesh_free(stdg_mesh* mesh);
  * T x T elements swept along the third axis (neighbour blocks stay in L2).
  * The upload picks columns of 8 for single-group meshes with small element
  * blocks, else Morton.  Results do not depend on the order (each output reads
- * only its element and its face neighbours).  STDG_E_ARG for other values. */
+ * only its element and its face neighbours).  STDG_E_ARG for other values.
+ * Synchronous (host to device copy of the lists); not to be called while work
+ * on the mesh is in flight. */
 int stdg_mesh_set_order(stdg_mesh* mesh, int32_t order);
 /* Autotuner: time `reps` preconditioned operator applies (precision prec,
  * scratch vectors allocated and freed inside the call) for each candidate
  * order (Morton, columns of 4, 8, 16), keep the fastest and return it in
- * *order_out.  Synchronises `stream`.  Callers that cache the choice (the
+ * *order_out.  Synchronises `stream`; not to be called while other work on
+ * the mesh is in flight.  Callers that cache the choice (the
  * Python binding keys a JSON file on the mesh's shape) apply it later with
  * stdg_mesh_set_order. */
 int stdg_mesh_autotune(stdg_mesh* mesh, int prec, double dt, int32_t reps, int32_t* order_out, void* stream);
