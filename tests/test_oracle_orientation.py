@@ -108,3 +108,23 @@ def test_energy_conserved_reoriented_trilinear():
     U = d.solve_direct(s0, 0.1)
     e0, e1 = d.energy(d.level_state(U, 0)), d.energy(d.level_state(U, 1))
     assert abs(e1 - e0) < 1e-12 * e0
+
+
+def test_relabelling_keeps_the_physical_mesh():
+    # every rotated element has the same vertex set and volume, and a face
+    # that does not match as a quadrilateral is refused
+    from oracle.geometry import face_map, face_vertices, jacobian
+    v, h = synth.box_mesh((2, 2, 2))
+    h2 = synth.reorient(h, seed=11)
+    for e in range(h.shape[0]):
+        assert sorted(h[e]) == sorted(h2[e])
+        det = np.linalg.det(jacobian(v[h2[e]], np.array([0.5, 0.5, 0.5])))
+        assert abs(det - np.linalg.det(jacobian(v[h[e]], np.array([0.5, 0.5, 0.5])))) < 1e-14
+    # element 1 meets element 0 across its face 0 (reference x = 0, corners
+    # 0, 2, 4, 6); two adjacent corners exchanged make the shared quadrilateral
+    # a bow-tie in element 1's numbering
+    assert sorted(face_vertices(h[0], 1)) == sorted(face_vertices(h[1], 0))
+    twisted = h[1].copy()
+    twisted[[0, 2]] = twisted[[2, 0]]
+    with pytest.raises(ValueError):
+        face_map(h[0], 1, twisted, 0)
