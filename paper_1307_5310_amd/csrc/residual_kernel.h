@@ -425,10 +425,6 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
 
   // The two uniform-degree paths come in two forms: elements whose
   // neighbours all meet them in canonical orientation (compile-time face
-  // axes, strides and components), and elements with a permuted face, whose
-  // neighbours are read on their own face f' through the face map.
-  // The two uniform-degree paths come in two forms: elements whose
-  // neighbours all meet them in canonical orientation (compile-time face
   // axes, strides and components), and, for affine kernels, elements with a
   // permuted face, whose neighbours are read on their own face f' through
   // the face map.  Trilinear kernels send permuted elements down the general
@@ -485,22 +481,22 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
           }
         __syncthreads();
         if (!face_lane) continue;
-          const int c = (alpha + 1 + (tc & 1)) % 3;
-          const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
-          const int ns = face_stride(alpha, A);
-          const T* src = stg + tc * CH + face_base(alpha, fu, fv, A);
-          // the neighbour's face sits at 1 - side: weights L_l(1 - side)
+        const int c = (alpha + 1 + (tc & 1)) % 3;
+        const T scale = pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + c] : T(1);
+        const int ns = face_stride(alpha, A);
+        const T* src = stg + tc * CH + face_base(alpha, fu, fv, A);
+        // the neighbour's face sits at 1 - side: weights L_l(1 - side)
 #pragma unroll
-          for (int ml = 0; ml < NL; ++ml) {
-            const int mp = ml + m0;
-            T tr = T(0);
+        for (int ml = 0; ml < NL; ++ml) {
+          const int mp = ml + m0;
+          T tr = T(0);
 #pragma unroll
-            for (int l = 0; l < A; ++l) tr += (side ? P.tab.tr0[l] : P.tab.tr1[l]) * src[ml * A3 + l * ns];
-            tr *= scale;
+          for (int l = 0; l < A; ++l) tr += (side ? P.tab.tr0[l] : P.tab.tr1[l]) * src[ml * A3 + l * ns];
+          tr *= scale;
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-              if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
-          }
+          for (int i = 0; i < Q; ++i)
+            if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
+        }
       }
     }
     __syncthreads();  // staging area is reused for the contracted levels
@@ -552,23 +548,23 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
           }
         __syncthreads();
         if (!face_lane) continue;
-          // the neighbour's face f' at the mapped mode, matched component and sign
-          const FaceMap fm = map_face(alpha, Ip->orient[g], (alpha + 1 + (tc & 1)) % 3, fu, fv);
-          const int slot = 2 * tf + (fm.cn == (fm.ax + 1) % 3 ? 0 : 1);
-          const T scale = (pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + fm.cn] : T(1)) * (fm.neg ? T(-1) : T(1));
-          const int ns = face_stride(fm.ax, A);
-          const T* src = stg + slot * CH + face_base(fm.ax, fm.mu, fm.mv, A);
+        // the neighbour's face f' at the mapped mode, matched component and sign
+        const FaceMap fm = map_face(alpha, Ip->orient[g], (alpha + 1 + (tc & 1)) % 3, fu, fv);
+        const int slot = 2 * tf + (fm.cn == (fm.ax + 1) % 3 ? 0 : 1);
+        const T scale = (pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + fm.cn] : T(1)) * (fm.neg ? T(-1) : T(1));
+        const int ns = face_stride(fm.ax, A);
+        const T* src = stg + slot * CH + face_base(fm.ax, fm.mu, fm.mv, A);
 #pragma unroll
-          for (int ml = 0; ml < NL; ++ml) {
-            const int mp = ml + m0;
-            T tr = T(0);
+        for (int ml = 0; ml < NL; ++ml) {
+          const int mp = ml + m0;
+          T tr = T(0);
 #pragma unroll
-            for (int l = 0; l < A; ++l) tr += (fm.so ? P.tab.tr1[l] : P.tab.tr0[l]) * src[ml * A3 + l * ns];
-            tr *= scale;
+          for (int l = 0; l < A; ++l) tr += (fm.so ? P.tab.tr1[l] : P.tab.tr0[l]) * src[ml * A3 + l * ns];
+          tr *= scale;
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-              if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
-          }
+          for (int i = 0; i < Q; ++i)
+            if (nnzN(i, mp)) acc[g][i] += P.tab.N[i][mp] * tr;
+        }
       }
     }
     __syncthreads();  // staging area is reused for the contracted levels
