@@ -57,7 +57,7 @@ extern "C" {
 typedef enum {
   STDG_OK = 0,
   STDG_E_ARG = -1,           /* invalid argument (null, size, range)           */
-  STDG_E_UNSUPPORTED = -2,   /* valid but not implemented (e.g. face orientation) */
+  STDG_E_UNSUPPORTED = -2,   /* valid but not implemented (e.g. a hanging face) */
   STDG_E_NOMEM = -3,         /* device or host allocation failed                */
   STDG_E_DEVICE = -4,        /* HIP runtime error or missing GPU                */
   STDG_E_NOT_CONVERGED = -5, /* solver hit its iteration limit (info is filled) */

@@ -51,6 +51,15 @@ def _mesh_desc(vertices, hexes, p, q, eps, mu):
     q = np.ascontiguousarray(q, dtype=np.int32)
     eps = np.ascontiguousarray(eps, dtype=np.float64)
     mu = np.ascontiguousarray(mu, dtype=np.float64)
+    # the library reads n_elements entries of every per-element array and
+    # 3 n_vertices / 8 n_elements of the coordinates and connectivity
+    if v.ndim != 2 or v.shape[1] != 3:
+        raise ValueError("vertices must have shape (n_vertices, 3), got %s" % (v.shape,))
+    if h.ndim != 2 or h.shape[1] != 8:
+        raise ValueError("hexes must have shape (n_elements, 8), got %s" % (h.shape,))
+    for name, a in (("p", p), ("q", q), ("eps", eps), ("mu", mu)):
+        if a.shape != (h.shape[0],):
+            raise ValueError("%s must have shape (%d,), got %s" % (name, h.shape[0], a.shape))
     d = MeshDesc(v.shape[0], v.ctypes.data, h.shape[0], h.ctypes.data, p.ctypes.data,
                  q.ctypes.data, eps.ctypes.data, mu.ctypes.data)
     return d, (v, h, p, q, eps, mu)

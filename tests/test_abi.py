@@ -35,3 +35,21 @@ def test_null_arguments_rejected():
     assert L.stdg_mesh_info(None, None) == -1
     assert L.stdg_finalize(None) == -1
     assert b"NULL" in L.stdg_last_error()
+
+
+def test_mesh_arrays_checked_before_the_library_reads_them():
+    # the library reads n_elements entries of each per-element array: the
+    # binding refuses arrays of other shapes before passing their addresses
+    import numpy as np
+    import synth
+    v, h = synth.box_mesh((2, 1, 1))
+    ok = [v, h, np.full(2, 2), np.full(2, 1), np.ones(2), np.ones(2)]
+    d, _keep = stdg._mesh_desc(*ok)
+    assert d.n_elements == 2 and d.n_vertices == v.shape[0]
+    bad = [(0, v[:, :2]), (0, v.ravel()), (1, h[:, :6]), (1, h.ravel()),
+           (2, np.full(1, 2)), (3, np.full(3, 1)), (4, np.ones((2, 1))), (5, np.ones(1))]
+    for k, arr in bad:
+        args = list(ok)
+        args[k] = arr
+        with pytest.raises(ValueError):
+            stdg._mesh_desc(*args)

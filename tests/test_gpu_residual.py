@@ -207,3 +207,34 @@ def test_work_order_and_autotune(lib, tmp_path):
         assert stdg.stdg_mesh_info(mh)["work_order"] == got
     finally:
         stdg.stdg_mesh_free(mh)
+
+
+def test_upload_refuses_invalid_meshes(lib):
+    # the library's own checks (STDG_E_ARG), each naming what is wrong; a
+    # valid mesh uploads after every refusal
+    stdg = lib.stdg
+    v, h = synth.box_mesh((2, 1, 1))
+    base = dict(v=v, h=h, p=np.full(2, 2, np.int32), q=np.full(2, 1, np.int32), eps=np.ones(2), mu=np.ones(2))
+
+    def upload(**kw):
+        a = dict(base)
+        a.update(kw)
+        return stdg.stdg_mesh_upload(lib.ctx, a["v"], a["h"], a["p"], a["q"], a["eps"], a["mu"])
+
+    inverted = h.copy()
+    inverted[1] = inverted[1][[1, 0, 3, 2, 5, 4, 7, 6]]       # mirrored along x-hat: negative Jacobian
+    far = h.copy()
+    far[1, 0] = v.shape[0]
+    cases = [("empty mesh", dict(h=h[:0], p=base["p"][:0], q=base["q"][:0], eps=base["eps"][:0], mu=base["mu"][:0])),
+             ("p must", dict(p=np.array([2, 9], np.int32))), ("p must", dict(p=np.array([0, 2], np.int32))),
+             ("q must", dict(q=np.array([7, 1], np.int32))), ("q must", dict(q=np.array([1, 0], np.int32))),
+             ("eps and mu", dict(eps=np.array([1.0, 0.0]))), ("eps and mu", dict(mu=np.array([1.0, np.nan]))),
+             ("vertex id", dict(h=far)), ("inverted", dict(h=inverted))]
+    for fragment, kw in cases:
+        note("refusal: %s" % fragment)
+        with pytest.raises(stdg.StdgError) as ei:
+            upload(**kw)
+        assert ei.value.status == -1 and fragment in str(ei.value), (fragment, str(ei.value))
+    mh = upload()
+    assert stdg.stdg_mesh_info(mh)["n_elements"] == 2
+    stdg.stdg_mesh_free(mh)
