@@ -53,3 +53,14 @@ def test_mesh_arrays_checked_before_the_library_reads_them():
         args[k] = arr
         with pytest.raises(ValueError):
             stdg._mesh_desc(*args)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no fallback path: without the built library every entry point raises
+    from paper_1307_5310_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libstdg.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError, match="no fallback"):
+        _lib.lib()
+    with pytest.raises(ImportError):
+        stdg.stdg_version()
