@@ -140,31 +140,56 @@ def _tune_key(mesh, prec):
         i["q_max"], i["unknown_size"], int(prec))
 
 
+def _tune_cache_read(path):
+    """The cached choices in `path`, or {} when the file is missing or not a
+    JSON object of integers (it is then rewritten on the next store)."""
+    import json
+    try:
+        with open(path) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    if not isinstance(table, dict) or not all(isinstance(v, int) for v in table.values()):
+        return {}
+    return table
+
+
+def _tune_cache_write(path, table):
+    """Replace `path` atomically (a temporary file of its own in the same
+    directory, so concurrent writers never share one)."""
+    import json
+    import os
+    import tempfile
+    fd, tmp = tempfile.mkstemp(prefix=os.path.basename(path) + ".", dir=os.path.dirname(os.path.abspath(path)))
+    try:
+        with os.fdopen(fd, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except BaseException:
+        if os.path.exists(tmp):
+            os.remove(tmp)
+        raise
+
+
 def stdg_mesh_autotune(mesh, prec=STDG_FP32, dt=0.01, reps=10, cache=None, stream=None):
     """Pick the kernels' element order for this mesh by timing (C ABI
     stdg_mesh_autotune) and return it.  With a cache file (argument, or the
     STDG_TUNE_CACHE environment variable) a choice stored for a mesh of the
     same shape is applied without timing, and new choices are stored."""
-    import json
     import os
     path = cache or os.environ.get("STDG_TUNE_CACHE")
     key = _tune_key(mesh, prec)
-    table = {}
-    if path and os.path.exists(path):
-        with open(path) as f:
-            table = json.load(f)
-        if key in table:
-            stdg_mesh_set_order(mesh, table[key])
-            return int(table[key])
+    table = _tune_cache_read(path) if path else {}
+    if key in table:
+        stdg_mesh_set_order(mesh, table[key])
+        return int(table[key])
     out = ctypes.c_int32()
     check(lib().stdg_mesh_autotune(mesh, int(prec), float(dt), int(reps), ctypes.byref(out),
                                    stream_handle(stream)))
     if path:
+        table = _tune_cache_read(path)   # keep what other processes stored meanwhile
         table[key] = int(out.value)
-        tmp = path + ".tmp"
-        with open(tmp, "w") as f:
-            json.dump(table, f, indent=1, sort_keys=True)
-        os.replace(tmp, path)
+        _tune_cache_write(path, table)
     return int(out.value)
 
 

@@ -64,3 +64,18 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         _lib.lib()
     with pytest.raises(ImportError):
         stdg.stdg_version()
+
+
+def test_tune_cache_read_and_write(tmp_path):
+    # a missing or damaged cache reads as empty; writes replace the file whole
+    path = str(tmp_path / "tune.json")
+    assert stdg._tune_cache_read(path) == {}
+    stdg._tune_cache_write(path, {"a": 8})
+    assert stdg._tune_cache_read(path) == {"a": 8}
+    for junk in ("{not json", "[1, 2]", '{"a": "x"}'):
+        with open(path, "w") as f:
+            f.write(junk)
+        assert stdg._tune_cache_read(path) == {}
+    stdg._tune_cache_write(path, {"a": 4, "b": 0})
+    assert stdg._tune_cache_read(path) == {"a": 4, "b": 0}
+    assert sorted(p.name for p in tmp_path.iterdir()) == ["tune.json"]
