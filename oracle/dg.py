@@ -455,10 +455,12 @@ class Discretisation:
         blk = U[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, qe + 1, a3)
         return blk.transpose(0, 1, 3, 2).reshape(2, 3 * a3, qe + 1)
 
-    def embed_unknowns(self, x, l0_state=None):
-        """Full trial vector from unknowns (m = 1..q) and an optional l_0 state."""
+    def embed_unknowns(self, x, l0_state=None, elements=None):
+        """Full trial vector from unknowns (m = 1..q) and an optional l_0 state.
+        With ``elements`` only those blocks are filled (others left 0)."""
         U = np.zeros(self.trial_off[-1])
-        for e in range(self.ne):
+        for e in (range(self.ne) if elements is None else elements):
+            e = int(e)
             a3 = int(self.a[e]) ** 3
             qe = int(self.q[e])
             blk = U[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, qe + 1, a3)
