@@ -90,6 +90,15 @@ int stdg_version(void);
 /* Thread-local message of the last failure on this thread ("" if none). */
 const char* stdg_last_error(void);
 
+/* sizeof() of each public struct below, so that a binding which mirrors the
+ * structs (ctypes, FFI) can check its layout against the built library before
+ * passing any of them; 0 for an unknown `which`.  Needs no device. */
+enum {
+  STDG_STRUCT_MESH_DESC = 0, STDG_STRUCT_MESH_INFO = 1, STDG_STRUCT_SOURCE = 2, STDG_STRUCT_SOLVE_OPTS = 3,
+  STDG_STRUCT_SOLVE_INFO = 4, STDG_STRUCT_SERVE_OPTS = 5, STDG_STRUCT_REQUEST = 6, STDG_STRUCT_RESULT = 7
+};
+size_t stdg_struct_size(int32_t which);
+
 /* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the
  * device memory the context's meshes, solvers and servers may allocate
  * (0 = 90% of the device's free memory).  Fails with STDG_E_DEVICE when no
@@ -320,6 +329,9 @@ typedef struct {
   const double* init_state;  /*   an FP64 state (host, state layout) if not NULL    */
   double c_diss;             /* >= 0: dissipative stabilisation D_h with this c, as  */
                              /*   stdg_mesh_set_dissipation (affine meshes; 0 = off) */
+  int64_t init_state_size;   /* entries at init_state: must equal the mesh's state
+                                size (sum of 6 (p+1)^3), else STDG_E_ARG; ignored
+                                when init_state is NULL                             */
 } stdg_request;
 
 typedef struct {

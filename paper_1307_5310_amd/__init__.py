@@ -297,9 +297,13 @@ def stdg_serve_submit(server, vertices, hexes, p, q, eps, mu, t0, dt, n_slabs, s
         keep2 += [mnl, abc]
         r.n_modes, r.mnl, r.abc = mnl.shape[0], mnl.ctypes.data, abc.ctypes.data
     if init_state is not None:
-        init_state = np.ascontiguousarray(init_state, dtype=np.float64)
+        init_state = np.ascontiguousarray(init_state, dtype=np.float64).ravel()
+        need = int((6 * (np.asarray(p, dtype=np.int64) + 1) ** 3).sum())
+        if init_state.size != need:
+            raise ValueError("init_state has %d entries, the mesh's state size is %d" % (init_state.size, need))
         keep2.append(init_state)
         r.init_state = init_state.ctypes.data
+        r.init_state_size = init_state.size
     t = ctypes.c_uint64()
     check(lib().stdg_serve_submit(server, ctypes.byref(r), ctypes.byref(t)))
     return t.value
@@ -310,6 +314,9 @@ def stdg_serve_poll(server, ticket, state_out=None):
     is written into state_out, a float64 numpy array, when given)."""
     res = Result()
     if state_out is not None:
+        if not (isinstance(state_out, np.ndarray) and state_out.dtype == np.float64
+                and state_out.flags["C_CONTIGUOUS"] and state_out.flags["WRITEABLE"]):
+            raise ValueError("state_out must be a writeable C-contiguous float64 numpy array")
         res.state = state_out.ctypes.data
         res.state_capacity = state_out.size
     st = lib().stdg_serve_poll(server, ctypes.c_uint64(int(ticket)), ctypes.byref(res))

@@ -85,7 +85,7 @@ class Request(ctypes.Structure):
     _fields_ = [("mesh", MeshDesc), ("t0", ctypes.c_double), ("dt", ctypes.c_double),
                 ("n_slabs", ctypes.c_int32), ("source", Source), ("n_modes", ctypes.c_int32),
                 ("mnl", ctypes.c_void_p), ("abc", ctypes.c_void_p), ("init_state", ctypes.c_void_p),
-                ("c_diss", ctypes.c_double)]
+                ("c_diss", ctypes.c_double), ("init_state_size", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):
@@ -97,6 +97,9 @@ class Result(ctypes.Structure):
                 ("eta_it", ctypes.c_double),
                 ("state", ctypes.c_void_p), ("state_capacity", ctypes.c_int64)]
 
+
+# in the order of the STDG_STRUCT_* indices of stdg_struct_size
+STRUCTS = (MeshDesc, MeshInfo, Source, SolveOpts, SolveInfo, ServeOpts, Request, Result)
 
 _lib = None
 
@@ -112,6 +115,7 @@ def lib():
         vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         sig = {
             "stdg_version": ([], ctypes.c_int),
+            "stdg_struct_size": ([i32], ctypes.c_size_t),
             "stdg_last_error": ([], ctypes.c_char_p),
             "stdg_init": ([ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)], ctypes.c_int),
             "stdg_finalize": ([vp], ctypes.c_int),
@@ -139,6 +143,11 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = res
+        # the structs mirrored here must match the library's layout
+        for which, st in enumerate(STRUCTS):
+            if L.stdg_struct_size(which) != ctypes.sizeof(st):
+                raise ImportError("libstdg.so struct %s is %d bytes, the binding's %d: rebuild the library"
+                                  % (st.__name__, L.stdg_struct_size(which), ctypes.sizeof(st)))
         _lib = L
     return _lib
 

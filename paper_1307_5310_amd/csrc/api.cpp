@@ -64,7 +64,21 @@ using namespace stdg;
 
 extern "C" {
 
-int stdg_version(void) { return (1 << 16) | 0; }
+int stdg_version(void) { return (1 << 16) | 1; }
+
+size_t stdg_struct_size(int32_t which) {
+  switch (which) {
+    case STDG_STRUCT_MESH_DESC: return sizeof(stdg_mesh_desc);
+    case STDG_STRUCT_MESH_INFO: return sizeof(stdg_mesh_info_t);
+    case STDG_STRUCT_SOURCE: return sizeof(stdg_source);
+    case STDG_STRUCT_SOLVE_OPTS: return sizeof(stdg_solve_opts);
+    case STDG_STRUCT_SOLVE_INFO: return sizeof(stdg_solve_info);
+    case STDG_STRUCT_SERVE_OPTS: return sizeof(stdg_serve_opts);
+    case STDG_STRUCT_REQUEST: return sizeof(stdg_request);
+    case STDG_STRUCT_RESULT: return sizeof(stdg_result);
+    default: return 0;
+  }
+}
 
 const char* stdg_last_error(void) { return g_last_error.c_str(); }
 

@@ -121,6 +121,11 @@ struct Mesh {
   std::vector<Group> groups;
   int n_affine, n_nonaffine, n_diag;
   int work_order = 0;  // work-list order of the groups: 0 Morton, T >= 2 columns of T x T
+  // bumped by every change that captured launches would not see: D_h switched
+  // on or off (its device coefficients are freed or allocated), the work lists
+  // rewritten, the preconditioner scratch reallocated.  A slab solver drops
+  // its captured graphs when the epoch differs from the one they were captured at.
+  uint64_t epoch = 0;
   // materials and metric bounds for the iteration-error bound: min eps, min mu,
   // and max over elements of 1 / lambda_min(|J| DF^{-1} DF^{-T}) (centre metric)
   double eps_min = 0.0, mu_min = 0.0, inv_gmin = 0.0;

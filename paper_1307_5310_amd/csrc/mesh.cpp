@@ -175,6 +175,7 @@ int default_work_order(const Mesh& m) {
 
 int set_work_order(Mesh* m, int order) {
   if (order != 0 && (order < 2 || order > 64)) return fail(STDG_E_ARG, "work order must be 0 (Morton) or 2..64");
+  ++m->epoch;
   const int64_t ne = m->ne;
   std::vector<std::array<double, 3>> cen(ne);
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -557,6 +558,7 @@ int set_dissipation(Mesh* m, double c) {
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(STDG_E_ARG, "dissipation coefficient must be finite and >= 0");
   if (c > 0.0 && m->n_nonaffine > 0)
     return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation needs affine elements (constant face metric)");
+  ++m->epoch;
   const size_t bytes = sizeof(double) * Mesh::kDissWords * m->ne, bytes32 = sizeof(float) * Mesh::kDissWords * m->ne;
   if (c == 0.0) {
     if (m->d_diss) {

@@ -111,13 +111,17 @@ int launch_residual(const ApplyArgs& a) {
   int mode = a.mode;
   const void* x = a.x;
   if (mode == STDG_OPERATOR_PRECOND && m->n_diag != m->ne) {
-    // non-diagonal metric somewhere: scale into the mesh's scratch, then plain operator
+    // non-diagonal metric somewhere: scale into the mesh's scratch, then plain
+    // operator.  The scratch is sized for FP64 on first use, so a later call in
+    // the other precision never moves it under captured launches; the epoch is
+    // bumped all the same should it ever be (re)allocated.
     Mesh* mm = const_cast<Mesh*>(m);
-    size_t need = (size_t)m->unk_off.back() * (a.prec == STDG_FP64 ? 8 : 4);
+    const size_t need = (size_t)m->unk_off.back() * sizeof(double);
     if (mm->scratch_bytes < need) {
       if (mm->d_scratch) dev_free(mm->ctx, mm->d_scratch, mm->scratch_bytes);
       mm->d_scratch = nullptr;
       mm->scratch_bytes = 0;
+      ++mm->epoch;
       int rc = dev_alloc(mm->ctx, &mm->d_scratch, need);
       if (rc != STDG_OK) return rc;
       mm->scratch_bytes = need;

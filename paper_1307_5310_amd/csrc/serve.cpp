@@ -422,7 +422,13 @@ int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ti
         r->mnl.assign(req->mnl, req->mnl + 3 * req->n_modes);
         r->abc.assign(req->abc, req->abc + 3 * req->n_modes);
       }
-      if (req->init_state) r->init.assign(req->init_state, req->init_state + r->n_state);
+      if (req->init_state) {
+        if (req->init_state_size != r->n_state)
+          rc = fail(STDG_E_ARG, "stdg_serve_submit: init_state_size " + std::to_string(req->init_state_size) +
+                                    " != the mesh's state size " + std::to_string(r->n_state));
+        else
+          r->init.assign(req->init_state, req->init_state + r->n_state);
+      }
       if (req->c_diss > 0.0 && m.n_nonaffine > 0)
         rc = fail(STDG_E_UNSUPPORTED, "stdg_serve_submit: dissipative stabilisation needs affine elements");
     }

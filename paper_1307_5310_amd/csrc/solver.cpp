@@ -268,9 +268,12 @@ int SlabSolver::launch_iteration() {
   // graphs for meshes with one kernel group (no side-stream fork); the first
   // use of an index runs directly (it also sizes any lazily allocated scratch)
   const bool graph = o_.use_graph && m_->groups.size() == 1;
-  if (graph && graph_dt_ != dt_) {
+  if (graph && (graph_dt_ != dt_ || graph_epoch_ != m_->epoch)) {
+    // a new dt, or a mesh change that moved or replaced what the captured
+    // launches read (D_h coefficients, work lists, scratch): recapture
     drop_graphs();
     graph_dt_ = dt_;
+    graph_epoch_ = m_->epoch;
   }
   if (graph && seen_[j]) {
     if (!gexec_[j]) {

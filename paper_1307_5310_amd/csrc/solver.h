@@ -104,6 +104,7 @@ class SlabSolver {
   hipStream_t cap_ = nullptr;  // capture stream (the caller's may be the null stream, which cannot capture)
   bool seen_[kMaxBasis] = {};
   double graph_dt_ = 0.0;
+  uint64_t graph_epoch_ = 0;  // mesh epoch the graphs were captured at
   DotWork dw_;
   double *hv_ = nullptr, *etmp_ = nullptr;  // device scalars (layout kH1.. in solver.cpp)
   double* hb_ = nullptr;                    // pinned host copy of the scalars

@@ -79,3 +79,28 @@ def test_tune_cache_read_and_write(tmp_path):
     stdg._tune_cache_write(path, {"a": 4, "b": 0})
     assert stdg._tune_cache_read(path) == {"a": 4, "b": 0}
     assert sorted(p.name for p in tmp_path.iterdir()) == ["tune.json"]
+
+
+def test_struct_layouts_match_the_library():
+    from paper_1307_5310_amd import _lib
+    L = stdg.lib()
+    for which, st in enumerate(_lib.STRUCTS):
+        assert L.stdg_struct_size(which) == ctypes.sizeof(st), st.__name__
+    assert L.stdg_struct_size(99) == 0
+
+
+def test_serving_buffers_checked_before_the_library_reads_them():
+    # poll copies the final state into state_out: only a writeable C-contiguous
+    # float64 array is accepted; submit reads init_state's declared length,
+    # which must be the mesh's state size (both refused before any call)
+    import numpy as np
+    import synth
+    for bad in (np.zeros(10, dtype=np.float32), np.zeros((10, 2))[:, 0], [0.0] * 10):
+        with pytest.raises(ValueError):
+            stdg.stdg_serve_poll(None, 1, state_out=bad)
+    v, h = synth.box_mesh((2, 1, 1))
+    n_state = 2 * 6 * 3 ** 3
+    for size in (n_state - 1, n_state + 5):
+        with pytest.raises(ValueError):
+            stdg.stdg_serve_submit(None, v, h, np.full(2, 2), np.full(2, 1), np.ones(2), np.ones(2), 0.0, 0.1, 1,
+                                   init_state=np.zeros(size))

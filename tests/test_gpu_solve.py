@@ -247,3 +247,60 @@ def test_graph_replay_is_bitwise(lib, inner, krylov):
             lib.stdg.stdg_mesh_free(mh)
         assert out[0][1] == out[1][1] and out[0][1] > 20
         assert np.array_equal(out[0][0], out[1][0])
+
+
+def _march(lib, m, steps, graph, state0):
+    """Run `steps` (callables taking (mesh handle, state tensor, graph flag)) on
+    a fresh upload of m; returns the states after each step."""
+    mh = lib.upload(m)
+    st = lib.dev(state0, lib.torch.float64)
+    out = []
+    try:
+        for step in steps:
+            step(mh, st, graph)
+            out.append(st.cpu().numpy().copy())
+    finally:
+        lib.stdg.stdg_mesh_free(mh)
+    return out
+
+
+def test_graphs_recaptured_after_mesh_changes(lib):
+    """Captured Arnoldi iterations are dropped when the mesh changes what they
+    read: the dissipative coefficients switched off between two graph solves,
+    and (sheared mesh) an FP64 preconditioned apply between two FP32 graph
+    solves.  Each sequence is bitwise the same sequence without graphs."""
+    stdg = lib.stdg
+    cfg = synth.cavity_two_material(n=4, p=3, q=2)
+    m = cfg["mesh"]
+    s0 = synth.random_vector(m.state_size(), 8)
+    opts = dict(inner_prec=1, krylov_prec=1, rtol=1e-12, max_iters=3000, max_refine=300)
+
+    def solve(mh, st, graph):
+        r = stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, st, use_graph=graph, **opts)
+        assert r["status"] == 0 and r["iters"] > 12
+
+    def diss(c):
+        return lambda mh, st, graph: stdg.stdg_mesh_set_dissipation(mh, c)
+    steps = [diss(0.5), solve, diss(0.0), solve, diss(0.8), solve]
+    note("graph epoch: dissipation on / off between graph solves")
+    ref = _march(lib, m, steps, False, s0)
+    got = _march(lib, m, steps, True, s0)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+    ms = synth.Mesh(synth.affine_transform(m.vertices, np.array([[1.0, 0.2, 0.0], [0.0, 1.0, 0.1],
+                                                                   [0.1, 0.0, 1.0]])),
+                    m.hexes, m.p, m.q, m.eps, m.mu, shape=m.shape)
+    xr = synth.random_vector(m.unknown_size(), 9)
+
+    def apply64(mh, st, graph):
+        x = lib.dev(xr, lib.torch.float64)
+        y = lib.torch.empty_like(x)
+        stdg.stdg_residual_apply(mh, cfg["dt"], stdg.STDG_FP64, stdg.STDG_OPERATOR_PRECOND, x, None, y)
+        lib.torch.cuda.synchronize()
+    steps = [solve, apply64, solve, solve]
+    note("graph epoch: sheared mesh, FP64 preconditioned apply between FP32 graph solves")
+    ref = _march(lib, ms, steps, False, s0)
+    got = _march(lib, ms, steps, True, s0)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
