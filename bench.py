@@ -40,6 +40,13 @@ def parse():
     # enough untimed applies (~0.1 s) for the GPU to reach steady clocks: with
     # 10 the timed applies still ran ~10% slower than in steady state
     ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--settle-s", type=float, default=1.0,
+                    help="seconds of untimed applies before the warm-up steps, so that the GPU's clocks "
+                         "have settled whatever --warmup is (a few warm-up steps alone leave the timed "
+                         "applies ~20%% slower)")
+    ap.add_argument("--dist-steps", type=int, default=50,
+                    help="extra applies timed one by one (an event pair each) after the timed region, "
+                         "for the p10/p50/p90 of the launch duration (0 = skip)")
     ap.add_argument("--n", type=int, default=32, help="mesh is n^3 elements")
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--q", type=int, default=3)
@@ -68,13 +75,47 @@ def parse():
     return ap.parse_args()
 
 
-def time_applies(stdg, torch, mh, dt, prec, mode, x, y, steps, warmup):
-    """Wall time of `steps` applies after `warmup` untimed ones, and the
-    average launch duration from one pair of HIP events on the launch stream
-    bracketing the timed launches (one kernel per apply on this mesh; the
-    average includes the short gaps between launches).  Events between the
-    launches would themselves add 1-3% to each step."""
+def settle(stdg, torch, mh, dt, prec, mode, x, y, seconds):
+    """Untimed applies for `seconds` of wall time (clock ramp-up)."""
+    if seconds <= 0:
+        return 0
     stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            stdg.stdg_residual_apply(mh, dt, prec, mode, x, None, y, stream)
+        n += 20
+        torch.cuda.synchronize()
+    return n
+
+
+def launch_distribution(stdg, torch, mh, dt, prec, mode, x, y, steps):
+    """p10 / p50 / p90 of the launch duration (ms), one event pair per apply,
+    measured after the timed region (the events themselves add a little)."""
+    if steps <= 0:
+        return None
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        stdg.stdg_residual_apply(mh, dt, prec, mode, x, None, y, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    d = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"p10_ms": round(float(np.percentile(d, 10)), 5), "p50_ms": round(float(np.percentile(d, 50)), 5),
+            "p90_ms": round(float(np.percentile(d, 90)), 5), "launches": steps}
+
+
+def time_applies(stdg, torch, mh, dt, prec, mode, x, y, steps, warmup, settle_s=0.0):
+    """Wall time of `steps` applies after `warmup` untimed ones (preceded by
+    `settle_s` seconds of untimed applies), and the average launch duration
+    from one pair of HIP events on the launch stream bracketing the timed
+    launches (one kernel per apply on this mesh; the average includes the
+    short gaps between launches).  Events between the launches would
+    themselves add 1-3% to each step."""
+    stream = torch.cuda.current_stream()
+    settle(stdg, torch, mh, dt, prec, mode, x, y, settle_s)
     for _ in range(warmup):
         stdg.stdg_residual_apply(mh, dt, prec, mode, x, None, y, stream)
     torch.cuda.synchronize()
@@ -112,6 +153,40 @@ def measured_traffic(prec, variant=""):
     return None
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_small():
+    """The oracle on the small cavity (4^3, p = 2, q = 1, dt = 0.05) in full:
+    one residual apply and the direct solve of its first slab from TE101."""
+    import synth
+    from oracle import fields
+    from oracle.dg import Discretisation
+    cfg = synth.cavity_small()
+    m = cfg["mesh"]
+    d = Discretisation(m.vertices, m.hexes, m.p, m.q, m.eps, m.mu)
+    U = synth.random_vector(d.trial_off[-1], 0)
+    d.residual(U, cfg["dt"])  # reference matrices cached outside the timing
+    t = time.perf_counter()
+    d.residual(U, cfg["dt"])
+    t_apply = time.perf_counter() - t
+    s0 = fields.project(d, fields.te101, 0.0)
+    t = time.perf_counter()
+    d.solve_direct(s0, cfg["dt"])
+    t_solve = time.perf_counter() - t
+    return {"apply_s": round(t_apply, 4), "slab_solve_direct_s": round(t_solve, 4),
+            "trial_dof": int(d.trial_off[-1])}
+
+
 def cpu_baseline(cfg, sample_n):
     """The oracle as it stands, on a bounded sample of the workload's elements."""
     from oracle.dg import Discretisation
@@ -140,7 +215,10 @@ def cpu_baseline(cfg, sample_n):
     a = int(m.p[0]) + 1
     q = int(m.q[0])
     dof = 6 * (q + 1) * a ** 3 * sample_n
-    return {"value": dof / el / 1e9, "unit": "GDoF/s", "cores": int(threads), "kind": "oracle",
+    small = oracle_small()
+    return {"value": dof / el / 1e9, "unit": "GDoF/s", "cores": int(threads), "cpu_model": cpu_model(),
+            "small_cavity": small,
+            "kind": "oracle",
             "sample": "%d random elements of the %d-element mesh, operator apply (dense local blocks), %.1f s"
                       % (sample_n, m.n_elements, el)}
 
@@ -187,11 +265,15 @@ def main():
         log("calibration copy of %d MiB done" % args.calib_copy_mib)
         del src, dst
 
-    log("FP32 apply: %d warmup + %d timed" % (args.warmup, args.steps))
+    log("FP32 apply: %.1f s settle + %d warmup + %d timed" % (args.settle_s, args.warmup, args.steps))
     torch.cuda.synchronize()
-    wall32, per32 = time_applies(stdg, torch, mh, dt, stdg.STDG_FP32, mode, x32, y32, args.steps, args.warmup)
-    log("FP64 apply: %d warmup + %d timed" % (args.warmup, args.steps))
-    wall64, per64 = time_applies(stdg, torch, mh, dt, stdg.STDG_FP64, mode, x64, y64, args.steps, args.warmup)
+    wall32, per32 = time_applies(stdg, torch, mh, dt, stdg.STDG_FP32, mode, x32, y32, args.steps, args.warmup,
+                                 args.settle_s)
+    dist32 = launch_distribution(stdg, torch, mh, dt, stdg.STDG_FP32, mode, x32, y32, args.dist_steps)
+    log("FP64 apply: %.1f s settle + %d warmup + %d timed" % (args.settle_s, args.warmup, args.steps))
+    wall64, per64 = time_applies(stdg, torch, mh, dt, stdg.STDG_FP64, mode, x64, y64, args.steps, args.warmup,
+                                 args.settle_s)
+    dist64 = launch_distribution(stdg, torch, mh, dt, stdg.STDG_FP64, mode, x64, y64, args.dist_steps)
     ms32 = wall32 * 1e3 / args.steps
     ms64 = wall64 * 1e3 / args.steps
     k32 = float(per32.mean())
@@ -269,8 +351,10 @@ def main():
                                % (args.n, args.p, args.q, dt),
                    "elements": ne, "trial_dof": trial_dof, "unknowns": nu,
                    "work_order": "Morton" if order == 0 else "columns of %d" % order},
+        "settle_s": args.settle_s,
+        "launch_ms_fp32": dist32,
         "fp64": {"value": round(gdofs64, 2), "unit": "GDoF/s", "ms_per_step": round(ms64, 5),
-                 "kernel_ms": round(k64, 5),
+                 "kernel_ms": round(k64, 5), "launch_ms": dist64,
                  "hbm_frac": round(bytes64 / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "fp32_over_fp64": round(gdofs32 / gdofs64, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -620,30 +620,37 @@ class Discretisation:
         time unless given); the H part is zero (g = 0).  J(x [P,3], t) -> [P,3]."""
         L = np.zeros(self.unk_off[-1])
         for e in range(self.ne):
-            a = int(self.a[e])
-            qe = int(self.q[e])
-            n = a + 2 if nx is None else nx
-            m = qe + 3 if nt is None else nt
-            pts, w = tensor_points(n)
-            tx, tw = basis.gauss01(m)
-            X = self.X(e)
-            x = map_point(X, pts)
-            DF = jacobian(X, pts)
-            det = np.linalg.det(DF)
-            Dinv = np.linalg.inv(DF)
-            Phi, _ = basis_at(a, pts)
-            acc = np.zeros((3, qe, a ** 3))
-            for tau, wt in zip(tx, tw):
-                Jv = J(x, t0 + tau * dt)                            # [P, 3]
-                # J . DF^{-T} e_c = (DF^{-1} J)_c
-                Jr = np.einsum("pcm,pm->pc", Dinv, Jv) * (det * w)[:, None]
-                proj = Jr.T @ Phi                                   # [3, a^3]
-                for i in range(qe):
-                    acc[:, i, :] += dt * wt * basis.L(i, tau) * proj
-            blk = np.zeros((2, 3, qe, a ** 3))
-            blk[0] = acc
-            L[self.unk_off[e]:self.unk_off[e + 1]] = blk.ravel()
+            L[self.unk_off[e]:self.unk_off[e + 1]] = self._load_block(e, J, t0, dt, nx, nt)
         return L
+
+    def load_rows(self, J, t0, dt, elements, nx=None, nt=None):
+        """The load blocks of the given elements only: {e: block}, each as in load()."""
+        return {int(e): self._load_block(int(e), J, t0, dt, nx, nt) for e in elements}
+
+    def _load_block(self, e, J, t0, dt, nx, nt):
+        a = int(self.a[e])
+        qe = int(self.q[e])
+        n = a + 2 if nx is None else nx
+        m = qe + 3 if nt is None else nt
+        pts, w = tensor_points(n)
+        tx, tw = basis.gauss01(m)
+        X = self.X(e)
+        x = map_point(X, pts)
+        DF = jacobian(X, pts)
+        det = np.linalg.det(DF)
+        Dinv = np.linalg.inv(DF)
+        Phi, _ = basis_at(a, pts)
+        acc = np.zeros((3, qe, a ** 3))
+        for tau, wt in zip(tx, tw):
+            Jv = J(x, t0 + tau * dt)                            # [P, 3]
+            # J . DF^{-T} e_c = (DF^{-1} J)_c
+            Jr = np.einsum("pcm,pm->pc", Dinv, Jv) * (det * w)[:, None]
+            proj = Jr.T @ Phi                                   # [3, a^3]
+            for i in range(qe):
+                acc[:, i, :] += dt * wt * basis.L(i, tau) * proj
+        blk = np.zeros((2, 3, qe, a ** 3))
+        blk[0] = acc
+        return blk.ravel()
 
     # -- global sparse slab matrix (tiny meshes) --------------------------------
     def slab_matrix(self, dt):

@@ -8,10 +8,35 @@ import synth
 
 
 def rel_err(got, ref):
+    """The larger of the relative 2-norm error ||got - ref|| / ||ref|| and the
+    largest entry error relative to the largest reference entry,
+    max|got - ref| / max|ref|: every parity bar bounds both (a single wrong
+    entry cannot hide in the norm of a long vector)."""
     ref = np.asarray(ref, dtype=np.float64)
     got = np.asarray(got, dtype=np.float64)
+    if got.shape != ref.shape:
+        raise ValueError("shapes differ: %s vs %s" % (got.shape, ref.shape))
+    if not np.all(np.isfinite(got)):
+        return float("inf")
     den = np.linalg.norm(ref)
-    return np.linalg.norm(got - ref) / (den if den > 0 else 1.0)
+    norm2 = np.linalg.norm(got - ref) / (den if den > 0 else 1.0)
+    top = np.abs(ref).max() if ref.size else 0.0
+    entry = (np.abs(got - ref).max() / (top if top > 0 else 1.0)) if ref.size else 0.0
+    return max(norm2, entry)
+
+
+def rel_err_dev(got, ref):
+    """rel_err of two device tensors, computed on the device (long vectors)."""
+    import torch
+    g = got.double()
+    r = ref.double()
+    if not bool(torch.isfinite(g).all()):
+        return float("inf")
+    den = float(torch.linalg.vector_norm(r))
+    norm2 = float(torch.linalg.vector_norm(g - r)) / (den if den > 0 else 1.0)
+    top = float(r.abs().max())
+    entry = float((g - r).abs().max()) / (top if top > 0 else 1.0)
+    return max(norm2, entry)
 
 
 def note(msg):

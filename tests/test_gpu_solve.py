@@ -8,7 +8,7 @@ import pytest
 
 import synth
 from oracle import fields
-from tests.gpu_util import Lib, note, oracle_disc, rel_err
+from tests.gpu_util import Lib, note, oracle_disc, rel_err, rel_err_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -151,42 +151,218 @@ def test_not_converged_reports_and_fills_info(lib):
     lib.stdg.stdg_mesh_free(mh)
 
 
-@pytest.mark.parametrize("inner,krylov", [(1, 0), (0, 0), (1, 1)])
-def test_two_material_32cubed_first_slab_properties(lib, inner, krylov):
-    """Full-size 32^3 p = 4 q = 3 solve of the first slab: energy conserved and
-    the oracle's residual on sampled elements of the GPU solution is small."""
-    cfg = synth.cavity_two_material()
-    m = cfg["mesh"]
-    modes = cfg["init"]
-    mh = lib.upload(m)
-    info_m = lib.stdg.stdg_mesh_info(mh)
-    st = lib.torch.zeros(info_m["state_size"], dtype=lib.torch.float64, device="cuda")
-    lib.stdg.stdg_project_modes(mh, modes.mnl, modes.abc, st)
-    s0 = st.cpu().numpy()
-    Ud = lib.torch.zeros(info_m["trial_size"], dtype=lib.torch.float64, device="cuda")
-    note("32^3 solve inner=%d krylov=%d" % (inner, krylov))
-    info = lib.stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, st, inner_prec=inner, rtol=1e-10, slab_U=Ud,
-                                    krylov_prec=krylov, max_iters=2000, max_refine=300)
-    note("32^3 solve inner=%d krylov=%d: %s" % (inner, krylov, info))
-    assert info["status"] == 0
-    assert abs(info["energy_end"] - info["energy_start"]) < 1e-9 * info["energy_start"]
-    d = oracle_disc(m)
-    U = Ud.cpu().numpy()
+def _initial_guess(d, s0, elements):
+    """The solver's initial guess on the given elements (others 0): constant
+    continuation, m = 1 block := the state at the slab start, higher levels 0."""
     x0 = np.zeros(d.unk_off[-1])
-    for e in range(d.ne):
+    for e in elements:
         a3 = int(d.a[e]) ** 3
         qe = int(d.q[e])
         x0[d.unk_off[e]:d.unk_off[e + 1]].reshape(2, 3, qe, a3)[:, :, 0, :] = \
             s0[d.state_off[e]:d.state_off[e + 1]].reshape(2, 3, a3)
-    U0 = d.embed_unknowns(x0, s0)   # the solver's initial guess: constant continuation
-    rng = np.random.default_rng(3)
-    sample = [int(e) for e in rng.choice(m.n_elements, 24, replace=False)]
-    r = d.residual(U, cfg["dt"], None, sample)
-    r0 = d.residual(U0, cfg["dt"], None, sample)
+    return d.embed_unknowns(x0, s0, elements)
+
+
+def _sampled_residual_ratio(d, U, U0, dt, load, sample):
+    """||R(U)|| / ||R(U0)|| of the oracle's residual on the sampled elements'
+    rows (R = B U - L; the load restricted to those rows)."""
+    r = d.residual(U, dt, None, sample)
+    r0 = d.residual(U0, dt, None, sample)
+    if load is not None:
+        for e in sample:
+            r[e] = r[e] - load[d.unk_off[e]:d.unk_off[e + 1]]
+            r0[e] = r0[e] - load[d.unk_off[e]:d.unk_off[e + 1]]
     num = np.sqrt(sum(np.sum(v ** 2) for v in r.values()))
     den = np.sqrt(sum(np.sum(v ** 2) for v in r0.values()))
-    assert num / den < 1e-8, num / den
-    lib.stdg.stdg_mesh_free(mh)
+    return num / den
+
+
+def _full_size_slab(lib, m, mh, d, s0, dt, load_dev, load_host, sample, rtol):
+    """One slab from s0 with plain FP64 and with FP32 applies inside FP64
+    refinement (FP32 basis): the end states match elementwise to 1e-10, the
+    slab solutions on the sampled elements and their neighbours too, and both
+    satisfy the oracle's equations on the sampled elements to 1e-10 of the
+    initial guess's residual.  Only those elements' trial blocks come back
+    to the host."""
+    t = lib.torch
+    needed = sorted(set(sample) | {int(k) for e in sample for k in d.nb[e] if k >= 0})
+    outs = {}
+    for name, inner, krylov in (("fp64", 0, 0), ("fp32_refine", 1, 1)):
+        st = lib.dev(s0, t.float64)
+        Ud = t.zeros(m.trial_size(), dtype=t.float64, device="cuda")
+        note("full-size slab %s rtol %g" % (name, rtol))
+        info = lib.stdg.stdg_slab_solve(mh, 0.0, dt, load_dev, st, inner_prec=inner, krylov_prec=krylov, rtol=rtol,
+                                        slab_U=Ud, max_iters=4000, max_refine=400)
+        note("full-size slab %s: %s" % (name, info))
+        assert info["status"] == 0 and info["rel_res"] <= rtol
+        U = np.zeros(d.trial_off[-1])
+        for e in needed:
+            U[d.trial_off[e]:d.trial_off[e + 1]] = Ud[d.trial_off[e]:d.trial_off[e + 1]].cpu().numpy()
+        outs[name] = (st.cpu().numpy(), U, info)
+        del st, Ud
+    err = rel_err(outs["fp32_refine"][0], outs["fp64"][0])
+    note("full-size slab: FP32+refinement vs FP64 end state %.3e" % err)
+    assert err < 1e-10
+    blocks = lambda U: np.concatenate([U[d.trial_off[e]:d.trial_off[e + 1]] for e in needed])
+    assert rel_err(blocks(outs["fp32_refine"][1]), blocks(outs["fp64"][1])) < 1e-10
+    U0 = _initial_guess(d, s0, needed)
+    for name in outs:
+        ratio = _sampled_residual_ratio(d, outs[name][1], U0, dt, load_host, sample)
+        note("full-size slab %s: oracle residual on %d sampled elements %.3e" % (name, len(sample), ratio))
+        assert ratio < 1e-10
+    return outs
+
+
+def test_two_material_32cubed_first_slab(lib):
+    """Full-size 32^3 p = 4 q = 3 two-material cavity, first slab from the
+    projected mode superposition: FP32+refinement and plain FP64 agree to 1e-10
+    elementwise, the oracle's residual on sampled elements is below 1e-10 of
+    its initial value, and the energy is conserved (Thm 3.1)."""
+    cfg = synth.cavity_two_material()
+    m = cfg["mesh"]
+    modes = cfg["init"]
+    mh = lib.upload(m)
+    try:
+        st = lib.torch.zeros(m.state_size(), dtype=lib.torch.float64, device="cuda")
+        lib.stdg.stdg_project_modes(mh, modes.mnl, modes.abc, st)
+        s0 = st.cpu().numpy()
+        d = oracle_disc(m)
+        sample = [int(e) for e in np.random.default_rng(3).choice(m.n_elements, 24, replace=False)]
+        outs = _full_size_slab(lib, m, mh, d, s0, cfg["dt"], None, None, sample, 1e-11)
+        for name, (_, _, info) in outs.items():
+            assert abs(info["energy_end"] - info["energy_start"]) < 1e-10 * info["energy_start"]
+    finally:
+        lib.stdg.stdg_mesh_free(mh)
+
+
+def test_two_material_32cubed_march_64_slabs(lib):
+    """The benchmark's 64-slab march of the 32^3 cavity at its tolerance (rtol
+    1e-10 per slab): on every slab, FP32 applies inside FP64 refinement (FP32
+    basis) reach the plain FP64 path's end state to 1e-10, each started from
+    the FP64 march's state; the FP64 march conserves the energy (Thm 3.1).
+    Two uploads of the mesh keep one cached solver per precision."""
+    t = lib.torch
+    cfg = synth.cavity_two_material()
+    m = cfg["mesh"]
+    modes = cfg["init"]
+    dt = cfg["dt"]
+    mh64 = lib.upload(m)
+    mh32 = lib.upload(m)
+    try:
+        st = t.zeros(m.state_size(), dtype=t.float64, device="cuda")
+        lib.stdg.stdg_project_modes(mh64, modes.mnl, modes.abc, st)
+        e0 = lib.stdg.stdg_energy(mh64, st)
+        worst = 0.0
+        for n in range(cfg["n_slabs"]):
+            s32 = st.clone()
+            r64 = lib.stdg.stdg_slab_solve(mh64, n * dt, dt, None, st, inner_prec=0, rtol=1e-10, max_iters=4000,
+                                           max_refine=400)
+            r32 = lib.stdg.stdg_slab_solve(mh32, n * dt, dt, None, s32, inner_prec=1, krylov_prec=1, rtol=1e-10,
+                                           max_iters=4000, max_refine=400)
+            assert r64["status"] == 0 and r32["status"] == 0
+            err = rel_err_dev(s32, st)
+            worst = max(worst, err)
+            if n % 8 == 0 or err >= 1e-10:
+                note("64-slab march: slab %d iters %d / %d, FP32+refinement vs FP64 %.3e"
+                     % (n, r64["iters"], r32["iters"], err))
+            assert err < 1e-10, (n, err)
+        e1 = lib.stdg.stdg_energy(mh64, st)
+        note("64-slab march: worst slab difference %.3e, energy drift %.3e" % (worst, (e1 - e0) / e0))
+        assert abs(e1 - e0) < 1e-8 * e0
+    finally:
+        lib.stdg.stdg_mesh_free(mh64)
+        lib.stdg.stdg_mesh_free(mh32)
+
+
+def test_graded_trilinear_24cubed_slab_with_source(lib):
+    """Full-size graded trilinear 24^3 mesh (p = 3..6, q = p - 2) driven by its
+    Gaussian-pulse current, one slab from a random field: FP32+refinement vs
+    FP64 to 1e-10 elementwise; the oracle's residual (its own load) on sampled
+    elements of every (p, q) ring below 1e-10 of its initial value."""
+    cfg = synth.graded_nonaffine()
+    m = cfg["mesh"]
+    dt = cfg["dt"]
+    src = cfg["source"]
+    mh = lib.upload(m)
+    try:
+        t0 = src.t0 - dt
+        Ld = lib.torch.zeros(m.unknown_size(), dtype=lib.torch.float64, device="cuda")
+        lib.stdg.stdg_load_assemble(mh, src, t0, dt, Ld)
+        d = oracle_disc(m)
+        rng = np.random.default_rng(24)
+        sample = []
+        for p in (3, 4, 5, 6):
+            ids = np.nonzero(m.p == p)[0]
+            sample += [int(e) for e in rng.choice(ids, 3, replace=False)]
+        J = fields.gaussian_pulse(src.amp, src.center, src.sigma_x, src.f0, src.t0, src.sigma_t, src.dir)
+        Ls = d.load_rows(J, t0, dt, sample)
+        Lg = Ld.cpu().numpy()
+        L_host = np.zeros(d.unk_off[-1])
+        for e in sample:
+            assert rel_err(Lg[d.unk_off[e]:d.unk_off[e + 1]], Ls[e]) < 1e-12
+            L_host[d.unk_off[e]:d.unk_off[e + 1]] = Ls[e]
+        s0 = 1e-3 * synth.random_vector(m.state_size(), 25)
+        _full_size_slab(lib, m, mh, d, s0, dt, Ld, L_host, sample, 1e-11)
+    finally:
+        lib.stdg.stdg_mesh_free(mh)
+
+
+def test_large_cavity_48cubed_slab_with_source(lib):
+    """Full-size 48^3 p = 6 q = 4 cavity (1.1e9 trial DoF) driven by its
+    current, one slab from a random field: FP32+refinement vs FP64 to 1e-10
+    elementwise and the oracle's residual on sampled elements below 1e-10."""
+    cfg = synth.large_cavity()
+    m = cfg["mesh"]
+    dt = cfg["dt"]
+    src = cfg["source"]
+    mh = lib.upload(m)
+    try:
+        t0 = src.t0 - dt
+        Ld = lib.torch.zeros(m.unknown_size(), dtype=lib.torch.float64, device="cuda")
+        lib.stdg.stdg_load_assemble(mh, src, t0, dt, Ld)
+        d = oracle_disc(m)
+        rng = np.random.default_rng(48)
+        sample = [int(e) for e in rng.choice(m.n_elements, 8, replace=False)] + [0, m.n_elements - 1]
+        J = fields.gaussian_pulse(src.amp, src.center, src.sigma_x, src.f0, src.t0, src.sigma_t, src.dir)
+        Ls = d.load_rows(J, t0, dt, sample)
+        Lg = Ld.cpu().numpy()
+        L_host = np.zeros(d.unk_off[-1])
+        for e in sample:
+            assert rel_err(Lg[d.unk_off[e]:d.unk_off[e + 1]], Ls[e]) < 1e-12
+            L_host[d.unk_off[e]:d.unk_off[e + 1]] = Ls[e]
+        s0 = 1e-3 * synth.random_vector(m.state_size(), 49)
+        _full_size_slab(lib, m, mh, d, s0, dt, Ld, L_host, sample, 1e-11)
+    finally:
+        lib.stdg.stdg_mesh_free(mh)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_iteration_counts_order_of_magnitude(lib, p):
+    """Solver realism (the iteration table of Section 5.4.1): an 8^3 cube with
+    a T_mm cavity mode, q = p, dt = h / (2p + 1), m = 1, 2, 3 for p in {1, 2},
+    {3, 4}, {5, 6}; the paper reports 8 to 25 GMRES iterations per slab for
+    exact solves (tolerance unstated).  Checked to an order of magnitude over
+    a few slabs at rtol 1e-10."""
+    v, h = synth.box_mesh((8, 8, 8))
+    ne = h.shape[0]
+    m = synth.Mesh(v, h, np.full(ne, p, np.int32), np.full(ne, p, np.int32), np.ones(ne), np.ones(ne),
+                   shape=(8, 8, 8))
+    mm = (p + 1) // 2
+    dt = (1.0 / 8) / (2 * p + 1)
+    mh = lib.upload(m)
+    try:
+        st = lib.torch.zeros(m.state_size(), dtype=lib.torch.float64, device="cuda")
+        lib.stdg.stdg_project_modes(mh, [[mm, 0, mm]], [[0.0, 1.0, 0.0]], st)
+        its = []
+        for n in range(4):
+            r = lib.stdg.stdg_slab_solve(mh, n * dt, dt, None, st, inner_prec=0, rtol=1e-10, max_iters=2000,
+                                         max_refine=200)
+            assert r["status"] == 0
+            its.append(r["iters"])
+        note("E1 p=%d: iterations per slab %s" % (p, its))
+        assert 3 <= np.mean(its) <= 100
+    finally:
+        lib.stdg.stdg_mesh_free(mh)
 
 
 def test_resume_from_saved_state_is_bitwise(lib):
