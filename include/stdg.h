@@ -198,6 +198,23 @@ int stdg_mesh_set_dissipation(stdg_mesh* mesh, double c);
 int stdg_residual_apply(const stdg_mesh* mesh, double dt, int prec, int mode,
                         const void* x_dev, const void* load_dev, void* y_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as stdg_residual_apply, same arguments and results, that
+ * allocates nothing.  Preconditioned applies on meshes with a non-diagonal
+ * metric (sheared or trilinear elements) scale the input by P^{-1} into a
+ * static device array of stdg_noalloc_scratch_bytes() bytes (64 MiB; each
+ * device holds its own copy until the process ends) instead of the mesh's
+ * scratch: STDG_E_CAPACITY when unknown_size * (4 or 8) exceeds it.  Meshes
+ * with several kernel groups launch the groups one after another on
+ * `stream` (no side streams).  Every call on a device shares that device's
+ * array, which keeps the last call's contents (each call overwrites what it
+ * reads): calls that overlap on one device, on different streams or threads,
+ * race and give wrong results.  Device pointers; asynchronous on `stream`. */
+int stdg_residual_apply_noalloc(const stdg_mesh* mesh, double dt, int prec, int mode,
+                                const void* x_dev, const void* load_dev, void* y_dev, void* stream);
+size_t stdg_noalloc_scratch_bytes(void);
+
 /* Current density of the load L(V) = (J, v) (eq. bilinearform:C):
  * kind 0 = none; kind 1 = J(x,t) = dir * amp * exp(-|x - center|^2 / (2 sigma_x^2))
  *                          * sin(2 pi f0 (t - t0)) * exp(-(t - t0)^2 / (2 sigma_t^2)). */

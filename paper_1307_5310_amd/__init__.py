@@ -24,7 +24,8 @@ __all__ = ["StdgError", "STDG_FP32", "STDG_FP64", "STDG_OPERATOR", "STDG_RESIDUA
            "STDG_OPERATOR_PRECOND", "stdg_version", "stdg_init", "stdg_finalize",
            "stdg_mesh_upload", "stdg_mesh_info", "stdg_mesh_offsets", "stdg_mesh_free", "stdg_mesh_set_dissipation",
            "stdg_mesh_set_order", "stdg_mesh_autotune",
-           "stdg_residual_apply", "stdg_load_assemble", "stdg_project_modes",
+           "stdg_residual_apply", "stdg_residual_apply_noalloc", "stdg_noalloc_scratch_bytes",
+           "stdg_load_assemble", "stdg_project_modes",
            "stdg_slab_solve", "stdg_energy", "stdg_residual_dual_norm", "stdg_serve_start", "stdg_serve_submit",
            "stdg_serve_poll", "stdg_serve_clock", "stdg_serve_stop", "exported_symbols"]
 
@@ -202,6 +203,22 @@ def stdg_residual_apply(mesh, dt, prec, mode, x, load, y, stream=None):
         _dev(y, nu, dtype, "y")
     check(lib().stdg_residual_apply(mesh, float(dt), int(prec), int(mode), ptr(x), ptr(load),
                                     ptr(y), stream_handle(stream)))
+
+
+def stdg_residual_apply_noalloc(mesh, dt, prec, mode, x, load, y, stream=None):
+    """stdg_residual_apply that allocates nothing (static device scratch)."""
+    if torch is not None and mesh:
+        nu, nt, _ = _sizes(mesh)
+        dtype = torch.float64 if int(prec) == STDG_FP64 else torch.float32
+        _dev(x, nt if int(mode) == STDG_RESIDUAL else nu, dtype, "x")
+        _dev(load, nu, dtype, "load", optional=True)
+        _dev(y, nu, dtype, "y")
+    check(lib().stdg_residual_apply_noalloc(mesh, float(dt), int(prec), int(mode), ptr(x), ptr(load),
+                                            ptr(y), stream_handle(stream)))
+
+
+def stdg_noalloc_scratch_bytes():
+    return lib().stdg_noalloc_scratch_bytes()
 
 
 def _source(src):

@@ -127,6 +127,8 @@ def lib():
             "stdg_mesh_set_order": ([vp, i32], ctypes.c_int),
             "stdg_mesh_autotune": ([vp, ctypes.c_int, dbl, i32, ctypes.POINTER(i32), vp], ctypes.c_int),
             "stdg_residual_apply": ([vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
+            "stdg_residual_apply_noalloc": ([vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
+            "stdg_noalloc_scratch_bytes": ([], ctypes.c_size_t),
             "stdg_load_assemble": ([vp, ctypes.POINTER(Source), dbl, dbl, vp, vp], ctypes.c_int),
             "stdg_project_modes": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
             "stdg_slab_solve": ([vp, dbl, dbl, vp, ctypes.POINTER(SolveOpts), vp, vp,

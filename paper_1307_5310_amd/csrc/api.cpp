@@ -98,6 +98,12 @@ int stdg_init(int hip_device, size_t hbm_budget_bytes, stdg_ctx** out) {
   STDG_HIP(hipMemGetInfo(&free_b, &total_b));
   stdg_ctx* c = new (std::nothrow) stdg_ctx;
   if (!c) return fail(STDG_E_NOMEM, "stdg_init: host allocation failed");
+  // this device's address of the static scratch of stdg_residual_apply_noalloc
+  int rc = noalloc_scratch_init(hip_device);
+  if (rc != STDG_OK) {
+    delete c;
+    return rc;
+  }
   c->c.device = hip_device;
   c->c.budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
   c->c.used = 0;
@@ -248,5 +254,24 @@ int stdg_residual_apply(const stdg_mesh* mesh, double dt, int prec, int mode, co
   ApplyArgs a{&mesh->m, dt, prec, mode, x_dev, load_dev, y_dev, (hipStream_t)stream};
   return launch_residual(a);
 }
+
+int stdg_residual_apply_noalloc(const stdg_mesh* mesh, double dt, int prec, int mode, const void* x_dev,
+                                const void* load_dev, void* y_dev, void* stream) {
+  if (!mesh) return fail(STDG_E_ARG, "stdg_residual_apply_noalloc: mesh is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    return fail(STDG_E_ARG, "stdg_residual_apply_noalloc: dt must be finite and > 0");
+  if (prec != STDG_FP64 && prec != STDG_FP32) return fail(STDG_E_ARG, "stdg_residual_apply_noalloc: unknown precision");
+  if (mode != STDG_OPERATOR && mode != STDG_RESIDUAL && mode != STDG_OPERATOR_PRECOND)
+    return fail(STDG_E_ARG, "stdg_residual_apply_noalloc: unknown mode");
+  if (!x_dev || !y_dev) return fail(STDG_E_ARG, "stdg_residual_apply_noalloc: x or y is NULL");
+  if (load_dev && mode != STDG_RESIDUAL)
+    return fail(STDG_E_ARG, "stdg_residual_apply_noalloc: load only in RESIDUAL mode");
+  if (x_dev == y_dev) return fail(STDG_E_ARG, "stdg_residual_apply_noalloc: x and y must not alias");
+  ApplyArgs a{&mesh->m, dt, prec, mode, x_dev, load_dev, y_dev, (hipStream_t)stream};
+  a.no_alloc = true;
+  return launch_residual(a);
+}
+
+size_t stdg_noalloc_scratch_bytes(void) { return noalloc_scratch_capacity(); }
 
 }  // extern "C"

@@ -173,8 +173,16 @@ struct ApplyArgs {
   const void* load;
   void* y;
   hipStream_t stream;
+  // the allocation-free variant: the preconditioner pre-pass uses the static
+  // device scratch, and several kernel groups run one after another on
+  // `stream` (no side streams or events are created)
+  bool no_alloc = false;
 };
 int launch_residual(const ApplyArgs& a);
+// Static device scratch of the allocation-free apply: look up this device's
+// address of the array (once per device; the device must be current).
+int noalloc_scratch_init(int device);
+size_t noalloc_scratch_capacity();
 int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s);
 
 // Mesh construction (mesh.cpp): host analysis (validation, faces, metric,

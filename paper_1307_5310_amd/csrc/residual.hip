@@ -1,10 +1,46 @@
 // Dispatch of the residual kernels over the (a, q, affine) groups of a mesh.
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "residual_kernel.h"
 
 namespace stdg {
+
+// Device scratch of stdg_residual_apply_noalloc, for callers that cannot
+// allocate: the P^{-1} pre-pass of preconditioned applies on meshes with a
+// non-diagonal metric writes the scaled input here instead of into the
+// mesh's lazily allocated scratch.  Each device holds its own copy until the
+// process ends.  In host code the array's name is not a device address: host
+// code uses only the address hipGetSymbolAddress returned for the current
+// device (kept per device below).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t noalloc_scratch_capacity() { return kNoAllocScratchBytes; }
+
+int noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(STDG_E_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return STDG_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+  g_scratch_ptr[device] = ptr;
+  return STDG_OK;
+}
+
+static void* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+}
 
 #define STDG_DECL(K, R, AA) int launch_##K##R##AA(int q, const KParams<R>& P, int64_t n, hipStream_t s);
 #define STDG_DECL_ALL(K, R) STDG_DECL(K, R, 2) STDG_DECL(K, R, 3) STDG_DECL(K, R, 4) STDG_DECL(K, R, 5) \
@@ -47,7 +83,7 @@ static int ensure_aux(Mesh* m) {
 // write disjoint outputs, so the result does not depend on their order).
 template <typename T>
 static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* load, T* y, hipStream_t s,
-                      Launcher<T>* affine, Launcher<T>* trilinear, const QTables<T>* d_qt) {
+                      Launcher<T>* affine, Launcher<T>* trilinear, const QTables<T>* d_qt, bool allow_fork) {
   KParams<T> P;
   P.info = m->d_info;
   P.metric = m->d_metric;
@@ -70,7 +106,7 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
   }
   auto work = [](const Group* g) { return g->count * (int64_t)g->q * g->a * g->a * g->a * (g->affine ? 1 : 3); };
   std::stable_sort(order.begin(), order.end(), [&](const Group* l, const Group* r) { return work(l) > work(r); });
-  const bool fork = order.size() > 1;
+  const bool fork = allow_fork && order.size() > 1;
   if (fork) {
     int rc = ensure_aux(const_cast<Mesh*>(m));
     if (rc != STDG_OK) return rc;
@@ -110,7 +146,23 @@ int launch_residual(const ApplyArgs& a) {
   const Mesh* m = a.mesh;
   int mode = a.mode;
   const void* x = a.x;
-  if (mode == STDG_OPERATOR_PRECOND && m->n_diag != m->ne) {
+  if (mode == STDG_OPERATOR_PRECOND && m->n_diag != m->ne && a.no_alloc) {
+    // the allocation-free variant: P^{-1} x into the static scratch of this device
+    const size_t need = (size_t)m->unk_off.back() * (a.prec == STDG_FP64 ? 8 : 4);
+    if (need > kNoAllocScratchBytes)
+      return fail(STDG_E_CAPACITY, "stdg_residual_apply_noalloc: the scaled input needs " + std::to_string(need) +
+                                       " bytes of scratch, the static scratch holds " +
+                                       std::to_string(kNoAllocScratchBytes));
+    int dev = -1;
+    STDG_HIP(hipGetDevice(&dev));
+    int rc = noalloc_scratch_init(dev);
+    if (rc != STDG_OK) return rc;
+    void* ptr = noalloc_scratch(dev);
+    rc = launch_precond_scale(m, a.prec, x, ptr, a.stream);
+    if (rc != STDG_OK) return rc;
+    x = ptr;
+    mode = STDG_OPERATOR;
+  } else if (mode == STDG_OPERATOR_PRECOND && m->n_diag != m->ne) {
     // non-diagonal metric somewhere: scale into the mesh's scratch, then plain
     // operator.  The scratch is sized for FP64 on first use, so a later call in
     // the other precision never moves it under captured launches; the epoch is
@@ -134,9 +186,11 @@ int launch_residual(const ApplyArgs& a) {
   const bool diss = m->d_diss != nullptr;
   if (a.prec == STDG_FP64)
     return run_groups<double>(m, a.dt, mode, (const double*)x, (const double*)a.load, (double*)a.y, a.stream,
-                              diss ? affine_diss_f64 : affine_f64, trilinear_f64, (const QTables<double>*)m->d_qt64);
+                              diss ? affine_diss_f64 : affine_f64, trilinear_f64, (const QTables<double>*)m->d_qt64,
+                              !a.no_alloc);
   return run_groups<float>(m, a.dt, mode, (const float*)x, (const float*)a.load, (float*)a.y, a.stream,
-                           diss ? affine_diss_f32 : affine_f32, trilinear_f32, (const QTables<float>*)m->d_qt32);
+                           diss ? affine_diss_f32 : affine_f32, trilinear_f32, (const QTables<float>*)m->d_qt32,
+                           !a.no_alloc);
 }
 
 }  // namespace stdg
