@@ -243,8 +243,10 @@ def main():
     mh = stdg.stdg_mesh_upload(ctx, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu)
     # element order of the kernels' work lists: the library's autotuner (timed
     # here, outside the timed region)
-    order = stdg.stdg_mesh_autotune(mh, stdg.STDG_FP32, dt, reps=10)
-    log("autotuned work-list order: %s" % ("Morton" if order == 0 else "columns of %d" % order))
+    tuned = stdg.stdg_mesh_autotune(mh, stdg.STDG_FP32, dt, reps=10)
+    order = tuned["order"]
+    log("autotuned work-list order: %s, launch variants %s"
+        % ("Morton" if order == 0 else "columns of %d" % order, tuned["variants"]))
     info = stdg.stdg_mesh_info(mh)
     nu = info["unknown_size"]
     x64 = torch.from_numpy(synth.random_vector(nu, 0)).cuda()
@@ -350,7 +352,8 @@ def main():
                                "preconditioned operator apply on N(0,1) coefficients (seed 0)"
                                % (args.n, args.p, args.q, dt),
                    "elements": ne, "trial_dof": trial_dof, "unknowns": nu,
-                   "work_order": "Morton" if order == 0 else "columns of %d" % order},
+                   "work_order": "Morton" if order == 0 else "columns of %d" % order,
+                   "launch_variants": tuned["variants"]},
         "settle_s": args.settle_s,
         "launch_ms_fp32": dist32,
         "fp64": {"value": round(gdofs64, 2), "unit": "GDoF/s", "ms_per_step": round(ms64, 5),

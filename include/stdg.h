@@ -95,7 +95,8 @@ const char* stdg_last_error(void);
  * passing any of them; 0 for an unknown `which`.  Needs no device. */
 enum {
   STDG_STRUCT_MESH_DESC = 0, STDG_STRUCT_MESH_INFO = 1, STDG_STRUCT_SOURCE = 2, STDG_STRUCT_SOLVE_OPTS = 3,
-  STDG_STRUCT_SOLVE_INFO = 4, STDG_STRUCT_SERVE_OPTS = 5, STDG_STRUCT_REQUEST = 6, STDG_STRUCT_RESULT = 7
+  STDG_STRUCT_SOLVE_INFO = 4, STDG_STRUCT_SERVE_OPTS = 5, STDG_STRUCT_REQUEST = 6, STDG_STRUCT_RESULT = 7,
+  STDG_STRUCT_GROUP_INFO = 8
 };
 size_t stdg_struct_size(int32_t which);
 
@@ -159,12 +160,33 @@ int stdg_mesh_free(stdg_mesh* mesh);
 int stdg_mesh_set_order(stdg_mesh* mesh, int32_t order);
 /* Autotuner: time `reps` preconditioned operator applies (precision prec,
  * scratch vectors allocated and freed inside the call) for each candidate
- * order (Morton, columns of 4, 8, 16), keep the fastest and return it in
- * *order_out.  Synchronises `stream`; not to be called while other work on
- * the mesh is in flight.  Callers that cache the choice (the
- * Python binding keys a JSON file on the mesh's shape) apply it later with
- * stdg_mesh_set_order. */
+ * order (Morton, columns of 4, 8, 16) and keep the fastest (returned in
+ * *order_out); then, in that order, time each affine kernel group in each
+ * launch variant of stdg_mesh_set_launch and keep the fastest per group
+ * (stdg_mesh_group reports it).  Synchronises `stream`; not to be called
+ * while other work on the mesh is in flight.  Callers that cache the choices
+ * (the Python binding keys a JSON file on the mesh's shape) apply them later
+ * with stdg_mesh_set_order and stdg_mesh_set_launch. */
 int stdg_mesh_autotune(stdg_mesh* mesh, int prec, double dt, int32_t reps, int32_t* order_out, void* stream);
+
+/* Kernel groups: the elements of one (p, q, affine) triple run through one
+ * residual kernel instantiation, one workgroup per element.
+ * stdg_mesh_group describes group 0 <= group < n_groups; stdg_mesh_set_launch
+ * picks the launch variant of its operator-mode kernels (group = -1: every
+ * group; affine groups without D_h, the others keep variant 0):
+ *   0  the element's outputs staged through LDS and written as contiguous
+ *      8-byte stores (whole cache lines), neighbour faces loaded 3 at a time;
+ *   1  outputs written per spatial position, neighbour faces 3 at a time;
+ *   2  outputs staged as in 0, neighbour faces loaded one at a time (fewer
+ *      registers, more resident waves).
+ * Results are bitwise the same in every variant.  STDG_E_ARG for an unknown
+ * group or variant.  Not to be called while work on the mesh is in flight. */
+typedef struct {
+  int32_t p, q, affine, variant;
+  int64_t n_elements;
+} stdg_group_info_t;
+int stdg_mesh_group(const stdg_mesh* mesh, int32_t group, stdg_group_info_t* out);
+int stdg_mesh_set_launch(stdg_mesh* mesh, int32_t group, int32_t variant);
 
 /* Dissipative upwind-type stabilisation D_h (the remark closing Section 4):
  * from this call on, every residual apply and slab solve on `mesh` uses

@@ -19,11 +19,12 @@ from ._lib import (StdgError, STDG_FP32, STDG_FP64, STDG_OPERATOR, STDG_RESIDUAL
                    STDG_OPERATOR_PRECOND, STDG_E_NOT_READY, MeshDesc, MeshInfo, Source, SolveOpts,
                    SolveInfo, ServeOpts, Request, Result, lib, check, ptr, stream_handle,
                    exported_symbols)
+from . import _lib
 
 __all__ = ["StdgError", "STDG_FP32", "STDG_FP64", "STDG_OPERATOR", "STDG_RESIDUAL",
            "STDG_OPERATOR_PRECOND", "stdg_version", "stdg_init", "stdg_finalize",
            "stdg_mesh_upload", "stdg_mesh_info", "stdg_mesh_offsets", "stdg_mesh_free", "stdg_mesh_set_dissipation",
-           "stdg_mesh_set_order", "stdg_mesh_autotune",
+           "stdg_mesh_set_order", "stdg_mesh_autotune", "stdg_mesh_set_launch", "stdg_mesh_group",
            "stdg_residual_apply", "stdg_residual_apply_noalloc", "stdg_noalloc_scratch_bytes",
            "stdg_load_assemble", "stdg_project_modes",
            "stdg_slab_solve", "stdg_energy", "stdg_residual_dual_norm", "stdg_serve_start", "stdg_serve_submit",
@@ -141,16 +142,22 @@ def _tune_key(mesh, prec):
         i["q_max"], i["unknown_size"], int(prec))
 
 
+def _tune_entry_ok(v):
+    return (isinstance(v, dict) and isinstance(v.get("order"), int) and isinstance(v.get("variants"), list)
+            and all(isinstance(k, int) for k in v["variants"]))
+
+
 def _tune_cache_read(path):
-    """The cached choices in `path`, or {} when the file is missing or not a
-    JSON object of integers (it is then rewritten on the next store)."""
+    """The cached choices in `path` ({key: {"order": int, "variants": [int per
+    group]}}), or {} when the file is missing or malformed (it is then
+    rewritten on the next store)."""
     import json
     try:
         with open(path) as f:
             table = json.load(f)
     except (OSError, ValueError):
         return {}
-    if not isinstance(table, dict) or not all(isinstance(v, int) for v in table.values()):
+    if not isinstance(table, dict) or not all(_tune_entry_ok(v) for v in table.values()):
         return {}
     return table
 
@@ -173,25 +180,41 @@ def _tune_cache_write(path, table):
 
 
 def stdg_mesh_autotune(mesh, prec=STDG_FP32, dt=0.01, reps=10, cache=None, stream=None):
-    """Pick the kernels' element order for this mesh by timing (C ABI
-    stdg_mesh_autotune) and return it.  With a cache file (argument, or the
-    STDG_TUNE_CACHE environment variable) a choice stored for a mesh of the
-    same shape is applied without timing, and new choices are stored."""
+    """Pick the kernels' element order and each group's launch variant for
+    this mesh by timing (C ABI stdg_mesh_autotune); returns
+    {"order": int, "variants": [int per group]}.  With a cache file
+    (argument, or the STDG_TUNE_CACHE environment variable) choices stored for
+    a mesh of the same shape are applied without timing, and new choices are
+    stored."""
     import os
     path = cache or os.environ.get("STDG_TUNE_CACHE")
     key = _tune_key(mesh, prec)
     table = _tune_cache_read(path) if path else {}
-    if key in table:
-        stdg_mesh_set_order(mesh, table[key])
-        return int(table[key])
+    n_groups = stdg_mesh_info(mesh)["n_groups"]
+    if key in table and len(table[key]["variants"]) == n_groups:
+        stdg_mesh_set_order(mesh, table[key]["order"])
+        for g, v in enumerate(table[key]["variants"]):
+            stdg_mesh_set_launch(mesh, g, v)
+        return dict(table[key])
     out = ctypes.c_int32()
     check(lib().stdg_mesh_autotune(mesh, int(prec), float(dt), int(reps), ctypes.byref(out),
                                    stream_handle(stream)))
+    choice = {"order": int(out.value), "variants": [stdg_mesh_group(mesh, g)["variant"] for g in range(n_groups)]}
     if path:
         table = _tune_cache_read(path)   # keep what other processes stored meanwhile
-        table[key] = int(out.value)
+        table[key] = choice
         _tune_cache_write(path, table)
-    return int(out.value)
+    return choice
+
+
+def stdg_mesh_set_launch(mesh, group, variant):
+    check(lib().stdg_mesh_set_launch(mesh, int(group), int(variant)))
+
+
+def stdg_mesh_group(mesh, group):
+    g = _lib.GroupInfo()
+    check(lib().stdg_mesh_group(mesh, int(group), ctypes.byref(g)))
+    return {name: getattr(g, name) for name, _ in _lib.GroupInfo._fields_}
 
 
 def stdg_residual_apply(mesh, dt, prec, mode, x, load, y, stream=None):

@@ -81,6 +81,11 @@ class ServeOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32)]
 
 
+class GroupInfo(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("q", ctypes.c_int32), ("affine", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("n_elements", ctypes.c_int64)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [("mesh", MeshDesc), ("t0", ctypes.c_double), ("dt", ctypes.c_double),
                 ("n_slabs", ctypes.c_int32), ("source", Source), ("n_modes", ctypes.c_int32),
@@ -99,7 +104,7 @@ class Result(ctypes.Structure):
 
 
 # in the order of the STDG_STRUCT_* indices of stdg_struct_size
-STRUCTS = (MeshDesc, MeshInfo, Source, SolveOpts, SolveInfo, ServeOpts, Request, Result)
+STRUCTS = (MeshDesc, MeshInfo, Source, SolveOpts, SolveInfo, ServeOpts, Request, Result, GroupInfo)
 
 _lib = None
 
@@ -125,6 +130,8 @@ def lib():
             "stdg_mesh_free": ([vp], ctypes.c_int),
             "stdg_mesh_set_dissipation": ([vp, dbl], ctypes.c_int),
             "stdg_mesh_set_order": ([vp, i32], ctypes.c_int),
+            "stdg_mesh_set_launch": ([vp, i32, i32], ctypes.c_int),
+            "stdg_mesh_group": ([vp, i32, ctypes.POINTER(GroupInfo)], ctypes.c_int),
             "stdg_mesh_autotune": ([vp, ctypes.c_int, dbl, i32, ctypes.POINTER(i32), vp], ctypes.c_int),
             "stdg_residual_apply": ([vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
             "stdg_residual_apply_noalloc": ([vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),

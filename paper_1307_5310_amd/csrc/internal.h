@@ -91,6 +91,7 @@ void gauss_rule01(int n, double* x, double* w);
 // Kernel work group of elements with the same (a, q, affine).
 struct Group {
   int a, q, affine;
+  int variant = 0;  // launch variant of the group's kernels (0..2, residual_kernel.h element_body)
   int64_t count;
   int32_t* d_list;           // element ids, locality order (device)
   std::vector<int32_t> ids;  // the same on the host

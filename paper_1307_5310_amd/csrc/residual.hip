@@ -116,6 +116,7 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
   for (size_t i = 0; i < order.size(); ++i) {
     const Group& g = *order[i];
     P.list = g.d_list;
+    P.variant = g.variant;
     P.qt = d_qt + g.a;
     int rc = (g.affine ? affine : trilinear)[g.a](g.q, P, g.count, fork ? m->aux[i % Mesh::kAux] : s);
     if (rc != STDG_OK) return rc;

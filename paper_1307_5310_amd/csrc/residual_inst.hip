@@ -39,27 +39,41 @@ static constexpr size_t shmem_bytes() {
   return sizeof(STDG_REAL) * KCfg<STDG_A>::template lds_elems<STDG_REAL, QQ, (bool)STDG_AFF, MODE, (bool)STDG_DISS>();
 }
 
+template <int QQ, int MODE, int VAR>
+static int launch_one(const KParams<STDG_REAL>& P, dim3 grid, dim3 block, hipStream_t stream) {
+  hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, MODE, (bool)STDG_AFF, (bool)STDG_DISS, VAR>), grid, block,
+                     (shmem_bytes<QQ, MODE>()), stream, P);
+  return STDG_OK;
+}
+
+// The launch variants (residual_kernel.h, element_body) exist for affine
+// groups without D_h in the operator modes, the ones a slab solve repeats;
+// every other kernel runs variant 0.
+template <int QQ, int MODE>
+static int launch_var(const KParams<STDG_REAL>& P, dim3 grid, dim3 block, hipStream_t stream) {
+#if STDG_AFF && !STDG_DISS
+  if (MODE != 1) {
+    if (P.variant == 1) return launch_one<QQ, MODE, 1>(P, grid, block, stream);
+    if (P.variant == 2) return launch_one<QQ, MODE, 2>(P, grid, block, stream);
+  }
+#endif
+  return launch_one<QQ, MODE, 0>(P, grid, block, stream);
+}
+
 template <int QQ>
 static int launch_q(const KParams<STDG_REAL>& P, dim3 grid, dim3 block, hipStream_t stream) {
   switch (P.mode) {
     case 0:
-      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 0, (bool)STDG_AFF, (bool)STDG_DISS>), grid, block, (shmem_bytes<QQ, 0>()),
-                         stream, P);
-      break;
+      return launch_var<QQ, 0>(P, grid, block, stream);
     case 1:
-      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 1, (bool)STDG_AFF, (bool)STDG_DISS>), grid, block, (shmem_bytes<QQ, 1>()),
-                         stream, P);
-      break;
+      return launch_var<QQ, 1>(P, grid, block, stream);
     default:
 #if STDG_AFF
-      hipLaunchKernelGGL((residual_kernel<STDG_REAL, STDG_A, QQ, 2, true, (bool)STDG_DISS>), grid, block, (shmem_bytes<QQ, 2>()), stream,
-                         P);
-      break;
+      return launch_var<QQ, 2>(P, grid, block, stream);
 #else
       return fail(STDG_E_UNSUPPORTED, "trilinear elements take P^{-1} in a separate pass");
 #endif
   }
-  return STDG_OK;
 }
 
 int STDG_CAT(STDG_CAT(STDG_CAT(launch_, STDG_KIND), STDG_REAL), STDG_A)(int q, const KParams<STDG_REAL>& P, int64_t n,

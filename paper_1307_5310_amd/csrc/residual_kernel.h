@@ -119,7 +119,8 @@ struct KParams {
   const QTables<T>* qt;   // mass rule of this group's a (trilinear elements)
   const T* diss;          // D_h coefficients per element (dissipative kernels)
   T dt;
-  int mode;  // kept for launch bookkeeping; the kernels take the mode as a template argument
+  int mode;     // kept for launch bookkeeping; the kernels take the mode as a template argument
+  int variant;  // launch variant (launch bookkeeping; the kernels take it as a template argument)
   Tables<T> tab;
 };
 
@@ -166,6 +167,13 @@ template <>
 __device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
   typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)byte_off, 0, kStoreNT);
+}
+
+// 8 bytes (two FP32 values or one FP64 value) at a byte offset that is a
+// multiple of 8, non-temporal like buf_store
+__device__ __forceinline__ void buf_store8(const void* lds_src, __amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(*reinterpret_cast<const u32x2*>(lds_src), r, (int)byte_off, 0, kStoreNT);
 }
 
 // stride along the normal and base offset of tangential mode (u, v) on a
@@ -352,8 +360,35 @@ __device__ __forceinline__ void trilinear_mass(T* __restrict__ bufA, T* __restri
   }
 }
 
-template <typename T, int A, int Q, int MODE, bool AFF, bool DISS = false>
-__global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
+// Element e's own block: all components and stored trial levels at this
+// thread's position (levels not stored in this mode are zero).
+template <typename T, int A, int Q, int MODE>
+__device__ __forceinline__ void load_own(const KParams<T>& P, int e, int tid, T (&xr)[6][Q + 1]) {
+  constexpr int A3 = KCfg<A>::A3;
+  constexpr bool resid = MODE == 1;
+  constexpr int m0 = resid ? 0 : 1;
+  constexpr int NL = Q + 1 - m0;
+  constexpr int BLK = 6 * NL * A3 * (int)sizeof(T);
+  const ElemInfo* Ip = P.info + e;
+  const T* xe = P.x + (resid ? Ip->trial_off : Ip->unk_off);
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)xe, (short)0, BLK, 0x00020000);
+  const uint32_t so = (uint32_t)tid * (uint32_t)sizeof(T);
+#pragma unroll
+  for (int fc = 0; fc < 6; ++fc)
+#pragma unroll
+    for (int m = 0; m <= Q; ++m)
+      xr[fc][m] = m >= m0 ? buf_load<T>(rsrc, so + (uint32_t)(((fc * NL + m - m0) * A3) * (int)sizeof(T))) : T(0);
+}
+
+// The residual of element e from its own block xr (already loaded) and its
+// face neighbours.  VAR selects the launch shape (tuned per kernel group):
+//   0  outputs staged through LDS and stored as contiguous 8-byte lanes,
+//      neighbour faces loaded 3 at a time;
+//   1  outputs stored per position (no LDS stage), faces 3 at a time;
+//   2  outputs staged, neighbour faces loaded one at a time (fewer registers).
+template <typename T, int A, int Q, int MODE, bool AFF, bool DISS, int VAR>
+__device__ __forceinline__ void element_body(const KParams<T>& P, const int e, const T (&xr)[6][Q + 1],
+                                             T* __restrict__ sm, const int tid) {
   using C = KCfg<A>;
   constexpr int A2 = C::A2, A3 = C::A3, NF = C::NF, ND = C::ND, LVL = C::lvl(DISS);
   constexpr int LC = C::template LC<T, Q, AFF, DISS>();
@@ -365,16 +400,6 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   constexpr int NL = Q + 1 - m0;                      // trial levels stored per component
   constexpr int BLK = 6 * NL * A3 * (int)sizeof(T);   // bytes of one element block of x
   constexpr int WORDS = (int)sizeof(T) / 4;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
-
-  const int tid = threadIdx.x;
-  // XCD-aware block order: consecutive work-list entries run on the same XCD
-  const uint32_t nblk = gridDim.x, b = blockIdx.x;
-  const uint32_t xcd = b & 7u, idx = b >> 3;
-  const uint32_t qq = nblk >> 3, rr = nblk & 7u;
-  const uint32_t logical = xcd * qq + (xcd < rr ? xcd : rr) + idx;
-  const int e = P.list[logical];
   const ElemInfo* Ip = P.info + e;
   const T* xe = P.x + (resid ? Ip->trial_off : Ip->unk_off);
   T* ye = P.y + Ip->unk_off;
@@ -408,18 +433,6 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   const int fu = t % A, fv = t / A;        // tangential mode (u, v)
   const int tf = tc >> 1;                  // field of that component
 
-  // ---- own block: all components and levels of position s ------------------
-  T xr[6][Q + 1];
-  {
-    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)xe, (short)0, BLK, 0x00020000);
-    const uint32_t so = (uint32_t)tid * (uint32_t)sizeof(T);
-#pragma unroll
-    for (int fc = 0; fc < 6; ++fc)
-#pragma unroll
-      for (int m = 0; m <= Q; ++m)
-        xr[fc][m] = m >= m0 ? buf_load<T>(rsrc, so + (uint32_t)(((fc * NL + m - m0) * A3) * (int)sizeof(T))) : T(0);
-  }
-
   // ---- neighbour traces, contracted in time: acc[face][i] --------------------
   T acc[6][Q];
 #pragma unroll
@@ -445,7 +458,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
     constexpr int CH = NL * A3;                     // entries per component block
     constexpr int KC = (CH + C::NT - 1) / C::NT;    // loads per thread per block
     constexpr int GBC0 = 96 / (4 * KC * WORDS);
-    constexpr int GBC = GBC0 < 1 ? 1 : (GBC0 > 3 ? 3 : GBC0);  // at most 3 faces in flight: fewer VGPRs, more waves
+    constexpr int GBC = VAR == 2 ? 1 : (GBC0 < 1 ? 1 : (GBC0 > 3 ? 3 : GBC0));  // at most 3 faces in flight: fewer VGPRs, more waves
     int nstaged = 0;  // staged faces so far (uniform): buffers strictly alternate
 #pragma unroll
     for (int g0 = 0; g0 < 6; g0 += GBC) {
@@ -512,7 +525,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
     constexpr int CH = NL * A3;                     // entries per component block
     constexpr int KC = (CH + C::NT - 1) / C::NT;    // loads per thread per block
     constexpr int GBC0 = 96 / (4 * KC * WORDS);
-    constexpr int GBC = GBC0 < 1 ? 1 : (GBC0 > 3 ? 3 : GBC0);  // at most 3 faces in flight: fewer VGPRs, more waves
+    constexpr int GBC = VAR == 2 ? 1 : (GBC0 < 1 ? 1 : (GBC0 > 3 ? 3 : GBC0));  // at most 3 faces in flight: fewer VGPRs, more waves
     int nstaged = 0;  // staged faces so far (uniform): buffers strictly alternate
 #pragma unroll
     for (int g0 = 0; g0 < 6; g0 += GBC) {
@@ -739,6 +752,10 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   const __amdgpu_buffer_rsrc_t lrs = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(has_load ? P.load + Ip->unk_off : ye), (short)0, 6 * Q * A3 * (int)sizeof(T), 0x00020000);
   const uint32_t so = (uint32_t)tid * (uint32_t)sizeof(T);
+  // outputs staged through LDS when every level is in one pass (the element's
+  // outputs are then one contiguous run, 8-byte aligned: 6 q a^3 is even)
+  constexpr bool kStageOut = VAR != 1 && LC == Q && 6 * Q * A3 <= C::template main_elems<T, Q, AFF, MODE, DISS>();
+  T yo[kStageOut ? Q : 1][6];
 
 #pragma unroll
   for (int i0 = 0; i0 < Q; i0 += LC) {
@@ -925,13 +942,55 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
             T out = mass + dt * (cu + lift + dl);
             const uint32_t o = so + (uint32_t)((((3 * f + c) * Q + i) * A3) * (int)sizeof(T));
             if (has_load) out -= buf_load<T>(lrs, o);
-            buf_store<T>(out, yrs, o);
+            if constexpr (kStageOut)
+              yo[ii][3 * f + c] = out;
+            else
+              buf_store<T>(out, yrs, o);
           }
         }
       }
     }
     if (i0 + LC < Q) __syncthreads();
   }
+  if constexpr (kStageOut) {
+    // The element's outputs (contiguous: all levels in one pass) go through
+    // LDS and leave as contiguous 8-byte stores, so each store instruction
+    // covers whole cache lines: per-position stores of the a^3-value runs
+    // left partial lines at every run boundary, which the streaming stores
+    // sent to memory as partial writes.  The staged levels are dead here.
+    __syncthreads();
+    if (pos_lane) {
+#pragma unroll
+      for (int ii = 0; ii < Q; ++ii)
+#pragma unroll
+        for (int fc = 0; fc < 6; ++fc) sm[(fc * Q + ii) * A3 + s] = yo[ii][fc];
+    }
+    __syncthreads();
+    constexpr int N8 = 6 * Q * A3 * (int)sizeof(T) / 8;  // 8-byte units of the element's outputs
+#pragma unroll
+    for (int k = 0; k < (N8 + C::NT - 1) / C::NT; ++k) {
+      const int u = tid + k * C::NT;
+      if (N8 % C::NT == 0 || u < N8) buf_store8(reinterpret_cast<const char*>(sm) + 8 * u, yrs, (uint32_t)(8 * u));
+    }
+  }
+}
+
+// One workgroup per element.  Consecutive work-list entries run on one XCD
+// (blocks are dispatched to the 8 XCDs round-robin), so neighbour blocks are
+// found in that XCD's L2.
+template <typename T, int A, int Q, int MODE, bool AFF, bool DISS = false, int VAR = 0>
+__global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x;
+  const uint32_t nblk = gridDim.x, b = blockIdx.x;
+  const uint32_t xcd = b & 7u, idx = b >> 3;
+  const uint32_t qq = nblk >> 3, rr = nblk & 7u;
+  const uint32_t logical = xcd * qq + (xcd < rr ? xcd : rr) + idx;
+  const int e = P.list[logical];
+  T xr[6][Q + 1];
+  load_own<T, A, Q, MODE>(P, e, tid, xr);
+  element_body<T, A, Q, MODE, AFF, DISS, VAR>(P, e, xr, sm, tid);
 }
 
 // P^{-1} applied blockwise (3x3 per spatial mode and level), for meshes whose

@@ -70,14 +70,17 @@ def test_tune_cache_read_and_write(tmp_path):
     # a missing or damaged cache reads as empty; writes replace the file whole
     path = str(tmp_path / "tune.json")
     assert stdg._tune_cache_read(path) == {}
-    stdg._tune_cache_write(path, {"a": 8})
-    assert stdg._tune_cache_read(path) == {"a": 8}
-    for junk in ("{not json", "[1, 2]", '{"a": "x"}'):
+    a = {"order": 8, "variants": [0, 2]}
+    stdg._tune_cache_write(path, {"a": a})
+    assert stdg._tune_cache_read(path) == {"a": a}
+    for junk in ("{not json", "[1, 2]", '{"a": "x"}', '{"a": 8}', '{"a": {"order": 8}}',
+                 '{"a": {"order": 8, "variants": ["x"]}}'):
         with open(path, "w") as f:
             f.write(junk)
         assert stdg._tune_cache_read(path) == {}
-    stdg._tune_cache_write(path, {"a": 4, "b": 0})
-    assert stdg._tune_cache_read(path) == {"a": 4, "b": 0}
+    b = {"order": 0, "variants": [1]}
+    stdg._tune_cache_write(path, {"a": a, "b": b})
+    assert stdg._tune_cache_read(path) == {"a": a, "b": b}
     assert sorted(p.name for p in tmp_path.iterdir()) == ["tune.json"]
 
 

@@ -1,9 +1,10 @@
 """GPU parity of stdg_residual_apply (the slab residual, Section 5 eq. residual)
 against the FP64 oracle on the same seeded inputs, through the C ABI.
 
-Bars: FP64 relative 2-norm error <= 1e-12; raw FP32 apply <= 1e-5 (the FP32
-inputs are the float32 roundings of the FP64 ones and the oracle is run on
-exactly those values)."""
+Bars: FP64 <= 1e-12, raw FP32 apply <= 1e-5, each for the relative 2-norm
+error and for the largest entry error relative to the largest reference entry
+(the FP32 inputs are the float32 roundings of the FP64 ones and the oracle is
+run on exactly those values)."""
 import numpy as np
 import pytest
 
@@ -176,9 +177,10 @@ def test_binding_checks_device_buffers(lib):
         stdg.stdg_mesh_free(mh)
 
 
-def test_work_order_and_autotune(lib, tmp_path):
-    # every element order gives bitwise the same apply; the autotuner returns
-    # one of its candidates, stores it in the cache and reuses it
+def test_work_order_launch_variants_and_autotune(lib, tmp_path):
+    # every element order and every launch variant gives bitwise the same
+    # apply; the autotuner returns one of its candidate orders and a variant
+    # per group, stores them in the cache and reuses them
     stdg = lib.stdg
     cfg = synth.cavity_two_material(n=8, p=3, q=2)
     m = cfg["mesh"]
@@ -190,21 +192,60 @@ def test_work_order_and_autotune(lib, tmp_path):
         for order in (0, 4, 8, 16, 3):
             stdg.stdg_mesh_set_order(mh, order)
             assert stdg.stdg_mesh_info(mh)["work_order"] == order
-            for prec in (0, 1):
-                y = lib.apply(mh, cfg["dt"], prec, stdg.STDG_OPERATOR_PRECOND, x)
-                ref.setdefault(prec, y)
-                assert np.array_equal(y, ref[prec])
+            for variant in (0, 1, 2):
+                stdg.stdg_mesh_set_launch(mh, -1, variant)
+                assert stdg.stdg_mesh_group(mh, 0)["variant"] == variant
+                for prec in (0, 1):
+                    for mode in (stdg.STDG_OPERATOR, stdg.STDG_OPERATOR_PRECOND):
+                        y = lib.apply(mh, cfg["dt"], prec, mode, x)
+                        ref.setdefault((prec, mode), y)
+                        assert np.array_equal(y, ref[(prec, mode)]), (order, variant, prec, mode)
         with pytest.raises(stdg.StdgError):
             stdg.stdg_mesh_set_order(mh, 1)
+        with pytest.raises(stdg.StdgError):
+            stdg.stdg_mesh_set_launch(mh, -1, 3)
+        with pytest.raises(stdg.StdgError):
+            stdg.stdg_mesh_set_launch(mh, 1, 0)
         cache = str(tmp_path / "tune.json")
         got = stdg.stdg_mesh_autotune(mh, stdg.STDG_FP32, cfg["dt"], reps=5, cache=cache)
-        assert got in (0, 4, 8, 16) and stdg.stdg_mesh_info(mh)["work_order"] == got
+        assert got["order"] in (0, 4, 8, 16) and stdg.stdg_mesh_info(mh)["work_order"] == got["order"]
+        assert len(got["variants"]) == 1 and got["variants"][0] in (0, 1, 2)
+        assert stdg.stdg_mesh_group(mh, 0)["variant"] == got["variants"][0]
         import json
         table = json.load(open(cache))
         assert list(table.values()) == [got]
-        stdg.stdg_mesh_set_order(mh, 0 if got else 4)
+        stdg.stdg_mesh_set_order(mh, 0 if got["order"] else 4)
+        stdg.stdg_mesh_set_launch(mh, -1, (got["variants"][0] + 1) % 3)
         assert stdg.stdg_mesh_autotune(mh, stdg.STDG_FP32, cfg["dt"], cache=cache) == got
-        assert stdg.stdg_mesh_info(mh)["work_order"] == got
+        assert stdg.stdg_mesh_info(mh)["work_order"] == got["order"]
+        assert stdg.stdg_mesh_group(mh, 0)["variant"] == got["variants"][0]
+        for prec in (0, 1):
+            assert np.array_equal(lib.apply(mh, cfg["dt"], prec, stdg.STDG_OPERATOR_PRECOND, x),
+                                  ref[(prec, stdg.STDG_OPERATOR_PRECOND)])
+    finally:
+        stdg.stdg_mesh_free(mh)
+
+
+def test_launch_variants_mixed_groups_match_oracle(lib):
+    # mixed degrees (several groups, staged and gathered neighbour paths,
+    # p-truncated faces) in every variant against the oracle
+    stdg = lib.stdg
+    m = random_mixed_mesh((3, 3, 2), 5, 3, 41)
+    d = oracle_disc(m)
+    mh = lib.upload(m)
+    try:
+        n_groups = stdg.stdg_mesh_info(mh)["n_groups"]
+        assert n_groups > 4
+        assert {stdg.stdg_mesh_group(mh, g)["affine"] for g in range(n_groups)} == {1}
+        x = synth.random_vector(m.unknown_size(), 42)
+        dt = 0.03
+        for prec in (0, 1):
+            xin = x.astype(np.float32).astype(np.float64) if prec == 1 else x
+            ref = d.operator(xin, dt)
+            for variant in (0, 1, 2):
+                stdg.stdg_mesh_set_launch(mh, -1, variant)
+                got = lib.apply(mh, dt, prec, stdg.STDG_OPERATOR, xin)
+                assert rel_err(got, ref) < TOL[prec], (prec, variant)
     finally:
         stdg.stdg_mesh_free(mh)
 
