@@ -279,12 +279,14 @@ typedef struct {
                           (eq. a_posteriori:iteration) is <= eta_tol^2; 0 = off  */
   double eta_t_final;  /* t_N of that bound (final time, slabs from t = 0), > 0
                           when eta_tol > 0                                       */
-  int32_t use_graph;   /* 1: replay each Arnoldi iteration (apply, CGS2 passes,
-                          scalar copy) as a captured HIP graph, one per basis
-                          index, kept with the mesh's solver (meshes with one
-                          kernel group; captured on the second use of an index,
-                          recaptured when dt changes); results are bitwise those
-                          of the direct launches.  0 = direct launches          */
+  int32_t use_graph;   /* 1: replay each restart cycle (start vector, up to
+                          `restart` Arnoldi iterations of apply and two basis
+                          passes, least-squares update of the iterate) as one
+                          captured HIP graph, kept with the mesh's solver
+                          (captured at the second cycle, recaptured when dt or
+                          the mesh's launch set-up changes); results are bitwise
+                          those of the direct launches.  0 = direct launches.
+                          Either way the host waits once per restart cycle.    */
 } stdg_solve_opts;
 
 typedef struct {

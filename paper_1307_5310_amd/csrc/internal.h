@@ -178,13 +178,16 @@ struct ApplyArgs {
   // device scratch, and several kernel groups run one after another on
   // `stream` (no side streams or events are created)
   bool no_alloc = false;
+  // device flag read by the kernels at entry: 0 = return at once (kernels of
+  // Arnoldi iterations past the end of a restart cycle); NULL = always run
+  const int* skip = nullptr;
 };
 int launch_residual(const ApplyArgs& a);
 // Static device scratch of the allocation-free apply: look up this device's
 // address of the array (once per device; the device must be current).
 int noalloc_scratch_init(int device);
 size_t noalloc_scratch_capacity();
-int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s);
+int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s, const int* skip = nullptr);
 
 // Mesh construction (mesh.cpp): host analysis (validation, faces, metric,
 // groups) and the device copies, separable so that a server can analyse a

@@ -1,19 +1,31 @@
-// Fused Arnoldi kernels of the slab GMRES (Section 5.4): classical
-// Gram-Schmidt applied twice, in three passes over the basis per iteration.
+// Arnoldi kernels of the slab GMRES (Section 5.4): classical Gram-Schmidt
+// applied twice, with the second projection of each new basis vector
+// delayed into the next iteration, so that an iteration makes two passes over
+// the basis instead of three; the Hessenberg column, its Givens rotation and
+// the stopping test run on the device, so that a whole restart cycle runs
+// without the host.
 //
-// The basis is stored unnormalised, V_j = s_j Vt_j with Vt_j in FP64 or FP32
-// and the scales s_j in FP64 on the device, so a new basis vector is written
-// once (no separate normalisation pass).  All sums are FP64.  Reductions are
-// deterministic: fixed-order reductions inside each block, per-block partials,
-// and the last block to finish (detected with a device-scope counter) sums the
-// partials in block order and resets the counter.
-//
-//   arnoldi_dot         d_j = Vt_j . w                       -> h_j = s_j d_j, c_j = s_j^2 d_j
-//   arnoldi_update_dot  w' = w - sum_j c_j Vt_j,  d'_j = Vt_j . w'  -> h', c'  (w' may overwrite w)
-//   arnoldi_update_norm Vt_{k} = w' - sum_j c'_j Vt_j (stored), ||Vt_k||^2, s_k = 1 / ||Vt_k||
-//
-// Each thread streams 4 consecutive entries per step with 16-byte loads;
-// basis slots therefore have a leading dimension that is a multiple of 64.
+// Iteration j (V_0 .. V_{j-1} formed and orthonormal; w the previous
+// iteration's vector after one projection, whose second-projection
+// coefficients hp = V^T w and norm estimate nu = sqrt(|w|^2 - |hp|^2) are
+// known; for j = 0 nothing is pending and V_0 is the start vector):
+//   z = B P^{-1} w (z = B P^{-1} V_0 for j = 0)                    [the apply]
+//   pass 1: c_l = V_l . z (l < j), d = w . z; then, with the pending
+//           V_j = (w - sum_l hp_l V_l) / nu, V_j . z = (d - hp . c) / nu, and
+//           A V_j = (z - V H hp) / nu gives the Hessenberg entries
+//           h_l = (V_l . z - (H hp)_l) / nu, l <= j
+//   pass 2: V_j formed and stored; w' = (z - sum_{l<=j} (V_l . z) V_l) / nu
+//           (the first projection of A V_j: the V H hp part lies in the
+//           span), e_l = V_l . w', |w'|^2; column j of H = h + e, its
+//           subdiagonal sqrt(|w'|^2 - |e|^2); Givens rotation, residual
+//           estimate |g_{j+1}| and the stopping test; w', e carried on.
+// At the cycle end the least-squares solution y = R^{-1} g combines the
+// formed vectors V_0 .. V_{k-1}.  All sums are FP64; reductions are
+// deterministic: fixed-order block reductions, per-block partials, and the
+// last block to finish (detected with a device-scope counter) sums the
+// partials in block order and resets the counter.  Each thread streams 4
+// consecutive entries per step with 16-byte loads; basis slots therefore
+// have a leading dimension that is a multiple of 64.
 #include "solver.h"
 
 namespace stdg {
@@ -141,6 +153,25 @@ __device__ __forceinline__ void for_vec4(int64_t n, Body body) {
   if (blockIdx.x == 0 && (int64_t)threadIdx.x < tail) body.template run<1>((n4 << 2) + threadIdx.x);
 }
 
+
+// Block-reduce acc[0..k) into per-block partials; in the last block to
+// finish, thread 0 gets the totals in tot[0..k) and true is returned there
+// (false everywhere else).  Resets the counter.
+template <int KM>
+__device__ __forceinline__ bool reduce_totals(const double (&acc)[KM], int k, double* __restrict__ partial,
+                                              unsigned* __restrict__ counter, double (&tot)[KM]) {
+  __shared__ double stot[KM];
+  bool mine = false;
+  reduce_and_finish<KM>(acc, k, partial, counter, [&](int j, double d) { stot[j] = d; mine = true; });
+  if (!mine) return false;
+#pragma unroll
+  for (int j = 0; j < KM; ++j) tot[j] = j < k ? stot[j] : 0.0;
+  return true;
+}
+
+template <typename TV>
+__device__ __forceinline__ double round_to(double v) { return (double)(TV)v; }
+
 template <typename TV, typename TW, int KM>
 struct DotBody {
   const TV* V;
@@ -180,102 +211,221 @@ dot_kernel(const TV* __restrict__ V, int64_t ldv, int k, const TW* __restrict__ 
   });
 }
 
-template <typename TV, typename TW, int KM>
-struct UpdateDotBody {
+
+template <typename TV, typename TZ, typename TW, int KM>
+struct Pass1Body {
   const TV* V;
   int64_t ldv;
-  int k;
+  int j;
+  const TZ* z;
   const TW* w;
-  const double* cc;
-  double* wout;
   double* acc;
   template <int W>
   __device__ __forceinline__ void run(int64_t i) {
-    double x[W];
-    ld<W>(w + i, x);
-    double vv[KM][W];
+    double zv[W];
+    ld<W>(z + i, zv);
 #pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      if (j < k) {
-        ld<W>(V + j * ldv + i, vv[j]);
+    for (int l = 0; l < KM; ++l) {
+      if (l < j) {
+        double vv[W];
+        ld<W>(V + l * ldv + i, vv);
 #pragma unroll
-        for (int e = 0; e < W; ++e) x[e] -= cc[j] * vv[j][e];
+        for (int e = 0; e < W; ++e) acc[l] += vv[e] * zv[e];
       }
     }
-    st<W>(wout + i, x);
+    double wv[W];
+    if (j > 0) ld<W>(w + i, wv); else ld<W>(V + i, wv);
 #pragma unroll
-    for (int j = 0; j < KM; ++j)
-      if (j < k) {
-#pragma unroll
-        for (int e = 0; e < W; ++e) acc[j] += vv[j][e] * x[e];
-      }
+    for (int e = 0; e < W; ++e) acc[j] += wv[e] * zv[e];
   }
 };
 
-template <typename TV, typename TW, int KM>
+// pass 1: c = V^T z (and d = w . z), then the Hessenberg entries h of
+// column j and the update coefficients of pass 2
+template <typename TV, typename TZ, typename TW, int KM>
 __global__ void __launch_bounds__(kThreads)
-update_dot_kernel(const TV* __restrict__ V, int64_t ldv, int k, const TW* w, const double* __restrict__ cin,
-                  double* wout, int64_t n, const double* __restrict__ s, double* __restrict__ h,
-                  double* __restrict__ c, double* __restrict__ partial, unsigned* __restrict__ counter) {
-  double cc[KM], acc[KM];
+pass1_kernel(const TV* __restrict__ V, int64_t ldv, int j, const TZ* __restrict__ z, const TW* __restrict__ w,
+             int64_t n, CycleCtl* __restrict__ ctl, double* __restrict__ partial, unsigned* __restrict__ counter) {
+  if (!ctl->active) return;
+  double acc[KM];
 #pragma unroll
-  for (int j = 0; j < KM; ++j) {
-    cc[j] = j < k ? cin[j] : 0.0;
-    acc[j] = 0.0;
+  for (int l = 0; l < KM; ++l) acc[l] = 0.0;
+  for_vec4(n, Pass1Body<TV, TZ, TW, KM>{V, ldv, j, z, w, acc});
+  double tot[KM];
+  if (!reduce_totals<KM>(acc, j + 1, partial, counter, tot)) return;
+  if (j == 0) {
+    ctl->h[0] = tot[0];
+    ctl->cz[0] = tot[0];
+    ctl->inv_nu = 1.0;
+    return;
   }
-  for_vec4(n, UpdateDotBody<TV, TW, KM>{V, ldv, k, w, cc, wout, acc});
-  reduce_and_finish<KM>(acc, k, partial, counter, [&](int j, double d) {
-    const double sj = s[j];
-    h[j] = sj * d;
-    c[j] = sj * sj * d;
-  });
+  const double inv = 1.0 / ctl->nu;
+  double c[kMaxBasis];
+  double t = tot[j];
+  for (int l = 0; l < j; ++l) {
+    c[l] = tot[l];
+    t -= ctl->hp[l] * tot[l];
+  }
+  c[j] = t * inv;
+  for (int l = 0; l <= j; ++l) {
+    double g = 0.0;  // (H hp)_l over the columns 0 .. j-1
+    for (int i = (l > 0 ? l - 1 : 0); i < j; ++i) g += ctl->Hraw[l * kMaxBasis + i] * ctl->hp[i];
+    ctl->h[l] = (c[l] - g) * inv;
+    ctl->cz[l] = c[l] * inv;
+  }
+  ctl->inv_nu = inv;
 }
 
-template <typename TV, int KM>
-struct UpdateNormBody {
-  const TV* V;
+template <typename TV, typename TZ, typename TW, int KM>
+struct Pass2Body {
+  TV* V;
   int64_t ldv;
-  int k;
-  const double* w;
-  const double* cc;
-  TV* vout;
+  int j;
+  const TZ* z;
+  TW* w;
+  float* w32;
+  const double* hp;  // second-projection coefficients of the pending vector
+  const double* cz;  // (V_l . z) / nu
+  double inv;
   double* acc;
   template <int W>
   __device__ __forceinline__ void run(int64_t i) {
-    double x[W];
-    ld<W>(w + i, x);
+    double vv[KM][W];
 #pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      if (j < k) {
-        double vv[W];
-        ld<W>(V + j * ldv + i, vv);
+    for (int l = 0; l < KM; ++l)
+      if (l < j) ld<W>(V + l * ldv + i, vv[l]);
+    double vj[W];
+    if (j > 0) {
+      double wv[W];
+      ld<W>(w + i, wv);
 #pragma unroll
-        for (int e = 0; e < W; ++e) x[e] -= cc[j] * vv[e];
+      for (int e = 0; e < W; ++e) {
+        double x = wv[e];
+#pragma unroll
+        for (int l = 0; l < KM; ++l)
+          if (l < j) x -= hp[l] * vv[l][e];
+        vj[e] = round_to<TV>(x * inv);
       }
+      st<W>(V + j * ldv + i, vj);
+    } else {
+      ld<W>(V + i, vj);
     }
-    // the norm of the stored (rounded) vector, so s normalises what is kept
+    double zv[W], wn[W];
+    ld<W>(z + i, zv);
 #pragma unroll
-    for (int e = 0; e < W; ++e) x[e] = (double)(TV)x[e];
-    st<W>(vout + i, x);
+    for (int e = 0; e < W; ++e) {
+      double x = zv[e] * inv;
 #pragma unroll
-    for (int e = 0; e < W; ++e) acc[0] += x[e] * x[e];
+      for (int l = 0; l < KM; ++l)
+        if (l < j) x -= cz[l] * vv[l][e];
+      x -= cz[j] * vj[e];
+      wn[e] = round_to<TW>(x);
+    }
+    st<W>(w + i, wn);
+    if (w32) st<W>(w32 + i, wn);
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+#pragma unroll
+      for (int l = 0; l < KM; ++l)
+        if (l < j) acc[l] += vv[l][e] * wn[e];
+      acc[j] += vj[e] * wn[e];
+      acc[j + 1] += wn[e] * wn[e];
+    }
   }
 };
 
-template <typename TV, int KM>
+// pass 2: V_j formed, w' = (z - V (V^T z)) / nu, e = V^T w', |w'|^2; then the
+// Hessenberg column, its Givens rotation and the stopping test
+template <typename TV, typename TZ, typename TW, int KM>
 __global__ void __launch_bounds__(kThreads)
-update_norm_kernel(const TV* __restrict__ V, int64_t ldv, int k, const double* __restrict__ w,
-                   const double* __restrict__ cin, TV* __restrict__ vout, int64_t n, double* __restrict__ norm2,
-                   double* __restrict__ s_next, double* __restrict__ partial, unsigned* __restrict__ counter) {
-  double cc[KM];
+pass2_kernel(TV* __restrict__ V, int64_t ldv, int j, const TZ* __restrict__ z, TW* w, float* w32, int64_t n,
+             CycleCtl* __restrict__ ctl, double* __restrict__ partial, unsigned* __restrict__ counter) {
+  if (!ctl->active) return;
+  double hp[KM], cz[KM], acc[KM];
 #pragma unroll
-  for (int j = 0; j < KM; ++j) cc[j] = j < k ? cin[j] : 0.0;
-  double acc[1] = {0.0};
-  for_vec4(n, UpdateNormBody<TV, KM>{V, ldv, k, w, cc, vout, acc});
-  reduce_and_finish<1>(acc, 1, partial, counter, [&](int, double d) {
-    *norm2 = d;
-    *s_next = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
-  });
+  for (int l = 0; l < KM; ++l) {
+    hp[l] = l < j ? ctl->hp[l] : 0.0;
+    cz[l] = l <= j ? ctl->cz[l] : 0.0;
+    acc[l] = 0.0;
+  }
+  const double inv = ctl->inv_nu;
+  for_vec4(n, Pass2Body<TV, TZ, TW, KM>{V, ldv, j, z, w, w32, hp, cz, inv, acc});
+  double tot[KM];
+  if (!reduce_totals<KM>(acc, j + 2, partial, counter, tot)) return;
+  // column j of H: both projections, and the subdiagonal from the norm of w'
+  // after its second projection (Pythagoras: V is orthonormal)
+  const double s2 = tot[j + 1];
+  double col[kMaxBasis + 1], e2 = 0.0;
+  for (int l = 0; l <= j; ++l) {
+    col[l] = ctl->h[l] + tot[l];
+    e2 += tot[l] * tot[l];
+    ctl->hp[l] = tot[l];
+  }
+  const double r2 = s2 - e2;
+  // breakdown: w' lies in the span of V to rounding (the Krylov space is invariant)
+  const double nu = (r2 > 1e-28 * s2 && r2 > 0.0) ? sqrt(r2) : 0.0;
+  col[j + 1] = nu;
+  ctl->nu = nu;
+  for (int l = 0; l <= j + 1; ++l) ctl->Hraw[l * kMaxBasis + j] = col[l];
+  for (int i = 0; i < j; ++i) {
+    const double t = ctl->cs[i] * col[i] + ctl->sn[i] * col[i + 1];
+    col[i + 1] = -ctl->sn[i] * col[i] + ctl->cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  const double cs = den > 0.0 ? col[j] / den : 1.0, sn = den > 0.0 ? col[j + 1] / den : 0.0;
+  ctl->cs[j] = cs;
+  ctl->sn[j] = sn;
+  col[j] = den;
+  ctl->g[j + 1] = -sn * ctl->g[j];
+  ctl->g[j] = cs * ctl->g[j];
+  for (int l = 0; l <= j; ++l) ctl->R[l * kMaxBasis + j] = col[l];
+  ctl->k = j + 1;
+  ctl->iters += 1;
+  bool finite = isfinite(nu) && isfinite(den) && isfinite(ctl->g[j + 1]);
+  if (!finite) ctl->bad = 1;
+  if (!finite || fabs(ctl->g[j + 1]) <= ctl->target || nu == 0.0 || den == 0.0 || j + 1 >= ctl->restart ||
+      ctl->iters >= ctl->max_iters)
+    ctl->active = 0;
+}
+
+// cycle start: V_0 = r / |r| from the residual r and its squared norm, the
+// least-squares state reset (one thread of block 0)
+template <typename TV>
+__global__ void __launch_bounds__(kThreads)
+cycle_start_kernel(const double* r, const double* __restrict__ norm2, TV* v0, float* __restrict__ v32, int64_t n,
+                   CycleCtl* __restrict__ ctl) {
+  // r and v0 may be the same memory (an FP64 basis holds the residual in slot 0): in place, entry by entry
+  const double beta = sqrt(*norm2);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = round_to<TV>(r[i] * inv);
+    v0[i] = (TV)v;
+    if (v32) v32[i] = (float)v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->active = beta > 0.0 ? 1 : 0;
+    ctl->k = 0;
+    ctl->bad = 0;
+    ctl->nu = 1.0;
+    ctl->g[0] = beta;
+    for (int l = 1; l <= kMaxBasis; ++l) ctl->g[l] = 0.0;
+  }
+}
+
+// cycle end: y = R^{-1} g over the k columns done, coefficients -y (the
+// Krylov system is solved for the negated residual)
+__global__ void least_squares_kernel(CycleCtl* __restrict__ ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int k = ctl->k;
+  double y[kMaxBasis];
+  for (int i = k - 1; i >= 0; --i) {
+    double t = ctl->g[i];
+    for (int l = i + 1; l < k; ++l) t -= ctl->R[i * kMaxBasis + l] * y[l];
+    y[i] = t / ctl->R[i * kMaxBasis + i];
+  }
+  for (int i = 0; i < kMaxBasis; ++i) ctl->y[i] = i < k ? -y[i] : 0.0;
 }
 
 template <typename TV, int KM>
@@ -305,8 +455,9 @@ struct CombineBody {
 
 template <typename TV, int KM>
 __global__ void __launch_bounds__(kThreads)
-combine_kernel(double* __restrict__ out, const TV* __restrict__ V, int64_t ldv, int k,
+combine_kernel(double* __restrict__ out, const TV* __restrict__ V, int64_t ldv, int k, const int* __restrict__ kdev,
                const double* __restrict__ coef, int64_t n) {
+  if (kdev) k = *kdev;
   double cc[KM];
 #pragma unroll
   for (int j = 0; j < KM; ++j) cc[j] = j < k ? coef[j] : 0.0;
@@ -363,75 +514,59 @@ int km_for(int k) { return k <= 4 ? 4 : (k <= 8 ? 8 : (k <= 12 ? 12 : (k <= 16 ?
     default: CALL(32); break;          \
   }
 
-int arnoldi_dot(const void* V, bool v32, int64_t ldv, int k, const void* w, bool w32, int64_t n, const double* s,
-                double* h, double* c, const DotWork& dw, hipStream_t st) {
-  if (k < 1 || k > kMaxBasis) return fail(STDG_E_ARG, "arnoldi_dot: basis size out of range");
-  if (ldv % 64) return fail(STDG_E_ARG, "arnoldi_dot: leading dimension must be a multiple of 64");
+// precision combinations of (basis, apply output, pending vector)
+#define STDG_PRECS(CALL, KM)                                   \
+  if (v32) { CALL(float, float, float, KM); }                  \
+  else if (z32) { CALL(double, float, double, KM); }           \
+  else { CALL(double, double, double, KM); }
+
+int arnoldi_pass1(const void* V, bool v32, int64_t ldv, int j, const void* z, bool z32, const void* w, int64_t n,
+                  CycleCtl* ctl, const DotWork& dw, hipStream_t st) {
+  if (j < 0 || j + 1 > kMaxBasis) return fail(STDG_E_ARG, "arnoldi_pass1: basis index out of range");
+  if (ldv % 64) return fail(STDG_E_ARG, "arnoldi_pass1: leading dimension must be a multiple of 64");
+  if (v32 && !z32) return fail(STDG_E_ARG, "arnoldi_pass1: an FP32 basis needs FP32 applies");
   const dim3 g(dot_blocks(n)), b(kThreads);
-#define STDG_LAUNCH(TV, TW, KM)                                                                                \
-  hipLaunchKernelGGL((dot_kernel<TV, TW, KM>), g, b, 0, st, (const TV*)V, ldv, k, (const TW*)w, n, s, h, c, \
-                     dw.partial, dw.counter)
-#define STDG_FF(KM) STDG_LAUNCH(float, float, KM)
-#define STDG_FD(KM) STDG_LAUNCH(float, double, KM)
-#define STDG_DF(KM) STDG_LAUNCH(double, float, KM)
-#define STDG_DD(KM) STDG_LAUNCH(double, double, KM)
-  const int km = km_for(k);
-  if (v32) {
-    if (w32) { STDG_KM_SWITCH(km, STDG_FF) } else { STDG_KM_SWITCH(km, STDG_FD) }
-  } else {
-    if (w32) { STDG_KM_SWITCH(km, STDG_DF) } else { STDG_KM_SWITCH(km, STDG_DD) }
-  }
-#undef STDG_FF
-#undef STDG_FD
-#undef STDG_DF
-#undef STDG_DD
-#undef STDG_LAUNCH
-  return check_launch("arnoldi_dot");
+#define STDG_L(TV, TZ, TW, KM)                                                                                 \
+  hipLaunchKernelGGL((pass1_kernel<TV, TZ, TW, KM>), g, b, 0, st, (const TV*)V, ldv, j, (const TZ*)z,        \
+                     (const TW*)w, n, ctl, dw.partial, dw.counter)
+#define STDG_K(KM) STDG_PRECS(STDG_L, KM)
+  STDG_KM_SWITCH(km_for(j + 1), STDG_K)
+#undef STDG_K
+#undef STDG_L
+  return check_launch("arnoldi_pass1");
 }
 
-int arnoldi_update_dot(const void* V, bool v32, int64_t ldv, int k, const void* w, bool w32, const double* cin,
-                       double* wout, int64_t n, const double* s, double* h, double* c, const DotWork& dw,
-                       hipStream_t st) {
-  if (k < 1 || k > kMaxBasis) return fail(STDG_E_ARG, "arnoldi_update_dot: basis size out of range");
-  if (ldv % 64) return fail(STDG_E_ARG, "arnoldi_update_dot: leading dimension must be a multiple of 64");
+int arnoldi_pass2(void* V, bool v32, int64_t ldv, int j, const void* z, bool z32, void* w, float* w32, int64_t n,
+                  CycleCtl* ctl, const DotWork& dw, hipStream_t st) {
+  if (j < 0 || j + 2 > kMaxBasis) return fail(STDG_E_ARG, "arnoldi_pass2: basis index out of range");
+  if (ldv % 64) return fail(STDG_E_ARG, "arnoldi_pass2: leading dimension must be a multiple of 64");
+  if (v32 && !z32) return fail(STDG_E_ARG, "arnoldi_pass2: an FP32 basis needs FP32 applies");
   const dim3 g(dot_blocks(n)), b(kThreads);
-#define STDG_LAUNCH(TV, TW, KM)                                                                                   \
-  hipLaunchKernelGGL((update_dot_kernel<TV, TW, KM>), g, b, 0, st, (const TV*)V, ldv, k, (const TW*)w, cin, wout, \
-                     n, s, h, c, dw.partial, dw.counter)
-#define STDG_FF(KM) STDG_LAUNCH(float, float, KM)
-#define STDG_FD(KM) STDG_LAUNCH(float, double, KM)
-#define STDG_DF(KM) STDG_LAUNCH(double, float, KM)
-#define STDG_DD(KM) STDG_LAUNCH(double, double, KM)
-  const int km = km_for(k);
-  if (v32) {
-    if (w32) { STDG_KM_SWITCH(km, STDG_FF) } else { STDG_KM_SWITCH(km, STDG_FD) }
-  } else {
-    if (w32) { STDG_KM_SWITCH(km, STDG_DF) } else { STDG_KM_SWITCH(km, STDG_DD) }
-  }
-#undef STDG_FF
-#undef STDG_FD
-#undef STDG_DF
-#undef STDG_DD
-#undef STDG_LAUNCH
-  return check_launch("arnoldi_update_dot");
+#define STDG_L(TV, TZ, TW, KM)                                                                                     \
+  hipLaunchKernelGGL((pass2_kernel<TV, TZ, TW, KM>), g, b, 0, st, (TV*)V, ldv, j, (const TZ*)z, (TW*)w, w32, n, \
+                     ctl, dw.partial, dw.counter)
+#define STDG_K(KM) STDG_PRECS(STDG_L, KM)
+  STDG_KM_SWITCH(km_for(j + 2), STDG_K)
+#undef STDG_K
+#undef STDG_L
+  return check_launch("arnoldi_pass2");
 }
 
-int arnoldi_update_norm(const void* V, bool v32, int64_t ldv, int k, const double* w, const double* cin, void* vout,
-                        int64_t n, double* norm2, double* s_next, const DotWork& dw, hipStream_t st) {
-  if (k < 1 || k > kMaxBasis) return fail(STDG_E_ARG, "arnoldi_update_norm: basis size out of range");
-  if (ldv % 64) return fail(STDG_E_ARG, "arnoldi_update_norm: leading dimension must be a multiple of 64");
-  const dim3 g(dot_blocks(n)), b(kThreads);
-#define STDG_LAUNCH(TV, KM)                                                                                    \
-  hipLaunchKernelGGL((update_norm_kernel<TV, KM>), g, b, 0, st, (const TV*)V, ldv, k, w, cin, (TV*)vout, n, \
-                     norm2, s_next, dw.partial, dw.counter)
-#define STDG_F(KM) STDG_LAUNCH(float, KM)
-#define STDG_D(KM) STDG_LAUNCH(double, KM)
-  const int km = km_for(k);
-  if (v32) { STDG_KM_SWITCH(km, STDG_F) } else { STDG_KM_SWITCH(km, STDG_D) }
-#undef STDG_F
-#undef STDG_D
-#undef STDG_LAUNCH
-  return check_launch("arnoldi_update_norm");
+#undef STDG_PRECS
+
+int cycle_start(const double* r, const double* norm2, void* v0, bool v32, float* v0_32, int64_t n, CycleCtl* ctl,
+                hipStream_t st) {
+  const dim3 g(stream_blocks(n)), b(kThreads);
+  if (v32)
+    hipLaunchKernelGGL(cycle_start_kernel<float>, g, b, 0, st, r, norm2, (float*)v0, v0_32, n, ctl);
+  else
+    hipLaunchKernelGGL(cycle_start_kernel<double>, g, b, 0, st, r, norm2, (double*)v0, v0_32, n, ctl);
+  return check_launch("cycle_start");
+}
+
+int cycle_least_squares(CycleCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(least_squares_kernel, dim3(1), dim3(64), 0, st, ctl);
+  return check_launch("cycle_least_squares");
 }
 
 int vec_dot(const double* a, const double* b, int64_t n, double* out, const DotWork& dw, hipStream_t st) {
@@ -441,13 +576,15 @@ int vec_dot(const double* a, const double* b, int64_t n, double* out, const DotW
   return check_launch("vec_dot");
 }
 
-int basis_combine(double* out, const void* V, bool v32, int64_t ldv, int k, const double* coef, int64_t n,
-                  hipStream_t st) {
+int basis_combine(double* out, const void* V, bool v32, int64_t ldv, int k, const int* kdev, const double* coef,
+                  int64_t n, hipStream_t st) {
   if (k < 1 || k > kMaxBasis) return fail(STDG_E_ARG, "basis_combine: basis size out of range");
   if (ldv % 64) return fail(STDG_E_ARG, "basis_combine: leading dimension must be a multiple of 64");
   const dim3 g(stream_blocks(n)), b(kThreads);
-#define STDG_F(KM) hipLaunchKernelGGL((combine_kernel<float, KM>), g, b, 0, st, out, (const float*)V, ldv, k, coef, n)
-#define STDG_D(KM) hipLaunchKernelGGL((combine_kernel<double, KM>), g, b, 0, st, out, (const double*)V, ldv, k, coef, n)
+#define STDG_F(KM) \
+  hipLaunchKernelGGL((combine_kernel<float, KM>), g, b, 0, st, out, (const float*)V, ldv, k, kdev, coef, n)
+#define STDG_D(KM) \
+  hipLaunchKernelGGL((combine_kernel<double, KM>), g, b, 0, st, out, (const double*)V, ldv, k, kdev, coef, n)
   const int km = km_for(k);
   if (v32) { STDG_KM_SWITCH(km, STDG_F) } else { STDG_KM_SWITCH(km, STDG_D) }
 #undef STDG_F

@@ -83,8 +83,10 @@ static int ensure_aux(Mesh* m) {
 // write disjoint outputs, so the result does not depend on their order).
 template <typename T>
 static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* load, T* y, hipStream_t s,
-                      Launcher<T>* affine, Launcher<T>* trilinear, const QTables<T>* d_qt, bool allow_fork) {
+                      Launcher<T>* affine, Launcher<T>* trilinear, const QTables<T>* d_qt, bool allow_fork,
+                      const int* skip) {
   KParams<T> P;
+  P.skip = skip;
   P.info = m->d_info;
   P.metric = m->d_metric;
   P.x = x;
@@ -130,14 +132,14 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
   return STDG_OK;
 }
 
-int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s) {
+int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s, const int* skip) {
   const dim3 grid((unsigned)m->ne), block(256);
   if (prec == STDG_FP64)
     hipLaunchKernelGGL(precond_scale_kernel<double>, grid, block, 0, s, m->d_info, m->d_metric, m->ne,
-                       (const double*)x, (double*)z);
+                       (const double*)x, (double*)z, skip);
   else
     hipLaunchKernelGGL(precond_scale_kernel<float>, grid, block, 0, s, m->d_info, m->d_metric, m->ne,
-                       (const float*)x, (float*)z);
+                       (const float*)x, (float*)z, skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "precond_scale launch");
   return STDG_OK;
@@ -159,7 +161,7 @@ int launch_residual(const ApplyArgs& a) {
     int rc = noalloc_scratch_init(dev);
     if (rc != STDG_OK) return rc;
     void* ptr = noalloc_scratch(dev);
-    rc = launch_precond_scale(m, a.prec, x, ptr, a.stream);
+    rc = launch_precond_scale(m, a.prec, x, ptr, a.stream, a.skip);
     if (rc != STDG_OK) return rc;
     x = ptr;
     mode = STDG_OPERATOR;
@@ -179,7 +181,7 @@ int launch_residual(const ApplyArgs& a) {
       if (rc != STDG_OK) return rc;
       mm->scratch_bytes = need;
     }
-    int rc = launch_precond_scale(m, a.prec, x, mm->d_scratch, a.stream);
+    int rc = launch_precond_scale(m, a.prec, x, mm->d_scratch, a.stream, a.skip);
     if (rc != STDG_OK) return rc;
     x = mm->d_scratch;
     mode = STDG_OPERATOR;
@@ -188,10 +190,10 @@ int launch_residual(const ApplyArgs& a) {
   if (a.prec == STDG_FP64)
     return run_groups<double>(m, a.dt, mode, (const double*)x, (const double*)a.load, (double*)a.y, a.stream,
                               diss ? affine_diss_f64 : affine_f64, trilinear_f64, (const QTables<double>*)m->d_qt64,
-                              !a.no_alloc);
+                              !a.no_alloc, a.skip);
   return run_groups<float>(m, a.dt, mode, (const float*)x, (const float*)a.load, (float*)a.y, a.stream,
                            diss ? affine_diss_f32 : affine_f32, trilinear_f32, (const QTables<float>*)m->d_qt32,
-                           !a.no_alloc);
+                           !a.no_alloc, a.skip);
 }
 
 }  // namespace stdg

@@ -118,6 +118,7 @@ struct KParams {
   const double* verts;    // [ne][8][3] (trilinear elements)
   const QTables<T>* qt;   // mass rule of this group's a (trilinear elements)
   const T* diss;          // D_h coefficients per element (dissipative kernels)
+  const int* skip;        // device flag: 0 = return at once (NULL: always run)
   T dt;
   int mode;     // kept for launch bookkeeping; the kernels take the mode as a template argument
   int variant;  // launch variant (launch bookkeeping; the kernels take it as a template argument)
@@ -980,6 +981,7 @@ __device__ __forceinline__ void element_body(const KParams<T>& P, const int e, c
 // found in that XCD's L2.
 template <typename T, int A, int Q, int MODE, bool AFF, bool DISS = false, int VAR = 0>
 __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
+  if (P.skip && *P.skip == 0) return;  // uniform: a finished restart cycle
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   const int tid = threadIdx.x;
@@ -996,7 +998,9 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
 // P^{-1} applied blockwise (3x3 per spatial mode and level), for meshes whose
 // metric is not diagonal: z = P^{-1} x on the unknowns layout.
 template <typename T>
-__global__ void precond_scale_kernel(const ElemInfo* info, const ElemMetric* metric, int64_t ne, const T* x, T* z) {
+__global__ void precond_scale_kernel(const ElemInfo* info, const ElemMetric* metric, int64_t ne, const T* x, T* z,
+                                     const int* skip) {
+  if (skip && *skip == 0) return;
   const int64_t e = blockIdx.x;
   if (e >= ne) return;
   const ElemInfo I = info[e];

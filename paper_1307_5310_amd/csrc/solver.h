@@ -15,17 +15,40 @@ struct DotWork {
   double* partial = nullptr;
   unsigned* counter = nullptr;
 };
-// Fused Arnoldi kernels (krylov.hip); V holds k basis vectors of length n
-// (leading dimension ld) in FP32 (v32) or FP64, w in FP32 (w32) or FP64.
-int arnoldi_dot(const void* V, bool v32, int64_t ld, int k, const void* w, bool w32, int64_t n, const double* s,
-                double* h, double* c, const DotWork& dw, hipStream_t st);
-int arnoldi_update_dot(const void* V, bool v32, int64_t ld, int k, const void* w, bool w32, const double* cin,
-                       double* wout, int64_t n, const double* s, double* h, double* c, const DotWork& dw,
-                       hipStream_t st);
-int arnoldi_update_norm(const void* V, bool v32, int64_t ld, int k, const double* w, const double* cin, void* vout,
-                        int64_t n, double* norm2, double* s_next, const DotWork& dw, hipStream_t st);
-int basis_combine(double* out, const void* V, bool v32, int64_t ld, int k, const double* coef, int64_t n,
-                  hipStream_t st);
+// Device state of one GMRES restart cycle (krylov.hip): the host writes
+// target, restart and max_iters before the cycle; the kernels keep the rest.
+struct CycleCtl {
+  double target;     // the cycle stops once the residual estimate |g_{j+1}| <= target
+  int32_t restart;   // columns at most
+  int32_t max_iters; // inner iterations allowed for the slab (counted in iters)
+  int32_t active;    // 1 while the cycle runs: kernels of later iterations return at once otherwise
+  int32_t k;         // columns done
+  int32_t iters;     // inner iterations of the slab so far
+  int32_t bad;       // a non-finite Hessenberg entry was met
+  double nu, inv_nu;        // norm estimate of the pending vector, and 1 / nu for pass 2
+  double hp[kMaxBasis];     // second-projection coefficients of the pending vector
+  double h[kMaxBasis];      // Hessenberg entries of the first projection, current column
+  double cz[kMaxBasis];     // (V_l . z) / nu, current column
+  double Hraw[kMaxBasis * kMaxBasis];  // Hessenberg matrix as built, row-major [l * kMaxBasis + j]
+  double R[kMaxBasis * kMaxBasis];     // the same after the Givens rotations (upper triangular)
+  double cs[kMaxBasis], sn[kMaxBasis], g[kMaxBasis + 1];
+  double y[kMaxBasis];      // combination coefficients at the cycle end
+};
+// Arnoldi passes (krylov.hip).  V: basis slots (leading dimension ldv) in
+// FP32 (v32) or FP64; z: apply output in FP32 (z32) or FP64; w: pending
+// vector, FP32 when v32 else FP64, with an optional FP32 copy w32 (the input
+// of FP32 applies next to an FP64 basis).
+int arnoldi_pass1(const void* V, bool v32, int64_t ldv, int j, const void* z, bool z32, const void* w, int64_t n,
+                  CycleCtl* ctl, const DotWork& dw, hipStream_t st);
+int arnoldi_pass2(void* V, bool v32, int64_t ldv, int j, const void* z, bool z32, void* w, float* w32, int64_t n,
+                  CycleCtl* ctl, const DotWork& dw, hipStream_t st);
+// V_0 = r / sqrt(*norm2) (and its FP32 copy v0_32 when not NULL); resets the cycle state
+int cycle_start(const double* r, const double* norm2, void* v0, bool v32, float* v0_32, int64_t n, CycleCtl* ctl,
+                hipStream_t st);
+int cycle_least_squares(CycleCtl* ctl, hipStream_t st);
+// out = sum_{l < k} coef_l V_l, with k read from kdev when not NULL
+int basis_combine(double* out, const void* V, bool v32, int64_t ld, int k, const int* kdev, const double* coef,
+                  int64_t n, hipStream_t st);
 int vec_dot(const double* a, const double* b, int64_t n, double* out, const DotWork& dw, hipStream_t st);
 int vec_store(void* out, bool out32, const double* in, int64_t n, hipStream_t st);
 
@@ -55,8 +78,10 @@ size_t slab_solver_bytes(int64_t n_unknowns, int64_t n_trial, int64_t ne, const 
 // Restarted right-preconditioned GMRES for one slab as a resumable state
 // machine: every step enqueues its device work on the solver's stream and
 // records event(); once the event has completed, advance() does the host part
-// (Givens rotations, convergence tests) and enqueues the next step.  The
-// blocking stdg_slab_solve and the serving loop both drive it.
+// (the tests between restart cycles) and enqueues the next step.  A restart
+// cycle (up to `restart` Arnoldi iterations, the least-squares update of the
+// iterate and its true FP64 residual) runs on the device without the host.
+// The blocking stdg_slab_solve and the serving loop both drive it.
 class SlabSolver {
  public:
   int init(Mesh* m, const SlabOpts& o, hipStream_t s);
@@ -78,11 +103,10 @@ class SlabSolver {
   double eta2 = 0.0;  // the slab's term of eta_it^2 at the final iterate (inexact solve only)
 
  private:
-  enum Phase { kIdle, kWaitStart, kWaitIter, kWaitCycle, kWaitEnd };
+  enum Phase { kIdle, kWaitStart, kWaitCycle, kWaitEnd };
   int launch_true_residual();
-  int start_cycle();
-  int launch_iteration();
-  int launch_cycle_end();
+  int launch_cycle();
+  int enqueue_cycle();  // the cycle's kernels, from the start vector to the updated iterate
   int launch_slab_end();
 
   Mesh* m_ = nullptr;
@@ -94,31 +118,33 @@ class SlabSolver {
   void* basis(int j) const { return (char*)V_ + (size_t)j * (size_t)ld_ * (o_.v32 ? 4 : 8); }
   int64_t ld_ = 0;  // basis leading dimension: n rounded up to a multiple of 64
   // device work vectors
-  void* V_ = nullptr;  // restart + 1 unnormalised basis vectors (FP32 or FP64)
-  double *w_ = nullptr, *x_ = nullptr, *r_ = nullptr, *U_ = nullptr, *d_ = nullptr, *pd_ = nullptr;
-  float *v32_ = nullptr, *w32_ = nullptr;
-  // captured Arnoldi iterations, one per basis index j (valid for graph_dt_)
-  int enqueue_iteration(int j);
+  void* V_ = nullptr;   // restart + 1 basis vectors (FP32 or FP64)
+  void* w_ = nullptr;   // the pending vector (FP32 with an FP32 basis, else FP64)
+  void* z_ = nullptr;   // apply output (FP32 with FP32 applies, else FP64)
+  float* w32_ = nullptr;  // FP32 copy of the apply input (FP32 applies, FP64 basis)
+  double *x_ = nullptr, *r_ = nullptr, *U_ = nullptr, *d_ = nullptr, *pd_ = nullptr;
+  CycleCtl* ctl_ = nullptr;
+  // a whole restart cycle captured as one graph (valid for graph_dt_ and the
+  // mesh epoch graph_epoch_), launched from the second cycle on
   void drop_graphs();
-  hipGraphExec_t gexec_[kMaxBasis] = {};
+  hipGraphExec_t gexec_ = nullptr;
   hipStream_t cap_ = nullptr;  // capture stream (the caller's may be the null stream, which cannot capture)
-  bool seen_[kMaxBasis] = {};
+  bool seen_ = false;
   double graph_dt_ = 0.0;
-  uint64_t graph_epoch_ = 0;  // mesh epoch the graphs were captured at
+  uint64_t graph_epoch_ = 0;
   DotWork dw_;
-  double *hv_ = nullptr, *etmp_ = nullptr;  // device scalars (layout kH1.. in solver.cpp)
+  double *hv_ = nullptr, *etmp_ = nullptr;  // device scalars (layout kBeta.. in solver.cpp)
   double* hb_ = nullptr;                    // pinned host copy of the scalars
-  double hs_[kMaxBasis + 1];                // basis scales s_j on the host
+  CycleCtl* hctl_ = nullptr;                // pinned host copy of the cycle parameters
   // slab state
   double dt_ = 0.0;
   const double* load_ = nullptr;
   double* state_ = nullptr;
   double* slabU_ = nullptr;
-  double beta0_ = 0.0, beta_ = 0.0, inner_target_ = 0.0;
+  double beta0_ = 0.0, beta_ = 0.0;
   double eta_term() const;  // eta_it^2 term of the residual in the scalars
-  int cycles_ = 0, j_ = 0;
+  int cycles_ = 0;
   bool converged_ = false;
-  double H_[kMaxBasis * kMaxBasis], cs_[kMaxBasis], sn_[kMaxBasis], g_[kMaxBasis + 1];
 };
 
 }  // namespace stdg
