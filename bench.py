@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--q", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-march", action="store_true", help="skip the 64-slab marches of the solve leg")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="elements in the oracle's timed sample (0 = sized to ~15 s)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -290,7 +291,7 @@ def main():
     solve = None
     if not args.no_solve:
         try:
-            solve = time_solves(stdg, torch, mh, m, cfg)
+            solve = time_solves(stdg, torch, mh, m, cfg, march=not args.no_march)
         except Exception as e:  # solver reported separately; the apply line still prints
             log("slab solve skipped: %s" % e)
 
@@ -620,67 +621,89 @@ def time_large(stdg, torch, ctx, steps, warmup):
     return out
 
 
-def time_solves(stdg, torch, mh, m, cfg):
+def _march(stdg, torch, mh, cfg, info, n_slabs, **opts):
+    """The workload's march of n_slabs slabs from the projected modes; wall
+    time, iterations and the energy drift (Thm 3.1: conserved without a
+    source)."""
+    modes = cfg["init"]
+    state = torch.zeros(info["state_size"], dtype=torch.float64, device="cuda")
+    stdg.stdg_project_modes(mh, modes.mnl, modes.abc, state)
+    e0 = stdg.stdg_energy(mh, state)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, eta2, worst = 0, 0.0, 0.0
+    for n in range(n_slabs):
+        r = stdg.stdg_slab_solve(mh, n * cfg["dt"], cfg["dt"], None, state, **opts)
+        iters += r["iters"]
+        eta2 += r["eta2"]
+        worst = max(worst, r["rel_res"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"s": round(el, 3), "slab_solves_per_s": round(n_slabs / el, 2), "iters_per_slab": round(iters / n_slabs, 2),
+            "max_rel_res": worst, "energy_drift": (r["energy_end"] - e0) / e0, "eta2": eta2, "e0": e0}
+
+
+def time_solves(stdg, torch, mh, m, cfg, march=True):
     """FP32-apply + FP64 refinement vs plain FP64: one slab from the projected
-    mode superposition, to rtol 1e-10."""
+    mode superposition to rtol 1e-10 (whole restart cycles replayed as
+    graphs), and the workload's 64-slab march in both paths."""
     info = stdg.stdg_mesh_info(mh)
     modes = cfg["init"]
     res = {}
-    for name, inner, krylov in (("fp32_refine", stdg.STDG_FP32, stdg.STDG_FP64),
-                                ("fp32_refine_fp32_basis", stdg.STDG_FP32, stdg.STDG_FP32),
-                                ("fp64", stdg.STDG_FP64, stdg.STDG_FP64)):
-        state = torch.zeros(info["state_size"], dtype=torch.float64, device="cuda")
-        stdg.stdg_project_modes(mh, modes.mnl, modes.abc, state)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, state, inner_prec=inner, rtol=1e-10,
-                                 max_iters=3000, max_refine=300, krylov_prec=krylov)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+    paths = (("fp32_refine", stdg.STDG_FP32, stdg.STDG_FP32), ("fp32_refine_fp64_basis", stdg.STDG_FP32, stdg.STDG_FP64),
+             ("fp64", stdg.STDG_FP64, stdg.STDG_FP64))
+    for name, inner, krylov in paths:
+        # the first solve of a path allocates its solver and captures its graph: untimed
+        for rep in range(2):
+            state = torch.zeros(info["state_size"], dtype=torch.float64, device="cuda")
+            stdg.stdg_project_modes(mh, modes.mnl, modes.abc, state)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, state, inner_prec=inner, rtol=1e-10,
+                                     max_iters=3000, max_refine=300, krylov_prec=krylov, use_graph=1)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
         res[name] = {"s_per_solve": round(el, 4), "solves_per_s": round(1.0 / el, 3), "iters": r["iters"],
                      "refinements": r["refinements"], "rel_res": r["rel_res"],
                      "energy_drift": (r["energy_end"] - r["energy_start"]) / max(r["energy_start"], 1e-300)}
         log("slab solve %s: %.3f s, %d iters" % (name, el, r["iters"]))
+    res["speedup_fp32_refine"] = round(res["fp64"]["s_per_solve"] / res["fp32_refine"]["s_per_solve"], 3)
+    res["speedup_fp32_refine_fp64_basis"] = round(
+        res["fp64"]["s_per_solve"] / res["fp32_refine_fp64_basis"]["s_per_solve"], 3)
+    n_slabs = cfg["n_slabs"]
+    if march:
+        # metric 2 of the workload: its 64 slabs solved exactly (rtol 1e-10 per slab) in both paths
+        for name, inner, krylov in (paths[0], paths[2]):
+            mr = _march(stdg, torch, mh, cfg, info, n_slabs, inner_prec=inner, krylov_prec=krylov, rtol=1e-10,
+                        max_iters=3000, max_refine=300, use_graph=1)
+            mr.pop("eta2")
+            mr.pop("e0")
+            res["march_%d_slabs_%s" % (n_slabs, name)] = mr
+            log("%d-slab march %s: %.2f s (%.1f slab solves/s)" % (n_slabs, name, mr["s"], mr["slab_solves_per_s"]))
+        res["march_speedup_fp32_refine"] = round(res["march_%d_slabs_fp64" % n_slabs]["s"] /
+                                                 res["march_%d_slabs_fp32_refine" % n_slabs]["s"], 3)
     # inexact solve (Section 5.3): stop at the iteration-error bound, with a
     # budget of eta_it <= 1e-3 sqrt(2 E(0)) over the workload's 64 slabs
     state = torch.zeros(info["state_size"], dtype=torch.float64, device="cuda")
     stdg.stdg_project_modes(mh, modes.mnl, modes.abc, state)
     e0 = stdg.stdg_energy(mh, state)
-    n_slabs = cfg["n_slabs"]
     eta_tol = 1e-3 * np.sqrt(2.0 * e0) / np.sqrt(n_slabs)
+    opts = dict(inner_prec=stdg.STDG_FP32, rtol=1e-10, max_iters=3000, max_refine=300, krylov_prec=stdg.STDG_FP32,
+                eta_tol=eta_tol, eta_t_final=n_slabs * cfg["dt"], use_graph=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, state, inner_prec=stdg.STDG_FP32, rtol=1e-10,
-                             max_iters=3000, max_refine=300, krylov_prec=stdg.STDG_FP32, eta_tol=eta_tol,
-                             eta_t_final=n_slabs * cfg["dt"])
+    r = stdg.stdg_slab_solve(mh, 0.0, cfg["dt"], None, state, **opts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    res["inexact_fp32_refine_fp32_basis"] = {"s_per_solve": round(el, 4), "solves_per_s": round(1.0 / el, 3),
-                                             "iters": r["iters"], "eta_it_term": float(np.sqrt(r["eta2"])),
-                                             "eta_tol": float(eta_tol), "rel_res": r["rel_res"]}
+    res["inexact_fp32_refine"] = {"s_per_solve": round(el, 4), "solves_per_s": round(1.0 / el, 3),
+                                  "iters": r["iters"], "eta_it_term": float(np.sqrt(r["eta2"])),
+                                  "eta_tol": float(eta_tol), "rel_res": r["rel_res"]}
     log("slab solve inexact: %.3f s, %d iters" % (el, r["iters"]))
-    # the whole 64-slab march of the workload with the inexact solve
-    state = torch.zeros(info["state_size"], dtype=torch.float64, device="cuda")
-    stdg.stdg_project_modes(mh, modes.mnl, modes.abc, state)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    eta2, iters = 0.0, 0
-    for n in range(n_slabs):
-        r = stdg.stdg_slab_solve(mh, n * cfg["dt"], cfg["dt"], None, state, inner_prec=stdg.STDG_FP32, rtol=1e-10,
-                                 max_iters=3000, max_refine=300, krylov_prec=stdg.STDG_FP32, eta_tol=eta_tol,
-                                 eta_t_final=n_slabs * cfg["dt"])
-        eta2 += r["eta2"]
-        iters += r["iters"]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    res["march_inexact_64_slabs"] = {"s": round(el, 3), "slab_solves_per_s": round(n_slabs / el, 2),
-                                     "iters_per_slab": round(iters / n_slabs, 2),
-                                     "eta_it_rel": float(np.sqrt(eta2) / np.sqrt(2.0 * e0)),
-                                     "energy_drift": (r["energy_end"] - e0) / e0}
-    log("64-slab inexact march: %.2f s (%.1f slab solves/s)" % (el, n_slabs / el))
-    res["speedup_fp32_refine"] = round(res["fp64"]["s_per_solve"] / res["fp32_refine"]["s_per_solve"], 3)
-    res["speedup_fp32_refine_fp32_basis"] = round(
-        res["fp64"]["s_per_solve"] / res["fp32_refine_fp32_basis"]["s_per_solve"], 3)
+    if march:
+        mr = _march(stdg, torch, mh, cfg, info, n_slabs, **opts)
+        mr["eta_it_rel"] = float(np.sqrt(mr.pop("eta2")) / np.sqrt(2.0 * mr.pop("e0")))
+        res["march_%d_slabs_inexact" % n_slabs] = mr
+        log("%d-slab inexact march: %.2f s (%.1f slab solves/s)" % (n_slabs, mr["s"], mr["slab_solves_per_s"]))
     return res
 
 

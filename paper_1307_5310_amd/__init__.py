@@ -275,8 +275,13 @@ def stdg_project_modes(mesh, mnl, abc, state, stream=None):
 
 
 def stdg_slab_solve(mesh, t0, dt, load, state, inner_prec=STDG_FP64, restart=10, max_iters=500,
-                    max_refine=100, rtol=1e-12, inner_rtol=1e-4, slab_U=None, stream=None, krylov_prec=STDG_FP64,
+                    max_refine=100, rtol=1e-12, inner_rtol=1e-4, slab_U=None, stream=None, krylov_prec=None,
                     eta_tol=0.0, eta_t_final=0.0, use_graph=False):
+    """One slab (C ABI stdg_slab_solve).  krylov_prec None: the basis in the
+    precision of the inner applies (FP32 with FP32 applies, whose refinement
+    against the FP64 residual corrects it; FP64 otherwise)."""
+    if krylov_prec is None:
+        krylov_prec = STDG_FP32 if int(inner_prec) == STDG_FP32 else STDG_FP64
     o = SolveOpts(int(inner_prec), int(restart), int(max_iters), int(max_refine), float(rtol),
                   float(inner_rtol), int(krylov_prec), float(eta_tol), float(eta_t_final), int(bool(use_graph)))
     info = SolveInfo()
@@ -311,8 +316,11 @@ def stdg_energy(mesh, state, stream=None):
 
 
 def stdg_serve_start(ctx, hbm_budget=0, max_active=0, inner_prec=STDG_FP32, restart=10, max_iters=500,
-                     max_refine=100, rtol=1e-10, inner_rtol=1e-4, krylov_prec=STDG_FP64, eta_rel=0.0,
+                     max_refine=100, rtol=1e-10, inner_rtol=1e-4, krylov_prec=None, eta_rel=0.0,
                      use_graph=False):
+    """Start a server (C ABI stdg_serve_start); krylov_prec None as in stdg_slab_solve."""
+    if krylov_prec is None:
+        krylov_prec = STDG_FP32 if int(inner_prec) == STDG_FP32 else STDG_FP64
     o = ServeOpts(int(hbm_budget), int(max_active), int(inner_prec), int(restart), int(max_iters),
                   int(max_refine), float(rtol), float(inner_rtol), int(krylov_prec), float(eta_rel),
                   int(bool(use_graph)))

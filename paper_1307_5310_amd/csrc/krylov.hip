@@ -260,7 +260,7 @@ pass1_kernel(const TV* __restrict__ V, int64_t ldv, int j, const TZ* __restrict_
     return;
   }
   const double inv = 1.0 / ctl->nu;
-  double c[kMaxBasis];
+  __shared__ double c[kMaxBasis];  // (thread 0 only; LDS keeps it out of scratch memory)
   double t = tot[j];
   for (int l = 0; l < j; ++l) {
     c[l] = tot[l];
@@ -290,44 +290,50 @@ struct Pass2Body {
   double* acc;
   template <int W>
   __device__ __forceinline__ void run(int64_t i) {
-    double vv[KM][W];
+    // first sweep over the basis: the pending vector's second projection
+    // and the first projection of z, one read of each V_l
+    double xj[W], xw[W];
+    if (j > 0) ld<W>(w + i, xj);
+    ld<W>(z + i, xw);
 #pragma unroll
-    for (int l = 0; l < KM; ++l)
-      if (l < j) ld<W>(V + l * ldv + i, vv[l]);
-    double vj[W];
-    if (j > 0) {
-      double wv[W];
-      ld<W>(w + i, wv);
+    for (int e = 0; e < W; ++e) xw[e] *= inv;
 #pragma unroll
-      for (int e = 0; e < W; ++e) {
-        double x = wv[e];
+    for (int l = 0; l < KM; ++l) {
+      if (l < j) {
+        double vv[W];
+        ld<W>(V + l * ldv + i, vv);
 #pragma unroll
-        for (int l = 0; l < KM; ++l)
-          if (l < j) x -= hp[l] * vv[l][e];
-        vj[e] = round_to<TV>(x * inv);
+        for (int e = 0; e < W; ++e) {
+          xj[e] -= hp[l] * vv[e];
+          xw[e] -= cz[l] * vv[e];
+        }
       }
+    }
+    double vj[W], wn[W];
+    if (j > 0) {
+#pragma unroll
+      for (int e = 0; e < W; ++e) vj[e] = round_to<TV>(xj[e] * inv);
       st<W>(V + j * ldv + i, vj);
     } else {
       ld<W>(V + i, vj);
     }
-    double zv[W], wn[W];
-    ld<W>(z + i, zv);
 #pragma unroll
-    for (int e = 0; e < W; ++e) {
-      double x = zv[e] * inv;
-#pragma unroll
-      for (int l = 0; l < KM; ++l)
-        if (l < j) x -= cz[l] * vv[l][e];
-      x -= cz[j] * vj[e];
-      wn[e] = round_to<TW>(x);
-    }
+    for (int e = 0; e < W; ++e) wn[e] = round_to<TW>(xw[e] - cz[j] * vj[e]);
     st<W>(w + i, wn);
     if (w32) st<W>(w32 + i, wn);
+    // second sweep: the dots with w' (the V_l entries are read again, from
+    // cache: keeping them in registers across both sweeps cost occupancy)
+#pragma unroll
+    for (int l = 0; l < KM; ++l) {
+      if (l < j) {
+        double vv[W];
+        ld<W>(V + l * ldv + i, vv);
+#pragma unroll
+        for (int e = 0; e < W; ++e) acc[l] += vv[e] * wn[e];
+      }
+    }
 #pragma unroll
     for (int e = 0; e < W; ++e) {
-#pragma unroll
-      for (int l = 0; l < KM; ++l)
-        if (l < j) acc[l] += vv[l][e] * wn[e];
       acc[j] += vj[e] * wn[e];
       acc[j + 1] += wn[e] * wn[e];
     }
@@ -355,7 +361,8 @@ pass2_kernel(TV* __restrict__ V, int64_t ldv, int j, const TZ* __restrict__ z, T
   // column j of H: both projections, and the subdiagonal from the norm of w'
   // after its second projection (Pythagoras: V is orthonormal)
   const double s2 = tot[j + 1];
-  double col[kMaxBasis + 1], e2 = 0.0;
+  __shared__ double col[kMaxBasis + 1];  // (thread 0 only; LDS keeps it out of scratch memory)
+  double e2 = 0.0;
   for (int l = 0; l <= j; ++l) {
     col[l] = ctl->h[l] + tot[l];
     e2 += tot[l] * tot[l];
@@ -419,7 +426,7 @@ cycle_start_kernel(const double* r, const double* __restrict__ norm2, TV* v0, fl
 __global__ void least_squares_kernel(CycleCtl* __restrict__ ctl) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int k = ctl->k;
-  double y[kMaxBasis];
+  __shared__ double y[kMaxBasis];
   for (int i = k - 1; i >= 0; --i) {
     double t = ctl->g[i];
     for (int l = i + 1; l < k; ++l) t -= ctl->R[i * kMaxBasis + l] * y[l];
@@ -501,14 +508,42 @@ int check_launch(const char* what) {
 }
 
 // smallest compiled basis bound that holds k vectors
-int km_for(int k) { return k <= 4 ? 4 : (k <= 8 ? 8 : (k <= 12 ? 12 : (k <= 16 ? 16 : 32))); }
+int km_for(int k) {
+  if (k <= 12) return k <= 2 ? 2 : (k <= 4 ? 4 : (k <= 6 ? 6 : (k <= 8 ? 8 : (k <= 10 ? 10 : 12))));
+  return k <= 16 ? 16 : 32;
+}
+
+// blocks for a grid-stride reduction kernel: as many as the device holds at
+// once (no partial second wave of blocks), at most kMaxDotBlocks partials
+template <typename K>
+int resident_blocks(K kernel, int64_t n) {
+  static int per_cu = 0, cus = 0;  // per instantiation; one device type per process
+  if (per_cu == 0) {
+    int nb = 0, dev = 0, c = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kThreads, 0) != hipSuccess || nb < 1) nb = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+      c = 256;
+    cus = c;
+    per_cu = nb;
+  }
+  int64_t b = (int64_t)per_cu * cus;
+  const int64_t need = (n + 4 * kThreads - 1) / (4 * kThreads);
+  if (b > need) b = need;
+  if (b > kMaxDotBlocks) b = kMaxDotBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
 
 }  // namespace
 
 #define STDG_KM_SWITCH(KMV, CALL) \
   switch (KMV) {                       \
+    case 2: CALL(2); break;            \
     case 4: CALL(4); break;            \
+    case 6: CALL(6); break;            \
     case 8: CALL(8); break;            \
+    case 10: CALL(10); break;          \
     case 12: CALL(12); break;          \
     case 16: CALL(16); break;          \
     default: CALL(32); break;          \
@@ -525,10 +560,10 @@ int arnoldi_pass1(const void* V, bool v32, int64_t ldv, int j, const void* z, bo
   if (j < 0 || j + 1 > kMaxBasis) return fail(STDG_E_ARG, "arnoldi_pass1: basis index out of range");
   if (ldv % 64) return fail(STDG_E_ARG, "arnoldi_pass1: leading dimension must be a multiple of 64");
   if (v32 && !z32) return fail(STDG_E_ARG, "arnoldi_pass1: an FP32 basis needs FP32 applies");
-  const dim3 g(dot_blocks(n)), b(kThreads);
+  const dim3 b(kThreads);
 #define STDG_L(TV, TZ, TW, KM)                                                                                 \
-  hipLaunchKernelGGL((pass1_kernel<TV, TZ, TW, KM>), g, b, 0, st, (const TV*)V, ldv, j, (const TZ*)z,        \
-                     (const TW*)w, n, ctl, dw.partial, dw.counter)
+  hipLaunchKernelGGL((pass1_kernel<TV, TZ, TW, KM>), dim3(resident_blocks(pass1_kernel<TV, TZ, TW, KM>, n)), b, \
+                     0, st, (const TV*)V, ldv, j, (const TZ*)z, (const TW*)w, n, ctl, dw.partial, dw.counter)
 #define STDG_K(KM) STDG_PRECS(STDG_L, KM)
   STDG_KM_SWITCH(km_for(j + 1), STDG_K)
 #undef STDG_K
@@ -541,10 +576,10 @@ int arnoldi_pass2(void* V, bool v32, int64_t ldv, int j, const void* z, bool z32
   if (j < 0 || j + 2 > kMaxBasis) return fail(STDG_E_ARG, "arnoldi_pass2: basis index out of range");
   if (ldv % 64) return fail(STDG_E_ARG, "arnoldi_pass2: leading dimension must be a multiple of 64");
   if (v32 && !z32) return fail(STDG_E_ARG, "arnoldi_pass2: an FP32 basis needs FP32 applies");
-  const dim3 g(dot_blocks(n)), b(kThreads);
+  const dim3 b(kThreads);
 #define STDG_L(TV, TZ, TW, KM)                                                                                     \
-  hipLaunchKernelGGL((pass2_kernel<TV, TZ, TW, KM>), g, b, 0, st, (TV*)V, ldv, j, (const TZ*)z, (TW*)w, w32, n, \
-                     ctl, dw.partial, dw.counter)
+  hipLaunchKernelGGL((pass2_kernel<TV, TZ, TW, KM>), dim3(resident_blocks(pass2_kernel<TV, TZ, TW, KM>, n)), b,  \
+                     0, st, (TV*)V, ldv, j, (const TZ*)z, (TW*)w, w32, n, ctl, dw.partial, dw.counter)
 #define STDG_K(KM) STDG_PRECS(STDG_L, KM)
   STDG_KM_SWITCH(km_for(j + 2), STDG_K)
 #undef STDG_K

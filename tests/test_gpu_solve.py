@@ -390,6 +390,37 @@ def test_resume_from_saved_state_is_bitwise(lib):
     assert np.array_equal(st2.cpu().numpy(), straight)
 
 
+@pytest.mark.parametrize("inner,krylov", [(0, 0), (1, 1), (1, 0)])
+def test_graph_replay_several_groups_is_bitwise(lib, inner, krylov):
+    """Restart cycles replayed as graphs on a mesh with several kernel groups
+    (the side-stream fork and join of the group launches are captured; a
+    trilinear mesh with mixed degrees, so the P^{-1} pre-pass too): bitwise the
+    direct launches over a march with a dt change."""
+    from tests.gpu_util import random_mixed_mesh
+    m = random_mixed_mesh((3, 3, 2), 4, 3, 77)
+    m = synth.Mesh(synth.perturb_interior(m.vertices, (3, 3, 2), 0.1, 78), m.hexes, m.p, m.q, m.eps, m.mu,
+                   shape=m.shape)
+    opts = dict(inner_prec=inner, krylov_prec=krylov, rtol=1e-12, max_iters=3000, max_refine=300)
+    s0 = synth.random_vector(m.state_size(), 79)
+    out = []
+    for graph in (False, True):
+        mh = lib.upload(m)
+        try:
+            assert lib.stdg.stdg_mesh_info(mh)["n_groups"] > 3
+            st = lib.dev(s0, lib.torch.float64)
+            iters = 0
+            for n, dt in enumerate((0.02, 0.02, 0.03)):
+                note("graph=%d several groups slab %d" % (graph, n))
+                r = lib.stdg.stdg_slab_solve(mh, 0.0, dt, None, st, use_graph=graph, **opts)
+                assert r["status"] == 0
+                iters += r["iters"]
+            out.append((st.cpu().numpy(), iters))
+        finally:
+            lib.stdg.stdg_mesh_free(mh)
+    assert out[0][1] == out[1][1] and out[0][1] > 20
+    assert np.array_equal(out[0][0], out[1][0])
+
+
 @pytest.mark.parametrize("inner,krylov", [(0, 0), (1, 1)])
 def test_graph_replay_is_bitwise(lib, inner, krylov):
     """Arnoldi iterations replayed as captured HIP graphs give bitwise the
