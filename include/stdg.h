@@ -163,7 +163,9 @@ int stdg_mesh_set_order(stdg_mesh* mesh, int32_t order);
  * order (Morton, columns of 4, 8, 16) and keep the fastest (returned in
  * *order_out); then, in that order, time each affine kernel group in each
  * launch variant of stdg_mesh_set_launch and keep the fastest per group
- * (stdg_mesh_group reports it).  Synchronises `stream`; not to be called
+ * (stdg_mesh_group reports it; trilinear groups are timed in the operator
+ * mode, which their preconditioned applies run after the P^{-1} pre-pass).
+ * Synchronises `stream`; not to be called
  * while other work on the mesh is in flight.  Callers that cache the choices
  * (the Python binding keys a JSON file on the mesh's shape) apply them later
  * with stdg_mesh_set_order and stdg_mesh_set_launch. */
@@ -173,12 +175,17 @@ int stdg_mesh_autotune(stdg_mesh* mesh, int prec, double dt, int32_t reps, int32
  * residual kernel instantiation, one workgroup per element.
  * stdg_mesh_group describes group 0 <= group < n_groups; stdg_mesh_set_launch
  * picks the launch variant of its operator-mode kernels (group = -1: every
- * group; affine groups without D_h, the others keep variant 0):
+ * group).  Affine groups (without D_h; with D_h they keep variant 0):
  *   0  the element's outputs staged through LDS and written as contiguous
  *      8-byte stores (whole cache lines), neighbour faces loaded 3 at a time;
  *   1  outputs written per spatial position, neighbour faces 3 at a time;
  *   2  outputs staged as in 0, neighbour faces loaded one at a time (fewer
  *      registers, more resident waves).
+ * Trilinear groups (variant 2 is taken as 0):
+ *   0  one workgroup per element;
+ *   1  one workgroup per element and test level (q times the workgroups,
+ *      each with one level's quadrature mass: for small groups of high
+ *      degree).
  * Results are bitwise the same in every variant.  STDG_E_ARG for an unknown
  * group or variant.  Not to be called while work on the mesh is in flight. */
 typedef struct {
@@ -315,9 +322,10 @@ int stdg_slab_solve(const stdg_mesh* mesh, double t0, double dt, const double* l
 
 /* Dual norms of a residual-layout FP64 vector r (e.g. from STDG_RESIDUAL) in
  * W_h' with the L2(I_n; L2(Omega)) norm (Section 5.3: the Riesz representor is
- * an L2 projection): norms_out[0] = ||r_E||^2, norms_out[1] = ||r_H||^2.  Exact
- * on affine elements; trilinear elements use the mass with the metric at the
- * element centre.  Synchronises `stream`. */
+ * an L2 projection): norms_out[0] = ||r_E||^2, norms_out[1] = ||r_H||^2.
+ * Exact on every element: affine elements invert their constant metric,
+ * trilinear ones solve with their quadrature mass (the residual's (p+2)-point
+ * rule) by preconditioned conjugate gradients to 1e-14.  Synchronises `stream`. */
 int stdg_residual_dual_norm(const stdg_mesh* mesh, double dt, const double* r_dev, double* norms_out,
                             void* stream);
 

@@ -188,8 +188,8 @@ int stdg_mesh_set_launch(stdg_mesh* mesh, int32_t group, int32_t variant) {
   for (int32_t k = 0; k < (int32_t)m->groups.size(); ++k) {
     if (group >= 0 && k != group) continue;
     Group& g = m->groups[k];
-    // the variants exist for affine groups; trilinear groups keep variant 0
-    g.variant = g.affine ? variant : 0;
+    // affine groups: variants 0..2; trilinear groups: 0 or 1 (2 is taken as 0)
+    g.variant = (g.affine || variant < 2) ? variant : 0;
   }
   ++m->epoch;  // captured launches carry the old variant
   return STDG_OK;
@@ -258,10 +258,11 @@ int stdg_mesh_autotune(stdg_mesh* mesh, int prec, double dt, int32_t reps, int32
   // other groups in their current variants
   for (size_t gi = 0; gi < m->groups.size() && rc == STDG_OK; ++gi) {
     Group& g = m->groups[gi];
-    if (!g.affine || g.count == 0) continue;
+    if (g.count == 0) continue;
     int vbest = g.variant;
     float vms = 0.0f;
-    for (int v = 0; v < 3 && rc == STDG_OK; ++v) {
+    const int nvar = g.affine ? 3 : 2;
+    for (int v = 0; v < nvar && rc == STDG_OK; ++v) {
       g.variant = v;
       float ms = 0.0f;
       if ((rc = time_applies(&ms)) != STDG_OK) break;

@@ -183,6 +183,9 @@ struct ApplyArgs {
   const int* skip = nullptr;
 };
 int launch_residual(const ApplyArgs& a);
+// per-element W_h' dual norms (both fields) of a residual-layout FP64 vector on
+// the trilinear elements, into partial[2 e], partial[2 e + 1] (dualnorm.hip)
+int launch_dual_norm_trilinear(const Mesh* m, const double* R, double* partial, hipStream_t s);
 // Static device scratch of the allocation-free apply: look up this device's
 // address of the array (once per device; the device must be current).
 int noalloc_scratch_init(int device);

@@ -356,6 +356,7 @@ __global__ void dual_norm_kernel(const ElemInfo* info, const ElemMetric* metric,
   const int64_t e = blockIdx.x;
   if (e >= ne) return;
   const ElemInfo I = info[e];
+  if (!(I.flags & kAffine)) return;  // trilinear elements: the exact mass solve of dualnorm.hip
   const int per = I.q * I.a * I.a * I.a;
   const double* mm = metric[e].m;
   const double kap[2] = {metric[e].eps, metric[e].mu};
@@ -438,6 +439,10 @@ int energy_async(const Mesh* m, const double* state, double* d_partial, double* 
 int dual_norms_async(const Mesh* m, double dt, const double* R, double* d_partial, double* d_out, hipStream_t s) {
   hipLaunchKernelGGL(dual_norm_kernel, dim3((unsigned)m->ne), dim3(256), 0, s, m->d_info, m->d_metric, m->ne, R,
                      d_partial);
+  if (m->n_nonaffine > 0) {
+    int rc = launch_dual_norm_trilinear(m, R, d_partial, s);
+    if (rc != STDG_OK) return rc;
+  }
   hipLaunchKernelGGL(sum2_kernel, dim3(1), dim3(512), 0, s, d_partial, m->ne, 1.0 / dt, d_out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "dual norm kernels");

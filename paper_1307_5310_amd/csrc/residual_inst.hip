@@ -47,14 +47,21 @@ static int launch_one(const KParams<STDG_REAL>& P, dim3 grid, dim3 block, hipStr
 }
 
 // The launch variants (residual_kernel.h, element_body) exist for affine
-// groups without D_h in the operator modes, the ones a slab solve repeats;
-// every other kernel runs variant 0.
+// groups without D_h in the operator modes and for trilinear groups in the
+// operator mode (the ones a slab solve repeats: trilinear elements take
+// P^{-1} in a pre-pass); every other kernel runs variant 0.
 template <int QQ, int MODE>
 static int launch_var(const KParams<STDG_REAL>& P, dim3 grid, dim3 block, hipStream_t stream) {
 #if STDG_AFF && !STDG_DISS
   if (MODE != 1) {
     if (P.variant == 1) return launch_one<QQ, MODE, 1>(P, grid, block, stream);
     if (P.variant == 2) return launch_one<QQ, MODE, 2>(P, grid, block, stream);
+  }
+#elif !STDG_AFF
+  // trilinear groups, variant 1: one workgroup per element and test level
+  if (MODE == 0 && P.variant == 1 && QQ > 1) {
+    if (grid.x > 0xffffffffu / QQ) return fail(STDG_E_ARG, "residual kernel: too many elements for the level split");
+    return launch_one<QQ, MODE, 3>(P, dim3(grid.x * QQ), block, stream);
   }
 #endif
   return launch_one<QQ, MODE, 0>(P, grid, block, stream);

@@ -386,10 +386,12 @@ __device__ __forceinline__ void load_own(const KParams<T>& P, int e, int tid, T 
 //   0  outputs staged through LDS and stored as contiguous 8-byte lanes,
 //      neighbour faces loaded 3 at a time;
 //   1  outputs stored per position (no LDS stage), faces 3 at a time;
-//   2  outputs staged, neighbour faces loaded one at a time (fewer registers).
+//   2  outputs staged, neighbour faces loaded one at a time (fewer registers);
+//   3  (trilinear elements) one workgroup per element and test level: only
+//      level only_level's outputs (and its quadrature mass) are computed.
 template <typename T, int A, int Q, int MODE, bool AFF, bool DISS, int VAR>
 __device__ __forceinline__ void element_body(const KParams<T>& P, const int e, const T (&xr)[6][Q + 1],
-                                             T* __restrict__ sm, const int tid) {
+                                             T* __restrict__ sm, const int tid, const int only_level) {
   using C = KCfg<A>;
   constexpr int A2 = C::A2, A3 = C::A3, NF = C::NF, ND = C::ND, LVL = C::lvl(DISS);
   constexpr int LC = C::template LC<T, Q, AFF, DISS>();
@@ -760,6 +762,7 @@ __device__ __forceinline__ void element_body(const KParams<T>& P, const int e, c
 
 #pragma unroll
   for (int i0 = 0; i0 < Q; i0 += LC) {
+    if (VAR == 3 && i0 != only_level) continue;  // uniform: this workgroup's test level only (LC = 1)
     // trilinear elements: the mass terms of these levels, by quadrature
     T mres[AFF ? 1 : LC][6];
     if constexpr (!AFF) {
@@ -951,7 +954,7 @@ __device__ __forceinline__ void element_body(const KParams<T>& P, const int e, c
         }
       }
     }
-    if (i0 + LC < Q) __syncthreads();
+    if (VAR != 3 && i0 + LC < Q) __syncthreads();
   }
   if constexpr (kStageOut) {
     // The element's outputs (contiguous: all levels in one pass) go through
@@ -976,7 +979,11 @@ __device__ __forceinline__ void element_body(const KParams<T>& P, const int e, c
   }
 }
 
-// One workgroup per element.  Consecutive work-list entries run on one XCD
+template <typename T, int A, int Q, bool AFF, bool DISS>
+constexpr bool C_LC1() { return KCfg<A>::template LC<T, Q, AFF, DISS>() == 1; }
+
+// One workgroup per element (per element and test level in variant 3).
+// Consecutive work-list entries run on one XCD
 // (blocks are dispatched to the 8 XCDs round-robin), so neighbour blocks are
 // found in that XCD's L2.
 template <typename T, int A, int Q, int MODE, bool AFF, bool DISS = false, int VAR = 0>
@@ -989,10 +996,13 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   const uint32_t xcd = b & 7u, idx = b >> 3;
   const uint32_t qq = nblk >> 3, rr = nblk & 7u;
   const uint32_t logical = xcd * qq + (xcd < rr ? xcd : rr) + idx;
-  const int e = P.list[logical];
+  static_assert(VAR != 3 || (!AFF && C_LC1<T, A, Q, AFF, DISS>()), "level split: trilinear elements, one level per pass");
+  // variant 3: blocks (element, level), the levels of an element consecutive (same XCD)
+  const int e = P.list[VAR == 3 ? logical / Q : logical];
+  const int lev = VAR == 3 ? (int)(logical % Q) : -1;
   T xr[6][Q + 1];
   load_own<T, A, Q, MODE>(P, e, tid, xr);
-  element_body<T, A, Q, MODE, AFF, DISS, VAR>(P, e, xr, sm, tid);
+  element_body<T, A, Q, MODE, AFF, DISS, VAR>(P, e, xr, sm, tid, lev);
 }
 
 // P^{-1} applied blockwise (3x3 per spatial mode and level), for meshes whose

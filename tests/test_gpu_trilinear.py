@@ -28,7 +28,7 @@ def _cast(prec):
     return (lambda v: v) if prec == 0 else (lambda v: v.astype(np.float32).astype(np.float64))
 
 
-def _check(lib, mesh, dt, seed, name, precs=(0, 1)):
+def _check(lib, mesh, dt, seed, name, precs=(0, 1), variants=(0,)):
     stdg = lib.stdg
     d = oracle_disc(mesh)
     mh = lib.upload(mesh)
@@ -40,21 +40,23 @@ def _check(lib, mesh, dt, seed, name, precs=(0, 1)):
     U = rng.standard_normal(d.trial_off[-1])
     L = rng.standard_normal(d.unk_off[-1])
     try:
+      for variant in variants:
+        stdg.stdg_mesh_set_launch(mh, -1, variant)
         for prec in precs:
             c = _cast(prec)
             xs, Us, Ls = c(x), c(U), c(L)
-            note("%s prec=%d operator" % (name, prec))
+            note("%s variant=%d prec=%d operator" % (name, variant, prec))
             got = lib.apply(mh, dt, prec, stdg.STDG_OPERATOR, xs)
             err = rel_err(got, d.operator(xs, dt))
-            assert err < TOL[prec], (name, prec, "operator", err)
-            note("%s prec=%d residual" % (name, prec))
+            assert err < TOL[prec], (name, variant, prec, "operator", err)
+            note("%s variant=%d prec=%d residual" % (name, variant, prec))
             got = lib.apply(mh, dt, prec, stdg.STDG_RESIDUAL, Us, Ls)
             err = rel_err(got, d.residual(Us, dt, Ls))
-            assert err < TOL[prec], (name, prec, "residual", err)
-            note("%s prec=%d precond" % (name, prec))
+            assert err < TOL[prec], (name, variant, prec, "residual", err)
+            note("%s variant=%d prec=%d precond" % (name, variant, prec))
             got = lib.apply(mh, dt, prec, stdg.STDG_OPERATOR_PRECOND, xs)
             err = rel_err(got, d.operator(d.precond_centre_solve(xs), dt))
-            assert err < TOL[prec], (name, prec, "precond", err)
+            assert err < TOL[prec], (name, variant, prec, "precond", err)
     finally:
         stdg.stdg_mesh_free(mh)
 
@@ -68,7 +70,7 @@ def test_trilinear_uniform_degrees(lib, p, q):
     rng = np.random.default_rng(p * 7 + q)
     mesh = synth.Mesh(v, h, np.full(ne, p, np.int32), np.full(ne, q, np.int32),
                       rng.uniform(1, 4, ne), rng.uniform(1, 2, ne))
-    _check(lib, mesh, 0.043, 200 + p, "trilinear p%d q%d" % (p, q))
+    _check(lib, mesh, 0.043, 200 + p, "trilinear p%d q%d" % (p, q), variants=(0, 1))
 
 
 def test_trilinear_and_affine_groups_in_one_mesh(lib):
@@ -83,13 +85,13 @@ def test_trilinear_and_affine_groups_in_one_mesh(lib):
     rng = np.random.default_rng(8)
     mesh = synth.Mesh(v, h, rng.integers(1, 6, ne).astype(np.int32), rng.integers(1, 5, ne).astype(np.int32),
                       rng.uniform(1, 4, ne), rng.uniform(1, 2, ne))
-    _check(lib, mesh, 0.05, 9, "trilinear+affine")
+    _check(lib, mesh, 0.05, 9, "trilinear+affine", variants=(0, 1, 2))
 
 
 def test_graded_hp_mesh_4cubed(lib):
     # the graded workload's recipe at 4^3: rings 1 and 3, p = 5, 3 and q = 3, 1
     cfg = synth.graded_nonaffine(n=4)
-    _check(lib, cfg["mesh"], 0.02, 10, "graded 4^3")
+    _check(lib, cfg["mesh"], 0.02, 10, "graded 4^3", variants=(0, 1))
 
 
 def test_trilinear_load_and_energy_graded_4cubed(lib):
