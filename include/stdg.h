@@ -181,7 +181,8 @@ int stdg_mesh_autotune(stdg_mesh* mesh, int prec, double dt, int32_t reps, int32
  *   1  outputs written per spatial position, neighbour faces 3 at a time;
  *   2  outputs staged as in 0, neighbour faces loaded one at a time (fewer
  *      registers, more resident waves).
- * Trilinear groups (variant 2 is taken as 0):
+ * Trilinear groups (variant 2, and variant 1 for q = 1 or q > 4, are taken
+ * as 0):
  *   0  one workgroup per element;
  *   1  one workgroup per element and test level (q times the workgroups,
  *      each with one level's quadrature mass: for small groups of high
@@ -273,7 +274,7 @@ int stdg_project_modes(const stdg_mesh* mesh, int32_t n_modes, const int32_t* mn
 typedef struct {
   int32_t inner_prec;  /* STDG_FP64: plain FP64 GMRES; STDG_FP32: FP32 operator inside
                           FP64 iterative refinement                              */
-  int32_t restart;     /* GMRES restart length (default 10)                      */
+  int32_t restart;     /* GMRES restart length (default 10, at most 15)          */
   int32_t max_iters;   /* total inner iterations allowed (default 500)           */
   int32_t max_refine;  /* FP64 residual re-evaluations allowed with FP32 inner    
                           applies (one per restart cycle; default 100)           */

@@ -188,8 +188,9 @@ int stdg_mesh_set_launch(stdg_mesh* mesh, int32_t group, int32_t variant) {
   for (int32_t k = 0; k < (int32_t)m->groups.size(); ++k) {
     if (group >= 0 && k != group) continue;
     Group& g = m->groups[k];
-    // affine groups: variants 0..2; trilinear groups: 0 or 1 (2 is taken as 0)
-    g.variant = (g.affine || variant < 2) ? variant : 0;
+    // affine groups: variants 0..2; trilinear groups: 0, or 1 when 1 < q <= 4
+    // (any other request is taken as 0)
+    g.variant = g.affine ? variant : (variant == 1 && g.q > 1 && g.q <= kMaxLevelSplitQ ? 1 : 0);
   }
   ++m->epoch;  // captured launches carry the old variant
   return STDG_OK;
@@ -261,7 +262,7 @@ int stdg_mesh_autotune(stdg_mesh* mesh, int prec, double dt, int32_t reps, int32
     if (g.count == 0) continue;
     int vbest = g.variant;
     float vms = 0.0f;
-    const int nvar = g.affine ? 3 : 2;
+    const int nvar = g.affine ? 3 : (g.q > 1 && g.q <= kMaxLevelSplitQ ? 2 : 1);
     for (int v = 0; v < nvar && rc == STDG_OK; ++v) {
       g.variant = v;
       float ms = 0.0f;

@@ -88,6 +88,10 @@ void fill_qtables_f32(int a, QTables<float>* t);
 // n-point Gauss-Legendre rule on [0, 1] (n <= 16), Newton iteration on P_n.
 void gauss_rule01(int n, double* x, double* w);
 
+// Largest q of the trilinear level-split launch variant (one workgroup per
+// element and test level).
+constexpr int kMaxLevelSplitQ = 4;
+
 // Kernel work group of elements with the same (a, q, affine).
 struct Group {
   int a, q, affine;

@@ -155,18 +155,26 @@ __device__ __forceinline__ void for_vec4(int64_t n, Body body) {
 
 
 // Block-reduce acc[0..k) into per-block partials; in the last block to
-// finish, thread 0 gets the totals in tot[0..k) and true is returned there
-// (false everywhere else).  Resets the counter.
+// finish, thread 0 gets the totals 0..k) as an LDS array (indexed at run time
+// without private scratch memory); NULL everywhere else.  Resets the counter.
 template <int KM>
-__device__ __forceinline__ bool reduce_totals(const double (&acc)[KM], int k, double* __restrict__ partial,
-                                              unsigned* __restrict__ counter, double (&tot)[KM]) {
+__device__ __forceinline__ const double* reduce_totals(const double (&acc)[KM], int k, double* __restrict__ partial,
+                                                       unsigned* __restrict__ counter) {
   __shared__ double stot[KM];
   bool mine = false;
   reduce_and_finish<KM>(acc, k, partial, counter, [&](int j, double d) { stot[j] = d; mine = true; });
-  if (!mine) return false;
-#pragma unroll
-  for (int j = 0; j < KM; ++j) tot[j] = j < k ? stot[j] : 0.0;
-  return true;
+  return mine ? stot : nullptr;
+}
+
+// coefficients c[0..k) (zero past k) into an LDS array: read by every thread
+// at each use instead of held in scalar registers, whose file is too small
+// for KM doubles
+template <int KM>
+__device__ __forceinline__ const double* coef_lds(const double* __restrict__ c, int k) {
+  __shared__ double sc[KM];
+  if ((int)threadIdx.x < KM) sc[threadIdx.x] = (int)threadIdx.x < k ? c[threadIdx.x] : 0.0;
+  __syncthreads();
+  return sc;
 }
 
 template <typename TV>
@@ -251,8 +259,8 @@ pass1_kernel(const TV* __restrict__ V, int64_t ldv, int j, const TZ* __restrict_
 #pragma unroll
   for (int l = 0; l < KM; ++l) acc[l] = 0.0;
   for_vec4(n, Pass1Body<TV, TZ, TW, KM>{V, ldv, j, z, w, acc});
-  double tot[KM];
-  if (!reduce_totals<KM>(acc, j + 1, partial, counter, tot)) return;
+  const double* tot = reduce_totals<KM>(acc, j + 1, partial, counter);
+  if (!tot) return;
   if (j == 0) {
     ctl->h[0] = tot[0];
     ctl->cz[0] = tot[0];
@@ -347,6 +355,9 @@ __global__ void __launch_bounds__(kThreads)
 pass2_kernel(TV* __restrict__ V, int64_t ldv, int j, const TZ* __restrict__ z, TW* w, float* w32, int64_t n,
              CycleCtl* __restrict__ ctl, double* __restrict__ partial, unsigned* __restrict__ counter) {
   if (!ctl->active) return;
+  // hp and cz stay uniform (scalar registers, spilled to vector lanes
+  // for large KM): held in LDS the compiler hoists them into vector
+  // registers instead, which costs two occupancy steps
   double hp[KM], cz[KM], acc[KM];
 #pragma unroll
   for (int l = 0; l < KM; ++l) {
@@ -356,8 +367,8 @@ pass2_kernel(TV* __restrict__ V, int64_t ldv, int j, const TZ* __restrict__ z, T
   }
   const double inv = ctl->inv_nu;
   for_vec4(n, Pass2Body<TV, TZ, TW, KM>{V, ldv, j, z, w, w32, hp, cz, inv, acc});
-  double tot[KM];
-  if (!reduce_totals<KM>(acc, j + 2, partial, counter, tot)) return;
+  const double* tot = reduce_totals<KM>(acc, j + 2, partial, counter);
+  if (!tot) return;
   // column j of H: both projections, and the subdiagonal from the norm of w'
   // after its second projection (Pythagoras: V is orthonormal)
   const double s2 = tot[j + 1];
@@ -465,9 +476,7 @@ __global__ void __launch_bounds__(kThreads)
 combine_kernel(double* __restrict__ out, const TV* __restrict__ V, int64_t ldv, int k, const int* __restrict__ kdev,
                const double* __restrict__ coef, int64_t n) {
   if (kdev) k = *kdev;
-  double cc[KM];
-#pragma unroll
-  for (int j = 0; j < KM; ++j) cc[j] = j < k ? coef[j] : 0.0;
+  const double* cc = coef_lds<KM>(coef, k);
   for_vec4(n, CombineBody<TV, KM>{V, ldv, k, cc, out});
 }
 
@@ -510,7 +519,7 @@ int check_launch(const char* what) {
 // smallest compiled basis bound that holds k vectors
 int km_for(int k) {
   if (k <= 12) return k <= 2 ? 2 : (k <= 4 ? 4 : (k <= 6 ? 6 : (k <= 8 ? 8 : (k <= 10 ? 10 : 12))));
-  return k <= 16 ? 16 : 32;
+  return 16;
 }
 
 // blocks for a grid-stride reduction kernel: as many as the device holds at
@@ -545,8 +554,7 @@ int resident_blocks(K kernel, int64_t n) {
     case 8: CALL(8); break;            \
     case 10: CALL(10); break;          \
     case 12: CALL(12); break;          \
-    case 16: CALL(16); break;          \
-    default: CALL(32); break;          \
+    default: CALL(16); break;          \
   }
 
 // precision combinations of (basis, apply output, pending vector)

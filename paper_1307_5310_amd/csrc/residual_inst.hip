@@ -59,9 +59,13 @@ static int launch_var(const KParams<STDG_REAL>& P, dim3 grid, dim3 block, hipStr
   }
 #elif !STDG_AFF
   // trilinear groups, variant 1: one workgroup per element and test level
-  if (MODE == 0 && P.variant == 1 && QQ > 1) {
-    if (grid.x > 0xffffffffu / QQ) return fail(STDG_E_ARG, "residual kernel: too many elements for the level split");
-    return launch_one<QQ, MODE, 3>(P, dim3(grid.x * QQ), block, stream);
+  // (built for 1 < q <= 4: past that the per-level selection of the element's
+  // registers goes through scratch memory)
+  if constexpr (MODE == 0 && QQ > 1 && QQ <= kMaxLevelSplitQ) {
+    if (P.variant == 1) {
+      if (grid.x > 0xffffffffu / QQ) return fail(STDG_E_ARG, "residual kernel: too many elements for the level split");
+      return launch_one<QQ, MODE, 3>(P, dim3(grid.x * QQ), block, stream);
+    }
   }
 #endif
   return launch_one<QQ, MODE, 0>(P, grid, block, stream);

@@ -49,7 +49,7 @@ int slab_opts_from(const stdg_solve_opts* o, SlabOpts* out) {
   r.f32 = o->inner_prec == STDG_FP32;
   r.v32 = o->krylov_prec == STDG_FP32;
   r.restart = o->restart > 0 ? o->restart : 10;
-  if (r.restart + 1 > kMaxBasis) return fail(STDG_E_ARG, "stdg_slab_solve: restart must be <= 31");
+  if (r.restart + 1 > kMaxBasis) return fail(STDG_E_ARG, "stdg_slab_solve: restart must be <= 15");
   r.max_iters = o->max_iters > 0 ? o->max_iters : 500;
   r.max_refine = o->max_refine > 0 ? o->max_refine : 100;
   r.rtol = o->rtol > 0 ? o->rtol : 1e-10;

@@ -6,7 +6,9 @@
 
 namespace stdg {
 
-constexpr int kMaxBasis = 32;   // restart + 1 <= 32
+// restart + 1 <= 16: the Arnoldi passes keep one FP64 accumulator per basis
+// vector in registers, and past 16 the compiler moves them to scratch memory
+constexpr int kMaxBasis = 16;
 constexpr int kMaxDotBlocks = 1024;
 
 // Scratch of the deterministic reductions: kMaxBasis * kMaxDotBlocks partials
