@@ -206,11 +206,14 @@ int stdg_mesh_set_launch(stdg_mesh* mesh, int32_t group, int32_t variant);
  * pi the temporal projection onto the common test space of the two elements
  * (the same truncation as S_h).  The energy then drops by the dissipation of
  * the slab instead of being conserved.  c = 0 switches it off (the device
- * coefficients are freed).  Needs affine elements (constant face metric):
- * STDG_E_UNSUPPORTED if the mesh has trilinear ones and c > 0; STDG_E_ARG for
- * c < 0 or non-finite.  Synchronous (host to device copy of 288 bytes per
- * element: the coefficients in FP64 and FP32); not to be called while work on
- * the mesh is in flight. */
+ * coefficients are freed).  On affine elements the face metric is constant
+ * and the residual kernels carry D_h; on trilinear elements a separate kernel
+ * adds it, integrating the face terms with max(a, a') + 2 Gauss points per
+ * direction (a, a' = p + 1 of the two sides; a + 2 on PEC faces) and the face
+ * metric of the trilinear map at each point.  STDG_E_ARG for c < 0 or
+ * non-finite.  Synchronous (host to device copy of 288 bytes per element: the
+ * coefficients in FP64 and FP32); not to be called while work on the mesh is
+ * in flight. */
 int stdg_mesh_set_dissipation(stdg_mesh* mesh, double c);
 
 /* The hot path: the matrix-free space-time residual of one slab (Section 5,
@@ -244,6 +247,16 @@ int stdg_residual_apply(const stdg_mesh* mesh, double dt, int prec, int mode,
 int stdg_residual_apply_noalloc(const stdg_mesh* mesh, double dt, int prec, int mode,
                                 const void* x_dev, const void* load_dev, void* y_dev, void* stream);
 size_t stdg_noalloc_scratch_bytes(void);
+
+/* Measurement utility, no operation of the method: copies `bytes` bytes from
+ * src to dst (device pointers, both 16-byte aligned, bytes a multiple of 16,
+ * no overlap) with the library's streaming kernel - 16-byte non-temporal
+ * loads and stores, grid-stride, 32 blocks per compute unit - so that
+ * 2 * bytes cross HBM.  Its rate is the practical bandwidth ceiling the
+ * memory-bound kernels are compared with, and its traffic counters calibrate
+ * theirs.  Asynchronous on `stream`.  STDG_E_ARG for NULL, misaligned or
+ * overlapping buffers; bytes = 0 does nothing. */
+int stdg_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Current density of the load L(V) = (J, v) (eq. bilinearform:C):
  * kind 0 = none; kind 1 = J(x,t) = dir * amp * exp(-|x - center|^2 / (2 sigma_x^2))
@@ -378,7 +391,7 @@ typedef struct {
   const double* abc;
   const double* init_state;  /*   an FP64 state (host, state layout) if not NULL    */
   double c_diss;             /* >= 0: dissipative stabilisation D_h with this c, as  */
-                             /*   stdg_mesh_set_dissipation (affine meshes; 0 = off) */
+                             /*   stdg_mesh_set_dissipation (0 = off)                */
   int64_t init_state_size;   /* entries at init_state: must equal the mesh's state
                                 size (sum of 6 (p+1)^3), else STDG_E_ARG; ignored
                                 when init_state is NULL                             */

@@ -26,7 +26,7 @@ __all__ = ["StdgError", "STDG_FP32", "STDG_FP64", "STDG_OPERATOR", "STDG_RESIDUA
            "stdg_mesh_upload", "stdg_mesh_info", "stdg_mesh_offsets", "stdg_mesh_free", "stdg_mesh_set_dissipation",
            "stdg_mesh_set_order", "stdg_mesh_autotune", "stdg_mesh_set_launch", "stdg_mesh_group",
            "stdg_residual_apply", "stdg_residual_apply_noalloc", "stdg_noalloc_scratch_bytes",
-           "stdg_load_assemble", "stdg_project_modes",
+           "stdg_stream_copy", "stdg_load_assemble", "stdg_project_modes",
            "stdg_slab_solve", "stdg_energy", "stdg_residual_dual_norm", "stdg_serve_start", "stdg_serve_submit",
            "stdg_serve_poll", "stdg_serve_clock", "stdg_serve_stop", "exported_symbols"]
 
@@ -242,6 +242,20 @@ def stdg_residual_apply_noalloc(mesh, dt, prec, mode, x, load, y, stream=None):
 
 def stdg_noalloc_scratch_bytes():
     return lib().stdg_noalloc_scratch_bytes()
+
+
+def stdg_stream_copy(src, dst, stream=None):
+    """dst[:] = src[:] by the library's streaming kernel (the practical HBM
+    ceiling); both contiguous device tensors of the same byte size."""
+    for t, name in ((src, "src"), (dst, "dst")):
+        if torch is None or not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor on the GPU" % name)
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous tensor on the GPU" % name)
+    nbytes = src.numel() * src.element_size()
+    if nbytes != dst.numel() * dst.element_size():
+        raise ValueError("src and dst differ in size")
+    check(lib().stdg_stream_copy(ptr(src), ptr(dst), ctypes.c_size_t(nbytes), stream_handle(stream)))
 
 
 def _source(src):

@@ -136,6 +136,7 @@ def lib():
             "stdg_residual_apply": ([vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
             "stdg_residual_apply_noalloc": ([vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
             "stdg_noalloc_scratch_bytes": ([], ctypes.c_size_t),
+            "stdg_stream_copy": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
             "stdg_load_assemble": ([vp, ctypes.POINTER(Source), dbl, dbl, vp, vp], ctypes.c_int),
             "stdg_project_modes": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
             "stdg_slab_solve": ([vp, dbl, dbl, vp, ctypes.POINTER(SolveOpts), vp, vp,

@@ -331,4 +331,14 @@ int stdg_residual_apply_noalloc(const stdg_mesh* mesh, double dt, int prec, int 
 
 size_t stdg_noalloc_scratch_bytes(void) { return noalloc_scratch_capacity(); }
 
+int stdg_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (bytes == 0) return STDG_OK;
+  if (!src || !dst) return fail(STDG_E_ARG, "stdg_stream_copy: NULL buffer");
+  if (bytes % 16 != 0 || (uintptr_t)src % 16 != 0 || (uintptr_t)dst % 16 != 0)
+    return fail(STDG_E_ARG, "stdg_stream_copy: buffers and size must be multiples of 16 bytes");
+  const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+  if (a < b + bytes && b < a + bytes) return fail(STDG_E_ARG, "stdg_stream_copy: buffers overlap");
+  return stream_copy(src, dst, bytes, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -54,6 +54,22 @@ __global__ void guess_kernel(double* __restrict__ x, const double* __restrict__ 
   }
 }
 
+// Streaming copy: 16-byte lanes, two chunks in flight per thread,
+// non-temporal loads and stores (the data is touched once), grid-stride.
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) stream_copy_kernel(const u4* __restrict__ src, u4* __restrict__ dst,
+                                                          int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + stride < n16; i += 2 * stride) {
+    const u4 a = __builtin_nontemporal_load(src + i);
+    const u4 b = __builtin_nontemporal_load(src + i + stride);
+    __builtin_nontemporal_store(a, dst + i);
+    __builtin_nontemporal_store(b, dst + i + stride);
+  }
+  if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 int grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
@@ -62,6 +78,21 @@ int grid_for(int64_t n) {
 }
 
 }  // namespace
+
+int stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return STDG_OK;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  // 32 blocks of 256 threads per compute unit: every CU full, one wave of blocks
+  int64_t g = (int64_t)cus * 32, need = (n16 + 255) / 256;
+  if (g > need) g = need;
+  hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)g), dim3(256), 0, s, (const u4*)src, (u4*)dst, n16);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? STDG_OK : hip_fail(e, "stream copy");
+}
 
 int blas_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(axpy_kernel, dim3(grid_for(n)), dim3(256), 0, s, y, x, a, n);

@@ -85,6 +85,18 @@ struct QTables {
 void fill_qtables_f64(int a, QTables<double>* t);
 void fill_qtables_f32(int a, QTables<float>* t);
 
+// Face rule of D_h on trilinear elements: the n-point Gauss rule on [0, 1]
+// (n = max(a, a') + 2 points for a face between degrees a and a') and the
+// orthonormal Legendre values at its points, L[k * kMaxA + j] = L_j(x_k).
+constexpr int kMaxFaceQ = kMaxA + 2;
+template <typename T>
+struct FaceRule {
+  T x[kMaxFaceQ], w[kMaxFaceQ];
+  T L[kMaxFaceQ * kMaxA];
+};
+void fill_face_rule_f64(int n, FaceRule<double>* r);
+void fill_face_rule_f32(int n, FaceRule<float>* r);
+
 // n-point Gauss-Legendre rule on [0, 1] (n <= 16), Newton iteration on P_n.
 void gauss_rule01(int n, double* x, double* w);
 
@@ -144,6 +156,9 @@ struct Mesh {
   // mass rules of trilinear elements, indexed by a (QTables<double>, QTables<float>)
   void* d_qt64 = nullptr;
   void* d_qt32 = nullptr;
+  // face rules of D_h on trilinear elements, indexed by n (FaceRule<double>, FaceRule<float>)
+  void* d_fr64 = nullptr;
+  void* d_fr32 = nullptr;
   // side streams for applies over several kernel groups (created on first use):
   // the groups run concurrently, forked from and joined back into the caller's stream
   static constexpr int kAux = 4;
@@ -156,7 +171,8 @@ struct Mesh {
   //   [g]      alpha_E of face g        [6 + g]  alpha_H of face g (0 on PEC faces)
   //   [12 + 3 alpha + (0, 1, 2)] = K_aa, K_bb, K_ab of the faces normal to alpha,
   // K = |t_a x t_b| g^{-1} the face metric of the tangent vectors t_a, t_b along
-  // the axes (alpha + 1) % 3, (alpha + 2) % 3 (constant on affine elements)
+  // the axes (alpha + 1) % 3, (alpha + 2) % 3 (constant on affine elements;
+  // unused on trilinear ones, whose kernel evaluates it at the face points)
   // the slab solver of stdg_slab_solve, kept between calls (its Krylov basis
   // and work vectors stay allocated: a march of slabs allocates once); a call
   // that finds it busy (another thread) uses a solver of its own
@@ -195,6 +211,12 @@ int launch_dual_norm_trilinear(const Mesh* m, const double* R, double* partial, 
 int noalloc_scratch_init(int device);
 size_t noalloc_scratch_capacity();
 int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s, const int* skip = nullptr);
+// bytes (a multiple of 16) from src to dst, both 16-byte aligned, no overlap (blas.hip)
+int stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+// D_h on the trilinear group g, added to y (dissipation.hip); mode 0 or STDG_RESIDUAL
+template <typename T>
+int launch_diss_trilinear(const Mesh* m, const Group& g, double dt, int mode, const T* x, T* y, hipStream_t s,
+                          const int* skip);
 
 // Mesh construction (mesh.cpp): host analysis (validation, faces, metric,
 // groups) and the device copies, separable so that a server can analyse a

@@ -541,6 +541,20 @@ int upload_mesh(Ctx* ctx, Mesh* m) {
     STDG_HIP(hipMemcpy(m->d_qt64, q64.data(), b64, hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d_qt32, q32.data(), b32, hipMemcpyHostToDevice));
   }
+  if (m->n_nonaffine > 0) {
+    std::vector<FaceRule<double>> f64(kMaxFaceQ + 1);
+    std::vector<FaceRule<float>> f32(kMaxFaceQ + 1);
+    for (int n = 1; n <= kMaxFaceQ; ++n) {
+      fill_face_rule_f64(n, &f64[n]);
+      fill_face_rule_f32(n, &f32[n]);
+    }
+    size_t b64 = sizeof(FaceRule<double>) * (kMaxFaceQ + 1), b32 = sizeof(FaceRule<float>) * (kMaxFaceQ + 1);
+    if ((rc = dev_alloc(ctx, &m->d_fr64, b64)) != STDG_OK) return rc;
+    if ((rc = dev_alloc(ctx, &m->d_fr32, b32)) != STDG_OK) return rc;
+    m->device_bytes += b64 + b32;
+    STDG_HIP(hipMemcpy(m->d_fr64, f64.data(), b64, hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d_fr32, f32.data(), b32, hipMemcpyHostToDevice));
+  }
   for (Group& g : m->groups) {
     if ((rc = dev_alloc(ctx, (void**)&g.d_list, sizeof(int32_t) * g.count)) != STDG_OK) return rc;
     m->device_bytes += sizeof(int32_t) * g.count;
@@ -549,15 +563,15 @@ int upload_mesh(Ctx* ctx, Mesh* m) {
   return STDG_OK;
 }
 
-// Coefficients of D_h (the dissipative remark closing Section 4) for affine
-// meshes: alpha_E = c / {sqrt(mu / eps)}, alpha_H = c / {sqrt(eps / mu)} per face
-// (the mean of both sides, the element's own value on PEC faces, where only the
-// E term exists), and per axis the face metric K that turns the physical
-// integral of (n x v) . (n x u) into sum K_cd v_c u_d over the reference face.
+// Coefficients of D_h (the dissipative remark closing Section 4):
+// alpha_E = c / {sqrt(mu / eps)}, alpha_H = c / {sqrt(eps / mu)} per face (the
+// mean of both sides, the element's own value on PEC faces, where only the E
+// term exists), and per axis the face metric K that turns the physical
+// integral of (n x v) . (n x u) into sum K_cd v_c u_d over the reference face
+// (constant on affine elements; the trilinear kernels evaluate it at the face
+// quadrature points from the vertices and leave these entries unused).
 int set_dissipation(Mesh* m, double c) {
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(STDG_E_ARG, "dissipation coefficient must be finite and >= 0");
-  if (c > 0.0 && m->n_nonaffine > 0)
-    return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation needs affine elements (constant face metric)");
   ++m->epoch;
   const size_t bytes = sizeof(double) * Mesh::kDissWords * m->ne, bytes32 = sizeof(float) * Mesh::kDissWords * m->ne;
   if (c == 0.0) {
@@ -647,6 +661,9 @@ void release_mesh(Mesh* m) {
   if (m->d_qt64) dev_free(ctx, m->d_qt64, sizeof(QTables<double>) * (kMaxA + 1));
   if (m->d_qt32) dev_free(ctx, m->d_qt32, sizeof(QTables<float>) * (kMaxA + 1));
   m->d_qt64 = m->d_qt32 = nullptr;
+  if (m->d_fr64) dev_free(ctx, m->d_fr64, sizeof(FaceRule<double>) * (kMaxFaceQ + 1));
+  if (m->d_fr32) dev_free(ctx, m->d_fr32, sizeof(FaceRule<float>) * (kMaxFaceQ + 1));
+  m->d_fr64 = m->d_fr32 = nullptr;
   for (auto& g : m->groups)
     if (g.d_list && ctx) dev_free(ctx, g.d_list, sizeof(int32_t) * g.count);
   if (m->d_scratch) dev_free(ctx, m->d_scratch, m->scratch_bytes);

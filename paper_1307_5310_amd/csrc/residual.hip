@@ -102,8 +102,6 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
     if (g.count == 0) continue;
     if (!g.affine && mode == STDG_OPERATOR_PRECOND)
       return fail(STDG_E_UNSUPPORTED, "trilinear elements take P^{-1} in a separate pass");
-    if (!g.affine && m->d_diss)
-      return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation needs affine elements");
     order.push_back(&g);
   }
   auto work = [](const Group* g) { return g->count * (int64_t)g->q * g->a * g->a * g->a * (g->affine ? 1 : 3); };
@@ -120,8 +118,14 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
     P.list = g.d_list;
     P.variant = g.variant;
     P.qt = d_qt + g.a;
-    int rc = (g.affine ? affine : trilinear)[g.a](g.q, P, g.count, fork ? m->aux[i % Mesh::kAux] : s);
+    const hipStream_t gs = fork ? m->aux[i % Mesh::kAux] : s;
+    int rc = (g.affine ? affine : trilinear)[g.a](g.q, P, g.count, gs);
     if (rc != STDG_OK) return rc;
+    // D_h on trilinear elements: added by its own kernel after the group's residual
+    if (!g.affine && m->d_diss) {
+      rc = launch_diss_trilinear<T>(m, g, dt, mode, x, y, gs, skip);
+      if (rc != STDG_OK) return rc;
+    }
   }
   if (fork) {
     for (int k = 0; k < Mesh::kAux && k < (int)order.size(); ++k) {

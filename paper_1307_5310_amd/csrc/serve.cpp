@@ -429,8 +429,6 @@ int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ti
         else
           r->init.assign(req->init_state, req->init_state + r->n_state);
       }
-      if (req->c_diss > 0.0 && m.n_nonaffine > 0)
-        rc = fail(STDG_E_UNSUPPORTED, "stdg_serve_submit: dissipative stabilisation needs affine elements");
     }
   } catch (const std::bad_alloc&) {
     rc = fail(STDG_E_NOMEM, "stdg_serve_submit: host allocation failed");

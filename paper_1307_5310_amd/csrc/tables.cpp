@@ -126,4 +126,26 @@ void fill_qtables_f32(int a, QTables<float>* t) {
   for (int i = 0; i <= kMaxA; ++i) t->x[i] = (float)d.x[i];
 }
 
+void fill_face_rule_f64(int n, FaceRule<double>* r) {
+  std::memset(r, 0, sizeof(*r));
+  if (n < 1 || n > kMaxFaceQ) return;
+  double x[kMaxFaceQ], w[kMaxFaceQ];
+  gauss_rule01(n, x, w);
+  for (int k = 0; k < n; ++k) {
+    r->x[k] = x[k];
+    r->w[k] = w[k];
+    for (int j = 0; j < kMaxA; ++j) r->L[k * kMaxA + j] = legendre01(j, x[k]);
+  }
+}
+
+void fill_face_rule_f32(int n, FaceRule<float>* r) {
+  FaceRule<double> d;
+  fill_face_rule_f64(n, &d);
+  for (int k = 0; k < kMaxFaceQ; ++k) {
+    r->x[k] = (float)d.x[k];
+    r->w[k] = (float)d.w[k];
+  }
+  for (int i = 0; i < kMaxFaceQ * kMaxA; ++i) r->L[i] = (float)d.L[i];
+}
+
 }  // namespace stdg

@@ -7,7 +7,8 @@ Bars as for the plain apply: FP64 <= 1e-12, raw FP32 <= 1e-5; the slab solve
 oracle's amount.  The three neighbour paths of the kernel are covered (FP32
 staged faces, gathered faces, mixed degrees), as are the PEC faces, jumps in
 eps and mu, sheared affine elements (full face metric) and switching back
-to c = 0."""
+to c = 0; on trilinear elements (face metric at the points of the face rule),
+next to affine ones, with mixed degrees, and in the slab solve."""
 import numpy as np
 import pytest
 
@@ -29,7 +30,9 @@ def _disc(mesh, c):
     return Discretisation(mesh.vertices, mesh.hexes, mesh.p, mesh.q, mesh.eps, mesh.mu, c_diss=c)
 
 
-def _check(lib, mesh, dt, c, seed, name, precs=(0, 1)):
+def _check(lib, mesh, dt, c, seed, name, precs=(0, 1), centre=False):
+    """centre: P^{-1} with the element-centre metric (trilinear elements;
+    exact on affine ones)"""
     stdg = lib.stdg
     d = _disc(mesh, c)
     mh = lib.upload(mesh)
@@ -50,7 +53,8 @@ def _check(lib, mesh, dt, c, seed, name, precs=(0, 1)):
             assert rel_err(got, d.residual(Us, dt, Ls)) < TOL[prec], (name, prec, "residual")
             note("%s prec=%d precond" % (name, prec))
             got = lib.apply(mh, dt, prec, stdg.STDG_OPERATOR_PRECOND, xs)
-            assert rel_err(got, d.operator(d.precond_solve(xs), dt)) < TOL[prec], (name, prec, "precond")
+            pre = d.precond_centre_solve(xs) if centre else d.precond_solve(xs)
+            assert rel_err(got, d.operator(pre, dt)) < TOL[prec], (name, prec, "precond")
     finally:
         stdg.stdg_mesh_free(mh)
 
@@ -108,16 +112,18 @@ def test_off_again_and_errors(lib):
             assert ei.value.status == -1
     finally:
         stdg.stdg_mesh_free(mh)
-    # trilinear elements: the face metric is not constant
+    # trilinear elements (D_h by its own kernel): on, then off again bitwise
     v, h = synth.box_mesh((2, 2, 2))
     v = synth.perturb_interior(v, (2, 2, 2), 0.15, seed=4)
     mesh = synth.Mesh(v, h, np.full(8, 2, np.int32), np.full(8, 1, np.int32), np.ones(8), np.ones(8))
     mh = lib.upload(mesh)
+    x = np.random.default_rng(4).standard_normal(stdg.stdg_mesh_info(mh)["unknown_size"])
     try:
-        with pytest.raises(stdg.StdgError) as ei:
-            stdg.stdg_mesh_set_dissipation(mh, 1.0)
-        assert ei.value.status == -2
+        plain = lib.apply(mh, 0.1, 0, stdg.STDG_OPERATOR, x)
+        stdg.stdg_mesh_set_dissipation(mh, 1.0)
+        assert rel_err(lib.apply(mh, 0.1, 0, stdg.STDG_OPERATOR, x), plain) > 1e-3
         stdg.stdg_mesh_set_dissipation(mh, 0.0)
+        assert np.array_equal(lib.apply(mh, 0.1, 0, stdg.STDG_OPERATOR, x), plain)
     finally:
         stdg.stdg_mesh_free(mh)
 
@@ -141,6 +147,78 @@ def test_slab_solve_energy_drops(lib, inner, krylov):
         lib.stdg.stdg_mesh_set_dissipation(mh, c)
         st = lib.dev(s0, lib.torch.float64)
         note("diss solve inner=%d krylov=%d" % (inner, krylov))
+        info = lib.stdg.stdg_slab_solve(mh, 0.0, dt, None, st, inner_prec=inner, rtol=1e-13, max_iters=600,
+                                        max_refine=60, krylov_prec=krylov)
+        got = st.cpu().numpy()
+    finally:
+        lib.stdg.stdg_mesh_free(mh)
+    assert info["status"] == 0, info
+    assert rel_err(got, ref) < 1e-10
+    e0, e1 = d.energy(s0), d.energy(ref)
+    assert e1 < (1 - 1e-3) * e0
+    assert abs(info["energy_end"] - e1) < 1e-10 * e0
+
+
+# ---- trilinear elements: the face metric varies over each face -------------
+
+def _trilinear(shape, p, q, seed, perturb=0.15):
+    v, h = synth.box_mesh(shape, hi=(0.9, 0.6, 0.7))
+    v = synth.perturb_interior(v, shape, perturb, seed=seed, hi=(0.9, 0.6, 0.7))
+    ne = h.shape[0]
+    rng = np.random.default_rng(seed)
+    p = np.broadcast_to(np.asarray(p, np.int32), (ne,)).copy()
+    q = np.broadcast_to(np.asarray(q, np.int32), (ne,)).copy()
+    return synth.Mesh(v, h, p, q, rng.uniform(1, 4, ne), rng.uniform(1, 2, ne))
+
+
+@pytest.mark.parametrize("p,q", [(1, 1), (2, 2), (3, 2), (6, 4)])
+def test_trilinear_uniform_degrees(lib, p, q):
+    mesh = _trilinear((3, 2, 2), p, q, 200 + p)
+    _check(lib, mesh, 0.06, 0.9, 200 + p, "diss trilinear p%d q%d" % (p, q), centre=True)
+
+
+def test_trilinear_mixed_degrees(lib):
+    # face rules of max(a, a') + 2 points between different degrees, the
+    # neighbour's time levels truncated at min(q, q')
+    rng = np.random.default_rng(210)
+    mesh = _trilinear((3, 2, 2), 1, 1, 210)
+    mesh.p[:] = rng.integers(1, 5, mesh.n_elements)
+    mesh.q[:] = rng.integers(1, 4, mesh.n_elements)
+    _check(lib, mesh, 0.05, 1.2, 210, "diss trilinear mixed", centre=True)
+
+
+def test_trilinear_next_to_affine(lib):
+    # one interior vertex moved: the eight elements around it are trilinear,
+    # the other four stay boxes (the affine D_h kernels meet trilinear neighbours)
+    v, h = synth.box_mesh((3, 2, 2))
+    idx = int(np.argmin(np.linalg.norm(v - np.array([1 / 3, 0.5, 0.5]), axis=1)))
+    v = v.copy()
+    v[idx] += np.array([0.05, -0.04, 0.03])
+    rng = np.random.default_rng(211)
+    mesh = synth.Mesh(v, h, rng.integers(1, 4, 12).astype(np.int32), rng.integers(1, 3, 12).astype(np.int32),
+                      rng.uniform(1, 4, 12), rng.uniform(1, 2, 12))
+    mh = lib.upload(mesh)
+    info = lib.stdg.stdg_mesh_info(mh)
+    lib.stdg.stdg_mesh_free(mh)
+    assert info["n_affine"] == 4 and info["n_nonaffine"] == 8, info
+    _check(lib, mesh, 0.05, 0.7, 211, "diss trilinear next to affine", centre=True)
+
+
+@pytest.mark.parametrize("inner,krylov", [(0, 0), (1, 1)])
+def test_trilinear_slab_solve_energy_drops(lib, inner, krylov):
+    mesh = _trilinear((2, 2, 2), 2, 1, 212)
+    mesh.q[:] = np.array([1, 2] * 4, np.int32)
+    c, dt = 0.7, 0.12
+    d = _disc(mesh, c)
+    rng = np.random.default_rng(212)
+    s0 = rng.standard_normal(d.state_off[-1])
+    note("diss trilinear solve: oracle")
+    ref = d.level_state(d.solve_direct(s0, dt), 1)
+    mh = lib.upload(mesh)
+    try:
+        lib.stdg.stdg_mesh_set_dissipation(mh, c)
+        st = lib.dev(s0, lib.torch.float64)
+        note("diss trilinear solve inner=%d krylov=%d" % (inner, krylov))
         info = lib.stdg.stdg_slab_solve(mh, 0.0, dt, None, st, inner_prec=inner, rtol=1e-13, max_iters=600,
                                         max_refine=60, krylov_prec=krylov)
         got = st.cpu().numpy()

@@ -194,3 +194,11 @@ def test_full_size_reoriented_dissipative_sampled(lib, prec):
             assert rel_err(got, ref) < TOL[prec]
     finally:
         stdg.stdg_mesh_free(mh)
+
+
+@pytest.mark.parametrize("p,q", [(2, 2), (3, 1)])
+def test_trilinear_dissipation_reoriented(lib, p, q):
+    # D_h on trilinear elements met in every orientation: the neighbour's face
+    # points and tangential components through the face map
+    m = _mesh((3, 2, 2), p, q, 48 + p, hi=(0.9, 0.5, 0.7), perturb=0.15)
+    _check(lib, m, 0.05, 48 + p, "reoriented trilinear D_h p%d q%d" % (p, q), c=0.9)

@@ -160,18 +160,21 @@ def test_trilinear_energy_conserved_without_source(lib):
     lib.stdg.stdg_mesh_free(mh)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_graded_24cubed_sampled(lib, prec):
+@pytest.mark.parametrize("prec,c_diss", [(0, 0.0), (1, 0.0), (0, 1.0), (1, 1.0)])
+def test_graded_24cubed_sampled(lib, prec, c_diss):
     """Full-size graded 24^3 trilinear mesh (p 3..6, q 1..4) in the launch
-    configuration of a preconditioned operator apply; the oracle checks sampled
-    elements from every ring."""
+    configuration of a preconditioned operator apply, also with D_h (c = 1);
+    the oracle checks sampled elements from every ring."""
+    from oracle.dg import Discretisation
     stdg = lib.stdg
     cfg = synth.graded_nonaffine()
     m = cfg["mesh"]
     dt = cfg["dt"]
     x = _cast(prec)(synth.random_vector(m.unknown_size(), 0))
     mh = lib.upload(m)
-    d = oracle_disc(m)
+    if c_diss > 0:
+        stdg.stdg_mesh_set_dissipation(mh, c_diss)
+    d = Discretisation(m.vertices, m.hexes, m.p, m.q, m.eps, m.mu, c_diss=c_diss)
     rng = np.random.default_rng(44)
     sample = []
     for p in (6, 5, 4, 3):
@@ -180,7 +183,7 @@ def test_graded_24cubed_sampled(lib, prec):
     sample += [0, m.n_elements - 1]
     needed = sorted(set(sample) | {int(k) for e in sample for k in d.nb[e] if k >= 0})
     for mode in (stdg.STDG_OPERATOR, stdg.STDG_OPERATOR_PRECOND):
-        note("graded 24^3 prec=%d mode=%d: apply" % (prec, mode))
+        note("graded 24^3 prec=%d c=%g mode=%d: apply" % (prec, c_diss, mode))
         y = lib.apply(mh, dt, prec, mode, x)
         assert np.all(np.isfinite(y))
         xin = d.precond_centre_solve(x, needed) if mode == stdg.STDG_OPERATOR_PRECOND else x
@@ -188,6 +191,6 @@ def test_graded_24cubed_sampled(lib, prec):
         got = np.concatenate([y[d.unk_off[e]:d.unk_off[e + 1]] for e in sample])
         ref = np.concatenate([rows[e] for e in sample])
         err = rel_err(got, ref)
-        note("graded 24^3 prec=%d mode=%d rel err %.3e" % (prec, mode, err))
+        note("graded 24^3 prec=%d c=%g mode=%d rel err %.3e" % (prec, c_diss, mode, err))
         assert err < TOL[prec]
     stdg.stdg_mesh_free(mh)
