@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--serve-max-active", type=int, default=16)
     ap.add_argument("--serve-krylov", choices=("fp32", "fp64"), default="fp32",
                     help="storage of the serving solver's Krylov basis (sums are FP64 either way)")
+    ap.add_argument("--serve-batch", type=int, default=1,
+                    help="1: requests of one kernel group run their restart cycles batched")
     ap.add_argument("--serve-graph", type=int, default=1,
                     help="1: the serving solvers replay Arnoldi iterations as captured HIP graphs")
     ap.add_argument("--serve-eta-rel", type=float, default=1e-3,
@@ -346,14 +348,14 @@ def main():
     if args.serve_requests > 0:
         log("serving stream: %d requests" % args.serve_requests)
         serving = time_serving(stdg, ctx, args.serve_requests, args.serve_budget_gb, args.serve_max_active,
-                               args.serve_krylov, graph=bool(args.serve_graph))
+                               args.serve_krylov, graph=bool(args.serve_graph), batch=bool(args.serve_batch))
         log("serving: %.2f solves/s, p50 %.3f s, p99 %.3f s" % (serving["solves_per_s"], serving["p50_latency_s"],
                                                                serving["p99_latency_s"]))
         if args.serve_eta_rel > 0:
             log("serving stream, inexact solves")
             serving["inexact"] = time_serving(stdg, ctx, args.serve_requests, args.serve_budget_gb,
                                               args.serve_max_active, args.serve_krylov, args.serve_eta_rel,
-                                              graph=bool(args.serve_graph))
+                                              graph=bool(args.serve_graph), batch=bool(args.serve_batch))
             log("serving inexact: %.2f solves/s, p50 %.3f s, p99 %.3f s" % (
                 serving["inexact"]["solves_per_s"], serving["inexact"]["p50_latency_s"],
                 serving["inexact"]["p99_latency_s"]))
@@ -416,7 +418,7 @@ def main():
     stdg.stdg_finalize(ctx)
 
 
-def time_serving(stdg, ctx, n_requests, budget_gb, max_active, krylov, eta_rel=0.0, graph=False):
+def time_serving(stdg, ctx, n_requests, budget_gb, max_active, krylov, eta_rel=0.0, graph=False, batch=True):
     """The serving stream: independent PEC cavity solves (n^3, n in {4,..,16},
     p in 2..6, q = p - 1, eps in {1,2,4} per element, 20 slabs, dt = h/(2p+1))
     arriving as a Poisson process at 50 per second, submitted at their arrival
@@ -427,7 +429,7 @@ def time_serving(stdg, ctx, n_requests, budget_gb, max_active, krylov, eta_rel=0
     srv = stdg.stdg_serve_start(ctx, hbm_budget=int(budget_gb * (1 << 30)), max_active=max_active,
                                 inner_prec=stdg.STDG_FP32, rtol=1e-10, max_iters=3000, max_refine=300,
                                 krylov_prec=stdg.STDG_FP32 if krylov == "fp32" else stdg.STDG_FP64,
-                                eta_rel=eta_rel, use_graph=graph)
+                                eta_rel=eta_rel, use_graph=graph, batch_cycles=batch)
     results = {}
     try:
         c0 = stdg.stdg_serve_clock(srv)
@@ -466,6 +468,8 @@ def time_serving(stdg, ctx, n_requests, budget_gb, max_active, krylov, eta_rel=0
             "iters_per_slab": round(sum(r["iters"] for r in res) / sum(r["slabs_done"] for r in res), 2),
             "max_rel_res": max(r["max_rel_res"] for r in res), "failed": bad,
             "hbm_budget_gb": budget_gb, "max_active": max_active, "krylov_basis": krylov, "graphs": bool(graph),
+            "batch_cycles": bool(batch), "batched_cycles": int(sum(r["batched_cycles"] for r in res)),
+            "requests_batched": int(sum(1 for r in res if r["batched_cycles"] > 0)),
             "stop": ("eta_it <= %g sqrt(2 E(0)) per request" % eta_rel) if eta_rel > 0 else "rtol 1e-10 per slab",
             "max_eta_it_rel": (max(r["eta_it"] / np.sqrt(2 * r["energy_start"]) for r in res if r["energy_start"] > 0)
                                if eta_rel > 0 else None),

@@ -379,6 +379,15 @@ typedef struct {
                             eta_it <= eta_rel sqrt(2 E(t0)) over the request;
                             0 = solve every slab to rtol                         */
   int32_t use_graph;     /* as stdg_solve_opts.use_graph, for every request      */
+  int32_t batch_cycles;  /* 1: requests whose meshes are one affine kernel group
+                            of the same (p, q) with a diagonal metric and no D_h
+                            (FP32 inner applies) run their restart cycles
+                            together: one launch per apply and per basis pass
+                            for up to 16 requests, each on its own segment of
+                            the grid with its own block partition, so results
+                            are bitwise those of the request alone; a pending
+                            cycle waits at most 0.5 ms for partners.  0: every
+                            request alone                                     */
 } stdg_serve_opts;
 
 typedef struct {
@@ -411,6 +420,7 @@ typedef struct {
   double eta_it;             /* with eta_rel: the accumulated iteration-error bound */
   double* state;             /* in: caller host buffer for the final state, or NULL */
   int64_t state_capacity;    /* in: entries available at state                      */
+  int64_t batched_cycles;    /* restart cycles run together with other requests     */
 } stdg_result;
 
 /* Start a server on the context's device.  The server thread owns the

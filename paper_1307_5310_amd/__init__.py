@@ -331,13 +331,13 @@ def stdg_energy(mesh, state, stream=None):
 
 def stdg_serve_start(ctx, hbm_budget=0, max_active=0, inner_prec=STDG_FP32, restart=10, max_iters=500,
                      max_refine=100, rtol=1e-10, inner_rtol=1e-4, krylov_prec=None, eta_rel=0.0,
-                     use_graph=False):
+                     use_graph=False, batch_cycles=True):
     """Start a server (C ABI stdg_serve_start); krylov_prec None as in stdg_slab_solve."""
     if krylov_prec is None:
         krylov_prec = STDG_FP32 if int(inner_prec) == STDG_FP32 else STDG_FP64
     o = ServeOpts(int(hbm_budget), int(max_active), int(inner_prec), int(restart), int(max_iters),
                   int(max_refine), float(rtol), float(inner_rtol), int(krylov_prec), float(eta_rel),
-                  int(bool(use_graph)))
+                  int(bool(use_graph)), int(bool(batch_cycles)))
     h = ctypes.c_void_p()
     check(lib().stdg_serve_start(ctx, ctypes.byref(o), ctypes.byref(h)))
     return h

@@ -78,7 +78,7 @@ class ServeOpts(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
                 ("krylov_prec", ctypes.c_int32), ("eta_rel", ctypes.c_double),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("batch_cycles", ctypes.c_int32)]
 
 
 class GroupInfo(ctypes.Structure):
@@ -100,7 +100,8 @@ class Result(ctypes.Structure):
                 ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
                 ("state_size", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("eta_it", ctypes.c_double),
-                ("state", ctypes.c_void_p), ("state_capacity", ctypes.c_int64)]
+                ("state", ctypes.c_void_p), ("state_capacity", ctypes.c_int64),
+                ("batched_cycles", ctypes.c_int64)]
 
 
 # in the order of the STDG_STRUCT_* indices of stdg_struct_size

@@ -61,6 +61,7 @@ REGISTER_BOUND = {
     ("float", "trilinear"): {9: 3},
 }
 _RESID = re.compile(r"residual_kernelI([fd])Li(\d+)ELi(\d+)ELi(\d+)ELb([01])ELb([01])ELi(\d+)E")
+_RESID_BATCH = re.compile(r"residual_batch_kernelI([fd])Li(\d+)ELi(\d+)E")  # affine, operator mode
 
 
 class ResourceError(RuntimeError):
@@ -86,11 +87,15 @@ def parse_resource_remarks(text):
 def allowed_counters(name):
     """The guarded counters that may be nonzero for this kernel symbol."""
     m = _RESID.search(name)
-    if not m:
-        return ()
+    if m:
+        kind = "diss" if m.group(6) == "1" else ("affine" if m.group(5) == "1" else "trilinear")
+    else:
+        m = _RESID_BATCH.search(name)
+        if not m:
+            return ()
+        kind = "affine"
     real = "float" if m.group(1) == "f" else "double"
     a, q = int(m.group(2)), int(m.group(3))
-    kind = "diss" if m.group(6) == "1" else ("affine" if m.group(5) == "1" else "trilinear")
     qmin = REGISTER_BOUND.get((real, kind), {}).get(a)
     if qmin is None or q < qmin:
         return ()

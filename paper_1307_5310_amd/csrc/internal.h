@@ -211,6 +211,20 @@ int launch_dual_norm_trilinear(const Mesh* m, const double* R, double* partial, 
 int noalloc_scratch_init(int device);
 size_t noalloc_scratch_capacity();
 int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s, const int* skip = nullptr);
+// One request's operands of a batched preconditioned operator apply (the
+// serving loop's lockstep restart cycles; residual.hip).
+struct BatchApplyArgs {
+  const Mesh* mesh;
+  double dt;
+  const void* x;
+  void* y;
+  const int* skip;
+};
+// a mesh that can join batched applies: one affine kernel group, a diagonal
+// metric (P^{-1} fused into the kernel), no D_h
+bool batchable_mesh(const Mesh* m);
+// up to 16 requests whose meshes are batchable with the same (a, q)
+int launch_residual_batch(const BatchApplyArgs* a, int count, int prec, hipStream_t s);
 // bytes (a multiple of 16) from src to dst, both 16-byte aligned, no overlap (blas.hip)
 int stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 // D_h on the trilinear group g, added to y (dissipation.hip); mode 0 or STDG_RESIDUAL

@@ -1,5 +1,6 @@
 // Dispatch of the residual kernels over the (a, q, affine) groups of a mesh.
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -54,8 +55,25 @@ STDG_DECL_ALL(affine_diss_, double)
 #undef STDG_DECL_ALL
 #undef STDG_DECL
 
+#define STDG_BDECL(R, AA) int launch_batch_##R##AA(int q, const BatchKParams<R>& B, uint32_t total, hipStream_t s);
+#define STDG_BDECL_ALL(R) STDG_BDECL(R, 2) STDG_BDECL(R, 3) STDG_BDECL(R, 4) STDG_BDECL(R, 5) STDG_BDECL(R, 6) \
+  STDG_BDECL(R, 7) STDG_BDECL(R, 8) STDG_BDECL(R, 9)
+STDG_BDECL_ALL(float)
+STDG_BDECL_ALL(double)
+#undef STDG_BDECL_ALL
+#undef STDG_BDECL
+
 template <typename T>
 using Launcher = int (*)(int, const KParams<T>&, int64_t, hipStream_t);
+template <typename T>
+using BatchLauncher = int (*)(int, const BatchKParams<T>&, uint32_t, hipStream_t);
+static BatchLauncher<float> batch_f32[kMaxA + 1] = {nullptr, nullptr, launch_batch_float2, launch_batch_float3,
+                                                    launch_batch_float4, launch_batch_float5, launch_batch_float6,
+                                                    launch_batch_float7, launch_batch_float8, launch_batch_float9};
+static BatchLauncher<double> batch_f64[kMaxA + 1] = {nullptr, nullptr, launch_batch_double2, launch_batch_double3,
+                                                     launch_batch_double4, launch_batch_double5, launch_batch_double6,
+                                                     launch_batch_double7, launch_batch_double8, launch_batch_double9};
+static_assert(kMaxApplyBatch >= 16, "batched applies hold the serving loop's batches");
 
 #define STDG_TABLE(K, R) \
   { nullptr, nullptr, launch_##K##R##2, launch_##K##R##3, launch_##K##R##4, launch_##K##R##5, \
@@ -134,6 +152,53 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
     }
   }
   return STDG_OK;
+}
+
+bool batchable_mesh(const Mesh* m) {
+  int groups = 0;
+  const Group* g0 = nullptr;
+  for (const Group& g : m->groups)
+    if (g.count > 0) {
+      ++groups;
+      g0 = &g;
+    }
+  return groups == 1 && g0->affine && m->n_diag == m->ne && m->d_diss == nullptr;
+}
+
+template <typename T>
+static int run_batch(const BatchApplyArgs* a, int count, hipStream_t s, BatchLauncher<T>* table) {
+  if (count < 1 || count > kMaxApplyBatch) return fail(STDG_E_ARG, "batched apply: 1 to 16 requests");
+  BatchKParams<T> B;
+  std::memset(&B, 0, sizeof(B));
+  const Group* g0 = nullptr;
+  uint64_t first = 0;
+  for (int i = 0; i < count; ++i) {
+    const Mesh* m = a[i].mesh;
+    if (!batchable_mesh(m)) return fail(STDG_E_ARG, "batched apply: mesh not batchable");
+    const Group* g = nullptr;
+    for (const Group& gg : m->groups)
+      if (gg.count > 0) g = &gg;
+    if (g0 && (g->a != g0->a || g->q != g0->q)) return fail(STDG_E_ARG, "batched apply: degrees differ");
+    g0 = g;
+    BatchMember<T>& M = B.m[i];
+    M.info = m->d_info;
+    M.metric = m->d_metric;
+    M.list = g->d_list;
+    M.x = (const T*)a[i].x;
+    M.y = (T*)a[i].y;
+    M.skip = a[i].skip;
+    M.dt = (T)a[i].dt;
+    M.first = (uint32_t)first;
+    first += (uint64_t)g->count;
+  }
+  if (first > 0xffffffffu) return fail(STDG_E_ARG, "batched apply: too many elements");
+  B.count = count;
+  if constexpr (sizeof(T) == 8) fill_tables_f64(&B.tab); else fill_tables_f32(&B.tab);
+  return table[g0->a](g0->q, B, (uint32_t)first, s);
+}
+
+int launch_residual_batch(const BatchApplyArgs* a, int count, int prec, hipStream_t s) {
+  return prec == STDG_FP64 ? run_batch<double>(a, count, s, batch_f64) : run_batch<float>(a, count, s, batch_f32);
 }
 
 int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s, const int* skip) {

@@ -108,4 +108,32 @@ int STDG_CAT(STDG_CAT(STDG_CAT(launch_, STDG_KIND), STDG_REAL), STDG_A)(int q, c
   return STDG_OK;
 }
 
+#if STDG_AFF && !STDG_DISS
+template <int QQ>
+static int launch_batch_q(const BatchKParams<STDG_REAL>& B, uint32_t total, hipStream_t stream) {
+  hipLaunchKernelGGL((residual_batch_kernel<STDG_REAL, STDG_A, QQ>), dim3(total), dim3(KCfg<STDG_A>::NT),
+                     (shmem_bytes<QQ, 2>()), stream, B);
+  return STDG_OK;
+}
+
+int STDG_CAT(STDG_CAT(launch_batch_, STDG_REAL), STDG_A)(int q, const BatchKParams<STDG_REAL>& B, uint32_t total,
+                                                        hipStream_t stream) {
+  int rc;
+  switch (q) {
+    case 1: rc = launch_batch_q<1>(B, total, stream); break;
+    case 2: rc = launch_batch_q<2>(B, total, stream); break;
+    case 3: rc = launch_batch_q<3>(B, total, stream); break;
+    case 4: rc = launch_batch_q<4>(B, total, stream); break;
+    case 5: rc = launch_batch_q<5>(B, total, stream); break;
+    case 6: rc = launch_batch_q<6>(B, total, stream); break;
+    default:
+      return fail(STDG_E_ARG, "q out of range");
+  }
+  if (rc != STDG_OK) return rc;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "batched residual kernel launch");
+  return STDG_OK;
+}
+#endif
+
 }  // namespace stdg

@@ -1005,6 +1005,66 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_kernel(KParams<T> P) {
   element_body<T, A, Q, MODE, AFF, DISS, VAR>(P, e, xr, sm, tid, lev);
 }
 
+// Batched preconditioned operator applies (mode 2) over the meshes of several
+// requests that share one affine (a, q) kernel group with a diagonal metric
+// and no D_h: the serving loop's restart cycles in lockstep.  Each request
+// takes a segment of the grid (its work list in order); the block-to-segment
+// lookup follows the same XCD-aware order as the plain kernel, and the
+// element body is the plain kernel's, so every output is bitwise the same.
+constexpr int kMaxApplyBatch = 16;
+template <typename T>
+struct BatchMember {
+  const ElemInfo* info;
+  const ElemMetric* metric;
+  const int32_t* list;
+  const T* x;
+  T* y;
+  const int* skip;  // device flag: 0 = this request's cycle has ended
+  T dt;
+  uint32_t first;   // the request's first logical block
+};
+template <typename T>
+struct BatchKParams {
+  BatchMember<T> m[kMaxApplyBatch];
+  int count;
+  Tables<T> tab;
+};
+
+template <typename T, int A, int Q>
+__global__ void __launch_bounds__(KCfg<A>::NT) residual_batch_kernel(BatchKParams<T> B) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x;
+  const uint32_t nblk = gridDim.x, b = blockIdx.x;
+  const uint32_t xcd = b & 7u, idx = b >> 3;
+  const uint32_t qq = nblk >> 3, rr = nblk & 7u;
+  const uint32_t logical = xcd * qq + (xcd < rr ? xcd : rr) + idx;
+  int mi = 0;
+  for (int k = 1; k < B.count; ++k)
+    if (logical >= B.m[k].first) mi = k;
+  const BatchMember<T>& M = B.m[mi];
+  if (M.skip && *M.skip == 0) return;  // uniform: that request's restart cycle has ended
+  KParams<T> P;
+  P.info = M.info;
+  P.metric = M.metric;
+  P.list = M.list;
+  P.x = M.x;
+  P.load = nullptr;
+  P.y = M.y;
+  P.verts = nullptr;
+  P.qt = nullptr;
+  P.diss = nullptr;
+  P.skip = M.skip;
+  P.dt = M.dt;
+  P.mode = 2;
+  P.variant = 0;
+  P.tab = B.tab;
+  const int e = P.list[logical - M.first];
+  T xr[6][Q + 1];
+  load_own<T, A, Q, 2>(P, e, tid, xr);
+  element_body<T, A, Q, 2, true, false, 0>(P, e, xr, sm, tid, -1);
+}
+
 // P^{-1} applied blockwise (3x3 per spatial mode and level), for meshes whose
 // metric is not diagonal: z = P^{-1} x on the unknowns layout.
 template <typename T>

@@ -73,6 +73,7 @@ struct Active {
   bool finishing = false;
   hipEvent_t done_ev = nullptr;
   double eta2 = 0.0;  // accumulated iteration-error bound (inexact solves)
+  double pend_since = -1.0;  // server clock when its pending restart cycle was left for a batch
   Finished out;
 };
 
@@ -136,6 +137,11 @@ struct Server {
   std::atomic<bool> stop{false};
   std::vector<Active*> active;  // server thread only
   std::thread th;
+  // batched restart cycles: streams (round-robin) and their events
+  static constexpr int kBatchStreams = 4;
+  hipStream_t bstream[kBatchStreams] = {};
+  hipEvent_t bev[kBatchStreams] = {};
+  int bnext = 0;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t_start).count(); }
   void run();
@@ -144,6 +150,7 @@ struct Server {
   int start_slab(Active* a);
   int step(Active* a, bool* finished_now);
   void retire(Active* a, int status);
+  void launch_pending_cycles();
 };
 
 namespace {
@@ -208,6 +215,7 @@ int Server::start(Active* a) {
     if (!(ro.eta_tol > 0.0)) ro.eta_tol = 0.0;  // zero field: solve to rtol
   }
   if ((rc = a->solver.init(&m, ro, a->stream)) != STDG_OK) return rc;
+  a->solver.set_defer_cycles(true);  // launched by launch_pending_cycles, alone or batched
   a->solver_ready = true;
   return start_slab(a);
 }
@@ -242,6 +250,7 @@ int Server::step(Active* a, bool* finished_now) {
   if (a->solver.status != STDG_OK) res.status = a->solver.status;
   res.slabs_done = ++a->slab;
   if (a->slab < a->rq->n_slabs) return start_slab(a);
+  res.batched_cycles = a->solver.batched_cycles;
   // final state to the host, then done
   a->out.state.resize((size_t)a->rq->n_state);
   STDG_HIP(hipMemcpyAsync(a->out.state.data(), a->state, sizeof(double) * a->rq->n_state, hipMemcpyDeviceToHost,
@@ -253,6 +262,9 @@ int Server::step(Active* a, bool* finished_now) {
 
 void Server::retire(Active* a, int status) {
   if (a->stream) (void)hipStreamSynchronize(a->stream);
+  if (status != STDG_OK)  // a batched cycle may still reach its vectors
+    for (int k = 0; k < kBatchStreams; ++k)
+      if (bstream[k]) (void)hipStreamSynchronize(bstream[k]);
   if (status != STDG_OK) {
     a->out.res.status = status;
     a->out.state.clear();
@@ -300,6 +312,69 @@ bool Server::admit_one() {
   return true;
 }
 
+// Restart cycles left pending by this tick's steps.  Requests that can share
+// batched cycles (same batch key) are launched together, up to kMaxBatch per
+// launch sequence; a pending cycle waits up to kBatchWait seconds while other
+// requests of its key still have a step in flight (their true residuals end
+// moments later), so that batches re-form after every cycle.  Everything
+// else runs alone.
+void Server::launch_pending_cycles() {
+  constexpr double kBatchWait = 0.5e-3;
+  const double t = now();
+  std::map<int, std::vector<Active*>> by_key;
+  std::vector<std::pair<Active*, int>> failed;
+  std::map<int, int> in_flight;  // per key: requests with a step in flight
+  for (Active* a : active) {
+    if (a->finishing || !a->solver_ready) continue;
+    const int key = opts.batch_cycles ? a->solver.batch_key() : -1;
+    if (a->solver.cycle_pending()) {
+      if (a->pend_since < 0.0) a->pend_since = t;
+      if (key < 0) {
+        int rc = a->solver.launch_pending_cycle();
+        a->pend_since = -1.0;
+        if (rc != STDG_OK) failed.push_back({a, rc});
+      } else {
+        by_key[key].push_back(a);
+      }
+    } else if (key >= 0) {
+      in_flight[key] += 1;
+    }
+  }
+  for (auto& kv : by_key) {
+    std::vector<Active*>& v = kv.second;
+    double oldest = t;
+    for (Active* a : v) oldest = std::min(oldest, a->pend_since);
+    // hold for partners still in flight (bounded wait)
+    if (in_flight[kv.first] > 0 && (int)v.size() < kMaxBatch && t - oldest < kBatchWait) continue;
+    for (size_t i0 = 0; i0 < v.size(); i0 += kMaxBatch) {
+      const int n = (int)std::min<size_t>(kMaxBatch, v.size() - i0);
+      int rc = STDG_OK;
+      if (n == 1) {
+        rc = v[i0]->solver.launch_pending_cycle();
+      } else {
+        if (!bstream[bnext]) {
+          if (hipStreamCreateWithFlags(&bstream[bnext], hipStreamNonBlocking) != hipSuccess ||
+              hipEventCreateWithFlags(&bev[bnext], hipEventDisableTiming) != hipSuccess)
+            rc = fail(STDG_E_DEVICE, "serve: cannot create a batch stream");
+        }
+        SlabSolver* ss[kMaxBatch];
+        for (int k = 0; k < n; ++k) ss[k] = &v[i0 + k]->solver;
+        if (rc == STDG_OK) rc = SlabSolver::launch_cycles_batched(ss, n, bstream[bnext], bev[bnext]);
+        bnext = (bnext + 1) % kBatchStreams;
+      }
+      for (int k = 0; k < n; ++k) {
+        v[i0 + k]->pend_since = -1.0;
+        if (rc != STDG_OK) failed.push_back({v[i0 + k], rc});
+      }
+    }
+  }
+  for (auto& f : failed) {
+    auto it = std::find(active.begin(), active.end(), f.first);
+    if (it != active.end()) active.erase(it);
+    retire(f.first, f.second);
+  }
+}
+
 void Server::run() {
   (void)hipSetDevice(ctx->device);
   while (!stop.load()) {
@@ -307,6 +382,10 @@ void Server::run() {
     while (admit_one()) progressed = true;
     for (size_t i = 0; i < active.size();) {
       Active* a = active[i];
+      if (!a->finishing && a->solver_ready && a->solver.cycle_pending()) {
+        ++i;  // no step in flight: its cycle waits for launch_pending_cycles
+        continue;
+      }
       hipError_t e = hipEventQuery(a->finishing ? a->done_ev : a->solver.event());
       if (e == hipErrorNotReady) {
         ++i;
@@ -323,6 +402,7 @@ void Server::run() {
       }
       ++i;
     }
+    launch_pending_cycles();
     if (!progressed) {
       if (active.empty()) {
         std::unique_lock<std::mutex> lk(mu);
@@ -334,6 +414,13 @@ void Server::run() {
   }
   for (Active* a : active) retire(a, STDG_E_CANCELLED);
   active.clear();
+  for (int k = 0; k < kBatchStreams; ++k) {
+    if (bstream[k]) (void)hipStreamSynchronize(bstream[k]);
+    if (bstream[k]) (void)hipStreamDestroy(bstream[k]);
+    if (bev[k]) (void)hipEventDestroy(bev[k]);
+    bstream[k] = nullptr;
+    bev[k] = nullptr;
+  }
   std::lock_guard<std::mutex> lk(mu);
   for (Request* r : pending) {
     finished[r->ticket].res.status = STDG_E_CANCELLED;

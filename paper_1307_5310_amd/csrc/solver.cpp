@@ -247,6 +247,87 @@ int SlabSolver::enqueue_cycle() {
 }
 
 int SlabSolver::launch_cycle() {
+  int rc = prepare_cycle();
+  if (rc != STDG_OK) return rc;
+  if (defer_) {
+    phase_ = kWantCycle;
+    return STDG_OK;
+  }
+  return run_cycle();
+}
+
+int SlabSolver::launch_pending_cycle() {
+  if (phase_ != kWantCycle) return fail(STDG_E_ARG, "slab solver: no restart cycle pending");
+  return run_cycle();
+}
+
+int SlabSolver::batch_key() const {
+  if (!o_.f32 || !batchable_mesh(m_)) return -1;
+  for (const Group& g : m_->groups)
+    if (g.count > 0) return ((g.a * 8 + g.q) * 2 + (o_.v32 ? 1 : 0)) * 64 + o_.restart;
+  return -1;
+}
+
+int SlabSolver::launch_cycles_batched(SlabSolver* const* S, int count, hipStream_t bs, hipEvent_t bev) {
+  if (count < 1 || count > kMaxBatch) return fail(STDG_E_ARG, "batched cycles: 1 to kMaxBatch solvers");
+  const int key = S[0]->batch_key();
+  for (int i = 0; i < count; ++i)
+    if (!S[i]->cycle_pending() || key < 0 || S[i]->batch_key() != key)
+      return fail(STDG_E_ARG, "batched cycles: solvers not pending or not of one batch key");
+  const SlabOpts& o = S[0]->o_;
+  const bool f32 = o.f32, v32 = o.v32;
+  CycleSeg seg[kMaxBatch];
+  BatchApplyArgs app[kMaxBatch];
+  for (int i = 0; i < count; ++i) {
+    SlabSolver& t = *S[i];
+    // the solver's previous step has completed (its event was seen): the wait is for order only
+    STDG_HIP(hipStreamWaitEvent(bs, t.ev_, 0));
+    STDG_HIP(hipMemcpyAsync(t.ctl_, t.hctl_, kCtlParams, hipMemcpyHostToDevice, bs));
+    CycleSeg& c = seg[i];
+    c.V = t.V_;
+    c.ldv = t.ld_;
+    c.z = t.z_;
+    c.w = t.w_;
+    c.w32 = (f32 && !v32) ? t.w32_ : nullptr;
+    c.r = v32 ? t.r_ : (const double*)t.basis(0);
+    c.norm2 = t.hv_ + kBeta;
+    c.out = t.d_;
+    c.n = t.n_;
+    c.ctl = t.ctl_;
+    c.dw = t.dw_;
+    app[i] = BatchApplyArgs{t.m_, t.dt_, nullptr, t.z_, &t.ctl_->active};
+  }
+  // the steps of enqueue_cycle, each one launch for all solvers
+  int rc;
+  if ((rc = cycle_start_batch(seg, count, v32, bs)) != STDG_OK) return rc;
+  for (int j = 0; j < o.restart; ++j) {
+    for (int i = 0; i < count; ++i) {
+      SlabSolver& t = *S[i];
+      app[i].x = (f32 && !v32) ? (const void*)t.w32_ : (j == 0 ? t.basis(0) : (const void*)t.w_);
+    }
+    if ((rc = launch_residual_batch(app, count, f32 ? STDG_FP32 : STDG_FP64, bs)) != STDG_OK) return rc;
+    if ((rc = arnoldi_pass1_batch(seg, count, v32, f32, j, bs)) != STDG_OK) return rc;
+    if ((rc = arnoldi_pass2_batch(seg, count, v32, f32, j, bs)) != STDG_OK) return rc;
+  }
+  if ((rc = cycle_least_squares_batch(seg, count, bs)) != STDG_OK) return rc;
+  if ((rc = basis_combine_batch(seg, count, v32, o.restart, bs)) != STDG_OK) return rc;
+  for (int i = 0; i < count; ++i) {
+    SlabSolver& t = *S[i];
+    if ((rc = launch_precond_scale(t.m_, STDG_FP64, t.d_, t.pd_, bs)) != STDG_OK) return rc;
+    if ((rc = blas_axpy(t.x_, t.pd_, 1.0, t.n_, bs)) != STDG_OK) return rc;
+  }
+  STDG_HIP(hipEventRecord(bev, bs));
+  for (int i = 0; i < count; ++i) {
+    SlabSolver& t = *S[i];
+    STDG_HIP(hipStreamWaitEvent(t.s_, bev, 0));
+    if ((rc = t.launch_true_residual()) != STDG_OK) return rc;
+    t.phase_ = kWaitCycle;
+    t.batched_cycles += 1;
+  }
+  return STDG_OK;
+}
+
+int SlabSolver::prepare_cycle() {
   ++cycles_;
   // the inner target: rtol of the initial residual (FP64 applies), or for
   // FP32 applies inner_rtol of this cycle's residual, but never below the
@@ -264,6 +345,10 @@ int SlabSolver::launch_cycle() {
   hctl_->target = inner;
   hctl_->restart = o_.restart;
   hctl_->max_iters = o_.max_iters;
+  return STDG_OK;
+}
+
+int SlabSolver::run_cycle() {
   STDG_HIP(hipMemcpyAsync(ctl_, hctl_, kCtlParams, hipMemcpyHostToDevice, s_));
   int rc;
   // the whole cycle as one captured graph, from the second cycle on (the first

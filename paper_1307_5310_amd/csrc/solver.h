@@ -52,6 +52,32 @@ int cycle_least_squares(CycleCtl* ctl, hipStream_t st);
 int basis_combine(double* out, const void* V, bool v32, int64_t ld, int k, const int* kdev, const double* coef,
                   int64_t n, hipStream_t st);
 int vec_dot(const double* a, const double* b, int64_t n, double* out, const DotWork& dw, hipStream_t st);
+
+// Batched cycle kernels: the restart cycles of up to kMaxBatch requests (the
+// serving loop), one launch per step, each request on a segment of the grid
+// with the block partition of its own unbatched launch (so that its
+// reductions, and every result, are bitwise those of a solve alone).  All
+// requests of a batch run the same iteration with the same precisions.
+constexpr int kMaxBatch = 16;
+struct CycleSeg {
+  void* V = nullptr;             // basis (slot 0 is the start vector)
+  int64_t ldv = 0;
+  const void* z = nullptr;       // apply output
+  void* w = nullptr;             // pending vector
+  float* w32 = nullptr;          // FP32 copy of the apply input (FP32 applies, FP64 basis)
+  const double* r = nullptr;     // cycle start: residual (FP64) and its squared norm
+  const double* norm2 = nullptr;
+  double* out = nullptr;         // cycle end: out = sum_l y_l V_l
+  int64_t n = 0;
+  CycleCtl* ctl = nullptr;
+  DotWork dw;
+};
+int cycle_start_batch(const CycleSeg* segs, int count, bool v32, hipStream_t st);
+int arnoldi_pass1_batch(const CycleSeg* segs, int count, bool v32, bool z32, int j, hipStream_t st);
+int arnoldi_pass2_batch(const CycleSeg* segs, int count, bool v32, bool z32, int j, hipStream_t st);
+int cycle_least_squares_batch(const CycleSeg* segs, int count, hipStream_t st);
+// out = sum_{l < ctl->k} ctl->y[l] V_l for each request (k <= kmax)
+int basis_combine_batch(const CycleSeg* segs, int count, bool v32, int kmax, hipStream_t st);
 int vec_store(void* out, bool out32, const double* in, int64_t n, hipStream_t st);
 
 int blas_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
@@ -98,6 +124,24 @@ class SlabSolver {
   // call once event() has completed; *done = true when the slab is finished
   int advance(bool* done);
 
+  // Deferred cycles (the serving loop): advance() does not enqueue a restart
+  // cycle itself but leaves it pending (cycle_pending()); the caller then
+  // launches it alone (launch_pending_cycle) or together with the pending
+  // cycles of other solvers of the same batch_key() (launch_cycles_batched),
+  // before it next polls event().
+  void set_defer_cycles(bool d) { defer_ = d; }
+  bool cycle_pending() const { return phase_ == kWantCycle; }
+  // key of the batched cycles this solver can join (the kernel group's a and q
+  // with the precisions), or -1: FP32 applies on a mesh of one affine kernel
+  // group with a diagonal metric and no D_h
+  int batch_key() const;
+  int launch_pending_cycle();
+  // one restart cycle of each of the count solvers (pending, same batch_key)
+  // on stream bs, one launch per step for all; then each solver's true
+  // residual on its own stream after event bev
+  static int launch_cycles_batched(SlabSolver* const* s, int count, hipStream_t bs, hipEvent_t bev);
+  int batched_cycles = 0;  // restart cycles run in a batch (of this solver's life)
+
   // results of the finished slab
   int status = 0;  // STDG_OK or STDG_E_NOT_CONVERGED
   int iters = 0, refinements = 0;
@@ -105,9 +149,12 @@ class SlabSolver {
   double eta2 = 0.0;  // the slab's term of eta_it^2 at the final iterate (inexact solve only)
 
  private:
-  enum Phase { kIdle, kWaitStart, kWaitCycle, kWaitEnd };
+  enum Phase { kIdle, kWaitStart, kWaitCycle, kWaitEnd, kWantCycle };
   int launch_true_residual();
   int launch_cycle();
+  int prepare_cycle();  // the cycle count, inner target and control parameters (host)
+  int run_cycle();      // the prepared cycle (graph or direct), then the true residual
+  bool defer_ = false;
   int enqueue_cycle();  // the cycle's kernels, from the start vector to the updated iterate
   int launch_slab_end();
 

@@ -127,3 +127,13 @@ def test_register_bound_policy():
     # every kernel outside the residual instantiations is strict
     with pytest.raises(B.ResourceError):
         B.check_resources({"_ZN4stdg12_GLOBAL__N_112pass2_kernelIdddLi16EEEv": scratch})
+
+
+def test_register_bound_policy_batched_applies():
+    scratch = {"AGPRs": 0, "ScratchSize [bytes/lane]": 64, "VGPRs Spill": 10, "SGPRs Spill": 0}
+    # the batched apply is an affine operator-mode kernel: FP64 a = 9, q >= 3 may spill, FP32 never
+    B.check_resources({"_ZN4stdg21residual_batch_kernelIdLi9ELi4EEEvNS_12BatchKParamsIT_EE": scratch})
+    for name in ("_ZN4stdg21residual_batch_kernelIfLi9ELi4EEEvNS_12BatchKParamsIT_EE",
+                 "_ZN4stdg21residual_batch_kernelIdLi5ELi3EEEvNS_12BatchKParamsIT_EE"):
+        with pytest.raises(B.ResourceError):
+            B.check_resources({name: scratch})

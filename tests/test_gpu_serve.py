@@ -3,7 +3,8 @@ marched slab by slab (Section 2.2), admitted by device footprint and run
 concurrently.
 
 * each request's result is bitwise the same alone, in a mix, and as the plain
-  stdg_slab_solve march of the same slabs;
+  stdg_slab_solve march of the same slabs, also when requests of one kernel
+  group run their restart cycles batched;
 * a small request matches the oracle's direct slab solves to 1e-10;
 * admission waits for memory; invalid requests are refused at submit, a
   failing request reports through its result without disturbing the others;
@@ -92,6 +93,37 @@ def test_serve_matches_slab_solve_alone_and_in_mix(lib, krylov, graph):
     note("serve: plain march of request 3")
     ref = _march(lib, reqs[3], **opts)
     assert np.array_equal(ref, mix[3]["state"])
+
+
+@pytest.mark.parametrize("krylov", [0, 1])
+def test_batched_cycles_bitwise(lib, krylov):
+    """A burst of requests of two kernel groups ((p, q) = (2, 1) and (3, 2)
+    cavities with their own materials and fields): with batched restart
+    cycles the requests of one group share launches (batched_cycles > 0), and
+    every final state is bitwise the one of the same server without batching
+    and of the plain march."""
+    stdg = lib.stdg
+    opts = dict(OPTS, krylov_prec=krylov)
+    reqs = _small_stream(12, sizes=(4, 6), degrees=(2, 3), n_slabs=2)
+    sizes = [r["mesh"].state_size() for r in reqs]
+    out = {}
+    for batch in (True, False):
+        note("serve: burst of 12, batch_cycles=%s krylov=%d" % (batch, krylov))
+        srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 30, max_active=12, batch_cycles=batch, **opts)
+        try:
+            out[batch] = _wait(stdg, srv, [_submit(stdg, srv, r) for r in reqs], sizes)
+        finally:
+            stdg.stdg_serve_stop(srv)
+    for r in out[True] + out[False]:
+        assert r["status"] == 0, r
+    assert sum(r["batched_cycles"] for r in out[True]) > 0
+    assert all(r["batched_cycles"] == 0 for r in out[False])
+    for a, b in zip(out[True], out[False]):
+        assert np.array_equal(a["state"], b["state"])
+        assert a["iters"] == b["iters"]
+    k = int(np.argmax([r["batched_cycles"] for r in out[True]]))
+    note("serve: plain march of request %d (%d batched cycles)" % (k, out[True][k]["batched_cycles"]))
+    assert np.array_equal(_march(lib, reqs[k], **opts), out[True][k]["state"])
 
 
 def test_serve_matches_oracle(lib):
@@ -224,28 +256,29 @@ def test_inexact_serving_within_eta(lib):
 
 
 def test_serving_with_dissipation(lib):
-    """A request with the dissipative stabilisation D_h (remark closing
-    Section 4): bitwise the plain march with stdg_mesh_set_dissipation, the
-    energy drops, and a trilinear mesh is refused at submit."""
+    """Requests with the dissipative stabilisation D_h (remark closing
+    Section 4), on an affine and on a trilinear mesh: bitwise the plain march
+    with stdg_mesh_set_dissipation, and the energy drops."""
     stdg = lib.stdg
     rq = _small_stream(1, sizes=(4,), degrees=(3,), n_slabs=3)[0]
     m = rq["mesh"]
     c = 0.6
+    v, h = synth.box_mesh((2, 2, 2))
+    v = synth.perturb_interior(v, (2, 2, 2), 0.1, seed=3)
+    tri = synth.Mesh(v, h, np.full(8, 2, np.int32), np.full(8, 1, np.int32), np.ones(8), np.ones(8))
+    init = np.random.default_rng(3).standard_normal(tri.state_size())
     srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 28, **OPTS)
     try:
         t = stdg.stdg_serve_submit(srv, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu, 0.0, rq["dt"], rq["n_slabs"],
                                    mnl=rq["init"].mnl, abc=rq["init"].abc, c_diss=c)
-        r = _wait(stdg, srv, [t], [m.state_size()])[0]
-        v, h = synth.box_mesh((2, 2, 2))
-        v = synth.perturb_interior(v, (2, 2, 2), 0.1, seed=3)
-        with pytest.raises(stdg.StdgError) as ei:
-            stdg.stdg_serve_submit(srv, v, h, np.full(8, 2), np.full(8, 1), np.ones(8), np.ones(8), 0.0, 0.05, 1,
-                                   init_state=np.ones(8 * 6 * 27), c_diss=c)
-        assert ei.value.status == -2
+        t2 = stdg.stdg_serve_submit(srv, tri.vertices, tri.hexes, tri.p, tri.q, tri.eps, tri.mu, 0.0, 0.05, 2,
+                                    init_state=init, c_diss=c)
+        r, r2 = _wait(stdg, srv, [t, t2], [m.state_size(), tri.state_size()])
     finally:
         stdg.stdg_serve_stop(srv)
-    assert r["status"] == 0
-    assert r["energy_end"] < r["energy_start"]
+    for x in (r, r2):
+        assert x["status"] == 0
+        assert x["energy_end"] < x["energy_start"]
     mh = lib.upload(m)
     try:
         stdg.stdg_mesh_set_dissipation(mh, c)
@@ -257,6 +290,16 @@ def test_serving_with_dissipation(lib):
     finally:
         stdg.stdg_mesh_free(mh)
     assert np.array_equal(ref, r["state"])
+    mh = lib.upload(tri)
+    try:
+        stdg.stdg_mesh_set_dissipation(mh, c)
+        st = lib.dev(init, lib.torch.float64)
+        for n in range(2):
+            assert stdg.stdg_slab_solve(mh, n * 0.05, 0.05, None, st, **OPTS)["status"] == 0
+        ref2 = st.cpu().numpy()
+    finally:
+        stdg.stdg_mesh_free(mh)
+    assert np.array_equal(ref2, r2["state"])
 
 
 def test_serving_trilinear_with_source(lib):
