@@ -11,7 +11,9 @@ integrated in physical space-time with
 * physical face normals and surface measures from the tangent vectors of the
   trilinear map, oriented away from the element;
 * neighbour traces at the same physical points, found by Newton inversion of
-  the neighbour's map; faces are matched by physical centroid;
+  the neighbour's map; faces are matched by physical centroid (2:1
+  hanging faces by their quarter centroids, the coarse face integrated
+  quarter by quarter);
 * the average / tangential-jump operators of Section 2.4 and the terms of
   C_h (eq. bilinearform:C), S_h (eq. bilinearform:S) and the dissipative D_h
   (the remark after Section 4) as written, with the temporal L2 projection
@@ -221,17 +223,55 @@ def assemble(vertices, hexes, p, q, eps, mu, dt, nvol_extra=2, nface_extra=2, nt
         for f in range(6):
             where.setdefault(fkey(e, f), []).append((e, f))
 
+    # 2:1 hanging faces, matched by physical centroids as well: a face whose
+    # four quarter centroids are centroids of four other faces is the coarse
+    # side; a face whose centroid is a quarter centroid of another face is a
+    # fine side
+    def quarter_keys(e, f):
+        out = []
+        for iv in range(2):
+            for iu in range(2):
+                xh, _ = _face_param(f, np.array([[(iu + 0.5) / 2, (iv + 0.5) / 2]]))
+                x, _, _ = els[e].geometry(xh)
+                out.append(((0.5 * iu, 0.5 * iv), tuple(np.round(x[0], 10))))
+        return out
+
+    quarter_of = {}
+    for e in range(ne):
+        for f in range(6):
+            for sub, key in quarter_keys(e, f):
+                quarter_of.setdefault(key, []).append((e, f))
+
+    def pieces(e, f):
+        """(neighbour or -1, own-face sub-square origin or None) pieces of face f of e"""
+        partners = [(k, g) for (k, g) in where[fkey(e, f)] if (k, g) != (e, f)]
+        if partners:
+            return [(partners[0][0], None)]
+        quarters = []
+        for sub, key in quarter_keys(e, f):
+            fine = [(k, g) for (k, g) in where.get(key, []) if k != e]
+            if len(fine) == 1:
+                quarters.append((fine[0][0], sub))
+        if len(quarters) == 4:
+            return quarters
+        coarse = [(k, g) for (k, g) in quarter_of.get(fkey(e, f), []) if k != e]
+        if len(coarse) == 1:
+            return [(coarse[0][0], None)]
+        return [(-1, None)]
+
     for e in range(ne):
         el = els[e]
         for f in range(6):
-            partners = [(k, g) for (k, g) in where[fkey(e, f)] if (k, g) != (e, f)]
-            k = partners[0][0] if partners else -1
+          for k, sub in pieces(e, f):
             nf = max(int(a[e]), int(a[k]) if k >= 0 else 0) + nface_extra
             g1, w1 = _gauss(nf)
             V, U = np.meshgrid(g1, g1, indexing="ij")
             WV, WU = np.meshgrid(w1, w1, indexing="ij")
             uv = np.stack([U.ravel(), V.ravel()], 1)
             wuv = (WU * WV).ravel()
+            if sub is not None:
+                uv = np.asarray(sub)[None, :] + 0.5 * uv
+                wuv = 0.25 * wuv
             xh, tang = _face_param(f, uv)
             x, DF, _ = el.geometry(xh)
             tu, tv = DF[:, :, tang[0]], DF[:, :, tang[1]]

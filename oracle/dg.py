@@ -43,7 +43,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import basis
-from .geometry import face_map, face_topology, jacobian, map_point
+from .geometry import face_map, face_topology, hanging_faces, jacobian, map_point
 
 LEVI = np.zeros((3, 3, 3))
 LEVI[0, 1, 2] = LEVI[1, 2, 0] = LEVI[2, 0, 1] = 1.0
@@ -176,20 +176,30 @@ def face_matrices(a, face, a_other=None, neighbour=False):
     return FE.reshape(3 * n3, 3 * m3), FH.reshape(3 * n3, 3 * m3)
 
 
-def face_matrices_oriented(a, face, ao, face_o, A, b):
+def face_matrices_oriented(a, face, ao, face_o, A, b, sub=None):
     """The neighbour face matrices of ``face_matrices`` for a neighbour met in
     any orientation: its basis is evaluated on its own face ``face_o`` at the
     points (u', v') = A (u, v) + b matched to K's face points, and its
     covariant reference components are carried into K's frame along the
     face, E-hat_{tau_i} = sum_j A[j, i] E-hat'_{tau'_j} (chain rule for the
     tangent vectors of the shared face; the normal components do not enter
-    the fluxes).  Geometry-free like the canonical case; exact quadrature."""
+    the fluxes).  Geometry-free like the canonical case; exact quadrature.
+
+    ``sub = (u0, v0)`` restricts the integral to the quarter
+    [u0, u0 + 1/2] x [v0, v0 + 1/2] of K's face (a 2:1 hanging face seen
+    from the coarse side, the neighbour covering that quarter; then A holds
+    2 times a signed permutation, and 1/2 times one seen from the fine side)."""
     alpha, side = divmod(face, 2)
     tang = [d for d in range(3) if d != alpha]
     alpha_o, side_o = divmod(face_o, 2)
     tang_o = [d for d in range(3) if d != alpha_o]
     n = max(a, ao) + 1
     pts, w = face_points(face, n)
+    if sub is not None:
+        pts = pts.copy()
+        pts[:, tang[0]] = sub[0] + 0.5 * pts[:, tang[0]]
+        pts[:, tang[1]] = sub[1] + 0.5 * pts[:, tang[1]]
+        w = 0.25 * w
     Phi, _ = basis_at(a, pts)
     uv = pts[:, tang]
     uvo = uv @ A.T + b[None, :]
@@ -297,8 +307,16 @@ class Discretisation:
             for f in range(6):
                 if self.nb[e, f] >= 0 and not self.canon[e, f]:
                     self.fmap[(e, f)] = face_map(self.hexes[e], f, self.hexes[self.nb[e, f]], int(self.nbf[e, f]))
+        # 2:1 hanging faces (four neighbours on a coarse face, one coarse
+        # neighbour on each fine face): interior faces without a conforming partner
+        self.hang = hanging_faces(self.vertices, self.hexes, self.nb)
+        self.interior = self.nb >= 0
+        for (e, f) in self.hang:
+            self.interior[e, f] = True
         self.mass_nq = mass_nq
         self.c_diss = float(c_diss)  # dissipative stabilisation D_h, c >= 0 (0 = off)
+        if self.c_diss > 0.0 and self.hang:
+            raise ValueError("D_h on meshes with hanging faces is not supported")
         a3 = self.a ** 3
         self.trial_size = 6 * (self.q + 1) * a3
         self.unk_size = 6 * self.q * a3
@@ -347,7 +365,7 @@ class Discretisation:
         """(SE, SH): E-rows/H-cols and H-rows/E-cols spatial matrices of the
         diagonal block: -C^T + sum_f w_f FE_self and C + sum_f w_f FH_self with
         w_f = 1/2 on interior faces and 1 on boundary faces."""
-        key = ("S", int(self.a[e]), tuple(self.nb[e] >= 0))
+        key = ("S", int(self.a[e]), tuple(self.interior[e]))
         if key not in self._cache:
             a = int(self.a[e])
             C = self.curl(a)
@@ -355,7 +373,7 @@ class Discretisation:
             SH = C.copy()
             for f in range(6):
                 FE, FH = self.face(a, f)
-                wgt = 0.5 if self.nb[e, f] >= 0 else 1.0
+                wgt = 0.5 if self.interior[e, f] else 1.0
                 SE += wgt * FE
                 SH += wgt * FH
             self._cache[key] = (SE, SH)
@@ -375,6 +393,19 @@ class Discretisation:
                (e, dt * N, SH, 1, 0),
                (e, D, self.mass(e, "mu"), 1, 1)]
         for f in range(6):
+            for (k, fk, A, b, sub) in self.hang.get((e, f), ()):
+                # a 2:1 hanging face: each neighbour couples over its part of the face
+                qk, ak = int(self.q[k]), int(self.a[k])
+                _, Nc = self.tables(qe, qk)
+                Nc = Nc.copy()
+                Nc[min(qe, qk):, :] = 0.0
+                key = ("FH", a, f, ak, int(fk), tuple(np.ravel(A)), tuple(np.ravel(b)), sub)
+                if key not in self._cache:
+                    self._cache[key] = face_matrices_oriented(a, f, ak, int(fk), np.asarray(A, float),
+                                                              np.asarray(b, float), sub)
+                FE, FH = self._cache[key]
+                out.append((k, dt * Nc, 0.5 * FE, 0, 1))
+                out.append((k, dt * Nc, -0.5 * FH, 1, 0))
             k = int(self.nb[e, f])
             if k < 0:
                 continue
@@ -718,7 +749,9 @@ class Discretisation:
     def spatial_operators(self):
         """(M, K) of the semi-discrete system M u' + K u = 0 on states
         [field][comp][s]: M = blockdiag(M_eps, M_mu) and K the curl + centred
-        flux operator (uniform q only)."""
+        flux operator (uniform q only; conforming faces)."""
+        if self.hang:
+            raise ValueError("spatial_operators: hanging faces are not supported")
         n = int(self.state_off[-1])
         M = np.zeros((n, n))
         K = np.zeros((n, n))

@@ -133,3 +133,78 @@ def is_affine(X, tol=1e-12):
     pred = x0[None, :] + CORNERS @ A.T
     scale = max(1.0, np.abs(X).max())
     return bool(np.abs(pred - X).max() <= tol * scale)
+
+
+def hanging_faces(vertices, hexes, nb, tol=1e-9):
+    """2:1 nonconforming faces (Section 5.2 sums the flux terms of a face over
+    the neighbours that share parts of it): a face without a conforming
+    partner whose four quarters are whole faces of four other elements.
+
+    The quarter corners are mesh vertices at the face's corners, edge
+    midpoints and centre (the bilinear face map at (i/2, j/2)); a quarter
+    matches the face of another element with the same four vertex ids.
+    Returns a dict keyed by (element, local face) with, for the coarse side,
+    four entries (k, f_k, A, b, (u0, v0)): own face coordinates (u, v) in the
+    quarter [u0, u0 + 1/2] x [v0, v0 + 1/2] map to the fine face's by
+    (u', v') = A (u, v) + b (A = 2 times a signed permutation); and for each
+    fine side one entry (k, f_k, A, b, None): its whole face maps into the
+    coarse face by (u', v') = A (u, v) + b (A = 1/2 times a signed
+    permutation).  Faces with a conforming partner (nb >= 0) are skipped."""
+    vertices = np.asarray(vertices, dtype=np.float64)
+    scale = max(1.0, float(np.abs(vertices).max()))
+    key_of = lambda x: tuple(np.round(np.asarray(x) / (tol * scale)).astype(np.int64))
+    vid = {}
+    for i, x in enumerate(vertices):
+        vid.setdefault(key_of(x), i)
+    ne = hexes.shape[0]
+    free = {}
+    for e in range(ne):
+        for f in range(6):
+            if nb[e, f] < 0:
+                free[tuple(sorted(face_vertices(hexes[e], f)))] = (e, f)
+    out = {}
+    for e in range(ne):
+        for f in range(6):
+            if nb[e, f] >= 0:
+                continue
+            ids = face_vertices(hexes[e], f)                 # (0,0), (1,0), (0,1), (1,1) in (u, v)
+            P = vertices[ids]
+            grid = {}
+            ok = True
+            for i in range(3):
+                for j in range(3):
+                    s, t = 0.5 * i, 0.5 * j
+                    x = (1 - s) * (1 - t) * P[0] + s * (1 - t) * P[1] + (1 - s) * t * P[2] + s * t * P[3]
+                    g = vid.get(key_of(x))
+                    if g is None:
+                        ok = False
+                        break
+                    grid[(i, j)] = g
+                if not ok:
+                    break
+            if not ok:
+                continue
+            where = {g: np.array([0.5 * i, 0.5 * j]) for (i, j), g in grid.items()}
+            quarters = []
+            for iv in range(2):
+                for iu in range(2):
+                    qids = tuple(sorted(grid[(iu + du, iv + dv)] for du in (0, 1) for dv in (0, 1)))
+                    if qids not in free:
+                        break
+                    quarters.append(((iu, iv), free[qids]))
+            if len(quarters) != 4:
+                continue
+            entries = []
+            for (iu, iv), (k, fk) in quarters:
+                fine = face_vertices(hexes[k], fk)
+                p00, p10, p01, p11 = (where[g] for g in fine)
+                Af = np.stack([p10 - p00, p01 - p00], axis=1)   # fine (u', v') -> coarse (u, v)
+                bf = p00.copy()
+                if not np.allclose(Af @ np.array([1.0, 1.0]) + bf, p11) or \
+                        sorted(np.abs(Af).sum(axis=0).tolist()) != [0.5, 0.5]:
+                    raise ValueError("hanging face: a quarter does not match as a quadrilateral")
+                Ac = np.linalg.inv(Af)
+                entries.append((k, fk, np.round(Ac), -np.round(Ac) @ bf, (0.5 * iu, 0.5 * iv)))
+                out[(k, fk)] = [(e, f, Af, bf, None)]
+            out[(e, f)] = entries
+    return out

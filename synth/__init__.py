@@ -7,14 +7,14 @@ size bookkeeping both sides need to allocate buffers.  It contains none of the
 discretisation's arithmetic (no basis functions, quadrature, fluxes or
 projections), and it imports neither the oracle nor the library.
 """
-from .meshes import (box_mesh, perturb_interior, affine_transform, centroids,
+from .meshes import (box_mesh, hanging_mesh, perturb_interior, affine_transform, centroids,
                      Mesh, trial_sizes, unknown_sizes, offsets, cube_rotations, reorient)
 from .configs import (cavity_small, cavity_two_material, graded_nonaffine,
                       serving_stream, large_cavity, random_vector, Source,
                       ModeSet)
 
 __all__ = [
-    "box_mesh", "perturb_interior", "affine_transform", "centroids", "Mesh",
+    "box_mesh", "hanging_mesh", "perturb_interior", "affine_transform", "centroids", "Mesh",
     "cube_rotations", "reorient",
     "trial_sizes", "unknown_sizes", "offsets", "cavity_small",
     "cavity_two_material", "graded_nonaffine", "serving_stream",

@@ -86,6 +86,41 @@ def box_mesh(shape, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
     return vertices, hexes
 
 
+def hanging_mesh(n=2, split=1, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    """A box of n^3 axis-aligned cells in which every cell with x index >=
+    ``split`` is refined into 2 x 2 x 2 halves: the faces between cells at x
+    index split - 1 and split are 2:1 hanging faces (one coarse face against
+    four fine faces).  Vertices are shared by position.  Returns
+    ``(vertices, hexes)``; cells in x-fastest order, each refined cell's eight
+    children in place of it (x fastest)."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    h = (hi - lo) / n
+    index = {}
+    verts = []
+
+    def vid(x):
+        key = tuple(np.round(x, 12))
+        if key not in index:
+            index[key] = len(verts)
+            verts.append(np.array(x, dtype=np.float64))
+        return index[key]
+
+    corners = np.array([[v & 1, (v >> 1) & 1, (v >> 2) & 1] for v in range(8)], dtype=np.float64)
+    hexes = []
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                x0 = lo + h * np.array([i, j, k], dtype=np.float64)
+                if i >= split:
+                    for c in range(8):
+                        y0 = x0 + 0.5 * h * corners[c]
+                        hexes.append([vid(y0 + 0.5 * h * corners[v]) for v in range(8)])
+                else:
+                    hexes.append([vid(x0 + h * corners[v]) for v in range(8)])
+    return np.array(verts), np.array(hexes, dtype=np.int64)
+
+
 def perturb_interior(vertices, shape, frac, seed, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
     """Shift every coordinate of every interior lattice vertex by an independent
     U(-frac*h_d, +frac*h_d) draw (h_d = lattice spacing along axis d).
