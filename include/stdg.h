@@ -57,7 +57,7 @@ extern "C" {
 typedef enum {
   STDG_OK = 0,
   STDG_E_ARG = -1,           /* invalid argument (null, size, range)           */
-  STDG_E_UNSUPPORTED = -2,   /* valid but not implemented (e.g. a hanging face) */
+  STDG_E_UNSUPPORTED = -2,   /* valid but not implemented (e.g. D_h with hanging faces) */
   STDG_E_NOMEM = -3,         /* device or host allocation failed                */
   STDG_E_DEVICE = -4,        /* HIP runtime error or missing GPU                */
   STDG_E_NOT_CONVERGED = -5, /* solver hit its iteration limit (info is filled) */
@@ -138,10 +138,17 @@ typedef struct {
  * accepted; STDG_E_ARG if the shared vertices do not match as a
  * quadrilateral), classify elements as affine (parallelepiped) or trilinear,
  * group them by (p, q, affine), compute offsets and copy everything to the
- * device.  Faces on exactly one element are PEC boundary faces; a face split
- * among smaller elements (2:1 refinement with hanging vertices, found by the
- * smaller faces' centroids at its quarter points) is refused with
- * STDG_E_UNSUPPORTED: conforming meshes only. */
+ * device.  Faces on exactly one element are PEC boundary faces, except 2:1
+ * hanging faces (Section 5.2 sums a face's flux terms over the neighbours
+ * sharing parts of it): a face whose four quarters are whole faces of four
+ * other elements, with mesh vertices at the corners, edge midpoints and
+ * centre of its bilinear map (any orientation of the smaller elements, any
+ * p and q on either side).  These couple through the centred flux, the
+ * neighbours' traces projected onto each side's face modes by half-interval
+ * Legendre restrictions, exact for affine faces.  A face split among smaller
+ * elements in any other way (found by their centroids at its quarter points)
+ * is refused with STDG_E_UNSUPPORTED.  Meshes with hanging faces do not take
+ * D_h (stdg_mesh_set_dissipation) and run their serving cycles alone. */
 int stdg_mesh_upload(stdg_ctx* ctx, const stdg_mesh_desc* desc, stdg_mesh** out);
 int stdg_mesh_info(const stdg_mesh* mesh, stdg_mesh_info_t* out);
 /* Host copies of the element offsets (n_elements + 1 entries each, any may be NULL). */

@@ -32,7 +32,33 @@ enum : int32_t {
   kDiagMass = 2,      // metric diagonal (axis-aligned box)
   kPermuted = 4,      // some neighbour meets this element in another orientation
   kBoundaryBase = 8,  // bit 3 + f: face f is a PEC boundary face
+  kHanging = 512,     // a face of this element is a 2:1 hanging face (ElemInfo.pad indexes HangRec)
+  kHangFaceBase = 1024,  // bit 10 + f: face f is a 2:1 hanging face (either side)
 };
+
+// 2:1 hanging faces (Section 5.2 sums the flux terms of a face over the
+// neighbours that share parts of it): a coarse face covered by the faces of
+// four smaller elements.  Per face of an element with kHanging:
+//   kind 0: conforming or boundary (ElemInfo.nb / orient apply);
+//   kind 1: coarse side, nb[j] covers the quarter (hu, hv) = (j & 1, j >> 1)
+//           of this face, [hu/2, (hu+1)/2] x [hv/2, (hv+1)/2] in (u, v);
+//   kind 2: fine side, nb[0] is the coarse element.
+// code[j]: bits 0-2 the neighbour's local face; bit 3 swap (our u runs along
+// the neighbour's v'); bit 4 (5): the neighbour coordinate matched with our
+// u (v) runs from 1 to 0; fine side only: bit 6 (7) the half of the coarse
+// face's coordinate matched with our u (v) that this face covers.
+// (u, v) are the two tangential reference axes of a face in increasing order.
+struct HangFace {
+  int32_t kind;
+  int32_t nb[4];
+  uint8_t code[4];
+};
+struct HangRec {
+  HangFace f[6];
+  int32_t elem;  // the element this record belongs to
+};
+// 1D half-interval restriction integrals S[h][k][m] = int_0^1 L_k(x) L_m((x + h) / 2) dx
+void fill_half_tables_f64(double* S);  // 2 * kMaxA * kMaxA entries
 
 // Orientation of interior face f as seen from its element (byte orient[f]):
 //   bits 0-2  the neighbour's local face f' (axis f' / 2, side f' % 2)
@@ -159,6 +185,13 @@ struct Mesh {
   // face rules of D_h on trilinear elements, indexed by n (FaceRule<double>, FaceRule<float>)
   void* d_fr64 = nullptr;
   void* d_fr32 = nullptr;
+  // 2:1 hanging faces: records of the elements with kHanging (ElemInfo.pad
+  // indexes them) and the half-interval restriction tables (FP64, FP32)
+  std::vector<HangRec> hang;
+  int64_t n_hanging_faces = 0;  // coarse faces with four fine neighbours
+  HangRec* d_hang = nullptr;
+  void* d_hs64 = nullptr;
+  void* d_hs32 = nullptr;
   // side streams for applies over several kernel groups (created on first use):
   // the groups run concurrently, forked from and joined back into the caller's stream
   static constexpr int kAux = 4;
@@ -227,6 +260,11 @@ bool batchable_mesh(const Mesh* m);
 int launch_residual_batch(const BatchApplyArgs* a, int count, int prec, hipStream_t s);
 // bytes (a multiple of 16) from src to dst, both 16-byte aligned, no overlap (blas.hip)
 int stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+// the neighbours' half of the centred flux on 2:1 hanging faces, added to y
+// after the residual kernels (hanging.hip); any mode (P^{-1} fused on
+// diagonal meshes, else x already scaled and mode 0)
+template <typename T>
+int launch_hanging(const Mesh* m, double dt, int mode, const T* x, T* y, hipStream_t s, const int* skip);
 // D_h on the trilinear group g, added to y (dissipation.hip); mode 0 or STDG_RESIDUAL
 template <typename T>
 int launch_diss_trilinear(const Mesh* m, const Group& g, double dt, int mode, const T* x, T* y, hipStream_t s,

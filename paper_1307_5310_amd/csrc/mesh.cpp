@@ -325,11 +325,167 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     i = j;
   }
 
-  // conformity: a face only partly shared (2:1 refinement, hanging vertices)
-  // leaves the coarse face and the four fine faces unmatched, so they would be
-  // taken for walls.  Such a coarse face has the centroids of the fine faces
-  // at its quarter points: look every boundary face's quarter points up among
-  // the boundary-face centroids (spatial hash, tolerance 1e-9 of the mesh size).
+  // 2:1 hanging faces: a coarse face and the four fine faces covering it
+  // are left unmatched above.  Such a coarse face has mesh vertices at its
+  // edge midpoints and centre (the bilinear face map at (i/2, j/2)), and its
+  // quarters are unmatched faces of four other elements with those vertex
+  // ids (positions compared with a spatial hash, tolerance 1e-9 of the mesh
+  // size).  Both sides are recorded (HangRec) and the faces become interior.
+  {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < nv; ++v)
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = std::min(lo[c], d->vertices[3 * v + c]);
+        hi[c] = std::max(hi[c], d->vertices[3 * v + c]);
+      }
+    const double diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                  (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    const double tol = 1e-9 * (diag > 0 ? diag : 1.0);
+    auto cell = [&](const double* x, int c) { return (int64_t)std::floor((x[c] - lo[c]) / (4 * tol)); };
+    std::map<std::array<int64_t, 3>, std::vector<int64_t>> vgrid;
+    for (int64_t v = 0; v < nv; ++v) {
+      const double* x = d->vertices + 3 * v;
+      vgrid[{cell(x, 0), cell(x, 1), cell(x, 2)}].push_back(v);
+    }
+    auto vertex_at = [&](const double x[3]) -> int64_t {
+      const int64_t c0 = cell(x, 0), c1 = cell(x, 1), c2 = cell(x, 2);
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            auto it = vgrid.find({c0 + dx, c1 + dy, c2 + dz});
+            if (it == vgrid.end()) continue;
+            for (int64_t v : it->second) {
+              const double* y = d->vertices + 3 * v;
+              if (std::fabs(y[0] - x[0]) <= tol && std::fabs(y[1] - x[1]) <= tol && std::fabs(y[2] - x[2]) <= tol)
+                return v;
+            }
+          }
+      return -1;
+    };
+    // unmatched faces by their sorted vertex ids
+    std::map<std::array<int64_t, 4>, std::pair<int64_t, int>> open;
+    for (int64_t e = 0; e < ne; ++e)
+      for (int f = 0; f < 6; ++f) {
+        if (m->info[e].nb[f] >= 0) continue;
+        auto lv = face_local_vertices(f);
+        std::array<int64_t, 4> key;
+        for (int k = 0; k < 4; ++k) key[k] = d->hexes[8 * e + lv[k]];
+        std::sort(key.begin(), key.end());
+        open[key] = {e, f};
+      }
+    auto record = [&](int64_t e) -> HangRec& {
+      ElemInfo& I = m->info[e];
+      if (!(I.flags & kHanging)) {
+        I.flags |= kHanging;
+        I.pad = (int32_t)m->hang.size();
+        HangRec r;
+        std::memset(&r, 0, sizeof(r));
+        r.elem = (int32_t)e;
+        m->hang.push_back(r);
+      }
+      return m->hang[I.pad];
+    };
+    for (int64_t e = 0; e < ne; ++e)
+      for (int f = 0; f < 6; ++f) {
+        if (m->info[e].nb[f] >= 0) continue;
+        if ((m->info[e].flags & kHanging) && m->hang[m->info[e].pad].f[f].kind != 0) continue;
+        auto lv = face_local_vertices(f);  // corners (0,0), (1,0), (0,1), (1,1)
+        int64_t grid[3][3];
+        bool ok = true;
+        for (int j = 0; j < 3 && ok; ++j)
+          for (int i = 0; i < 3 && ok; ++i) {
+            const double s_ = 0.5 * i, t_ = 0.5 * j;
+            const double wt[4] = {(1 - s_) * (1 - t_), s_ * (1 - t_), (1 - s_) * t_, s_ * t_};
+            double x[3] = {0, 0, 0};
+            for (int k = 0; k < 4; ++k)
+              for (int c = 0; c < 3; ++c) x[c] += wt[k] * d->vertices[3 * d->hexes[8 * e + lv[k]] + c];
+            grid[i][j] = vertex_at(x);
+            ok = grid[i][j] >= 0;
+          }
+        if (!ok) continue;
+        std::pair<int64_t, int> fine[4];
+        for (int qd = 0; qd < 4 && ok; ++qd) {
+          const int hu = qd & 1, hv = qd >> 1;
+          std::array<int64_t, 4> key = {grid[hu][hv], grid[hu + 1][hv], grid[hu][hv + 1], grid[hu + 1][hv + 1]};
+          std::sort(key.begin(), key.end());
+          auto it = open.find(key);
+          ok = it != open.end() && it->second.first != e;
+          if (ok) fine[qd] = it->second;
+        }
+        if (!ok) continue;
+        if (m->info[e].q < 1) return fail(STDG_E_ARG, "hanging face: invalid element");
+        HangFace hc;
+        std::memset(&hc, 0, sizeof(hc));
+        hc.kind = 1;
+        for (int qd = 0; qd < 4; ++qd) {
+          const int64_t k = fine[qd].first;
+          const int fk = fine[qd].second;
+          if (k > INT32_MAX || e > INT32_MAX) return fail(STDG_E_ARG, "too many elements");
+          // the fine face's corners in the coarse face's coordinates (halves)
+          auto fv = face_local_vertices(fk);
+          int cu[4], cv[4];
+          for (int t = 0; t < 4; ++t) {
+            const int64_t g = d->hexes[8 * k + fv[t]];
+            cu[t] = cv[t] = -1;
+            for (int j = 0; j < 3; ++j)
+              for (int i = 0; i < 3; ++i)
+                if (grid[i][j] == g) {
+                  cu[t] = i;
+                  cv[t] = j;
+                }
+            if (cu[t] < 0) return fail(STDG_E_ARG, "hanging face: a fine face does not match its quarter");
+          }
+          // fine (u, v) -> coarse (2u', 2v') = A (u, v) + b (entries of A: 0, +-1 in half units)
+          const int A00 = cu[1] - cu[0], A10 = cv[1] - cv[0], A01 = cu[2] - cu[0], A11 = cv[2] - cv[0];
+          if (cu[3] != cu[0] + A00 + A01 || cv[3] != cv[0] + A10 + A11 || std::abs(A00) + std::abs(A01) != 1 ||
+              std::abs(A10) + std::abs(A11) != 1 || std::abs(A00) + std::abs(A10) != 1)
+            return fail(STDG_E_ARG, "hanging face: a fine face does not match its quarter as a quadrilateral");
+          const bool swap = A00 == 0;
+          // fine side: the coarse coordinate matched with fine u is u' (or v' when swapped)
+          const bool fu_flip = swap ? A10 < 0 : A00 < 0;
+          const bool fv_flip = swap ? A01 < 0 : A11 < 0;
+          const int wu0 = swap ? cv[0] : cu[0], wv0 = swap ? cu[0] : cv[0];  // in half units at fine (0, 0)
+          const int hu_f = wu0 - (fu_flip ? 1 : 0), hv_f = wv0 - (fv_flip ? 1 : 0);
+          if (hu_f < 0 || hu_f > 1 || hv_f < 0 || hv_f > 1) return fail(STDG_E_ARG, "hanging face: bad quarter");
+          HangRec& rf = record(k);
+          HangFace& hf = rf.f[fk];
+          hf.kind = 2;
+          hf.nb[0] = (int32_t)e;
+          hf.code[0] = (uint8_t)(f | (swap ? 8 : 0) | (fu_flip ? 16 : 0) | (fv_flip ? 32 : 0) | (hu_f << 6) | (hv_f << 7));
+          // coarse side: the inverse map, 2 times the transposed signed permutation
+          const int B00 = A00, B01 = A10, B10 = A01, B11 = A11;  // P^T (P is a signed permutation)
+          const bool cswap = B00 == 0;
+          const bool cu_flip = cswap ? B10 < 0 : B00 < 0;
+          const bool cv_flip = cswap ? B01 < 0 : B11 < 0;
+          const int qu = std::min(std::min(cu[0], cu[1]), std::min(cu[2], cu[3]));
+          const int qv = std::min(std::min(cv[0], cv[1]), std::min(cv[2], cv[3]));
+          const int slot = qu + 2 * qv;
+          hc.nb[slot] = (int32_t)k;
+          hc.code[slot] = (uint8_t)(fk | (cswap ? 8 : 0) | (cu_flip ? 16 : 0) | (cv_flip ? 32 : 0));
+          m->info[k].nb[fk] = (int32_t)e;
+          m->info[k].orient[fk] = (uint8_t)(fk ^ 1);
+          m->info[k].flags &= ~(kBoundaryBase << fk);
+          m->info[k].flags |= (kHangFaceBase << fk);
+        }
+        HangRec& rc = record(e);
+        rc.f[f] = hc;
+        m->info[e].nb[f] = hc.nb[0];
+        m->info[e].orient[f] = (uint8_t)(f ^ 1);
+        m->info[e].flags &= ~(kBoundaryBase << f);
+        m->info[e].flags |= (kHangFaceBase << f);
+        m->n_hanging_faces += 1;
+        m->n_bnd_faces -= 5;
+        m->n_int_faces += 4;
+      }
+  }
+
+  // a face split among smaller elements that did not match as a 2:1 hanging
+  // face above (its quarters are not whole faces with the corner, edge-midpoint
+  // and centre vertices of the face's bilinear map) would be taken for a wall:
+  // refuse it.  Such a face has the centroids of the smaller faces at its
+  // quarter points: look every remaining boundary face's quarter points up
+  // among the boundary-face centroids (spatial hash, tolerance 1e-9 of the
+  // mesh size).
   {
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t v = 0; v < nv; ++v)
@@ -373,7 +529,7 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
                   if (std::fabs(y[0] - x[0]) <= tol && std::fabs(y[1] - x[1]) <= tol && std::fabs(y[2] - x[2]) <= tol)
                     return fail(STDG_E_UNSUPPORTED, "nonconforming mesh: face " + std::to_string(f) + " of element " +
                                                         std::to_string(e) +
-                                                        " is split among smaller elements (hanging vertices)");
+                                                        " is split among smaller elements that are not its four quarters");
               }
         }
       }
@@ -509,6 +665,11 @@ size_t mesh_device_bytes(const Mesh& m) {
   size_t b = r256(sizeof(ElemInfo) * m.ne) + r256(sizeof(ElemMetric) * m.ne) + r256(sizeof(double) * 24 * m.ne) +
              r256(sizeof(QTables<double>) * (kMaxA + 1)) + r256(sizeof(QTables<float>) * (kMaxA + 1)) +
              r256(sizeof(int64_t) * (m.ne + 1));
+  if (m.n_nonaffine > 0)
+    b += r256(sizeof(FaceRule<double>) * (kMaxFaceQ + 1)) + r256(sizeof(FaceRule<float>) * (kMaxFaceQ + 1));
+  if (!m.hang.empty())
+    b += r256(sizeof(HangRec) * m.hang.size()) + r256(sizeof(double) * 2 * kMaxA * kMaxA) +
+         r256(sizeof(float) * 2 * kMaxA * kMaxA);
   for (const Group& g : m.groups) b += r256(sizeof(int32_t) * g.count);
   return b;
 }
@@ -555,6 +716,19 @@ int upload_mesh(Ctx* ctx, Mesh* m) {
     STDG_HIP(hipMemcpy(m->d_fr64, f64.data(), b64, hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d_fr32, f32.data(), b32, hipMemcpyHostToDevice));
   }
+  if (!m->hang.empty()) {
+    const size_t bh = sizeof(HangRec) * m->hang.size();
+    std::vector<double> s64(2 * kMaxA * kMaxA);
+    fill_half_tables_f64(s64.data());
+    std::vector<float> s32(s64.begin(), s64.end());
+    if ((rc = dev_alloc(ctx, (void**)&m->d_hang, bh)) != STDG_OK) return rc;
+    if ((rc = dev_alloc(ctx, &m->d_hs64, sizeof(double) * s64.size())) != STDG_OK) return rc;
+    if ((rc = dev_alloc(ctx, &m->d_hs32, sizeof(float) * s32.size())) != STDG_OK) return rc;
+    m->device_bytes += bh + sizeof(double) * s64.size() + sizeof(float) * s32.size();
+    STDG_HIP(hipMemcpy(m->d_hang, m->hang.data(), bh, hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d_hs64, s64.data(), sizeof(double) * s64.size(), hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d_hs32, s32.data(), sizeof(float) * s32.size(), hipMemcpyHostToDevice));
+  }
   for (Group& g : m->groups) {
     if ((rc = dev_alloc(ctx, (void**)&g.d_list, sizeof(int32_t) * g.count)) != STDG_OK) return rc;
     m->device_bytes += sizeof(int32_t) * g.count;
@@ -572,6 +746,8 @@ int upload_mesh(Ctx* ctx, Mesh* m) {
 // quadrature points from the vertices and leave these entries unused).
 int set_dissipation(Mesh* m, double c) {
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(STDG_E_ARG, "dissipation coefficient must be finite and >= 0");
+  if (c > 0.0 && !m->hang.empty())
+    return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation on meshes with hanging faces");
   ++m->epoch;
   const size_t bytes = sizeof(double) * Mesh::kDissWords * m->ne, bytes32 = sizeof(float) * Mesh::kDissWords * m->ne;
   if (c == 0.0) {
@@ -661,6 +837,11 @@ void release_mesh(Mesh* m) {
   if (m->d_qt64) dev_free(ctx, m->d_qt64, sizeof(QTables<double>) * (kMaxA + 1));
   if (m->d_qt32) dev_free(ctx, m->d_qt32, sizeof(QTables<float>) * (kMaxA + 1));
   m->d_qt64 = m->d_qt32 = nullptr;
+  if (m->d_hang) dev_free(ctx, m->d_hang, sizeof(HangRec) * m->hang.size());
+  if (m->d_hs64) dev_free(ctx, m->d_hs64, sizeof(double) * 2 * kMaxA * kMaxA);
+  if (m->d_hs32) dev_free(ctx, m->d_hs32, sizeof(float) * 2 * kMaxA * kMaxA);
+  m->d_hang = nullptr;
+  m->d_hs64 = m->d_hs32 = nullptr;
   if (m->d_fr64) dev_free(ctx, m->d_fr64, sizeof(FaceRule<double>) * (kMaxFaceQ + 1));
   if (m->d_fr32) dev_free(ctx, m->d_fr32, sizeof(FaceRule<float>) * (kMaxFaceQ + 1));
   m->d_fr64 = m->d_fr32 = nullptr;

@@ -151,6 +151,8 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
       STDG_HIP(hipStreamWaitEvent(s, m->join_ev[k], 0));
     }
   }
+  // 2:1 hanging faces: the neighbours' half of their fluxes, after every group
+  if (!m->hang.empty()) return launch_hanging<T>(m, dt, mode, x, y, s, skip);
   return STDG_OK;
 }
 
@@ -162,7 +164,7 @@ bool batchable_mesh(const Mesh* m) {
       ++groups;
       g0 = &g;
     }
-  return groups == 1 && g0->affine && m->n_diag == m->ne && m->d_diss == nullptr;
+  return groups == 1 && g0->affine && m->n_diag == m->ne && m->d_diss == nullptr && m->hang.empty();
 }
 
 template <typename T>

@@ -451,7 +451,8 @@ __device__ __forceinline__ void element_body(const KParams<T>& P, const int e, c
   // path.  (Written out rather than as one generic lambda: the lambda form
   // cost the trilinear kernels up to 57 VGPRs and an occupancy step.)
   const bool permuted = (Ip->flags & kPermuted) != 0;
-  if (!AFF && permuted) fast = false;
+  const bool hanging = (Ip->flags & kHanging) != 0;  // 2:1 hanging faces take the general path
+  if ((!AFF && permuted) || hanging) fast = false;
   const bool fast_perm = AFF && fast && permuted;
   if (fast && !fast_perm && C::template stage<T, Q>()) {
     // Neighbour blocks are read with unit-stride (coalesced) loads - thread
@@ -662,6 +663,9 @@ __device__ __forceinline__ void element_body(const KParams<T>& P, const int e, c
     for (int g = 0; g < 6; ++g) {
       const int alpha = g >> 1;
       if (nb_id[g] < 0) continue;
+      // 2:1 hanging faces: the neighbours' part of the flux is added by the
+      // hanging-face kernel after this one (the own part is taken here)
+      if (Ip->flags & (kHangFaceBase << g)) continue;
       const int c = (alpha + 1 + (tc & 1)) % 3;
       const FaceMap fm = map_face(alpha, Ip->orient[g], c, fu, fv);
       const T scale = (pre ? (T)P.metric[nb_id[g]].m[12 + 6 * tf + fm.cn] : T(1)) * (fm.neg ? T(-1) : T(1));

@@ -126,6 +126,20 @@ void fill_qtables_f32(int a, QTables<float>* t) {
   for (int i = 0; i <= kMaxA; ++i) t->x[i] = (float)d.x[i];
 }
 
+void fill_half_tables_f64(double* S) {
+  // exact: the integrand has degree < 2 kMaxA, the rule 2 kMaxA points
+  const int n = 2 * kMaxA;
+  double x[2 * kMaxA], w[2 * kMaxA];
+  gauss_rule01(n, x, w);
+  for (int h = 0; h < 2; ++h)
+    for (int k = 0; k < kMaxA; ++k)
+      for (int m = 0; m < kMaxA; ++m) {
+        double v = 0.0;
+        for (int g = 0; g < n; ++g) v += w[g] * legendre01(k, x[g]) * legendre01(m, 0.5 * (x[g] + h));
+        S[(h * kMaxA + k) * kMaxA + m] = v;
+      }
+}
+
 void fill_face_rule_f64(int n, FaceRule<double>* r) {
   std::memset(r, 0, sizeof(*r));
   if (n < 1 || n > kMaxFaceQ) return;

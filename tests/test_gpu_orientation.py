@@ -129,35 +129,6 @@ def test_slab_solve_same_as_canonical_numbering(lib):
     assert rel_err(g1, ref) < 1e-10
 
 
-def test_hanging_node_mesh_is_refused(lib):
-    # a unit cube next to four half-size cubes: its face x = 1 is split in
-    # four (nonconforming, hanging vertices); the upload refuses it instead of
-    # taking the split faces for PEC walls
-    pts, idx = [], {}
-
-    def vid(x, y, z):
-        key = (round(x, 9), round(y, 9), round(z, 9))
-        if key not in idx:
-            idx[key] = len(pts)
-            pts.append(key)
-        return idx[key]
-
-    def hexa(x0, y0, z0, hx, hy, hz):
-        return [vid(x0 + hx * (v & 1), y0 + hy * ((v >> 1) & 1), z0 + hz * ((v >> 2) & 1)) for v in range(8)]
-
-    hexes = [hexa(0, 0, 0, 1, 1, 1)] + [hexa(1, 0.5 * j, 0.5 * k, 0.5, 0.5, 0.5) for j in range(2) for k in range(2)]
-    mesh = synth.Mesh(np.array(pts, dtype=np.float64), np.array(hexes, dtype=np.int64), np.full(5, 2, np.int32),
-                      np.full(5, 1, np.int32), np.ones(5), np.ones(5))
-    with pytest.raises(lib.stdg.StdgError) as ei:
-        lib.upload(mesh)
-    assert ei.value.status == -2
-    # the same five cells as one conforming 1 + 4 lattice column are accepted
-    v, h = synth.box_mesh((2, 2, 2))
-    mh = lib.upload(synth.Mesh(v, synth.reorient(h, seed=47), np.full(8, 2, np.int32), np.full(8, 1, np.int32),
-                               np.ones(8), np.ones(8)))
-    lib.stdg.stdg_mesh_free(mh)
-
-
 @pytest.mark.parametrize("prec", [0, 1])
 def test_full_size_reoriented_dissipative_sampled(lib, prec):
     """The 32^3, p = 4, q = 3 two-material cavity, every element's numbering
