@@ -15,7 +15,9 @@ into dense local blocks and applied block by block (Section 5.2 only reorganises
 these integrals).  Pieces:
 
 * ``basis``   1D orthonormal / integrated Legendre functions and the time and
-              derivative tables, all by quadrature (Section 5.1, eq. def:ilegendre).
+              derivative tables, all by quadrature (Section 5.1, eq. def:ilegendre),
+              and the tables of bisected slab intervals (local time steps,
+              Section 2.2) with the projection of S_h.
 * ``geometry``trilinear element maps and the face topology of a hex mesh.
 * ``dg``      dense local element and face matrices, slab blocks, the residual
               (Section 5, eq. residual), the load, the energy (eq.

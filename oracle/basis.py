@@ -99,3 +99,86 @@ def derivative_table(a):
 def trace_values(a):
     """(L_j(0), L_j(1)) for j = 0..a-1: the face evaluations of the spatial basis."""
     return legendre_matrix(a, np.array([0.0]))[0], legendre_matrix(a, np.array([1.0]))[0]
+
+
+# ----------------------------------------------------------------------------
+# local time steps: a macro-element's interval bisected into n equal
+# sub-intervals (Section 2.2), trial space continuous piecewise P_q and test
+# space piecewise P_{q-1} (eq. spaces:local:patch)
+# ----------------------------------------------------------------------------
+
+def trial_level(q, n, j, m):
+    """Level of the local trial function l_m of sub-interval j (of n) in the
+    flattened trial block of 1 + n q levels.  Level 0 is the value at the slab
+    start, level 1 the value at the slab end (as for n = 1); sub-interval j
+    then owns the q levels 2 + j q .. 1 + (j + 1) q: its interior functions
+    l_2..l_q, then (j < n - 1) the value at its right end, which is also l_0
+    of sub-interval j + 1 (continuity in time inside the slab).  For n = 1
+    this is the identity m -> m."""
+    if m == 0:
+        return 0 if j == 0 else 1 + j * q
+    if m == 1:
+        return 1 if j == n - 1 else 1 + (j + 1) * q
+    return 2 + j * q + (m - 2)
+
+
+def subinterval_trial_values(q, n, s):
+    """Values and d/ds of the 1 + n q flattened trial functions at slab
+    coordinates s in (0, 1) that are not sub-interval ends: [..., level]."""
+    s = np.asarray(s, dtype=np.float64)
+    j = np.minimum((s * n).astype(np.int64), n - 1)
+    xi = n * s - j
+    V = np.zeros(s.shape + (1 + n * q,))
+    dV = np.zeros_like(V)
+    for m in range(q + 1):
+        lev = np.array([trial_level(q, n, int(jj), m) for jj in np.ravel(j)]).reshape(s.shape)
+        np.add.at(V, (np.arange(s.size), lev.ravel()), ltrial(m, xi).ravel())
+        np.add.at(dV, (np.arange(s.size), lev.ravel()), n * dltrial(m, xi).ravel())
+    return V, dV
+
+
+def subinterval_test_values(q, n, s):
+    """Test functions L_i^(j)(s) = L_i(n s - j) on sub-interval j, zero
+    elsewhere; column j q + i."""
+    s = np.asarray(s, dtype=np.float64)
+    j = np.minimum((s * n).astype(np.int64), n - 1)
+    xi = n * s - j
+    V = np.zeros(s.shape + (n * q,))
+    for jj in range(n):
+        on = j == jj
+        for i in range(q):
+            V[on, jj * q + i] = L(i, xi[on])
+    return V
+
+
+def subinterval_time_table(qr, nr, qc, nc, deriv=False, proj=None):
+    """T[(j, i), M] = int_0^1 (pi L_i^(j))(s) phi_M(s) ds over the slab in
+    its unit coordinate s = (t - t_{n-1}) / dt: test function i of sub-interval
+    j of the row element (degree qr, nr sub-intervals) against flattened trial
+    level M of the column element (qc, nc), or against d phi_M / ds with
+    ``deriv``.  ``proj = (r, n_p)`` applies pi, the L2 projection onto
+    piecewise polynomials of degree < r on n_p equal sub-intervals, to the
+    test function (the common temporal test space of S_h, Section 4.1 eq.
+    bilinearform:S); without it pi is the identity.  All n are powers of two,
+    so the partitions nest and a composite Gauss rule on the finest one
+    integrates every product exactly."""
+    nf = max(nr, nc, proj[1] if proj is not None else 1)
+    xg, wg = gauss01(qr + qc + 2)
+    s = ((np.arange(nf)[:, None] + xg[None, :]) / nf).ravel()
+    w = np.tile(wg, nf) / nf
+    test = subinterval_test_values(qr, nr, s)
+    if proj is not None:
+        r, npj = proj
+        c = np.minimum((s * npj).astype(np.int64), npj - 1)
+        xi = npj * s - c
+        out = np.zeros_like(test)
+        for cc in range(npj):
+            on = c == cc
+            for rho in range(r):
+                Lr = L(rho, xi[on])
+                # coefficient of L_rho(n_p s - cc), whose square integrates to 1 / n_p
+                beta = npj * np.sum((w[on] * Lr)[:, None] * test[on], axis=0)
+                out[on] += Lr[:, None] * beta[None, :]
+        test = out
+    V, dV = subinterval_trial_values(qc, nc, s)
+    return (test * w[:, None]).T @ (dV if deriv else V)

@@ -17,7 +17,9 @@ integrated in physical space-time with
 * the average / tangential-jump operators of Section 2.4 and the terms of
   C_h (eq. bilinearform:C), S_h (eq. bilinearform:S) and the dissipative D_h
   (the remark after Section 4) as written, with the temporal L2 projection
-  pi-tilde computed by quadrature;
+  pi-tilde computed by quadrature from the Gram matrix of a basis of the
+  common test space (piecewise polynomials on the coarser of two nested
+  partitions when slab intervals are bisected, Section 2.2);
 * its own Legendre evaluation by the three-term recurrence.
 
 Only tiny meshes are feasible (dense matrices, many quadrature points).
@@ -57,6 +59,36 @@ def _time_functions(q, tau):
         lt.append(np.sqrt(2 * m - 1) * 0.5 * (P[m] - P[m - 2]) / (2 * m - 1))
         dlt.append(V[..., m - 1])
     return np.stack(lt, -1), np.stack(dlt, -1), V[..., :q]
+
+
+def _level(q, n, j, m):
+    """Column of local trial function l_m of sub-interval j in the flattened
+    block of 1 + n q trial levels (the layout of the slab matrix's columns):
+    0 = slab start, 1 = slab end, then per sub-interval its l_2..l_q and the
+    value at its right end if that end is interior."""
+    if m == 0:
+        return 0 if j == 0 else 1 + j * q
+    if m == 1:
+        return 1 if j == n - 1 else 1 + (j + 1) * q
+    return 2 + j * q + m - 2
+
+
+def _slab_functions(q, n, tau):
+    """At slab coordinates tau (inside sub-intervals of every partition in
+    use): flattened trial functions [tau, 1 + n q] with d/dtau, and test
+    functions [tau, n q], L_i(n tau - j) on sub-interval j."""
+    j = np.minimum(np.floor(tau * n).astype(np.int64), n - 1)
+    xi = tau * n - j
+    lt, dlt, Lt = _time_functions(q, xi)
+    trial = np.zeros((tau.size, 1 + n * q))
+    dtrial = np.zeros_like(trial)
+    test = np.zeros((tau.size, n * q))
+    for p in range(tau.size):
+        for m in range(q + 1):
+            trial[p, _level(q, n, int(j[p]), m)] += lt[p, m]
+            dtrial[p, _level(q, n, int(j[p]), m)] += n * dlt[p, m]
+        test[p, j[p] * q:(j[p] + 1) * q] = Lt[p, :q]
+    return trial, dtrial, test
 
 
 class _Element:
@@ -147,44 +179,52 @@ def _face_param(face, uv):
     return xh, tang
 
 
-def assemble(vertices, hexes, p, q, eps, mu, dt, nvol_extra=2, nface_extra=2, nt=None, c_diss=0.0):
+def assemble(vertices, hexes, p, q, eps, mu, dt, nvol_extra=2, nface_extra=2, nt=None, c_diss=0.0, nk=None):
     """Dense slab matrix B[test dof, trial dof] of B_h = C_h + S_h (+ D_h for
-    c_diss > 0) by physical quadrature.  Row layout per element [field][c][i][s];
-    column layout per element [field][d][m][t] (m = 0..q)."""
+    c_diss > 0) by physical quadrature.  Element e's slab interval is bisected
+    into nk[e] equal sub-intervals (powers of two, default 1; Section 2.2).
+    Row layout per element [field][c][(j, i)][s] (i < q on sub-interval j);
+    column layout per element [field][d][m][t] over the 1 + nk q flattened
+    trial levels of ``_level``."""
     vertices = np.asarray(vertices, dtype=np.float64)
     hexes = np.asarray(hexes)
     ne = hexes.shape[0]
     a = np.asarray(p, dtype=np.int64) + 1
     q = np.asarray(q, dtype=np.int64)
+    nk = np.ones(ne, dtype=np.int64) if nk is None else np.asarray(nk, dtype=np.int64)
+    ntest = nk * q
     els = [_Element(vertices[hexes[e]], a[e]) for e in range(ne)]
-    roff = np.concatenate([[0], np.cumsum(6 * q * a ** 3)])
-    coff = np.concatenate([[0], np.cumsum(6 * (q + 1) * a ** 3)])
+    roff = np.concatenate([[0], np.cumsum(6 * ntest * a ** 3)])
+    coff = np.concatenate([[0], np.cumsum(6 * (ntest + 1) * a ** 3)])
     B = np.zeros((roff[-1], coff[-1]))
     ntq = (int(q.max()) + 3) if nt is None else nt
-    tg, tw = _gauss(ntq)
+    # composite Gauss rule on the finest partition (all partitions nest in it)
+    nfine = int(nk.max())
+    g0, w0 = _gauss(ntq)
+    tg = ((np.arange(nfine)[:, None] + g0[None, :]) / nfine).ravel()
+    tw = np.tile(w0, nfine) / nfine
 
-    def time_int(qr, qc, kind, r=None):
-        """Integrals over the slab (t = t0 + dt tau) of test L_i (i < qr) against
-        trial l_m (m <= qc): 'D' -> int L_i d_t l_m dt, 'N' -> int L_i l_m dt,
-        'Nd' -> int (pi L_i - L_i) l_m dt with pi the L2 projection onto
-        polynomials of degree < r in time."""
-        lt, dlt, _ = _time_functions(qc, tg)
-        _, _, Lt = _time_functions(max(qr, r or 0, 1), tg)
-        Lt = Lt[:, :max(qr, 1)]
+    def time_int(er, ec, kind, proj=None):
+        """Integrals over the slab (t = t0 + dt tau) of the test functions of
+        element er against the trial functions of element ec: 'D' -> int L d_t l
+        dt, 'N' -> int L l dt, 'Nd' -> int (pi L - L) l dt with pi the L2
+        projection onto proj = (r, n_p): piecewise polynomials of degree < r
+        on n_p equal sub-intervals, by its Gram matrix."""
+        _, _, Lt = _slab_functions(int(q[er]), int(nk[er]), tg)
+        lt, dlt, _ = _slab_functions(int(q[ec]), int(nk[ec]), tg)
         if kind == "D":
-            return (Lt[:, :qr] * (tw * dt)[:, None]).T @ (dlt / dt)
+            return (Lt * (tw * dt)[:, None]).T @ (dlt / dt)
         if kind == "N":
-            return (Lt[:, :qr] * (tw * dt)[:, None]).T @ lt
-        _, _, Lr = _time_functions(max(r, 1), tg)
-        Lr = Lr[:, :r]
-        G = (Lt[:, :qr] * tw[:, None]).T @ Lr               # int L_i L_k, k < r
-        piL = Lr @ G.T                                       # [tau, i]
-        dL = piL - Lt[:, :qr]
-        return (dL * (tw * dt)[:, None]).T @ lt
+            return (Lt * (tw * dt)[:, None]).T @ lt
+        r, npj = proj
+        _, _, Bp = _slab_functions(r, npj, tg)              # a basis of the projection space
+        G = (Bp * tw[:, None]).T @ Bp
+        piL = Bp @ np.linalg.solve(G, (Bp * tw[:, None]).T @ Lt)
+        return ((piL - Lt) * (tw * dt)[:, None]).T @ lt
 
     def put(e_row, fr, e_col, fc, T, S):
         ar3, ac3 = int(a[e_row]) ** 3, int(a[e_col]) ** 3
-        qr, qc = int(q[e_row]), int(q[e_col])
+        qr, qc = int(ntest[e_row]), int(ntest[e_col])
         blk = np.einsum("im,csdt->cisdmt", T, S.reshape(3, ar3, 3, ac3)).reshape(3 * qr * ar3, 3 * (qc + 1) * ac3)
         r0 = roff[e_row] + fr * 3 * qr * ar3
         c0 = coff[e_col] + fc * 3 * (qc + 1) * ac3
@@ -204,9 +244,8 @@ def assemble(vertices, hexes, p, q, eps, mu, dt, nvol_extra=2, nface_extra=2, nt
         mass = np.einsum("p,pak,pbk->ab", dx, val, val)
         curl_test = np.einsum("p,pak,pbk->ab", dx, curl, val)    # int curl(v_a) . u_b
         curl_trial = np.einsum("p,pak,pbk->ab", dx, val, curl)   # int w_a . curl(u_b)
-        qe = int(q[e])
-        Dt = time_int(qe, qe, "D")
-        Nt = time_int(qe, qe, "N")
+        Dt = time_int(e, e, "D")
+        Nt = time_int(e, e, "N")
         put(e, 0, e, 0, Dt, eps[e] * mass)            # (eps d_t E, v)
         put(e, 1, e, 1, Dt, mu[e] * mass)             # (mu d_t H, w)
         put(e, 0, e, 1, Nt, -curl_test)               # -(H, curl v)
@@ -282,10 +321,9 @@ def assemble(vertices, hexes, p, q, eps, mu, dt, nvol_extra=2, nface_extra=2, nt
             n1 = n1 * sgn[:, None]
             wS = wuv * dS
             _, v1, _, _ = el.fields(xh, with_curl=False)
-            qe = int(q[e])
             n1xv1 = np.cross(n1[:, None, :], v1)
             if k < 0:
-                Nt = time_int(qe, qe, "N")
+                Nt = time_int(e, e, "N")
                 Pb = np.einsum("p,pbk,pak->ab", wS, v1, n1xv1)        # int u . (n x v)
                 Rb = np.einsum("p,pbk,pak->ab", wS, np.cross(n1[:, None, :], v1), v1)  # int (n x u) . w
                 put(e, 0, e, 1, Nt, Pb)
@@ -299,11 +337,11 @@ def assemble(vertices, hexes, p, q, eps, mu, dt, nvol_extra=2, nface_extra=2, nt
             xh2 = elk.invert(x)
             _, v2, _, _ = elk.fields(xh2, with_curl=False)
             n2 = -n1
-            r = min(qe, int(q[k]))
+            # the common temporal test space of the two sides (Section 4.1)
+            proj = (min(int(q[e]), int(q[k])), min(int(nk[e]), int(nk[k])))
             for side_l, (kk, ul, nl) in enumerate(((e, v1, n1), (k, v2, n2))):
-                qk = int(q[kk])
-                Nt = time_int(qe, qk, "N")
-                Nd = time_int(qe, qk, "Nd", r)
+                Nt = time_int(e, kk, "N")
+                Nd = time_int(e, kk, "Nd", proj)
                 Pl = 0.5 * np.einsum("p,pbk,pak->ab", wS, ul, n1xv1)              # 1/2 int u_l . (n1 x v1)
                 Ql = 0.5 * np.einsum("p,pbk,pak->ab", wS, np.cross(nl[:, None, :], ul), v1)  # 1/2 int (n_l x u_l) . v1
                 # E-row: ({H}, [v]_T) + 1/2 (({H}, [dv]_T) + ([H]_T, {dv}))

@@ -30,9 +30,20 @@ Readings where the paper is silent or garbled (each pinned by a test):
 * S_h with one temporal element per slab: pi-tilde truncates the orthonormal
   Legendre test modes to i < min(q_K, q_K'); only the neighbour coupling is
   truncated.  The derivation from eq. bilinearform:S is checked by ``brute``.
+* local time steps (Section 2.2): element K's slab interval is bisected into
+  n_K equal sub-intervals, n_K a power of two, so the partitions of two
+  neighbours nest; the common temporal test space of S_h is then piecewise
+  P_{min(q_K, q_K') - 1} on the coarser of the two partitions, and S_h again
+  reduces to the neighbour coupling with the own test function projected
+  onto it (the self terms keep weight 1/2, unprojected).  Test functions of
+  sub-interval j are L_i(n_K s - j), s the unit slab coordinate; the trial
+  levels are flattened as in basis.trial_level (slab start and end values at
+  levels 0 and 1).
+* D_h with local time steps: the same projection on the test function.
 * mass quadrature: n_q = p + 2 Gauss points per direction (exact on affine
   elements); the same rule is used by the library.
-* load quadrature: p + 3 points per space direction, q + 3 in time.
+* load quadrature: p + 3 points per space direction, q + 3 in time per
+  sub-interval.
 * D_h: the projection on interior faces acts on the test function (rows
   i >= min(q_K, q_K') vanish for own and neighbour trial), the trial jump is
   not projected; on PEC faces nothing is projected and g = 0; {.} of the
@@ -285,13 +296,17 @@ class Discretisation:
     """Slab discretisation of a hexahedral mesh with per-element (p, q, eps, mu).
 
     Coefficient layouts (element-major, canonical):
-      full trial U : per element [field E,H][comp x,y,z][m = 0..q][s]
-      unknowns  x  : per element [field][comp][m = 1..q][s]
-      residual  y  : per element [field][comp][i = 0..q-1][s]
+      full trial U : per element [field E,H][comp x,y,z][m = 0..n q][s]
+      unknowns  x  : per element [field][comp][m = 1..n q][s]
+      residual  y  : per element [field][comp][i = 0..n q-1][s]
       state        : per element [field][comp][s]   (fields at one time)
-    with s = j + a (k + a l), j the x-hat index."""
+    with s = j + a (k + a l), j the x-hat index, and n the element's number of
+    temporal sub-intervals (``nk``, a power of two, default 1; Section 2.2):
+    trial level m is the flattened level of basis.trial_level (level 0 the
+    slab start, level 1 the slab end), test level j q + i the test function
+    L_i of sub-interval j."""
 
-    def __init__(self, vertices, hexes, p, q, eps, mu, mass_nq=None, c_diss=0.0):
+    def __init__(self, vertices, hexes, p, q, eps, mu, mass_nq=None, c_diss=0.0, nk=None):
         self.vertices = np.asarray(vertices, dtype=np.float64)
         self.hexes = np.asarray(hexes, dtype=np.int64)
         self.p = np.asarray(p, dtype=np.int64)
@@ -317,9 +332,13 @@ class Discretisation:
         self.c_diss = float(c_diss)  # dissipative stabilisation D_h, c >= 0 (0 = off)
         if self.c_diss > 0.0 and self.hang:
             raise ValueError("D_h on meshes with hanging faces is not supported")
+        self.nk = np.ones(self.ne, dtype=np.int64) if nk is None else np.asarray(nk, dtype=np.int64)
+        if self.nk.shape != (self.ne,) or np.any(self.nk < 1) or np.any(self.nk & (self.nk - 1)):
+            raise ValueError("nk: one power of two >= 1 per element (temporal bisection)")
+        self.nt = self.nk * self.q           # test levels per element; trial levels nt + 1
         a3 = self.a ** 3
-        self.trial_size = 6 * (self.q + 1) * a3
-        self.unk_size = 6 * self.q * a3
+        self.trial_size = 6 * (self.nt + 1) * a3
+        self.unk_size = 6 * self.nt * a3
         self.state_size = 6 * a3
         self.trial_off = np.concatenate([[0], np.cumsum(self.trial_size)])
         self.unk_off = np.concatenate([[0], np.cumsum(self.unk_size)])
@@ -360,6 +379,41 @@ class Discretisation:
             self._cache[key] = basis.time_tables(int(qt), int(qr))
         return self._cache[key]
 
+    def own_tables(self, e):
+        """(D, N) of element e's own terms over the slab: D[I, M] = int L_I
+        d_s phi_M and N[I, M] = int L_I phi_M (s the unit slab coordinate;
+        with n sub-intervals the blocks of each sub-interval are D and N / n)."""
+        qe, ne_ = int(self.q[e]), int(self.nk[e])
+        if ne_ == 1:
+            return self.tables(qe, qe)
+        key = ("TO", qe, ne_)
+        if key not in self._cache:
+            self._cache[key] = (basis.subinterval_time_table(qe, ne_, qe, ne_, deriv=True),
+                                basis.subinterval_time_table(qe, ne_, qe, ne_))
+        return self._cache[key]
+
+    def coupling_table(self, e, k, trial=None):
+        """Time factor of the neighbour coupling of S_h (Section 4.1, eq.
+        bilinearform:S): C[I, M] = int (pi L_I) phi_M over the slab, test
+        function I of e projected onto the common temporal test space of e and
+        k (piecewise degree < min(q_e, q_k) on the coarser of the two
+        partitions), against the trial levels of ``trial`` (default k).
+        With one sub-interval on both sides the projection keeps the test
+        levels i < min(q_e, q_k) and removes the others."""
+        trial = k if trial is None else trial
+        qe, qk, qt = int(self.q[e]), int(self.q[k]), int(self.q[trial])
+        ne_, nk_, nt_ = int(self.nk[e]), int(self.nk[k]), int(self.nk[trial])
+        r, npj = min(qe, qk), min(ne_, nk_)
+        if ne_ == 1 and nk_ == 1 and nt_ == 1:
+            _, Nc = self.tables(qe, qt)
+            Nc = Nc.copy()
+            Nc[r:, :] = 0.0
+            return Nc
+        key = ("TC", qe, ne_, qt, nt_, r, npj)
+        if key not in self._cache:
+            self._cache[key] = basis.subinterval_time_table(qe, ne_, qt, nt_, proj=(r, npj))
+        return self._cache[key]
+
     # -- spatial pieces of element e's own block ------------------------------
     def self_spatial(self, e):
         """(SE, SH): E-rows/H-cols and H-rows/E-cols spatial matrices of the
@@ -384,9 +438,8 @@ class Discretisation:
         """Terms of block row e: list of (col element, T, S, row field, col field)
         meaning rows [field_r][c][i][s] of e receive (T kron S) applied to the
         trial coefficients [field_c][d][m][t] of the column element."""
-        qe = int(self.q[e])
         a = int(self.a[e])
-        D, N = self.tables(qe, qe)
+        D, N = self.own_tables(e)
         SE, SH = self.self_spatial(e)
         out = [(e, D, self.mass(e, "eps"), 0, 0),
                (e, dt * N, SE, 0, 1),
@@ -395,10 +448,8 @@ class Discretisation:
         for f in range(6):
             for (k, fk, A, b, sub) in self.hang.get((e, f), ()):
                 # a 2:1 hanging face: each neighbour couples over its part of the face
-                qk, ak = int(self.q[k]), int(self.a[k])
-                _, Nc = self.tables(qe, qk)
-                Nc = Nc.copy()
-                Nc[min(qe, qk):, :] = 0.0
+                ak = int(self.a[k])
+                Nc = self.coupling_table(e, k)
                 key = ("FH", a, f, ak, int(fk), tuple(np.ravel(A)), tuple(np.ravel(b)), sub)
                 if key not in self._cache:
                     self._cache[key] = face_matrices_oriented(a, f, ak, int(fk), np.asarray(A, float),
@@ -409,10 +460,8 @@ class Discretisation:
             k = int(self.nb[e, f])
             if k < 0:
                 continue
-            qk, ak = int(self.q[k]), int(self.a[k])
-            _, Nc = self.tables(qe, qk)
-            Nc = Nc.copy()
-            Nc[min(qe, qk):, :] = 0.0            # S_h: neighbour coupling only on common test modes
+            ak = int(self.a[k])
+            Nc = self.coupling_table(e, k)       # S_h: neighbour coupling on the common test space
             if (e, f) in self.fmap:
                 A, b = self.fmap[(e, f)]
                 key = ("FO", a, f, ak, int(self.nbf[e, f]), tuple(A.ravel()), tuple(b))
@@ -434,7 +483,6 @@ class Discretisation:
         so rows i >= min(q, q') vanish for own and neighbour trial alike); on
         PEC faces (alpha_E [E]_T, [v]_T) with g = 0.  alpha_E = c / {sqrt(mu/eps)},
         alpha_H = c / {sqrt(eps/mu)}."""
-        qe = int(self.q[e])
         a = int(self.a[e])
         Xe = self.X(e)
         out = []
@@ -457,20 +505,16 @@ class Discretisation:
         for f in range(6):
             k = int(self.nb[e, f])
             if k < 0:
-                _, N = self.tables(qe, qe)
+                _, N = self.own_tables(e)
                 Ds, _ = face_mats(f, -1)
                 out.append((e, dt * N, (self.c_diss / ze) * Ds, 0, 0))
                 continue
-            qk, ak = int(self.q[k]), int(self.a[k])
-            r = min(qe, qk)
+            ak = int(self.a[k])
             aE = self.c_diss / (0.5 * (ze + np.sqrt(self.mu[k] / self.eps[k])))
             aH = self.c_diss / (0.5 * (zh + np.sqrt(self.eps[k] / self.mu[k])))
             Ds, Dn = face_mats(f, k)
-            _, Ns = self.tables(qe, qe)
-            _, Nk = self.tables(qe, qk)
-            Ns, Nk = Ns.copy(), Nk.copy()
-            Ns[r:, :] = 0.0
-            Nk[r:, :] = 0.0
+            Ns = self.coupling_table(e, k, trial=e)
+            Nk = self.coupling_table(e, k)
             out.append((e, dt * Ns, aE * Ds, 0, 0))
             out.append((e, dt * Ns, aH * Ds, 1, 1))
             out.append((k, dt * Nk, -aE * Dn, 0, 0))
@@ -482,9 +526,9 @@ class Discretisation:
         """[2][3 a^3][q+1] view-friendly reshape of element e's trial block ->
         array T[field, (d,t), m]."""
         a3 = int(self.a[e]) ** 3
-        qe = int(self.q[e])
-        blk = U[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, qe + 1, a3)
-        return blk.transpose(0, 1, 3, 2).reshape(2, 3 * a3, qe + 1)
+        te = int(self.nt[e])
+        blk = U[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, te + 1, a3)
+        return blk.transpose(0, 1, 3, 2).reshape(2, 3 * a3, te + 1)
 
     def embed_unknowns(self, x, l0_state=None, elements=None):
         """Full trial vector from unknowns (m = 1..q) and an optional l_0 state.
@@ -493,9 +537,9 @@ class Discretisation:
         for e in (range(self.ne) if elements is None else elements):
             e = int(e)
             a3 = int(self.a[e]) ** 3
-            qe = int(self.q[e])
-            blk = U[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, qe + 1, a3)
-            blk[:, :, 1:, :] = x[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, qe, a3)
+            te = int(self.nt[e])
+            blk = U[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, te + 1, a3)
+            blk[:, :, 1:, :] = x[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, te, a3)
             if l0_state is not None:
                 blk[:, :, 0, :] = l0_state[self.state_off[e]:self.state_off[e + 1]].reshape(2, 3, a3)
         return U
@@ -504,8 +548,8 @@ class Discretisation:
         x = np.zeros(self.unk_off[-1])
         for e in range(self.ne):
             a3 = int(self.a[e]) ** 3
-            qe = int(self.q[e])
-            blk = U[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, qe + 1, a3)
+            te = int(self.nt[e])
+            blk = U[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, te + 1, a3)
             x[self.unk_off[e]:self.unk_off[e + 1]] = blk[:, :, 1:, :].ravel()
         return x
 
@@ -515,8 +559,8 @@ class Discretisation:
         S = np.zeros(self.state_off[-1])
         for e in range(self.ne):
             a3 = int(self.a[e]) ** 3
-            qe = int(self.q[e])
-            blk = U[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, qe + 1, a3)
+            te = int(self.nt[e])
+            blk = U[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, te + 1, a3)
             S[self.state_off[e]:self.state_off[e + 1]] = blk[:, :, m, :].ravel()
         return S
 
@@ -529,13 +573,13 @@ class Discretisation:
         res = {}
         for e in elements:
             e = int(e)
-            qe = int(self.q[e])
+            te = int(self.nt[e])
             a3 = int(self.a[e]) ** 3
-            Y = np.zeros((2, 3 * a3, qe))
+            Y = np.zeros((2, 3 * a3, te))
             for (k, T, S, fr, fc) in self.blocks(e, dt):
                 Uk = self.split_trial(U, k)[fc]             # [(d,t), m]
                 Y[fr] += S @ Uk @ T.T                       # (T kron S) u  =  S U T^T
-            res[e] = Y.reshape(2, 3, a3, qe).transpose(0, 1, 3, 2).ravel()
+            res[e] = Y.reshape(2, 3, a3, te).transpose(0, 1, 3, 2).ravel()
         return res
 
     def residual(self, U, dt, load=None, elements=None):
@@ -561,20 +605,27 @@ class Discretisation:
     # -- preconditioner (Section 5.4, eq. preconditioner) -----------------------
     def precond_solve(self, y, elements=None):
         """P^{-1} y with P the time-derivative terms restricted to the unknowns:
-        block diagonal D (identity on m >= 1) kron the element mass matrix.
-        With ``elements`` only those blocks are computed (others left 0)."""
+        block diagonal D_u kron the element mass matrix, D_u the columns m >= 1
+        of the element's D (the identity with one sub-interval; with several,
+        row (j, i) holds +1 at the level of l_{i+1} of sub-interval j, and row
+        (j, 0), j > 0, also -1 at the value of node j, which is l_0 of
+        sub-interval j).  With ``elements`` only those blocks are computed
+        (others left 0)."""
         out = np.zeros_like(y)
         for e in (range(self.ne) if elements is None else elements):
             e = int(e)
             a3 = int(self.a[e]) ** 3
-            qe = int(self.q[e])
-            blk = y[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, qe, a3)
+            te = int(self.nt[e])
+            blk = y[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, te, a3)
+            Du = self.own_tables(e)[0][:, 1:]
             res = np.zeros_like(blk)
             for fld, which in ((0, "eps"), (1, "mu")):
                 M = self.mass(e, which)
-                rhs = blk[fld].transpose(0, 2, 1).reshape(3 * a3, qe)
-                sol = np.linalg.solve(M, rhs)
-                res[fld] = sol.reshape(3, a3, qe).transpose(0, 2, 1)
+                rhs = blk[fld].transpose(0, 2, 1).reshape(3 * a3, te)
+                sol = np.linalg.solve(M, rhs)                  # [(c,s), I]
+                if self.nk[e] > 1:                             # sum_m Du[I, m] x_m = z_I
+                    sol = np.linalg.solve(Du, sol.T).T
+                res[fld] = sol.reshape(3, a3, te).transpose(0, 2, 1)
             out[self.unk_off[e]:self.unk_off[e + 1]] = res.ravel()
         return out
 
@@ -589,11 +640,15 @@ class Discretisation:
         for e in (range(self.ne) if elements is None else elements):
             e = int(e)
             a3 = int(self.a[e]) ** 3
-            qe = int(self.q[e])
+            te = int(self.nt[e])
             DF = jacobian(self.X(e), np.array([[0.5, 0.5, 0.5]]))[0]
             Di = np.linalg.inv(DF)
             G = np.linalg.det(DF) * Di @ Di.T
-            blk = y[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, qe * a3)
+            Du = self.own_tables(e)[0][:, 1:]
+            blk = y[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, te, a3)
+            if self.nk[e] > 1:
+                blk = np.einsum("mI,fcIs->fcms", np.linalg.inv(Du), blk)
+            blk = blk.reshape(2, 3, te * a3)
             res = np.empty_like(blk)
             res[0] = np.linalg.solve(self.eps[e] * G, blk[0])
             res[1] = np.linalg.solve(self.mu[e] * G, blk[1])
@@ -606,22 +661,23 @@ class Discretisation:
         L2(I_n; L2(Omega)) norm (Section 5.3): the Riesz representor of a
         residual-layout vector R [f][c][i][s] solves (dt M_K) z_i = R_i per
         element and test level (test functions orthonormal in time on [0, 1],
-        dx dt = dt dx dtau), M_K the unit-coefficient element mass; the norm is
-        R . z."""
+        dx dt = dt dx dtau; with n sub-intervals each test function lives on
+        one of length dt / n, so the factor is dt / n), M_K the unit-coefficient
+        element mass; the norm is R . z."""
         out = np.zeros(2)
         for e in (range(self.ne) if elements is None else elements):
             e = int(e)
             a = int(self.a[e])
             a3 = a ** 3
-            qe = int(self.q[e])
+            te = int(self.nt[e])
             key = ("M1", a, self.nq(e), tuple(np.round((self.X(e) - self.X(e)[0]).ravel(), 14)))
             if key not in self._cache:
                 self._cache[key] = mass_matrix(self.X(e), a, 1.0, self.nq(e))
             M = self._cache[key]
-            blk = R[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, qe, a3)
+            blk = R[self.unk_off[e]:self.unk_off[e + 1]].reshape(2, 3, te, a3)
             for f in range(2):
-                rhs = blk[f].transpose(0, 2, 1).reshape(3 * a3, qe)
-                z = np.linalg.solve(M, rhs) / dt
+                rhs = blk[f].transpose(0, 2, 1).reshape(3 * a3, te)
+                z = np.linalg.solve(M, rhs) / (dt / int(self.nk[e]))
                 out[f] += float(np.sum(rhs * z))
         return out
 
@@ -648,7 +704,8 @@ class Discretisation:
     def load(self, J, t0, dt, nx=None, nt=None):
         """L_E[c, i, s] = int_{I_n} int_K J . (DF^{-T} e_c phi_s) L_i dx dt by
         tensor Gauss quadrature (p + 3 points per space direction, q + 3 in
-        time unless given); the H part is zero (g = 0).  J(x [P,3], t) -> [P,3]."""
+        time per sub-interval unless given); the H part is zero (g = 0).
+        J(x [P,3], t) -> [P,3]."""
         L = np.zeros(self.unk_off[-1])
         for e in range(self.ne):
             L[self.unk_off[e]:self.unk_off[e + 1]] = self._load_block(e, J, t0, dt, nx, nt)
@@ -661,6 +718,7 @@ class Discretisation:
     def _load_block(self, e, J, t0, dt, nx, nt):
         a = int(self.a[e])
         qe = int(self.q[e])
+        nsub = int(self.nk[e])
         n = a + 2 if nx is None else nx
         m = qe + 3 if nt is None else nt
         pts, w = tensor_points(n)
@@ -671,15 +729,16 @@ class Discretisation:
         det = np.linalg.det(DF)
         Dinv = np.linalg.inv(DF)
         Phi, _ = basis_at(a, pts)
-        acc = np.zeros((3, qe, a ** 3))
-        for tau, wt in zip(tx, tw):
-            Jv = J(x, t0 + tau * dt)                            # [P, 3]
-            # J . DF^{-T} e_c = (DF^{-1} J)_c
-            Jr = np.einsum("pcm,pm->pc", Dinv, Jv) * (det * w)[:, None]
-            proj = Jr.T @ Phi                                   # [3, a^3]
-            for i in range(qe):
-                acc[:, i, :] += dt * wt * basis.L(i, tau) * proj
-        blk = np.zeros((2, 3, qe, a ** 3))
+        acc = np.zeros((3, nsub * qe, a ** 3))
+        for j in range(nsub):
+            for tau, wt in zip(tx, tw):
+                Jv = J(x, t0 + (j + tau) * dt / nsub)           # [P, 3]
+                # J . DF^{-T} e_c = (DF^{-1} J)_c
+                Jr = np.einsum("pcm,pm->pc", Dinv, Jv) * (det * w)[:, None]
+                proj = Jr.T @ Phi                               # [3, a^3]
+                for i in range(qe):
+                    acc[:, j * qe + i, :] += (dt / nsub) * wt * basis.L(i, tau) * proj
+        blk = np.zeros((2, 3, nsub * qe, a ** 3))
         blk[0] = acc
         return blk.ravel()
 
@@ -688,15 +747,15 @@ class Discretisation:
         """Sparse B with rows = test dofs (residual layout), cols = full trial dofs."""
         rows, cols, vals = [], [], []
         for e in range(self.ne):
-            qe = int(self.q[e])
+            te = int(self.nt[e])
             a3 = int(self.a[e]) ** 3
             for (k, T, S, fr, fc) in self.blocks(e, dt):
-                qk = int(self.q[k])
+                tk = int(self.nt[k])
                 ak3 = int(self.a[k]) ** 3
                 S4 = S.reshape(3, a3, 3, ak3)
-                Bk = np.einsum("im,csdt->cisdmt", T, S4).reshape(3 * qe * a3, 3 * (qk + 1) * ak3)
-                r0 = self.unk_off[e] + fr * 3 * qe * a3
-                c0 = self.trial_off[k] + fc * 3 * (qk + 1) * ak3
+                Bk = np.einsum("im,csdt->cisdmt", T, S4).reshape(3 * te * a3, 3 * (tk + 1) * ak3)
+                r0 = self.unk_off[e] + fr * 3 * te * a3
+                c0 = self.trial_off[k] + fc * 3 * (tk + 1) * ak3
                 ii, jj = np.nonzero(Bk)
                 rows.append(r0 + ii)
                 cols.append(c0 + jj)
@@ -711,8 +770,8 @@ class Discretisation:
         mask = np.zeros(self.trial_off[-1], dtype=bool)
         for e in range(self.ne):
             a3 = int(self.a[e]) ** 3
-            qe = int(self.q[e])
-            blk = mask[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, qe + 1, a3)
+            te = int(self.nt[e])
+            blk = mask[self.trial_off[e]:self.trial_off[e + 1]].reshape(2, 3, te + 1, a3)
             blk[:, :, 1:, :] = True
         return mask
 
