@@ -118,6 +118,8 @@ typedef struct {
   const int32_t* q;         /* [n_elements] temporal degree, 1 <= q <= 6          */
   const double* eps;        /* [n_elements] permittivity > 0                      */
   const double* mu;         /* [n_elements] permeability > 0                      */
+  const int32_t* nsub;      /* [n_elements] temporal sub-intervals: 1, 2, 4 or 8
+                               (n q <= 24), or NULL for one per element          */
 } stdg_mesh_desc;
 
 typedef struct {
@@ -148,7 +150,25 @@ typedef struct {
  * Legendre restrictions, exact for affine faces.  A face split among smaller
  * elements in any other way (found by their centroids at its quarter points)
  * is refused with STDG_E_UNSUPPORTED.  Meshes with hanging faces do not take
- * D_h (stdg_mesh_set_dissipation) and run their serving cycles alone. */
+ * D_h (stdg_mesh_set_dissipation) and run their serving cycles alone.
+ *
+ * Local time steps (Section 2.2: each macro-element's slab interval bisected
+ * in time; trial space continuous piecewise P_q, test space piecewise
+ * P_{q-1}, eq. spaces:local:patch): an element with n = nsub[e] > 1 equal
+ * sub-intervals holds 1 + n q trial levels and n q test levels per field and
+ * component.  Trial level 0 is the value at the slab start and level 1 the
+ * value at the slab end (as with n = 1, so slab transfer, the initial guess
+ * and stdg_energy are unchanged); sub-interval j then owns levels
+ * 2 + j q .. 1 + (j + 1) q: its interior functions l_2..l_q and, for
+ * j < n - 1, the value at its right end.  Test level j q + i is L_i on
+ * sub-interval j (L_i(n s - j), s the unit slab coordinate).  Neighbours
+ * couple through S_h (Section 4.1, eq. bilinearform:S): the test function
+ * projected onto their common temporal test space, piecewise P_{min(q,q')-1}
+ * on the coarser of the two partitions.  Such elements and their face
+ * neighbours must be affine, and the mesh may not have hanging faces
+ * (STDG_E_UNSUPPORTED); D_h, stdg_load_assemble, dual norms and inexact
+ * solves, batched applies and serving requests refuse meshes with local time
+ * steps. */
 int stdg_mesh_upload(stdg_ctx* ctx, const stdg_mesh_desc* desc, stdg_mesh** out);
 int stdg_mesh_info(const stdg_mesh* mesh, stdg_mesh_info_t* out);
 /* Host copies of the element offsets (n_elements + 1 entries each, any may be NULL). */

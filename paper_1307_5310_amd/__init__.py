@@ -45,8 +45,9 @@ def stdg_finalize(ctx):
     check(lib().stdg_finalize(ctx))
 
 
-def _mesh_desc(vertices, hexes, p, q, eps, mu):
-    """MeshDesc over contiguous copies; returns (desc, arrays kept alive)."""
+def _mesh_desc(vertices, hexes, p, q, eps, mu, nsub=None):
+    """MeshDesc over contiguous copies; returns (desc, arrays kept alive).
+    ``nsub``: temporal sub-intervals per element (local time steps), or None."""
     v = np.ascontiguousarray(vertices, dtype=np.float64)
     h = np.ascontiguousarray(hexes, dtype=np.int64)
     p = np.ascontiguousarray(p, dtype=np.int32)
@@ -59,16 +60,17 @@ def _mesh_desc(vertices, hexes, p, q, eps, mu):
         raise ValueError("vertices must have shape (n_vertices, 3), got %s" % (v.shape,))
     if h.ndim != 2 or h.shape[1] != 8:
         raise ValueError("hexes must have shape (n_elements, 8), got %s" % (h.shape,))
-    for name, a in (("p", p), ("q", q), ("eps", eps), ("mu", mu)):
-        if a.shape != (h.shape[0],):
+    ns = None if nsub is None else np.ascontiguousarray(nsub, dtype=np.int32)
+    for name, a in (("p", p), ("q", q), ("eps", eps), ("mu", mu), ("nsub", ns)):
+        if a is not None and a.shape != (h.shape[0],):
             raise ValueError("%s must have shape (%d,), got %s" % (name, h.shape[0], a.shape))
     d = MeshDesc(v.shape[0], v.ctypes.data, h.shape[0], h.ctypes.data, p.ctypes.data,
-                 q.ctypes.data, eps.ctypes.data, mu.ctypes.data)
-    return d, (v, h, p, q, eps, mu)
+                 q.ctypes.data, eps.ctypes.data, mu.ctypes.data, None if ns is None else ns.ctypes.data)
+    return d, (v, h, p, q, eps, mu, ns)
 
 
-def stdg_mesh_upload(ctx, vertices, hexes, p, q, eps, mu):
-    d, _keep = _mesh_desc(vertices, hexes, p, q, eps, mu)
+def stdg_mesh_upload(ctx, vertices, hexes, p, q, eps, mu, nsub=None):
+    d, _keep = _mesh_desc(vertices, hexes, p, q, eps, mu, nsub)
     out = ctypes.c_void_p()
     check(lib().stdg_mesh_upload(ctx, ctypes.byref(d), ctypes.byref(out)))
     return out

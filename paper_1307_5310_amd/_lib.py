@@ -37,7 +37,8 @@ class MeshDesc(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_int64), ("vertices", ctypes.c_void_p),
                 ("n_elements", ctypes.c_int64), ("hexes", ctypes.c_void_p),
                 ("p", ctypes.c_void_p), ("q", ctypes.c_void_p),
-                ("eps", ctypes.c_void_p), ("mu", ctypes.c_void_p)]
+                ("eps", ctypes.c_void_p), ("mu", ctypes.c_void_p),
+                ("nsub", ctypes.c_void_p)]
 
 
 class MeshInfo(ctypes.Structure):

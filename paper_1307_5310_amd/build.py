@@ -26,7 +26,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstdg.so")
 
 HOST_SOURCES = ["api.cpp", "mesh.cpp", "tables.cpp", "solver.cpp", "serve.cpp"]
-HIP_SOURCES = ["residual.hip", "blas.hip", "krylov.hip", "load.hip", "dualnorm.hip", "dissipation.hip", "hanging.hip"]
+HIP_SOURCES = ["residual.hip", "blas.hip", "krylov.hip", "load.hip", "dualnorm.hip", "dissipation.hip", "hanging.hip",
+               "local_time.hip"]
 # (precision, a, affine, dissipative): the dissipative variants exist for affine elements only
 SLICES = [(real, a, aff, 0) for real in ("float", "double") for a in range(2, 10) for aff in (1, 0)] + \
          [(real, a, 1, 1) for real in ("float", "double") for a in range(2, 10)]

@@ -13,13 +13,13 @@ __global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ x
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] += a * x[i];
 }
 
-// full trial U (per element [f][c][m=0..q][s]) from unknowns x ([f][c][m=1..q][s])
-// and a state ([f][c][s]) for the l_0 block
+// full trial U (per element [f][c][m=0..n q][s]) from unknowns x ([f][c][m=1..n q][s])
+// and a state ([f][c][s]) for the l_0 block (n = sub-intervals, usually 1)
 __global__ void embed_kernel(double* __restrict__ U, const double* __restrict__ x, const double* __restrict__ st,
                              const ElemInfo* __restrict__ info, const int64_t* __restrict__ soff) {
   const int64_t e = blockIdx.x;
   const ElemInfo I = info[e];
-  const int a3 = I.a * I.a * I.a, q = I.q;
+  const int a3 = I.a * I.a * I.a, q = I.q * I.nsub;
   const int per = (q + 1) * a3;
   for (int idx = threadIdx.x; idx < 6 * per; idx += blockDim.x) {
     const int fc = idx / per, rest = idx - fc * per;
@@ -33,24 +33,26 @@ __global__ void level_kernel(double* __restrict__ st, const double* __restrict__
                              const ElemInfo* __restrict__ info, const int64_t* __restrict__ soff) {
   const int64_t e = blockIdx.x;
   const ElemInfo I = info[e];
-  const int a3 = I.a * I.a * I.a, q = I.q;
+  const int a3 = I.a * I.a * I.a, q = I.q * I.nsub;
   for (int idx = threadIdx.x; idx < 6 * a3; idx += blockDim.x) {
     const int fc = idx / a3, s = idx - fc * a3;
     st[soff[e] + idx] = x[I.unk_off + ((int64_t)fc * q + lev - 1) * a3 + s];
   }
 }
 
-// unknowns initial guess: level 1 = state (constant continuation), others 0
+// unknowns initial guess, the constant continuation: the values at the slab
+// end (level 1) and, with sub-intervals, at their interior ends (levels
+// 1 + j q) = state, the interior functions 0
 __global__ void guess_kernel(double* __restrict__ x, const double* __restrict__ st, const ElemInfo* __restrict__ info,
                              const int64_t* __restrict__ soff) {
   const int64_t e = blockIdx.x;
   const ElemInfo I = info[e];
   const int a3 = I.a * I.a * I.a, q = I.q;
-  const int per = q * a3;
+  const int per = q * I.nsub * a3;
   for (int idx = threadIdx.x; idx < 6 * per; idx += blockDim.x) {
     const int fc = idx / per, rest = idx - fc * per;
-    const int m = rest / a3, s = rest - m * a3;
-    x[I.unk_off + idx] = m == 0 ? st[soff[e] + (int64_t)fc * a3 + s] : 0.0;
+    const int m = rest / a3, s = rest - m * a3;  // unknown m is trial level m + 1
+    x[I.unk_off + idx] = m % q == 0 ? st[soff[e] + (int64_t)fc * a3 + s] : 0.0;
   }
 }
 

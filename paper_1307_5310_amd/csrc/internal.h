@@ -34,7 +34,38 @@ enum : int32_t {
   kBoundaryBase = 8,  // bit 3 + f: face f is a PEC boundary face
   kHanging = 512,     // a face of this element is a 2:1 hanging face (ElemInfo.pad indexes HangRec)
   kHangFaceBase = 1024,  // bit 10 + f: face f is a 2:1 hanging face (either side)
+  kLocalTime = 1 << 16,  // this element or a face neighbour has several temporal sub-intervals:
+                         // its row runs in the local-time kernel (ElemInfo.pad indexes LTRec)
 };
+
+// Local time steps (Section 2.2): the slab interval of an element bisected
+// into n = ElemInfo.nsub equal sub-intervals (a power of two, 1..kMaxSub).
+// Its trial block holds 1 + n q levels (continuous piecewise P_q in time):
+// level 0 the value at the slab start, level 1 the value at the slab end,
+// then per sub-interval j the q levels 2 + j q .. 1 + (j + 1) q: its l_2..l_q
+// and, for j < n - 1, the value at its right end (also l_0 of sub-interval
+// j + 1).  Its n q test levels are L_i on sub-interval j at j q + i.
+constexpr int kMaxSub = 8;
+constexpr int kMaxLocalLevels = 24;  // n q <= 24 test levels
+inline int local_trial_level(int q, int n, int j, int m) {
+  if (m == 0) return j == 0 ? 0 : 1 + j * q;
+  if (m == 1) return j == n - 1 ? 1 : 1 + (j + 1) * q;
+  return 2 + j * q + m - 2;
+}
+// Row of an element with kLocalTime: offsets into the table bank of its own
+// time tables (D[I][M] = int L_I d_s phi_M, N[I][M] = int L_I phi_M over the
+// unit slab coordinate s; n q rows, 1 + n q columns) and, per face, of the
+// neighbour coupling C[I][M'] = int (pi L_I) phi'_M' (pi the projection onto
+// the common temporal test space of S_h, Section 4.1; 1 + n' q' columns);
+// -1 on boundary faces.
+struct LTRec {
+  int32_t elem;
+  int32_t d_off, n_off;
+  int32_t c_off[6];
+};
+// Time tables of local time steps into `bank` (tables.cpp); returns the offset.
+int local_time_tables(int q, int n, std::vector<double>* bank, int32_t* d_off, int32_t* n_off);
+int local_coupling_table(int q, int n, int qk, int nk, std::vector<double>* bank);
 
 // 2:1 hanging faces (Section 5.2 sums the flux terms of a face over the
 // neighbours that share parts of it): a coarse face covered by the faces of
@@ -75,7 +106,8 @@ struct ElemInfo {
   int64_t trial_off, unk_off;
   int32_t nb[6];
   uint8_t orient[6];
-  uint8_t pad2[2];
+  uint8_t nsub;  // temporal sub-intervals (1 = one temporal element per slab)
+  uint8_t pad2;
 };
 static_assert(sizeof(ElemInfo) == 64, "ElemInfo layout");
 
@@ -192,6 +224,15 @@ struct Mesh {
   HangRec* d_hang = nullptr;
   void* d_hs64 = nullptr;
   void* d_hs32 = nullptr;
+  // local time steps: sub-intervals per element, the rows of the local-time
+  // kernel (elements with kLocalTime, left out of the kernel groups) and the
+  // time-table bank (FP64, FP32)
+  std::vector<int32_t> nsub;
+  std::vector<LTRec> lt;
+  std::vector<double> lt_bank;
+  LTRec* d_lt = nullptr;
+  void* d_ltb64 = nullptr;
+  void* d_ltb32 = nullptr;
   // side streams for applies over several kernel groups (created on first use):
   // the groups run concurrently, forked from and joined back into the caller's stream
   static constexpr int kAux = 4;
@@ -265,6 +306,11 @@ int stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 // diagonal meshes, else x already scaled and mode 0)
 template <typename T>
 int launch_hanging(const Mesh* m, double dt, int mode, const T* x, T* y, hipStream_t s, const int* skip);
+// the rows of the elements with kLocalTime, written to y (local_time.hip);
+// mode 0 or STDG_RESIDUAL (preconditioned applies take the P^{-1} pre-pass)
+template <typename T>
+int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* load, T* y, hipStream_t s,
+                      const int* skip);
 // D_h on the trilinear group g, added to y (dissipation.hip); mode 0 or STDG_RESIDUAL
 template <typename T>
 int launch_diss_trilinear(const Mesh* m, const Group& g, double dt, int mode, const T* x, T* y, hipStream_t s,

@@ -437,6 +437,7 @@ int energy_async(const Mesh* m, const double* state, double* d_partial, double* 
 }
 
 int dual_norms_async(const Mesh* m, double dt, const double* R, double* d_partial, double* d_out, hipStream_t s) {
+  if (!m->lt.empty()) return fail(STDG_E_UNSUPPORTED, "dual norms with local time steps");
   hipLaunchKernelGGL(dual_norm_kernel, dim3((unsigned)m->ne), dim3(256), 0, s, m->d_info, m->d_metric, m->ne, R,
                      d_partial);
   if (m->n_nonaffine > 0) {
@@ -472,6 +473,7 @@ int stdg_load_assemble(const stdg_mesh* mesh, const stdg_source* src, double t0,
   if (src->kind == 1 && (!(src->sigma_x > 0.0) || !(src->sigma_t > 0.0)))
     return fail(STDG_E_ARG, "stdg_load_assemble: sigma_x and sigma_t must be > 0");
   const Mesh& m = mesh->m;
+  if (!m.lt.empty()) return fail(STDG_E_UNSUPPORTED, "stdg_load_assemble: local time steps");
   LoadParams P;
   P.info = m.d_info;
   P.verts = m.d_verts;

@@ -1,0 +1,218 @@
+// Rows of the elements with local time steps (Section 2.2: a macro-element's
+// slab interval bisected into n equal sub-intervals; eq. spaces:local:patch)
+// and of their face neighbours: one workgroup per such element, every test
+// level I = j q + i in turn.  The same terms as the residual kernels, with the
+// time factors read from tables instead of the one-interval shift and N:
+//   mass   R_F[c,I,s] += sum_d M_F[c][d] sum_M D[I][M] x_F[d,M,s]
+//   curl   with the contracted fields F~_I = sum_M N[I][M] x_F[., M]:
+//          R_H[c] += dt (sum_n Dh[s_c1][n] E~_c2(s_c1 -> n) - sum_n Dh[s_c2][n] E~_c1(s_c2 -> n))
+//          R_E[c] += dt (sum_n Dh[n][s_c1] H~_c2(s_c1 -> n) - sum_n Dh[n][s_c2] H~_c1(s_c2 -> n))
+//          ((c1, c2) = (c + 1, c + 2) mod 3)
+//   faces  F = 1/2 T_self(H~) + 1/2 T_nb(H), G = -1/2 T_self(E~) + 1/2 T_nb(E)
+//          (interior), F = T_self(H~), G = -T_self(E~) (PEC), lifted as
+//          R_E[c] += dt sigma eps(c,d,alpha) L_{s_alpha}(side) F_d,
+//          R_H[c] -= dt sigma eps(c,d,alpha) L_{s_alpha}(side) G_d,  d = 3 - c - alpha
+// where T_nb contracts the neighbour's trial levels with the coupling table
+// C[I][M'] = int (pi L_I) phi'_M' of S_h (Section 4.1, eq. bilinearform:S: the
+// test function projected onto the common temporal test space), in this
+// element's covariant frame through the face orientation, modes < min(a, a').
+// D[I][M] = int L_I d_s phi_M and N[I][M] = int L_I phi_M are the element's own
+// tables over the unit slab coordinate s.  Elements with one sub-interval
+// whose neighbour has several run here too (their coupling changes).
+#include "internal.h"
+
+namespace stdg {
+
+namespace {
+
+constexpr int kLThreads = 256;
+
+template <typename T>
+struct LParams {
+  const ElemInfo* info;
+  const ElemMetric* metric;
+  const LTRec* rec;
+  const T* bank;    // time tables (LTRec offsets)
+  const T* x;
+  const T* load;    // residual mode: subtracted (may be NULL)
+  T* y;
+  const int* skip;
+  T dt;
+  int resid;        // x is the full trial vector (levels 0..), else the unknowns (levels 1..)
+  Tables<T> tab;    // Dh and the face traces
+};
+
+__device__ inline int axis_stride(int axis, int a) { return axis == 0 ? 1 : (axis == 1 ? a : a * a); }
+
+template <typename T>
+__global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
+  if (P.skip && *P.skip == 0) return;
+  __shared__ T xn[6 * kMaxA * kMaxA * kMaxA];  // contracted own fields [F][c][s] of level I
+  __shared__ T fl[6 * 4 * kMaxA * kMaxA];      // [face][F_u, F_v, G_u, G_v][face mode]
+  const LTRec* R = P.rec + blockIdx.x;  // read through the pointer (no private copy)
+  const int e = R->elem;
+  const ElemInfo* Ie = P.info + e;
+  const int a = Ie->a, q = Ie->q, a2 = a * a, a3 = a2 * a;
+  const int nt = q * Ie->nsub;  // test levels
+  const int ncol = nt + 1;      // trial levels (columns of the own tables)
+  const int m0 = P.resid ? 0 : 1;
+  const int nst = ncol - m0;    // stored trial levels
+  const T* D = P.bank + R->d_off;
+  const T* N = P.bank + R->n_off;
+  const T* xe = P.x + (P.resid ? Ie->trial_off : Ie->unk_off);
+  T* ye = P.y + Ie->unk_off;
+  const T* le = (P.resid && P.load) ? P.load + Ie->unk_off : nullptr;
+  const double* Me = P.metric[e].m;
+  const int tid = threadIdx.x;
+  for (int I = 0; I < nt; ++I) {
+    __syncthreads();  // the previous level's readers of xn and fl are done
+    for (int t = tid; t < 6 * a3; t += kLThreads) {
+      const int fc = t / a3, s = t - fc * a3;
+      const T* xp = xe + (int64_t)fc * nst * a3 + s;
+      T v = T(0);
+      for (int M = m0; M < ncol; ++M) {
+        const T w = N[I * ncol + M];
+        if (w != T(0)) v += w * xp[(int64_t)(M - m0) * a3];
+      }
+      xn[t] = v;
+    }
+    __syncthreads();
+    for (int t = tid; t < 24 * a2; t += kLThreads) {
+      const int g = t / (4 * a2), rest = t - g * 4 * a2, ft = rest / a2, jj = rest - ft * a2;
+      const int fu = jj % a, fv = jj / a;
+      const int alpha = g >> 1, side = g & 1;
+      const int ua = alpha == 0 ? 1 : 0, va = alpha == 2 ? 1 : 2;
+      const int which = ft >> 1;           // 0: F (H traces), 1: G (E traces)
+      const bool slot_u = (ft & 1) == 0;   // tangential component along u (else v)
+      const int fld = which == 0 ? 1 : 0;  // field of the traces
+      const int d = slot_u ? ua : va;
+      // own trace of the contracted field
+      const T* own = xn + (3 * fld + d) * a3 + fu * axis_stride(ua, a) + fv * axis_stride(va, a);
+      const int sn = axis_stride(alpha, a);
+      T ts = T(0);
+      for (int l = 0; l < a; ++l) ts += (side ? P.tab.tr1[l] : P.tab.tr0[l]) * own[l * sn];
+      const int k = Ie->nb[g];
+      T val;
+      if (k < 0) {
+        val = which == 0 ? ts : -ts;
+      } else {
+        const uint8_t code = Ie->orient[g];
+        const int fo = code & 7, alo = fo >> 1, sdo = fo & 1;
+        const int uo = alo == 0 ? 1 : 0, vo = alo == 2 ? 1 : 2;
+        const bool swap = (code & kOrientSwap) != 0, flu = (code & kOrientFlipU) != 0, flv = (code & kOrientFlipV) != 0;
+        const int mu_ax = swap ? vo : uo, mv_ax = swap ? uo : vo;  // the neighbour's axes matched with our u, v
+        const int cn = slot_u ? mu_ax : mv_ax;
+        const ElemInfo* Ik = P.info + k;
+        const int ak = Ik->a, ak3 = ak * ak * ak;
+        T tn = T(0);
+        if (fu < ak && fv < ak) {
+          const int nck = Ik->q * Ik->nsub + 1;  // the neighbour's trial levels
+          const int nstk = nck - m0;
+          const T* C = P.bank + R->c_off[g] + I * nck;
+          const T* xk = P.x + (P.resid ? Ik->trial_off : Ik->unk_off) + (int64_t)(3 * fld + cn) * nstk * ak3 +
+                        fu * axis_stride(mu_ax, ak) + fv * axis_stride(mv_ax, ak);
+          const int snk = axis_stride(alo, ak);
+          for (int M = m0; M < nck; ++M) {
+            const T w = C[M];
+            if (w == T(0)) continue;
+            const T* xp = xk + (int64_t)(M - m0) * ak3;
+            T tr = T(0);
+            for (int l = 0; l < ak; ++l) tr += (sdo ? P.tab.tr1[l] : P.tab.tr0[l]) * xp[l * snk];
+            tn += w * tr;
+          }
+          // covariant component along a reversed axis, and odd modes along reversed axes
+          const bool neg = (slot_u ? flu : flv) ^ (flu && (fu & 1)) ^ (flv && (fv & 1));
+          if (neg) tn = -tn;
+        }
+        val = T(0.5) * ((which == 0 ? ts : -ts) + tn);
+      }
+      fl[t] = val;
+    }
+    __syncthreads();
+    for (int t = tid; t < 6 * a3; t += kLThreads) {
+      const int fc = t / a3, s = t - fc * a3;
+      const int f = fc / 3, c = fc - 3 * f;
+      const int s0 = s % a, s1 = (s / a) % a, s2 = s / a2;
+      auto si = [&](int axis) { return axis == 0 ? s0 : (axis == 1 ? s1 : s2); };  // no private array
+      // mass: the metric block of field f applied to the D-contracted levels
+      const T* xp = xe + (int64_t)(3 * f) * nst * a3 + s;
+      T xd[3];
+#pragma unroll
+      for (int dd = 0; dd < 3; ++dd) {
+        T v = T(0);
+        for (int M = m0; M < ncol; ++M) {
+          const T w = D[I * ncol + M];
+          if (w != T(0)) v += w * xp[((int64_t)dd * nst + M - m0) * a3];
+        }
+        xd[dd] = v;
+      }
+      const double* Mf = Me + 6 * f;
+      const T mass = (T)Mf[c == 0 ? 0 : (c == 1 ? 3 : 4)] * xd[0] + (T)Mf[c == 0 ? 3 : (c == 1 ? 1 : 5)] * xd[1] +
+                     (T)Mf[c == 0 ? 4 : (c == 1 ? 5 : 2)] * xd[2];
+      // curl of the other field's contracted level
+      const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      const T* src = xn + (f == 0 ? 3 : 0) * a3;
+      const int st1 = axis_stride(c1, a), st2 = axis_stride(c2, a);
+      const int b1 = s - si(c1) * st1, b2 = s - si(c2) * st2;
+      T curl = T(0);
+      for (int n = 0; n < a; ++n) {
+        const T d1 = f == 0 ? P.tab.Dh[n][si(c1)] : P.tab.Dh[si(c1)][n];
+        const T d2 = f == 0 ? P.tab.Dh[n][si(c2)] : P.tab.Dh[si(c2)][n];
+        curl += d1 * src[c2 * a3 + b1 + n * st1] - d2 * src[c1 * a3 + b2 + n * st2];
+      }
+      // lifts of the face values
+      T lift = T(0);
+      for (int alpha = 0; alpha < 3; ++alpha) {
+        if (alpha == c) continue;
+        const int d = 3 - c - alpha;
+        const int ua = alpha == 0 ? 1 : 0, va = alpha == 2 ? 1 : 2;
+        const int slot = d == ua ? 0 : 1;
+        const T epsv = alpha == (c + 2) % 3 ? T(1) : T(-1);  // eps(c, d, alpha)
+        const int jj = si(ua) + a * si(va);
+        const int l = si(alpha);
+        const int ft = (f == 0 ? 0 : 2) + slot;  // E rows lift F, H rows G
+        for (int side = 0; side < 2; ++side) {
+          const T sl = side ? P.tab.tr1[l] : -P.tab.tr0[l];  // sigma L_l(side)
+          lift += (f == 0 ? epsv : -epsv) * sl * fl[((2 * alpha + side) * 4 + ft) * a2 + jj];
+        }
+      }
+      const int64_t o = ((int64_t)fc * nt + I) * a3 + s;
+      T out = mass + P.dt * (curl + lift);
+      if (le) out -= le[o];
+      ye[o] = out;
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* load, T* y, hipStream_t s,
+                      const int* skip) {
+  if (m->lt.empty()) return STDG_OK;
+  if (!m->d_lt) return fail(STDG_E_ARG, "local time steps: device records missing");
+  if (mode != STDG_OPERATOR && mode != STDG_RESIDUAL)
+    return fail(STDG_E_ARG, "local time steps: preconditioned applies take the P^{-1} pre-pass");
+  LParams<T> P;
+  P.info = m->d_info;
+  P.metric = m->d_metric;
+  P.rec = m->d_lt;
+  P.bank = (const T*)(sizeof(T) == 8 ? m->d_ltb64 : m->d_ltb32);
+  P.x = x;
+  P.load = load;
+  P.y = y;
+  P.skip = skip;
+  P.dt = (T)dt;
+  P.resid = mode == STDG_RESIDUAL ? 1 : 0;
+  if constexpr (sizeof(T) == 8) fill_tables_f64(&P.tab); else fill_tables_f32(&P.tab);
+  hipLaunchKernelGGL(local_time_kernel<T>, dim3((unsigned)m->lt.size()), dim3(kLThreads), 0, s, P);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? STDG_OK : hip_fail(e, "local-time kernel");
+}
+
+template int launch_local_time<float>(const Mesh*, double, int, const float*, const float*, float*, hipStream_t,
+                                      const int*);
+template int launch_local_time<double>(const Mesh*, double, int, const double*, const double*, double*, hipStream_t,
+                                       const int*);
+
+}  // namespace stdg

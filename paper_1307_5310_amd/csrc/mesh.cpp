@@ -246,11 +246,17 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
   m->nv = nv;
   m->p.assign(d->p, d->p + ne);
   m->q.assign(d->q, d->q + ne);
+  if (d->nsub) m->nsub.assign(d->nsub, d->nsub + ne); else m->nsub.assign(ne, 1);
   for (int64_t e = 0; e < ne; ++e) {
     if (m->p[e] < 1 || m->p[e] > kMaxA - 1)
       return fail(STDG_E_ARG, "element " + std::to_string(e) + ": p must be in 1..8");
     if (m->q[e] < 1 || m->q[e] > kMaxQ)
       return fail(STDG_E_ARG, "element " + std::to_string(e) + ": q must be in 1..6");
+    const int32_t ns = m->nsub[e];
+    if (ns < 1 || ns > kMaxSub || (ns & (ns - 1)))
+      return fail(STDG_E_ARG, "element " + std::to_string(e) + ": sub-intervals must be 1, 2, 4 or 8");
+    if (ns > 1 && ns * m->q[e] > kMaxLocalLevels)
+      return fail(STDG_E_ARG, "element " + std::to_string(e) + ": sub-intervals times q must be <= 24");
     if (!(d->eps[e] > 0.0) || !(d->mu[e] > 0.0) || !std::isfinite(d->eps[e]) || !std::isfinite(d->mu[e]))
       return fail(STDG_E_ARG, "element " + std::to_string(e) + ": eps and mu must be finite and > 0");
     for (int v = 0; v < 8; ++v) {
@@ -267,8 +273,9 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
   m->state_off.assign(ne + 1, 0);
   for (int64_t e = 0; e < ne; ++e) {
     int64_t a3 = (int64_t)(m->p[e] + 1) * (m->p[e] + 1) * (m->p[e] + 1);
-    m->trial_off[e + 1] = m->trial_off[e] + 6 * (m->q[e] + 1) * a3;
-    m->unk_off[e + 1] = m->unk_off[e] + 6 * m->q[e] * a3;
+    const int64_t nl = (int64_t)m->q[e] * m->nsub[e];  // test levels; trial levels nl + 1
+    m->trial_off[e + 1] = m->trial_off[e] + 6 * (nl + 1) * a3;
+    m->unk_off[e + 1] = m->unk_off[e] + 6 * nl * a3;
     m->state_off[e + 1] = m->state_off[e] + 6 * a3;
   }
 
@@ -291,6 +298,7 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     ElemInfo& I = m->info[e];
     I.a = m->p[e] + 1;
     I.q = m->q[e];
+    I.nsub = (uint8_t)m->nsub[e];
     I.flags = 0;
     I.trial_off = m->trial_off[e];
     I.unk_off = m->unk_off[e];
@@ -635,9 +643,55 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
                                     " share a face but do not lie on its two sides");
     }
 
+  // local time steps: the rows of elements with several sub-intervals, and of
+  // their face neighbours (whose coupling then runs through the projection
+  // onto a piecewise common test space), leave the kernel groups for the
+  // local-time kernel
+  m->lt.clear();
+  m->lt_bank.clear();
+  if (*std::max_element(m->nsub.begin(), m->nsub.end()) > 1) {
+    if (!m->hang.empty()) return fail(STDG_E_UNSUPPORTED, "local time steps on meshes with 2:1 hanging faces");
+    std::map<std::pair<int, int>, std::pair<int32_t, int32_t>> own;
+    std::map<std::tuple<int, int, int, int>, int32_t> cpl;
+    for (int64_t e = 0; e < ne; ++e) {
+      ElemInfo& I = m->info[e];
+      bool local = m->nsub[e] > 1;
+      for (int f = 0; f < 6; ++f)
+        if (I.nb[f] >= 0 && m->nsub[I.nb[f]] > 1) local = true;
+      if (!local) continue;
+      if (!(I.flags & kAffine))
+        return fail(STDG_E_UNSUPPORTED, "element " + std::to_string(e) +
+                                            ": local time steps need affine elements (and their face neighbours)");
+      LTRec R;
+      R.elem = (int32_t)e;
+      auto ok = own.find({m->q[e], m->nsub[e]});
+      if (ok == own.end()) {
+        int32_t d_off, n_off;
+        local_time_tables(m->q[e], m->nsub[e], &m->lt_bank, &d_off, &n_off);
+        ok = own.emplace(std::make_pair(m->q[e], m->nsub[e]), std::make_pair(d_off, n_off)).first;
+      }
+      R.d_off = ok->second.first;
+      R.n_off = ok->second.second;
+      for (int f = 0; f < 6; ++f) {
+        R.c_off[f] = -1;
+        const int32_t k = I.nb[f];
+        if (k < 0) continue;
+        auto key = std::make_tuple(m->q[e], m->nsub[e], m->q[k], m->nsub[k]);
+        auto it = cpl.find(key);
+        if (it == cpl.end())
+          it = cpl.emplace(key, local_coupling_table(m->q[e], m->nsub[e], m->q[k], m->nsub[k], &m->lt_bank)).first;
+        R.c_off[f] = it->second;
+      }
+      I.flags |= kLocalTime;
+      I.pad = (int32_t)m->lt.size();
+      m->lt.push_back(R);
+    }
+  }
+
   // kernel groups by (a, q, affine); their work-list order is set below
   std::map<std::tuple<int, int, int>, std::vector<std::pair<uint64_t, int32_t>>> gm;
   for (int64_t e = 0; e < ne; ++e) {
+    if (m->info[e].flags & kLocalTime) continue;
     auto key = std::make_tuple(m->p[e] + 1, m->q[e], (m->info[e].flags & kAffine) ? 1 : 0);
     gm[key].push_back({0, (int32_t)e});
   }
@@ -670,6 +724,9 @@ size_t mesh_device_bytes(const Mesh& m) {
   if (!m.hang.empty())
     b += r256(sizeof(HangRec) * m.hang.size()) + r256(sizeof(double) * 2 * kMaxA * kMaxA) +
          r256(sizeof(float) * 2 * kMaxA * kMaxA);
+  if (!m.lt.empty())
+    b += r256(sizeof(LTRec) * m.lt.size()) + r256(sizeof(double) * m.lt_bank.size()) +
+         r256(sizeof(float) * m.lt_bank.size());
   for (const Group& g : m.groups) b += r256(sizeof(int32_t) * g.count);
   return b;
 }
@@ -729,6 +786,17 @@ int upload_mesh(Ctx* ctx, Mesh* m) {
     STDG_HIP(hipMemcpy(m->d_hs64, s64.data(), sizeof(double) * s64.size(), hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d_hs32, s32.data(), sizeof(float) * s32.size(), hipMemcpyHostToDevice));
   }
+  if (!m->lt.empty()) {
+    const size_t bl = sizeof(LTRec) * m->lt.size(), nb = m->lt_bank.size();
+    std::vector<float> b32(m->lt_bank.begin(), m->lt_bank.end());
+    if ((rc = dev_alloc(ctx, (void**)&m->d_lt, bl)) != STDG_OK) return rc;
+    if ((rc = dev_alloc(ctx, &m->d_ltb64, sizeof(double) * nb)) != STDG_OK) return rc;
+    if ((rc = dev_alloc(ctx, &m->d_ltb32, sizeof(float) * nb)) != STDG_OK) return rc;
+    m->device_bytes += bl + (sizeof(double) + sizeof(float)) * nb;
+    STDG_HIP(hipMemcpy(m->d_lt, m->lt.data(), bl, hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d_ltb64, m->lt_bank.data(), sizeof(double) * nb, hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d_ltb32, b32.data(), sizeof(float) * nb, hipMemcpyHostToDevice));
+  }
   for (Group& g : m->groups) {
     if ((rc = dev_alloc(ctx, (void**)&g.d_list, sizeof(int32_t) * g.count)) != STDG_OK) return rc;
     m->device_bytes += sizeof(int32_t) * g.count;
@@ -748,6 +816,8 @@ int set_dissipation(Mesh* m, double c) {
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(STDG_E_ARG, "dissipation coefficient must be finite and >= 0");
   if (c > 0.0 && !m->hang.empty())
     return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation on meshes with hanging faces");
+  if (c > 0.0 && !m->lt.empty())
+    return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation with local time steps");
   ++m->epoch;
   const size_t bytes = sizeof(double) * Mesh::kDissWords * m->ne, bytes32 = sizeof(float) * Mesh::kDissWords * m->ne;
   if (c == 0.0) {
@@ -842,6 +912,11 @@ void release_mesh(Mesh* m) {
   if (m->d_hs32) dev_free(ctx, m->d_hs32, sizeof(float) * 2 * kMaxA * kMaxA);
   m->d_hang = nullptr;
   m->d_hs64 = m->d_hs32 = nullptr;
+  if (m->d_lt) dev_free(ctx, m->d_lt, sizeof(LTRec) * m->lt.size());
+  if (m->d_ltb64) dev_free(ctx, m->d_ltb64, sizeof(double) * m->lt_bank.size());
+  if (m->d_ltb32) dev_free(ctx, m->d_ltb32, sizeof(float) * m->lt_bank.size());
+  m->d_lt = nullptr;
+  m->d_ltb64 = m->d_ltb32 = nullptr;
   if (m->d_fr64) dev_free(ctx, m->d_fr64, sizeof(FaceRule<double>) * (kMaxFaceQ + 1));
   if (m->d_fr32) dev_free(ctx, m->d_fr32, sizeof(FaceRule<float>) * (kMaxFaceQ + 1));
   m->d_fr64 = m->d_fr32 = nullptr;

@@ -153,6 +153,8 @@ static int run_groups(const Mesh* m, double dt, int mode, const T* x, const T* l
   }
   // 2:1 hanging faces: the neighbours' half of their fluxes, after every group
   if (!m->hang.empty()) return launch_hanging<T>(m, dt, mode, x, y, s, skip);
+  // local time steps: the rows left out of the groups
+  if (!m->lt.empty()) return launch_local_time<T>(m, dt, mode, x, load, y, s, skip);
   return STDG_OK;
 }
 
@@ -164,7 +166,8 @@ bool batchable_mesh(const Mesh* m) {
       ++groups;
       g0 = &g;
     }
-  return groups == 1 && g0->affine && m->n_diag == m->ne && m->d_diss == nullptr && m->hang.empty();
+  return groups == 1 && g0->affine && m->n_diag == m->ne && m->d_diss == nullptr && m->hang.empty() &&
+         m->lt.empty();
 }
 
 template <typename T>
@@ -220,7 +223,10 @@ int launch_residual(const ApplyArgs& a) {
   const Mesh* m = a.mesh;
   int mode = a.mode;
   const void* x = a.x;
-  if (mode == STDG_OPERATOR_PRECOND && m->n_diag != m->ne && a.no_alloc) {
+  // P^{-1} as a pre-pass: on meshes with a non-diagonal metric somewhere, and
+  // with local time steps (P^{-1} then also mixes the time levels)
+  const bool prepass = m->n_diag != m->ne || !m->lt.empty();
+  if (mode == STDG_OPERATOR_PRECOND && prepass && a.no_alloc) {
     // the allocation-free variant: P^{-1} x into the static scratch of this device
     const size_t need = (size_t)m->unk_off.back() * (a.prec == STDG_FP64 ? 8 : 4);
     if (need > kNoAllocScratchBytes)
@@ -236,7 +242,7 @@ int launch_residual(const ApplyArgs& a) {
     if (rc != STDG_OK) return rc;
     x = ptr;
     mode = STDG_OPERATOR;
-  } else if (mode == STDG_OPERATOR_PRECOND && m->n_diag != m->ne) {
+  } else if (mode == STDG_OPERATOR_PRECOND && prepass) {
     // non-diagonal metric somewhere: scale into the mesh's scratch, then plain
     // operator.  The scratch is sized for FP64 on first use, so a later call in
     // the other precision never moves it under captured launches; the epoch is

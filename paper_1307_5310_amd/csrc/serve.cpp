@@ -486,6 +486,9 @@ int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ti
   if (d.n_elements <= 0 || d.n_vertices <= 0 || !d.vertices || !d.hexes || !d.p || !d.q || !d.eps || !d.mu)
     return fail(STDG_E_ARG, "stdg_serve_submit: empty mesh or NULL array");
   if (d.n_elements > (int64_t)INT32_MAX) return fail(STDG_E_ARG, "stdg_serve_submit: too many elements");
+  if (d.nsub)
+    for (int64_t e = 0; e < d.n_elements; ++e)
+      if (d.nsub[e] != 1) return fail(STDG_E_UNSUPPORTED, "stdg_serve_submit: local time steps");
   if (!(req->dt > 0.0) || req->n_slabs < 1) return fail(STDG_E_ARG, "stdg_serve_submit: need dt > 0 and n_slabs >= 1");
   if (req->source.kind != 0 && req->source.kind != 1) return fail(STDG_E_ARG, "stdg_serve_submit: unknown source kind");
   if (req->n_modes < 0 || (req->n_modes > 0 && (!req->mnl || !req->abc)))

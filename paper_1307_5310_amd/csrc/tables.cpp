@@ -9,6 +9,7 @@
 //   Dh[n][j] = int L_n L_j' = 2 sqrt((2n+1)(2j+1)) for n < j, j - n odd;
 //   traces L_j(0) = (-1)^j sqrt(2j+1), L_j(1) = sqrt(2j+1);
 // and the Gauss-Legendre mass rule of trilinear elements (n = p + 2 points).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -160,6 +161,85 @@ void fill_face_rule_f32(int n, FaceRule<float>* r) {
     r->w[k] = (float)d.w[k];
   }
   for (int i = 0; i < kMaxFaceQ * kMaxA; ++i) r->L[i] = (float)d.L[i];
+}
+
+// Local time steps (Section 2.2): tables of a slab interval bisected into n
+// equal sub-intervals, in the unit slab coordinate s, with the flattened trial
+// levels of local_trial_level.  Own terms: on sub-interval j the mass factor
+// is the shift delta_{m,i+1} - delta_{i0} delta_{m0} and the curl and flux
+// factor N[i][m] / n (the sub-interval has length 1 / n).
+static double ilegendre01(int m, double xi) {
+  if (m == 0) return 1.0 - xi;
+  if (m == 1) return xi;
+  return (legendre01(m, xi) / std::sqrt(2.0 * m + 1.0) - legendre01(m - 2, xi) / std::sqrt(2.0 * m - 3.0)) /
+         (2.0 * std::sqrt(2.0 * m - 1.0));
+}
+
+int local_time_tables(int q, int n, std::vector<double>* bank, int32_t* d_off, int32_t* n_off) {
+  Tables<double> t;
+  fill_double(&t);
+  const int rows = n * q, cols = 1 + n * q;
+  *d_off = (int32_t)bank->size();
+  bank->resize(bank->size() + 2 * (size_t)rows * cols, 0.0);
+  *n_off = *d_off + rows * cols;
+  double* D = bank->data() + *d_off;
+  double* N = bank->data() + *n_off;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < q; ++i) {
+      const int I = j * q + i;
+      D[I * cols + local_trial_level(q, n, j, i + 1)] += 1.0;
+      if (i == 0) D[I * cols + local_trial_level(q, n, j, 0)] -= 1.0;
+      for (int m = 0; m <= q; ++m) N[I * cols + local_trial_level(q, n, j, m)] += t.N[i][m] / n;
+    }
+  return *d_off;
+}
+
+// Coupling of S_h across a face between partitions of n and nk sub-intervals
+// (powers of two, so they nest): C[(j, i)][M'] = int_0^1 (pi L_i^(j)) phi'_M'
+// ds, pi the L2 projection onto the common temporal test space, piecewise
+// P_{r-1} (r = min(q, qk)) on the coarser partition.
+//   n <= nk: L_i^(j) already lies on the coarser partition, so pi keeps it for
+//     i < r and removes it otherwise; the integral runs over the nk / n
+//     sub-intervals of the neighbour inside sub-interval j (Gauss rule).
+//   n > nk: sub-interval j lies in the neighbour's sub-interval c; pi L_i^(j)
+//     = sum_{rho < r} beta_rho L_rho^(c) with beta_rho = nk int_{I_j} L_i^(j)
+//     L_rho^(c), and int_{I_c} L_rho^(c) l_m'^(c) = N[rho][m'] / nk.
+int local_coupling_table(int q, int n, int qk, int nk, std::vector<double>* bank) {
+  Tables<double> t;
+  fill_double(&t);
+  const int rows = n * q, cols = 1 + nk * qk, r = std::min(q, qk);
+  const int off = (int)bank->size();
+  bank->resize(bank->size() + (size_t)rows * cols, 0.0);
+  double* C = bank->data() + off;
+  const int ng = q + qk + 2;
+  double xg[32], wg[32];
+  gauss_rule01(ng, xg, wg);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < r; ++i) {
+      double* row = C + (size_t)(j * q + i) * cols;
+      if (n <= nk) {
+        const int ratio = nk / n;
+        for (int jr = 0; jr < ratio; ++jr) {
+          const int jk = j * ratio + jr;
+          for (int m = 0; m <= qk; ++m) {
+            // s = (jk + xi) / nk, n s - j = (jr + xi) / ratio
+            double v = 0.0;
+            for (int g = 0; g < ng; ++g) v += wg[g] * legendre01(i, (jr + xg[g]) / ratio) * ilegendre01(m, xg[g]);
+            row[local_trial_level(qk, nk, jk, m)] += v / nk;
+          }
+        }
+      } else {
+        const int ratio = n / nk, c = j / ratio, jr = j - c * ratio;
+        for (int rho = 0; rho < r; ++rho) {
+          // beta = nk int_{I_j} L_i(n s - j) L_rho(nk s - c) ds, s = (j + xi) / n
+          double beta = 0.0;
+          for (int g = 0; g < ng; ++g) beta += wg[g] * legendre01(i, xg[g]) * legendre01(rho, (jr + xg[g]) / ratio);
+          beta *= (double)nk / n;
+          for (int m = 0; m <= qk; ++m) row[local_trial_level(qk, nk, c, m)] += beta * t.N[rho][m] / nk;
+        }
+      }
+    }
+  return off;
 }
 
 }  // namespace stdg

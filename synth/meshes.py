@@ -26,16 +26,21 @@ class Mesh:
     mu: np.ndarray                  # [ne] float64
     shape: tuple = None             # (nx, ny, nz) for lattice meshes, else None
     meta: dict = field(default_factory=dict)
+    nsub: np.ndarray = None         # [ne] temporal sub-intervals (local time steps), None = 1
 
     @property
     def n_elements(self):
         return int(self.hexes.shape[0])
 
+    def levels(self):
+        """Temporal degree times sub-intervals: the test levels per element."""
+        return self.q if self.nsub is None else np.asarray(self.q) * np.asarray(self.nsub)
+
     def trial_size(self):
-        return int(trial_sizes(self.p, self.q).sum())
+        return int(trial_sizes(self.p, self.levels()).sum())
 
     def unknown_size(self):
-        return int(unknown_sizes(self.p, self.q).sum())
+        return int(unknown_sizes(self.p, self.levels()).sum())
 
     def state_size(self):
         a = self.p.astype(np.int64) + 1

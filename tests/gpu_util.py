@@ -56,7 +56,7 @@ class Lib:
 
     def upload(self, mesh):
         return self.stdg.stdg_mesh_upload(self.ctx, mesh.vertices, mesh.hexes, mesh.p, mesh.q,
-                                          mesh.eps, mesh.mu)
+                                          mesh.eps, mesh.mu, getattr(mesh, "nsub", None))
 
     def dev(self, arr, dtype):
         t = self.torch
@@ -90,4 +90,5 @@ def random_mixed_mesh(shape, pmax, qmax, seed, perturb=None):
 
 def oracle_disc(mesh):
     from oracle.dg import Discretisation
-    return Discretisation(mesh.vertices, mesh.hexes, mesh.p, mesh.q, mesh.eps, mesh.mu)
+    return Discretisation(mesh.vertices, mesh.hexes, mesh.p, mesh.q, mesh.eps, mesh.mu,
+                          nk=getattr(mesh, "nsub", None))

@@ -76,13 +76,16 @@ static Built lattice(int nx, int ny, int nz, unsigned seed, bool rotate) {
   return b;
 }
 
-static int build(const Built& b, int p = 2, int q = 2, double eps = 1.0, int64_t* hanging = nullptr) {
+static int build(const Built& b, int p = 2, int q = 2, double eps = 1.0, int64_t* hanging = nullptr,
+                 const std::vector<int32_t>* nsub = nullptr, stdg::Mesh* keep = nullptr) {
   std::vector<int32_t> pp(b.ne, p), qq(b.ne, q);
   std::vector<double> e(b.ne, eps), mu(b.ne, 1.0);
-  stdg_mesh_desc d{(int64_t)(b.v.size() / 3), b.v.data(), b.ne, b.h.data(), pp.data(), qq.data(), e.data(), mu.data()};
+  stdg_mesh_desc d{(int64_t)(b.v.size() / 3), b.v.data(), b.ne, b.h.data(), pp.data(), qq.data(), e.data(), mu.data(),
+                   nsub ? nsub->data() : nullptr};
   stdg::Mesh m;
-  const int rc = stdg::build_mesh_host(&d, &m);
-  if (hanging) *hanging = m.n_hanging_faces;
+  stdg::Mesh& mm = keep ? *keep : m;
+  const int rc = stdg::build_mesh_host(&d, &mm);
+  if (hanging) *hanging = mm.n_hanging_faces;
   return rc;
 }
 
@@ -140,6 +143,9 @@ int main() {
       for (int k = 0; k < 2; ++k) hexa(1, 0.5 * j, 0.5 * k, 0.5);
     int64_t nh = -1;
     expect("2:1 hanging face", build(b, 2, 2, 1.0, &nh), STDG_OK);
+    std::vector<int32_t> ns(b.ne, 1);
+    ns[2] = 2;
+    expect("local time steps with hanging faces", build(b, 2, 2, 1.0, nullptr, &ns), STDG_E_UNSUPPORTED);
     if (nh != 1) {
       std::printf("FAIL 2:1 hanging face: %lld hanging faces recorded, expected 1\n", (long long)nh);
       ++bad;
@@ -158,6 +164,48 @@ int main() {
     for (int v = 0; v < 8; ++v)
       if (c.h[8 * 1 + v] == centre) c.h[8 * 1 + v] = dup;
     expect("split face, not quarters", build(c), STDG_E_UNSUPPORTED);
+  }
+  // local time steps: sub-intervals per element; the rows of elements with
+  // several, and of their face neighbours, leave the kernel groups
+  {
+    Built b = lattice(3, 3, 3, 11, true);
+    std::vector<int32_t> ns(b.ne, 1);
+    ns[0] = 2;
+    ns[13] = 4;
+    ns[26] = 8;
+    stdg::Mesh m;
+    expect("local time steps", build(b, 2, 2, 1.0, nullptr, &ns, &m), STDG_OK);
+    int64_t grouped = 0, local = 0, want = 0;
+    for (const auto& g : m.groups) grouped += g.count;
+    for (int64_t e = 0; e < b.ne; ++e) {
+      bool l = ns[e] > 1;
+      for (int f = 0; f < 6; ++f)
+        if (m.info[e].nb[f] >= 0 && ns[m.info[e].nb[f]] > 1) l = true;
+      want += l;
+      local += (m.info[e].flags & stdg::kLocalTime) != 0;
+    }
+    if (local != want || (int64_t)m.lt.size() != want || grouped + want != b.ne) {
+      std::printf("FAIL local time rows: %lld flagged, %zu records, %lld grouped, expected %lld local of %lld\n",
+                  (long long)local, m.lt.size(), (long long)grouped, (long long)want, (long long)b.ne);
+      ++bad;
+    }
+    int64_t unk = 0;
+    for (int64_t e = 0; e < b.ne; ++e) unk += 6 * 2 * ns[e] * 27;
+    if (m.unk_off.back() != unk || m.trial_off.back() != unk + 6 * 27 * b.ne) {
+      std::printf("FAIL local time offsets\n");
+      ++bad;
+    }
+    for (int bad_n : {3, 16, 0}) {
+      std::vector<int32_t> nb(b.ne, 1);
+      nb[5] = bad_n;
+      expect("sub-intervals not a power of two in 1..8", build(b, 2, 2, 1.0, nullptr, &nb), STDG_E_ARG);
+    }
+    std::vector<int32_t> big(b.ne, 1);
+    big[5] = 8;
+    expect("sub-intervals times q > 24", build(b, 2, 4, 1.0, nullptr, &big), STDG_E_ARG);
+    Built t = b;
+    t.v[3 * (1 + 4 * (1 + 4 * 1)) + 2] += 0.05;  // an interior vertex moved: trilinear elements
+    expect("local time steps on trilinear elements", build(t, 2, 2, 1.0, nullptr, &ns), STDG_E_UNSUPPORTED);
   }
   // tables
   for (int n = 1; n <= 16; ++n) {
