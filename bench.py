@@ -59,6 +59,8 @@ def parse():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-graded", action="store_true", help="skip the graded trilinear 24^3 leg")
     ap.add_argument("--no-large", action="store_true", help="skip the 48^3 p=6 q=4 leg")
+    ap.add_argument("--no-local-time", action="store_true",
+                    help="skip the leg with local time steps (32^3 two-material cavity, 4/2/1 sub-intervals)")
     ap.add_argument("--no-diss", action="store_true", help="skip the dissipative (D_h, c = 1) leg")
     ap.add_argument("--no-reoriented", action="store_true",
                     help="skip the leg with every element's vertices relabelled by a random cube rotation")
@@ -336,6 +338,11 @@ def main():
         reoriented = time_reoriented(stdg, torch, ctx, mh, cfg, args, (("fp32", stdg.STDG_FP32, x32, y32),
                                                                       ("fp64", stdg.STDG_FP64, x64, y64)))
 
+    local_time = None
+    if not args.no_local_time:
+        log("local time steps: two-material 32^3 cavity, 4/2/1 sub-intervals")
+        local_time = time_local_time(stdg, torch, ctx, 20, 5)
+
     graded = large = None
     if not args.no_graded:
         log("graded trilinear 24^3")
@@ -407,6 +414,8 @@ def main():
         out["dissipative"] = diss
     if reoriented is not None:
         out["reoriented"] = reoriented
+    if local_time is not None:
+        out["local_time_steps"] = local_time
     if graded is not None:
         out["graded_trilinear"] = graded
     if large is not None:
@@ -653,6 +662,50 @@ def time_large(stdg, torch, ctx, steps, warmup):
     out["slab_fp32_refine_fp32_basis"] = _slab_with_source(stdg, torch, mh, info, cfg, stdg.STDG_FP32, stdg.STDG_FP32)
     log("large: one slab %.2f s" % out["slab_fp32_refine_fp32_basis"]["s_per_slab"])
     stdg.stdg_mesh_free(mh)
+    return out
+
+
+def time_local_time(stdg, torch, ctx, steps, warmup):
+    """Local time steps: the two-material 32^3 cavity (p = 4, q = 3) with 4 /
+    2 / 1 sub-intervals per slab by region.  Operator and preconditioned
+    applies (the rows of elements with sub-intervals and of their neighbours
+    run in the local-time kernel, the rest in the kernel groups), the same
+    mesh without sub-intervals for comparison, and a march of slabs with the
+    energy drift (Thm 4.1: conserved without a source)."""
+    import synth
+    cfg = synth.local_time_cavity()
+    m = cfg["mesh"]
+    a = m.p.astype(np.int64) + 1
+    nt = m.q.astype(np.int64) * m.nsub.astype(np.int64)
+    out = {"workload": cfg["name"] + ", dt = %g" % cfg["dt"], "elements": m.n_elements,
+           "sub_intervals": {str(k): int((m.nsub == k).sum()) for k in (1, 2, 4)},
+           "trial_dof": int((6 * (nt + 1) * a ** 3).sum())}
+    res = {}
+    for label, nsub in (("local", m.nsub), ("uniform", None)):
+        mh = stdg.stdg_mesh_upload(ctx, m.vertices, m.hexes, m.p, m.q, m.eps, m.mu, nsub)
+        info = stdg.stdg_mesh_info(mh)
+        x64 = torch.from_numpy(synth.random_vector(info["unknown_size"], 0)).cuda()
+        lev = nt if nsub is not None else m.q.astype(np.int64)
+        for name, prec, x in (("fp32", stdg.STDG_FP32, x64.float()), ("fp64", stdg.STDG_FP64, x64)):
+            y = torch.empty_like(x)
+            ms = _time_mode(stdg, torch, mh, cfg["dt"], prec, stdg.STDG_OPERATOR, x, y, steps, warmup)
+            ms_pre = _time_mode(stdg, torch, mh, cfg["dt"], prec, stdg.STDG_OPERATOR_PRECOND, x, y, steps, warmup)
+            sz = 4 if prec == stdg.STDG_FP32 else 8
+            bytes_ = float((12 * lev * a ** 3).sum() * sz)
+            trial = float((6 * (lev + 1) * a ** 3).sum())
+            res.setdefault(label, {})[name] = {
+                "operator_ms": round(ms, 4), "precond_operator_ms": round(ms_pre, 4),
+                "gdof_per_s": round(trial / (ms * 1e-3) / 1e9, 2),
+                "hbm_frac": round(bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": bytes_}
+            log("local time (%s) %s: operator %.3f ms, preconditioned %.3f ms" % (label, name, ms, ms_pre))
+        if nsub is not None:
+            out["march_fp32_refine"] = _march(stdg, torch, mh, cfg, info, cfg["n_slabs"],
+                                              inner_prec=stdg.STDG_FP32, krylov_prec=stdg.STDG_FP32, rtol=1e-10,
+                                              max_iters=3000, max_refine=300, use_graph=1)
+            log("local time march: %.2f slab solves/s, drift %.2e" % (
+                out["march_fp32_refine"]["slab_solves_per_s"], out["march_fp32_refine"]["energy_drift"]))
+        stdg.stdg_mesh_free(mh)
+    out.update(res)
     return out
 
 

@@ -47,7 +47,7 @@ enum : int32_t {
 // j + 1).  Its n q test levels are L_i on sub-interval j at j q + i.
 constexpr int kMaxSub = 8;
 constexpr int kMaxLocalLevels = 24;  // n q <= 24 test levels
-inline int local_trial_level(int q, int n, int j, int m) {
+__host__ __device__ inline int local_trial_level(int q, int n, int j, int m) {
   if (m == 0) return j == 0 ? 0 : 1 + j * q;
   if (m == 1) return j == n - 1 ? 1 : 1 + (j + 1) * q;
   return 2 + j * q + m - 2;
@@ -229,8 +229,12 @@ struct Mesh {
   // time-table bank (FP64, FP32)
   std::vector<int32_t> nsub;
   std::vector<LTRec> lt;
+  std::vector<int32_t> lt_work;  // workgroups of the local-time kernel: record * kMaxSub + sub-interval,
+                                 // grouped by a: lt_work[lt_a_off[a] .. lt_a_off[a + 1]) have p + 1 = a
+  std::vector<int64_t> lt_a_off;
   std::vector<double> lt_bank;
   LTRec* d_lt = nullptr;
+  int32_t* d_lt_work = nullptr;
   void* d_ltb64 = nullptr;
   void* d_ltb32 = nullptr;
   // side streams for applies over several kernel groups (created on first use):

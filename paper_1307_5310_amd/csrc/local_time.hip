@@ -19,6 +19,14 @@
 // D[I][M] = int L_I d_s phi_M and N[I][M] = int L_I phi_M are the element's own
 // tables over the unit slab coordinate s.  Elements with one sub-interval
 // whose neighbour has several run here too (their coupling changes).
+// One workgroup per (element, sub-interval): the q test levels of one
+// sub-interval, whose table rows are staged in LDS first.  When they fit
+// (dynamic LDS, 64 KB), the sub-interval's q + 1 own trial levels and the
+// neighbours' traces contracted for all q levels (each neighbour level read
+// once per workgroup) are staged as well, and the level loop reads only LDS;
+// otherwise every level gathers from global memory.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace stdg {
@@ -36,48 +44,131 @@ struct LParams {
   const T* x;
   const T* load;    // residual mode: subtracted (may be NULL)
   T* y;
+  const int32_t* work;  // per workgroup: record index * kMaxSub + sub-interval
   const int* skip;
   T dt;
   int resid;        // x is the full trial vector (levels 0..), else the unknowns (levels 1..)
+  int staged;       // the own levels and the neighbours' traces of a sub-interval fit in LDS
   Tables<T> tab;    // Dh and the face traces
 };
 
 __device__ inline int axis_stride(int axis, int a) { return axis == 0 ? 1 : (axis == 1 ? a : a * a); }
 
-template <typename T>
+template <typename T, int A>
 __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
   if (P.skip && *P.skip == 0) return;
-  __shared__ T xn[6 * kMaxA * kMaxA * kMaxA];  // contracted own fields [F][c][s] of level I
-  __shared__ T fl[6 * 4 * kMaxA * kMaxA];      // [face][F_u, F_v, G_u, G_v][face mode]
-  const LTRec* R = P.rec + blockIdx.x;  // read through the pointer (no private copy)
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  constexpr int TW = kMaxLocalLevels + 1;  // row width of the staged tables
+  const int32_t wk = P.work[blockIdx.x];
+  const LTRec* R = P.rec + wk / kMaxSub;  // read through the pointer (no private copy)
+  const int jsub = wk % kMaxSub;
   const int e = R->elem;
   const ElemInfo* Ie = P.info + e;
-  const int a = Ie->a, q = Ie->q, a2 = a * a, a3 = a2 * a;
-  const int nt = q * Ie->nsub;  // test levels
+  constexpr int a = A, a2 = A * A, a3 = A * A * A;  // this launch's rows all have a = p + 1 = A
+  const int q = Ie->q, ns = Ie->nsub;
+  const int nt = q * ns;        // test levels
   const int ncol = nt + 1;      // trial levels (columns of the own tables)
   const int m0 = P.resid ? 0 : 1;
   const int nst = ncol - m0;    // stored trial levels
-  const T* D = P.bank + R->d_off;
-  const T* N = P.bank + R->n_off;
+  const int nf = 24 * a2;       // face items: [face][F_u, F_v, G_u, G_v][face mode]
+  // LDS: table rows [D, N, C_0..C_5][i][M] of this sub-interval's q test
+  // levels, the contracted own fields, the face values; staged: the own
+  // trial levels of the sub-interval and the neighbours' contracted traces
+  T* tr = (T*)lds_raw;          // L_l(0), L_l(1), Dh (copied from the kernel arguments)
+  T* dh = tr + 2 * kMaxA;
+  T* tb = dh + kMaxA * kMaxA;
+  T* xn = tb + 8 * q * TW;
+  T* fl = xn + 6 * a3;
+  T* xo = fl + nf;              // [m = 0..q][F][c][s]          (staged)
+  T* nbt = xo + (q + 1) * 6 * a3;  // [i][face item]          (staged)
+  const bool staged = P.staged != 0;
   const T* xe = P.x + (P.resid ? Ie->trial_off : Ie->unk_off);
   T* ye = P.y + Ie->unk_off;
   const T* le = (P.resid && P.load) ? P.load + Ie->unk_off : nullptr;
   const double* Me = P.metric[e].m;
   const int tid = threadIdx.x;
-  for (int I = 0; I < nt; ++I) {
-    __syncthreads();  // the previous level's readers of xn and fl are done
+  for (int t = tid; t < 2 * kMaxA + kMaxA * kMaxA; t += kLThreads) {
+    const int u = t - 2 * kMaxA;
+    tr[t] = t < kMaxA ? P.tab.tr0[t] : (t < 2 * kMaxA ? P.tab.tr1[t - kMaxA] : P.tab.Dh[u / kMaxA][u % kMaxA]);
+  }
+  for (int t = tid; t < 8 * q * TW; t += kLThreads) {
+    const int r = t / (q * TW), rest = t - r * q * TW, i = rest / TW, M = rest - i * TW;
+    const int I = jsub * q + i;
+    T v = T(0);
+    if (r == 0 && M < ncol) v = P.bank[R->d_off + I * ncol + M];
+    if (r == 1 && M < ncol) v = P.bank[R->n_off + I * ncol + M];
+    if (r >= 2) {
+      const int g = r - 2, k = Ie->nb[g];
+      if (k >= 0) {
+        const int nck = P.info[k].q * P.info[k].nsub + 1;
+        if (M < nck) v = P.bank[R->c_off[g] + I * nck + M];
+      }
+    }
+    tb[t] = v;
+  }
+  __syncthreads();
+  if (staged) {
+    for (int t = tid; t < (q + 1) * 6 * a3; t += kLThreads) {
+      const int m = t / (6 * a3), rest = t - m * 6 * a3, fc = rest / a3, s = rest - fc * a3;
+      const int L = local_trial_level(q, ns, jsub, m);
+      xo[t] = L >= m0 ? xe[((int64_t)fc * nst + L - m0) * a3 + s] : T(0);
+    }
+    for (int t = tid; t < nf; t += kLThreads) {
+      for (int i = 0; i < q; ++i) nbt[i * nf + t] = T(0);
+      const int g = t / (4 * a2), k = Ie->nb[g];
+      if (k < 0) continue;
+      const int rest = t - g * 4 * a2, ft = rest / a2, jj = rest - ft * a2;
+      const int fu = jj % a, fv = jj / a;
+      const bool slot_u = (ft & 1) == 0;
+      const int fld = (ft >> 1) == 0 ? 1 : 0;
+      const uint8_t code = Ie->orient[g];
+      const int fo = code & 7, alo = fo >> 1, sdo = fo & 1;
+      const int uo = alo == 0 ? 1 : 0, vo = alo == 2 ? 1 : 2;
+      const bool swap = (code & kOrientSwap) != 0, flu = (code & kOrientFlipU) != 0, flv = (code & kOrientFlipV) != 0;
+      const int mu_ax = swap ? vo : uo, mv_ax = swap ? uo : vo;
+      const int cn = slot_u ? mu_ax : mv_ax;
+      const ElemInfo* Ik = P.info + k;
+      const int ak = Ik->a, ak3 = ak * ak * ak;
+      if (fu >= ak || fv >= ak) continue;
+      const int nck = Ik->q * Ik->nsub + 1;
+      const T* xk = P.x + (P.resid ? Ik->trial_off : Ik->unk_off) + (int64_t)(3 * fld + cn) * (nck - m0) * ak3 +
+                    fu * axis_stride(mu_ax, ak) + fv * axis_stride(mv_ax, ak);
+      const int snk = axis_stride(alo, ak);
+      const bool neg = (slot_u ? flu : flv) ^ (flu && (fu & 1)) ^ (flv && (fv & 1));
+      const T* C = tb + (2 + g) * q * TW;
+      for (int M = m0; M < nck; ++M) {
+        bool any = false;
+        for (int i = 0; i < q; ++i) any = any || C[i * TW + M] != T(0);
+        if (!any) continue;
+        const T* xp = xk + (int64_t)(M - m0) * ak3;
+        T v = T(0);
+        for (int l = 0; l < ak; ++l) v += tr[sdo * kMaxA + l] * xp[l * snk];
+        if (neg) v = -v;
+        for (int i = 0; i < q; ++i) nbt[i * nf + t] += C[i * TW + M] * v;
+      }
+    }
+  }
+  for (int i = 0; i < q; ++i) {
+    const int I = jsub * q + i;
+    const T* tD = tb + i * TW;
+    const T* tN = tb + (q + i) * TW;
+    __syncthreads();  // staging done, or the previous level's readers of xn and fl are done
     for (int t = tid; t < 6 * a3; t += kLThreads) {
       const int fc = t / a3, s = t - fc * a3;
-      const T* xp = xe + (int64_t)fc * nst * a3 + s;
       T v = T(0);
-      for (int M = m0; M < ncol; ++M) {
-        const T w = N[I * ncol + M];
-        if (w != T(0)) v += w * xp[(int64_t)(M - m0) * a3];
+      if (staged) {
+        for (int m = 0; m <= q; ++m) v += tN[local_trial_level(q, ns, jsub, m)] * xo[m * 6 * a3 + t];
+      } else {
+        const T* xp = xe + (int64_t)fc * nst * a3 + s;
+        for (int M = m0; M < ncol; ++M) {
+          const T w = tN[M];
+          if (w != T(0)) v += w * xp[(int64_t)(M - m0) * a3];
+        }
       }
       xn[t] = v;
     }
     __syncthreads();
-    for (int t = tid; t < 24 * a2; t += kLThreads) {
+    for (int t = tid; t < nf; t += kLThreads) {
       const int g = t / (4 * a2), rest = t - g * 4 * a2, ft = rest / a2, jj = rest - ft * a2;
       const int fu = jj % a, fv = jj / a;
       const int alpha = g >> 1, side = g & 1;
@@ -90,39 +181,44 @@ __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
       const T* own = xn + (3 * fld + d) * a3 + fu * axis_stride(ua, a) + fv * axis_stride(va, a);
       const int sn = axis_stride(alpha, a);
       T ts = T(0);
-      for (int l = 0; l < a; ++l) ts += (side ? P.tab.tr1[l] : P.tab.tr0[l]) * own[l * sn];
+#pragma unroll
+      for (int l = 0; l < A; ++l) ts += tr[side * kMaxA + l] * own[l * sn];
       const int k = Ie->nb[g];
       T val;
       if (k < 0) {
         val = which == 0 ? ts : -ts;
       } else {
-        const uint8_t code = Ie->orient[g];
-        const int fo = code & 7, alo = fo >> 1, sdo = fo & 1;
-        const int uo = alo == 0 ? 1 : 0, vo = alo == 2 ? 1 : 2;
-        const bool swap = (code & kOrientSwap) != 0, flu = (code & kOrientFlipU) != 0, flv = (code & kOrientFlipV) != 0;
-        const int mu_ax = swap ? vo : uo, mv_ax = swap ? uo : vo;  // the neighbour's axes matched with our u, v
-        const int cn = slot_u ? mu_ax : mv_ax;
-        const ElemInfo* Ik = P.info + k;
-        const int ak = Ik->a, ak3 = ak * ak * ak;
         T tn = T(0);
-        if (fu < ak && fv < ak) {
-          const int nck = Ik->q * Ik->nsub + 1;  // the neighbour's trial levels
-          const int nstk = nck - m0;
-          const T* C = P.bank + R->c_off[g] + I * nck;
-          const T* xk = P.x + (P.resid ? Ik->trial_off : Ik->unk_off) + (int64_t)(3 * fld + cn) * nstk * ak3 +
-                        fu * axis_stride(mu_ax, ak) + fv * axis_stride(mv_ax, ak);
-          const int snk = axis_stride(alo, ak);
-          for (int M = m0; M < nck; ++M) {
-            const T w = C[M];
-            if (w == T(0)) continue;
-            const T* xp = xk + (int64_t)(M - m0) * ak3;
-            T tr = T(0);
-            for (int l = 0; l < ak; ++l) tr += (sdo ? P.tab.tr1[l] : P.tab.tr0[l]) * xp[l * snk];
-            tn += w * tr;
+        if (staged) {
+          tn = nbt[i * nf + t];
+        } else {
+          const uint8_t code = Ie->orient[g];
+          const int fo = code & 7, alo = fo >> 1, sdo = fo & 1;
+          const int uo = alo == 0 ? 1 : 0, vo = alo == 2 ? 1 : 2;
+          const bool swap = (code & kOrientSwap) != 0, flu = (code & kOrientFlipU) != 0,
+                     flv = (code & kOrientFlipV) != 0;
+          const int mu_ax = swap ? vo : uo, mv_ax = swap ? uo : vo;  // the neighbour's axes matched with our u, v
+          const int cn = slot_u ? mu_ax : mv_ax;
+          const ElemInfo* Ik = P.info + k;
+          const int ak = Ik->a, ak3 = ak * ak * ak;
+          if (fu < ak && fv < ak) {
+            const int nck = Ik->q * Ik->nsub + 1;  // the neighbour's trial levels
+            const T* C = tb + ((2 + g) * q + i) * TW;
+            const T* xk = P.x + (P.resid ? Ik->trial_off : Ik->unk_off) + (int64_t)(3 * fld + cn) * (nck - m0) * ak3 +
+                          fu * axis_stride(mu_ax, ak) + fv * axis_stride(mv_ax, ak);
+            const int snk = axis_stride(alo, ak);
+            for (int M = m0; M < nck; ++M) {
+              const T w = C[M];
+              if (w == T(0)) continue;
+              const T* xp = xk + (int64_t)(M - m0) * ak3;
+              T v = T(0);
+              for (int l = 0; l < ak; ++l) v += tr[sdo * kMaxA + l] * xp[l * snk];
+              tn += w * v;
+            }
+            // covariant component along a reversed axis, and odd modes along reversed axes
+            const bool neg = (slot_u ? flu : flv) ^ (flu && (fu & 1)) ^ (flv && (fv & 1));
+            if (neg) tn = -tn;
           }
-          // covariant component along a reversed axis, and odd modes along reversed axes
-          const bool neg = (slot_u ? flu : flv) ^ (flu && (fu & 1)) ^ (flv && (fv & 1));
-          if (neg) tn = -tn;
         }
         val = T(0.5) * ((which == 0 ? ts : -ts) + tn);
       }
@@ -135,14 +231,19 @@ __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
       const int s0 = s % a, s1 = (s / a) % a, s2 = s / a2;
       auto si = [&](int axis) { return axis == 0 ? s0 : (axis == 1 ? s1 : s2); };  // no private array
       // mass: the metric block of field f applied to the D-contracted levels
-      const T* xp = xe + (int64_t)(3 * f) * nst * a3 + s;
       T xd[3];
 #pragma unroll
       for (int dd = 0; dd < 3; ++dd) {
         T v = T(0);
-        for (int M = m0; M < ncol; ++M) {
-          const T w = D[I * ncol + M];
-          if (w != T(0)) v += w * xp[((int64_t)dd * nst + M - m0) * a3];
+        if (staged) {
+          for (int m = 0; m <= q; ++m)
+            v += tD[local_trial_level(q, ns, jsub, m)] * xo[m * 6 * a3 + (3 * f + dd) * a3 + s];
+        } else {
+          const T* xp = xe + ((int64_t)(3 * f + dd) * nst) * a3 + s;
+          for (int M = m0; M < ncol; ++M) {
+            const T w = tD[M];
+            if (w != T(0)) v += w * xp[(int64_t)(M - m0) * a3];
+          }
         }
         xd[dd] = v;
       }
@@ -155,9 +256,11 @@ __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
       const int st1 = axis_stride(c1, a), st2 = axis_stride(c2, a);
       const int b1 = s - si(c1) * st1, b2 = s - si(c2) * st2;
       T curl = T(0);
-      for (int n = 0; n < a; ++n) {
-        const T d1 = f == 0 ? P.tab.Dh[n][si(c1)] : P.tab.Dh[si(c1)][n];
-        const T d2 = f == 0 ? P.tab.Dh[n][si(c2)] : P.tab.Dh[si(c2)][n];
+      const int j1 = si(c1), j2 = si(c2);
+#pragma unroll
+      for (int n = 0; n < A; ++n) {
+        const T d1 = f == 0 ? dh[n * kMaxA + j1] : dh[j1 * kMaxA + n];
+        const T d2 = f == 0 ? dh[n * kMaxA + j2] : dh[j2 * kMaxA + n];
         curl += d1 * src[c2 * a3 + b1 + n * st1] - d2 * src[c1 * a3 + b2 + n * st2];
       }
       // lifts of the face values
@@ -172,7 +275,7 @@ __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
         const int l = si(alpha);
         const int ft = (f == 0 ? 0 : 2) + slot;  // E rows lift F, H rows G
         for (int side = 0; side < 2; ++side) {
-          const T sl = side ? P.tab.tr1[l] : -P.tab.tr0[l];  // sigma L_l(side)
+          const T sl = side ? tr[kMaxA + l] : -tr[l];  // sigma L_l(side)
           lift += (f == 0 ? epsv : -epsv) * sl * fl[((2 * alpha + side) * 4 + ft) * a2 + jj];
         }
       }
@@ -190,7 +293,7 @@ template <typename T>
 int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* load, T* y, hipStream_t s,
                       const int* skip) {
   if (m->lt.empty()) return STDG_OK;
-  if (!m->d_lt) return fail(STDG_E_ARG, "local time steps: device records missing");
+  if (!m->d_lt || !m->d_lt_work) return fail(STDG_E_ARG, "local time steps: device records missing");
   if (mode != STDG_OPERATOR && mode != STDG_RESIDUAL)
     return fail(STDG_E_ARG, "local time steps: preconditioned applies take the P^{-1} pre-pass");
   LParams<T> P;
@@ -205,7 +308,26 @@ int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* l
   P.dt = (T)dt;
   P.resid = mode == STDG_RESIDUAL ? 1 : 0;
   if constexpr (sizeof(T) == 8) fill_tables_f64(&P.tab); else fill_tables_f32(&P.tab);
-  hipLaunchKernelGGL(local_time_kernel<T>, dim3((unsigned)m->lt.size()), dim3(kLThreads), 0, s, P);
+  // one launch per a (rows grouped by a on upload), dynamic LDS for the
+  // largest q among its rows
+  using K = void (*)(LParams<T>);
+  static const K kern[kMaxA + 1] = {nullptr, nullptr, local_time_kernel<T, 2>, local_time_kernel<T, 3>,
+                                    local_time_kernel<T, 4>, local_time_kernel<T, 5>, local_time_kernel<T, 6>,
+                                    local_time_kernel<T, 7>, local_time_kernel<T, 8>, local_time_kernel<T, 9>};
+  for (int a = 2; a <= kMaxA; ++a) {
+    const int64_t b0 = m->lt_a_off[a], b1 = m->lt_a_off[a + 1];
+    if (b1 == b0) continue;
+    int qmax = 1;
+    for (int64_t b = b0; b < b1; ++b) qmax = std::max(qmax, m->info[m->lt[m->lt_work[b] / kMaxSub].elem].q);
+    const size_t a2 = (size_t)a * a, a3 = a2 * a;
+    const size_t base = 2 * kMaxA + kMaxA * kMaxA + (size_t)8 * qmax * (kMaxLocalLevels + 1) + 6 * a3 + 24 * a2;
+    const size_t full = base + (size_t)(qmax + 1) * 6 * a3 + (size_t)qmax * 24 * a2;
+    constexpr size_t kLdsCap = 65536;
+    P.staged = full * sizeof(T) <= kLdsCap ? 1 : 0;
+    P.work = m->d_lt_work + b0;
+    const size_t lds = (P.staged ? full : base) * sizeof(T);
+    hipLaunchKernelGGL(kern[a], dim3((unsigned)(b1 - b0)), dim3(kLThreads), lds, s, P);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? STDG_OK : hip_fail(e, "local-time kernel");
 }

@@ -648,6 +648,7 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
   // onto a piecewise common test space), leave the kernel groups for the
   // local-time kernel
   m->lt.clear();
+  m->lt_work.clear();
   m->lt_bank.clear();
   if (*std::max_element(m->nsub.begin(), m->nsub.end()) > 1) {
     if (!m->hang.empty()) return fail(STDG_E_UNSUPPORTED, "local time steps on meshes with 2:1 hanging faces");
@@ -684,9 +685,17 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
       }
       I.flags |= kLocalTime;
       I.pad = (int32_t)m->lt.size();
+      for (int j = 0; j < m->nsub[e]; ++j) m->lt_work.push_back((int32_t)m->lt.size() * kMaxSub + j);
       m->lt.push_back(R);
     }
+    // the local-time kernel is instantiated per a: group its work by a
+    std::stable_sort(m->lt_work.begin(), m->lt_work.end(), [&](int32_t x, int32_t y) {
+      return m->info[m->lt[x / kMaxSub].elem].a < m->info[m->lt[y / kMaxSub].elem].a;
+    });
   }
+  m->lt_a_off.assign(kMaxA + 2, 0);
+  for (int32_t w : m->lt_work) ++m->lt_a_off[m->info[m->lt[w / kMaxSub].elem].a + 1];
+  for (int a = 1; a <= kMaxA + 1; ++a) m->lt_a_off[a] += m->lt_a_off[a - 1];
 
   // kernel groups by (a, q, affine); their work-list order is set below
   std::map<std::tuple<int, int, int>, std::vector<std::pair<uint64_t, int32_t>>> gm;
@@ -725,8 +734,8 @@ size_t mesh_device_bytes(const Mesh& m) {
     b += r256(sizeof(HangRec) * m.hang.size()) + r256(sizeof(double) * 2 * kMaxA * kMaxA) +
          r256(sizeof(float) * 2 * kMaxA * kMaxA);
   if (!m.lt.empty())
-    b += r256(sizeof(LTRec) * m.lt.size()) + r256(sizeof(double) * m.lt_bank.size()) +
-         r256(sizeof(float) * m.lt_bank.size());
+    b += r256(sizeof(LTRec) * m.lt.size()) + r256(sizeof(int32_t) * m.lt_work.size()) +
+         r256(sizeof(double) * m.lt_bank.size()) + r256(sizeof(float) * m.lt_bank.size());
   for (const Group& g : m.groups) b += r256(sizeof(int32_t) * g.count);
   return b;
 }
@@ -790,10 +799,12 @@ int upload_mesh(Ctx* ctx, Mesh* m) {
     const size_t bl = sizeof(LTRec) * m->lt.size(), nb = m->lt_bank.size();
     std::vector<float> b32(m->lt_bank.begin(), m->lt_bank.end());
     if ((rc = dev_alloc(ctx, (void**)&m->d_lt, bl)) != STDG_OK) return rc;
+    if ((rc = dev_alloc(ctx, (void**)&m->d_lt_work, sizeof(int32_t) * m->lt_work.size())) != STDG_OK) return rc;
     if ((rc = dev_alloc(ctx, &m->d_ltb64, sizeof(double) * nb)) != STDG_OK) return rc;
     if ((rc = dev_alloc(ctx, &m->d_ltb32, sizeof(float) * nb)) != STDG_OK) return rc;
-    m->device_bytes += bl + (sizeof(double) + sizeof(float)) * nb;
+    m->device_bytes += bl + sizeof(int32_t) * m->lt_work.size() + (sizeof(double) + sizeof(float)) * nb;
     STDG_HIP(hipMemcpy(m->d_lt, m->lt.data(), bl, hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d_lt_work, m->lt_work.data(), sizeof(int32_t) * m->lt_work.size(), hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d_ltb64, m->lt_bank.data(), sizeof(double) * nb, hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d_ltb32, b32.data(), sizeof(float) * nb, hipMemcpyHostToDevice));
   }
@@ -913,6 +924,8 @@ void release_mesh(Mesh* m) {
   m->d_hang = nullptr;
   m->d_hs64 = m->d_hs32 = nullptr;
   if (m->d_lt) dev_free(ctx, m->d_lt, sizeof(LTRec) * m->lt.size());
+  if (m->d_lt_work) dev_free(ctx, m->d_lt_work, sizeof(int32_t) * m->lt_work.size());
+  m->d_lt_work = nullptr;
   if (m->d_ltb64) dev_free(ctx, m->d_ltb64, sizeof(double) * m->lt_bank.size());
   if (m->d_ltb32) dev_free(ctx, m->d_ltb32, sizeof(float) * m->lt_bank.size());
   m->d_lt = nullptr;

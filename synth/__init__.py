@@ -10,7 +10,7 @@ projections), and it imports neither the oracle nor the library.
 from .meshes import (box_mesh, hanging_mesh, perturb_interior, affine_transform, centroids,
                      Mesh, trial_sizes, unknown_sizes, offsets, cube_rotations, reorient)
 from .configs import (cavity_small, cavity_two_material, graded_nonaffine,
-                      serving_stream, large_cavity, random_vector, Source,
+                      serving_stream, large_cavity, local_time_cavity, random_vector, Source,
                       ModeSet)
 
 __all__ = [
@@ -18,5 +18,5 @@ __all__ = [
     "cube_rotations", "reorient",
     "trial_sizes", "unknown_sizes", "offsets", "cavity_small",
     "cavity_two_material", "graded_nonaffine", "serving_stream",
-    "large_cavity", "random_vector", "Source", "ModeSet",
+    "large_cavity", "local_time_cavity", "random_vector", "Source", "ModeSet",
 ]

@@ -90,6 +90,21 @@ def cavity_two_material(n=32, p=4, q=3, seed=0):
                 n_slabs=64, source=Source(), init=mode_superposition(seed))
 
 
+def local_time_cavity(n=32, p=4, q=3, seed=0):
+    """The two-material cavity (eps = 1 for centroid x < 0.5, else 4; mu = 1)
+    with local time steps in the faster material: 4 sub-intervals per slab
+    where x < 0.25, 2 where 0.25 <= x < 0.5, 1 in the eps = 4 half (the
+    1 / 2 / 4 local steps of the paper's local-refinement experiments);
+    16 slabs of dt = 0.01 from a seeded superposition of 8 cavity fields."""
+    cfg = cavity_two_material(n, p, q, seed)
+    m = cfg["mesh"]
+    c = centroids(m.vertices, m.hexes)
+    m.nsub = np.where(c[:, 0] < 0.25, 4, np.where(c[:, 0] < 0.5, 2, 1)).astype(np.int32)
+    cfg["name"] = f"cavity {n}^3 p{p} q{q} two-material, local time steps 4/2/1"
+    cfg["n_slabs"] = 16
+    return cfg
+
+
 def graded_nonaffine(n=24, seed=0, n_slabs=40, dt=0.005):
     """Unit cube, n^3 trilinear hexahedra with interior vertices perturbed by
     U(-0.1 h, 0.1 h) per coordinate; ring k = min(3, floor(d / 0.125)) with d the
