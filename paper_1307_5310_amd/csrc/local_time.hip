@@ -19,12 +19,13 @@
 // D[I][M] = int L_I d_s phi_M and N[I][M] = int L_I phi_M are the element's own
 // tables over the unit slab coordinate s.  Elements with one sub-interval
 // whose neighbour has several run here too (their coupling changes).
-// One workgroup per (element, sub-interval): the q test levels of one
-// sub-interval, whose table rows are staged in LDS first.  When they fit
-// (dynamic LDS, 64 KB), the sub-interval's q + 1 own trial levels and the
-// neighbours' traces contracted for all q levels (each neighbour level read
-// once per workgroup) are staged as well, and the level loop reads only LDS;
-// otherwise every level gathers from global memory.
+// One workgroup per (element, sub-interval), one thread per spatial
+// position, instantiated per a = p + 1: the q test levels of one
+// sub-interval.  Its table rows are staged in LDS, each thread keeps the
+// sub-interval's q + 1 own trial levels of its position (all six components)
+// in registers, and when they fit (dynamic LDS, 64 KB) the neighbours' traces
+// contracted for all q levels are staged once (each neighbour level read once
+// per workgroup); otherwise every level gathers them from global memory.
 #include <algorithm>
 
 #include "internal.h"
@@ -32,8 +33,6 @@
 namespace stdg {
 
 namespace {
-
-constexpr int kLThreads = 256;
 
 template <typename T>
 struct LParams {
@@ -54,44 +53,49 @@ struct LParams {
 
 __device__ inline int axis_stride(int axis, int a) { return axis == 0 ? 1 : (axis == 1 ? a : a * a); }
 
+template <int A>
+struct LCfg {
+  static constexpr int NT = ((A * A * A + 63) / 64) * 64;  // one spatial position per thread
+};
+
 template <typename T, int A>
-__global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
+__global__ void __launch_bounds__(LCfg<A>::NT) local_time_kernel(LParams<T> P) {
   if (P.skip && *P.skip == 0) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   constexpr int TW = kMaxLocalLevels + 1;  // row width of the staged tables
+  constexpr int a = A, a2 = A * A, a3 = A * A * A;  // this launch's rows all have a = p + 1 = A
+  constexpr int NT = LCfg<A>::NT, nf = 24 * a2;     // face items: [face][F_u, F_v, G_u, G_v][face mode]
+  constexpr int QM = kMaxQ + 1;                     // trial levels of one sub-interval, at most
   const int32_t wk = P.work[blockIdx.x];
   const LTRec* R = P.rec + wk / kMaxSub;  // read through the pointer (no private copy)
   const int jsub = wk % kMaxSub;
   const int e = R->elem;
   const ElemInfo* Ie = P.info + e;
-  constexpr int a = A, a2 = A * A, a3 = A * A * A;  // this launch's rows all have a = p + 1 = A
   const int q = Ie->q, ns = Ie->nsub;
   const int nt = q * ns;        // test levels
   const int ncol = nt + 1;      // trial levels (columns of the own tables)
   const int m0 = P.resid ? 0 : 1;
   const int nst = ncol - m0;    // stored trial levels
-  const int nf = 24 * a2;       // face items: [face][F_u, F_v, G_u, G_v][face mode]
-  // LDS: table rows [D, N, C_0..C_5][i][M] of this sub-interval's q test
-  // levels, the contracted own fields, the face values; staged: the own
-  // trial levels of the sub-interval and the neighbours' contracted traces
-  T* tr = (T*)lds_raw;          // L_l(0), L_l(1), Dh (copied from the kernel arguments)
+  // LDS: L_l(0), L_l(1), Dh; the table rows [D, N, C_0..C_5][i][M] of this
+  // sub-interval's q test levels; the contracted own fields of one level; the
+  // face values; staged: the neighbours' traces contracted for all q levels
+  T* tr = (T*)lds_raw;
   T* dh = tr + 2 * kMaxA;
   T* tb = dh + kMaxA * kMaxA;
   T* xn = tb + 8 * q * TW;
   T* fl = xn + 6 * a3;
-  T* xo = fl + nf;              // [m = 0..q][F][c][s]          (staged)
-  T* nbt = xo + (q + 1) * 6 * a3;  // [i][face item]          (staged)
+  T* nbt = fl + nf;
   const bool staged = P.staged != 0;
   const T* xe = P.x + (P.resid ? Ie->trial_off : Ie->unk_off);
   T* ye = P.y + Ie->unk_off;
   const T* le = (P.resid && P.load) ? P.load + Ie->unk_off : nullptr;
   const double* Me = P.metric[e].m;
   const int tid = threadIdx.x;
-  for (int t = tid; t < 2 * kMaxA + kMaxA * kMaxA; t += kLThreads) {
+  for (int t = tid; t < 2 * kMaxA + kMaxA * kMaxA; t += NT) {
     const int u = t - 2 * kMaxA;
     tr[t] = t < kMaxA ? P.tab.tr0[t] : (t < 2 * kMaxA ? P.tab.tr1[t - kMaxA] : P.tab.Dh[u / kMaxA][u % kMaxA]);
   }
-  for (int t = tid; t < 8 * q * TW; t += kLThreads) {
+  for (int t = tid; t < 8 * q * TW; t += NT) {
     const int r = t / (q * TW), rest = t - r * q * TW, i = rest / TW, M = rest - i * TW;
     const int I = jsub * q + i;
     T v = T(0);
@@ -106,19 +110,39 @@ __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
     }
     tb[t] = v;
   }
+  // the trial levels of this sub-interval (own tables have no other columns
+  // in its rows), and this thread's position and its own levels in registers
+  int lev[QM];
+#pragma unroll
+  for (int m = 0; m < QM; ++m) lev[m] = m <= q ? local_trial_level(q, ns, jsub, m) : 0;
+  const int s = tid;
+  const bool pos = s < a3;
+  const int s0 = s % A, s1 = (s / A) % A, s2 = s / a2;
+  auto si = [&](int axis) { return axis == 0 ? s0 : (axis == 1 ? s1 : s2); };  // no private array
+  // (a = 9, 768 threads: too few registers per thread; read the levels at each use)
+  constexpr bool REG = NT <= 512;
+  constexpr int UF = REG ? 6 : 1, UM = REG ? QM : 1;  // unrolled (register operands) or rolled loops
+  auto load_own = [&](int fc, int m) {
+    return (pos && m <= q && lev[m] >= m0) ? xe[((int64_t)fc * nst + lev[m] - m0) * a3 + s] : T(0);
+  };
+  T xo[REG ? 6 : 1][REG ? QM : 1];
+  if constexpr (REG) {
+#pragma unroll
+    for (int fc = 0; fc < 6; ++fc)
+#pragma unroll
+      for (int m = 0; m < QM; ++m) xo[fc][m] = load_own(fc, m);
+  }
+  auto own_level = [&](int fc, int m) {
+    if constexpr (REG) return xo[fc][m]; else return load_own(fc, m);
+  };
   __syncthreads();
   if (staged) {
-    for (int t = tid; t < (q + 1) * 6 * a3; t += kLThreads) {
-      const int m = t / (6 * a3), rest = t - m * 6 * a3, fc = rest / a3, s = rest - fc * a3;
-      const int L = local_trial_level(q, ns, jsub, m);
-      xo[t] = L >= m0 ? xe[((int64_t)fc * nst + L - m0) * a3 + s] : T(0);
-    }
-    for (int t = tid; t < nf; t += kLThreads) {
+    for (int t = tid; t < nf; t += NT) {
       for (int i = 0; i < q; ++i) nbt[i * nf + t] = T(0);
       const int g = t / (4 * a2), k = Ie->nb[g];
       if (k < 0) continue;
       const int rest = t - g * 4 * a2, ft = rest / a2, jj = rest - ft * a2;
-      const int fu = jj % a, fv = jj / a;
+      const int fu = jj % A, fv = jj / A;
       const bool slot_u = (ft & 1) == 0;
       const int fld = (ft >> 1) == 0 ? 1 : 0;
       const uint8_t code = Ie->orient[g];
@@ -153,24 +177,20 @@ __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
     const T* tD = tb + i * TW;
     const T* tN = tb + (q + i) * TW;
     __syncthreads();  // staging done, or the previous level's readers of xn and fl are done
-    for (int t = tid; t < 6 * a3; t += kLThreads) {
-      const int fc = t / a3, s = t - fc * a3;
-      T v = T(0);
-      if (staged) {
-        for (int m = 0; m <= q; ++m) v += tN[local_trial_level(q, ns, jsub, m)] * xo[m * 6 * a3 + t];
-      } else {
-        const T* xp = xe + (int64_t)fc * nst * a3 + s;
-        for (int M = m0; M < ncol; ++M) {
-          const T w = tN[M];
-          if (w != T(0)) v += w * xp[(int64_t)(M - m0) * a3];
-        }
+    if (pos) {
+#pragma unroll UF
+      for (int fc = 0; fc < 6; ++fc) {
+        T v = T(0);
+#pragma unroll UM
+        for (int m = 0; m < QM; ++m)
+          if (m <= q) v += tN[lev[m]] * own_level(fc, m);
+        xn[fc * a3 + s] = v;
       }
-      xn[t] = v;
     }
     __syncthreads();
-    for (int t = tid; t < nf; t += kLThreads) {
+    for (int t = tid; t < nf; t += NT) {
       const int g = t / (4 * a2), rest = t - g * 4 * a2, ft = rest / a2, jj = rest - ft * a2;
-      const int fu = jj % a, fv = jj / a;
+      const int fu = jj % A, fv = jj / A;
       const int alpha = g >> 1, side = g & 1;
       const int ua = alpha == 0 ? 1 : 0, va = alpha == 2 ? 1 : 2;
       const int which = ft >> 1;           // 0: F (H traces), 1: G (E traces)
@@ -225,26 +245,18 @@ __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
       fl[t] = val;
     }
     __syncthreads();
-    for (int t = tid; t < 6 * a3; t += kLThreads) {
-      const int fc = t / a3, s = t - fc * a3;
+    if (!pos) continue;
+#pragma unroll UF
+    for (int fc = 0; fc < 6; ++fc) {
       const int f = fc / 3, c = fc - 3 * f;
-      const int s0 = s % a, s1 = (s / a) % a, s2 = s / a2;
-      auto si = [&](int axis) { return axis == 0 ? s0 : (axis == 1 ? s1 : s2); };  // no private array
       // mass: the metric block of field f applied to the D-contracted levels
       T xd[3];
 #pragma unroll
       for (int dd = 0; dd < 3; ++dd) {
         T v = T(0);
-        if (staged) {
-          for (int m = 0; m <= q; ++m)
-            v += tD[local_trial_level(q, ns, jsub, m)] * xo[m * 6 * a3 + (3 * f + dd) * a3 + s];
-        } else {
-          const T* xp = xe + ((int64_t)(3 * f + dd) * nst) * a3 + s;
-          for (int M = m0; M < ncol; ++M) {
-            const T w = tD[M];
-            if (w != T(0)) v += w * xp[(int64_t)(M - m0) * a3];
-          }
-        }
+#pragma unroll UM
+        for (int m = 0; m < QM; ++m)
+          if (m <= q) v += tD[lev[m]] * own_level(3 * f + dd, m);
         xd[dd] = v;
       }
       const double* Mf = Me + 6 * f;
@@ -254,9 +266,9 @@ __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
       const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
       const T* src = xn + (f == 0 ? 3 : 0) * a3;
       const int st1 = axis_stride(c1, a), st2 = axis_stride(c2, a);
-      const int b1 = s - si(c1) * st1, b2 = s - si(c2) * st2;
-      T curl = T(0);
       const int j1 = si(c1), j2 = si(c2);
+      const int b1 = s - j1 * st1, b2 = s - j2 * st2;
+      T curl = T(0);
 #pragma unroll
       for (int n = 0; n < A; ++n) {
         const T d1 = f == 0 ? dh[n * kMaxA + j1] : dh[j1 * kMaxA + n];
@@ -265,6 +277,7 @@ __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
       }
       // lifts of the face values
       T lift = T(0);
+#pragma unroll
       for (int alpha = 0; alpha < 3; ++alpha) {
         if (alpha == c) continue;
         const int d = 3 - c - alpha;
@@ -274,6 +287,7 @@ __global__ void __launch_bounds__(kLThreads) local_time_kernel(LParams<T> P) {
         const int jj = si(ua) + a * si(va);
         const int l = si(alpha);
         const int ft = (f == 0 ? 0 : 2) + slot;  // E rows lift F, H rows G
+#pragma unroll
         for (int side = 0; side < 2; ++side) {
           const T sl = side ? tr[kMaxA + l] : -tr[l];  // sigma L_l(side)
           lift += (f == 0 ? epsv : -epsv) * sl * fl[((2 * alpha + side) * 4 + ft) * a2 + jj];
@@ -314,6 +328,8 @@ int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* l
   static const K kern[kMaxA + 1] = {nullptr, nullptr, local_time_kernel<T, 2>, local_time_kernel<T, 3>,
                                     local_time_kernel<T, 4>, local_time_kernel<T, 5>, local_time_kernel<T, 6>,
                                     local_time_kernel<T, 7>, local_time_kernel<T, 8>, local_time_kernel<T, 9>};
+  static const int nthreads[kMaxA + 1] = {0, 0, LCfg<2>::NT, LCfg<3>::NT, LCfg<4>::NT, LCfg<5>::NT,
+                                          LCfg<6>::NT, LCfg<7>::NT, LCfg<8>::NT, LCfg<9>::NT};
   for (int a = 2; a <= kMaxA; ++a) {
     const int64_t b0 = m->lt_a_off[a], b1 = m->lt_a_off[a + 1];
     if (b1 == b0) continue;
@@ -321,12 +337,12 @@ int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* l
     for (int64_t b = b0; b < b1; ++b) qmax = std::max(qmax, m->info[m->lt[m->lt_work[b] / kMaxSub].elem].q);
     const size_t a2 = (size_t)a * a, a3 = a2 * a;
     const size_t base = 2 * kMaxA + kMaxA * kMaxA + (size_t)8 * qmax * (kMaxLocalLevels + 1) + 6 * a3 + 24 * a2;
-    const size_t full = base + (size_t)(qmax + 1) * 6 * a3 + (size_t)qmax * 24 * a2;
+    const size_t full = base + (size_t)qmax * 24 * a2;
     constexpr size_t kLdsCap = 65536;
     P.staged = full * sizeof(T) <= kLdsCap ? 1 : 0;
     P.work = m->d_lt_work + b0;
     const size_t lds = (P.staged ? full : base) * sizeof(T);
-    hipLaunchKernelGGL(kern[a], dim3((unsigned)(b1 - b0)), dim3(kLThreads), lds, s, P);
+    hipLaunchKernelGGL(kern[a], dim3((unsigned)(b1 - b0)), dim3((unsigned)nthreads[a]), lds, s, P);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? STDG_OK : hip_fail(e, "local-time kernel");

@@ -9,7 +9,8 @@ Bars: FP64 <= 1e-12, raw FP32 <= 1e-5 (relative 2-norm and largest entry);
 slab solves <= 1e-10 against the oracle's direct solve with the energy
 conserved.  Covered: mixed n with mixed p and q, reoriented elements, a
 sheared (non-diagonal metric) mesh, a larger mesh where most rows stay in the
-kernel groups, all three modes (the preconditioned one through the P^{-1}
+kernel groups, p = 6 and 8 (the widest workgroups, FP64 traces gathered per
+level), all three modes (the preconditioned one through the P^{-1}
 pre-pass that mixes the time levels), the allocation-free entry point, slab
 solves in FP64 and FP32 inner precision; refusals of what the path does not
 take."""
@@ -93,6 +94,17 @@ def test_larger_mesh_few_local_rows(lib):
     m = _mesh((4, 4, 4), p=2, q=2, nsub=(1,), seed=412)
     m.nsub[[5, 42]] = (2, 4)
     _check(lib, m, 0.04, 412, "local time 4^3")
+
+
+def test_high_degrees(lib):
+    # p = 6 and 8 side by side: 384 and 768 threads per workgroup, the own
+    # levels read at each use for p = 8, and its FP64 neighbour traces
+    # gathered per level (the staged ones exceed 64 KB of LDS)
+    v, h = synth.box_mesh((2, 1, 1))
+    rng = np.random.default_rng(417)
+    m = synth.Mesh(v, h, np.array([6, 8], np.int32), np.array([2, 1], np.int32), rng.uniform(1, 4, 2),
+                   rng.uniform(1, 2, 2), nsub=np.array([2, 1], np.int32))
+    _check(lib, m, 0.05, 417, "local time p6|p8")
 
 
 def test_noalloc_entry_point(lib):
