@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--q", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--no-march", action="store_true", help="skip the 64-slab marches of the solve leg")
+    ap.add_argument("--no-march", action="store_true",
+                    help="skip the 64-slab marches of the solve leg and the march of the local-time leg")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="elements in the oracle's timed sample (0 = sized to ~15 s)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -341,7 +342,7 @@ def main():
     local_time = None
     if not args.no_local_time:
         log("local time steps: two-material 32^3 cavity, 4/2/1 sub-intervals")
-        local_time = time_local_time(stdg, torch, ctx, 20, 5)
+        local_time = time_local_time(stdg, torch, ctx, 20, 5, march=not args.no_march)
 
     graded = large = None
     if not args.no_graded:
@@ -665,7 +666,7 @@ def time_large(stdg, torch, ctx, steps, warmup):
     return out
 
 
-def time_local_time(stdg, torch, ctx, steps, warmup):
+def time_local_time(stdg, torch, ctx, steps, warmup, march=True):
     """Local time steps: the two-material 32^3 cavity (p = 4, q = 3) with 4 /
     2 / 1 sub-intervals per slab by region.  Operator and preconditioned
     applies (the rows of elements with sub-intervals and of their neighbours
@@ -698,7 +699,7 @@ def time_local_time(stdg, torch, ctx, steps, warmup):
                 "gdof_per_s": round(trial / (ms * 1e-3) / 1e9, 2),
                 "hbm_frac": round(bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": bytes_}
             log("local time (%s) %s: operator %.3f ms, preconditioned %.3f ms" % (label, name, ms, ms_pre))
-        if nsub is not None:
+        if nsub is not None and march:
             out["march_fp32_refine"] = _march(stdg, torch, mh, cfg, info, cfg["n_slabs"],
                                               inner_prec=stdg.STDG_FP32, krylov_prec=stdg.STDG_FP32, rtol=1e-10,
                                               max_iters=3000, max_refine=300, use_graph=1)
