@@ -202,7 +202,7 @@ struct Mesh {
   // its captured graphs when the epoch differs from the one they were captured at.
   uint64_t epoch = 0;
   // materials and metric bounds for the iteration-error bound: min eps, min mu,
-  // and max over elements of 1 / lambda_min(|J| DF^{-1} DF^{-T}) (centre metric)
+  // and max over elements of n / lambda_min(|J| DF^{-1} DF^{-T}) (centre metric; n sub-intervals)
   double eps_min = 0.0, mu_min = 0.0, inv_gmin = 0.0;
   int p_max, q_max;
   // device copies

@@ -103,6 +103,8 @@ __device__ double inv3(const double A[3][3], double B[3][3]) {
 
 // Space-time separable current J(x, t) = dir amp g(x) h(t) (stdg_source kind 1):
 //   L_E[c, i, s] = T_i S_c(s),  T_i = dt sum_t w_t L_i(tau_t) h(t0 + tau_t dt),
+// (with n sub-intervals, test level j q + i: (dt / n) sum_t w_t L_i(tau_t)
+// h(t0 + (j + tau_t) dt / n), the rule applied per sub-interval),
 //   S_c(s) = amp sum_g w_g phi_s(x_g) g(F(x_g)) |J| (DF^{-1} dir)_c,
 // with Gauss rules of q + 3 points in time and p + 3 per space direction; S is
 // sum factorised like the projection (point values in shared memory, then one
@@ -110,13 +112,15 @@ __device__ double inv3(const double A[3][3], double B[3][3]) {
 // doubles, nx = a + 2.
 __global__ void load_kernel(LoadParams P) {
   extern __shared__ double sh[];
-  __shared__ double qx[kMaxA + 2], qw[kMaxA + 2], Bt[(kMaxA + 2) * kMaxA], tx[kMaxQ + 3], tw[kMaxQ + 3], Ti[kMaxQ];
+  __shared__ double qx[kMaxA + 2], qw[kMaxA + 2], Bt[(kMaxA + 2) * kMaxA], tx[kMaxQ + 3], tw[kMaxQ + 3],
+      Ti[kMaxLocalLevels];
   const int e = blockIdx.x;
   const ElemInfo I = P.info[e];
   const int a = I.a, q = I.q, a2 = a * a, a3 = a2 * a;
+  const int ns = I.nsub, nl = q * ns;  // sub-intervals, test levels
   double* out = P.out + I.unk_off;
   if (P.src.kind != 1) {
-    for (int idx = threadIdx.x; idx < 6 * q * a3; idx += blockDim.x) out[idx] = 0.0;
+    for (int idx = threadIdx.x; idx < 6 * nl * a3; idx += blockDim.x) out[idx] = 0.0;
     return;
   }
   const int nx = a + 2, nx2 = nx * nx, nx3 = nx2 * nx, nt = q + 3;
@@ -126,15 +130,16 @@ __global__ void load_kernel(LoadParams P) {
   }
   __syncthreads();
   const stdg_source& S = P.src;
-  if ((int)threadIdx.x < q) {
-    const int i = threadIdx.x;
+  if ((int)threadIdx.x < nl) {
+    const int j = (int)threadIdx.x / q, i = (int)threadIdx.x - j * q;
+    const double hs = P.dt / ns;
     double v = 0.0;
     for (int g = 0; g < nt; ++g) {
-      const double tt = P.t0 + tx[g] * P.dt - S.t0;
+      const double tt = P.t0 + (j + tx[g]) * hs - S.t0;
       const double h = sin(2.0 * M_PI * S.f0 * tt) * exp(-tt * tt / (2.0 * S.sigma_t * S.sigma_t));
       v += tw[g] * leg(i, tx[g]) * h;
     }
-    Ti[i] = P.dt * v;
+    Ti[threadIdx.x] = hs * v;
   }
   for (int k = threadIdx.x; k < nx * a; k += blockDim.x) {
     const int g = k / a, j = k - g * a;
@@ -176,9 +181,9 @@ __global__ void load_kernel(LoadParams P) {
       const int jk = s % a2, l = s / a2;
       double acc = 0.0;
       for (int g3 = 0; g3 < nx; ++g3) acc += Bt[g3 * a + l] * T2[g3 * a2 + jk];
-      for (int i = 0; i < q; ++i) {
-        out[((int64_t)c * q + i) * a3 + s] = Ti[i] * acc;      // E part
-        out[((int64_t)(3 + c) * q + i) * a3 + s] = 0.0;        // H part: g = 0
+      for (int i = 0; i < nl; ++i) {
+        out[((int64_t)c * nl + i) * a3 + s] = Ti[i] * acc;      // E part
+        out[((int64_t)(3 + c) * nl + i) * a3 + s] = 0.0;        // H part: g = 0
       }
     }
     __syncthreads();
@@ -351,13 +356,14 @@ __global__ void energy_kernel(const ElemInfo* info, const ElemMetric* metric, co
 // and spatial modes of R_f . (G^{-1} R_f) with the unit-coefficient metric
 // (exact mass inverse on affine elements; the centre metric on trilinear ones).
 // partial[2 e + f] for the fields f = E, H (divided by dt by the caller).
+// With n sub-intervals a test function lives on dt / n: the sum times n.
 __global__ void dual_norm_kernel(const ElemInfo* info, const ElemMetric* metric, int64_t ne, const double* R,
                                  double* partial) {
   const int64_t e = blockIdx.x;
   if (e >= ne) return;
   const ElemInfo I = info[e];
   if (!(I.flags & kAffine)) return;  // trilinear elements: the exact mass solve of dualnorm.hip
-  const int per = I.q * I.a * I.a * I.a;
+  const int per = I.q * I.nsub * I.a * I.a * I.a;
   const double* mm = metric[e].m;
   const double kap[2] = {metric[e].eps, metric[e].mu};
   __shared__ double red[2][256];
@@ -382,8 +388,8 @@ __global__ void dual_norm_kernel(const ElemInfo* info, const ElemMetric* metric,
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partial[2 * e] = red[0][0];
-    partial[2 * e + 1] = red[1][0];
+    partial[2 * e] = red[0][0] * I.nsub;
+    partial[2 * e + 1] = red[1][0] * I.nsub;
   }
 }
 
@@ -437,7 +443,6 @@ int energy_async(const Mesh* m, const double* state, double* d_partial, double* 
 }
 
 int dual_norms_async(const Mesh* m, double dt, const double* R, double* d_partial, double* d_out, hipStream_t s) {
-  if (!m->lt.empty()) return fail(STDG_E_UNSUPPORTED, "dual norms with local time steps");
   hipLaunchKernelGGL(dual_norm_kernel, dim3((unsigned)m->ne), dim3(256), 0, s, m->d_info, m->d_metric, m->ne, R,
                      d_partial);
   if (m->n_nonaffine > 0) {
@@ -473,7 +478,6 @@ int stdg_load_assemble(const stdg_mesh* mesh, const stdg_source* src, double t0,
   if (src->kind == 1 && (!(src->sigma_x > 0.0) || !(src->sigma_t > 0.0)))
     return fail(STDG_E_ARG, "stdg_load_assemble: sigma_x and sigma_t must be > 0");
   const Mesh& m = mesh->m;
-  if (!m.lt.empty()) return fail(STDG_E_UNSUPPORTED, "stdg_load_assemble: local time steps");
   LoadParams P;
   P.info = m.d_info;
   P.verts = m.d_verts;

@@ -602,7 +602,8 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     }
     sym_inverse(M.m, M.m + 12);
     sym_inverse(M.m + 6, M.m + 18);
-    m->inv_gmin = std::max(m->inv_gmin, 1.0 / sym_lambda_min(G));
+    // with n sub-intervals a test function lives on dt / n: the dual-norm bound scales by n
+    m->inv_gmin = std::max(m->inv_gmin, m->nsub[e] / sym_lambda_min(G));
     m->eps_min = e == 0 ? d->eps[e] : std::min(m->eps_min, d->eps[e]);
     m->mu_min = e == 0 ? d->mu[e] : std::min(m->mu_min, d->mu[e]);
     bool diag = affine && std::fabs(G[3]) <= 1e-13 * (G[0] + G[1] + G[2]) &&

@@ -463,8 +463,6 @@ extern "C" int stdg_slab_solve(const stdg_mesh* mesh, double t0, double dt, cons
   if (rc != STDG_OK) return rc;
   std::memset(info, 0, sizeof(*info));
   Mesh* m = const_cast<Mesh*>(&mesh->m);
-  if (o.eta_tol > 0.0 && !m->lt.empty())
-    return fail(STDG_E_UNSUPPORTED, "stdg_slab_solve: inexact solves (eta_tol) with local time steps");
   hipStream_t s = (hipStream_t)stream;
   // the mesh's cached solver (allocated on the first call, kept until the
   // mesh is freed or the precisions / restart change), or a private one if

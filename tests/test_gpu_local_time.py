@@ -12,8 +12,9 @@ sheared (non-diagonal metric) mesh, a larger mesh where most rows stay in the
 kernel groups, p = 6 and 8 (the widest workgroups, FP64 traces gathered per
 level), all three modes (the preconditioned one through the P^{-1}
 pre-pass that mixes the time levels), the allocation-free entry point, slab
-solves in FP64 and FP32 inner precision; refusals of what the path does not
-take."""
+solves in FP64 and FP32 inner precision, the load per sub-interval with a
+source-driven solve, dual norms and an inexact march within eta_it;
+refusals of what the path does not take."""
 import numpy as np
 import pytest
 
@@ -147,6 +148,70 @@ def test_slab_solve_and_energy(lib, inner, krylov):
     e0 = d.energy(s0)
     assert abs(d.energy(ref) - e0) < 1e-11 * e0
     assert abs(info["energy_end"] - e0) < 1e-10 * e0
+
+
+def test_load_and_slab_solve_with_source(lib):
+    # the load per sub-interval, and a source-driven slab solve
+    from oracle import fields
+    mesh = _mesh((3, 2, 1), p=2, q=2, nsub=(1, 2, 4), seed=418, mixed=True)
+    d = oracle_disc(mesh)
+    src = synth.Source(kind=1, amp=2.0, center=(0.4, 0.6, 0.5), sigma_x=0.2, f0=2.0, t0=0.05,
+                       sigma_t=0.1, dir=(0.2, 1.0, -0.4))
+    J = fields.gaussian_pulse(src.amp, src.center, src.sigma_x, src.f0, src.t0, src.sigma_t, src.dir)
+    t0, dt = 0.02, 0.04
+    note("local time load: oracle")
+    L_ref = d.load(J, t0, dt)
+    mh = lib.upload(mesh)
+    try:
+        t = lib.torch
+        Ld = t.zeros(d.unk_off[-1], dtype=t.float64, device="cuda")
+        note("local time load")
+        lib.stdg.stdg_load_assemble(mh, src, t0, dt, Ld)
+        assert rel_err(Ld.cpu().numpy(), L_ref) < 1e-12
+        s0 = np.random.default_rng(418).standard_normal(d.state_off[-1])
+        U_ref = d.solve_direct(s0, dt, L_ref)
+        st = lib.dev(s0, t.float64)
+        Ud = t.zeros(d.trial_off[-1], dtype=t.float64, device="cuda")
+        note("local time solve with source")
+        info = lib.stdg.stdg_slab_solve(mh, t0, dt, Ld, st, inner_prec=1, rtol=1e-13, max_iters=800,
+                                        max_refine=80, slab_U=Ud, krylov_prec=1)
+        assert info["status"] == 0, info
+        assert rel_err(Ud.cpu().numpy(), U_ref) < 1e-10
+    finally:
+        lib.stdg.stdg_mesh_free(mh)
+
+
+def test_dual_norm_and_inexact_march(lib):
+    # dual norms with test functions on dt / n, and eta_it bounding the
+    # iteration error of an inexact march (Section 5.3)
+    mesh = _mesh((2, 2, 1), p=2, q=2, nsub=(1, 2, 4), seed=419, mixed=True)
+    d = oracle_disc(mesh)
+    rng = np.random.default_rng(419)
+    dt, n_slabs = 0.05, 3
+    mh = lib.upload(mesh)
+    try:
+        R = rng.standard_normal(d.unk_off[-1])
+        note("local time dual norm")
+        got = lib.stdg.stdg_residual_dual_norm(mh, dt, lib.dev(R, lib.torch.float64))
+        ref = d.dual_norms(R, dt)
+        assert np.abs(np.asarray(got) - ref).max() < 1e-12 * ref.max()
+        s = rng.standard_normal(d.state_off[-1])
+        e0 = d.energy(s)
+        eta_tol = 1e-4 * np.sqrt(2 * e0)
+        st = lib.dev(s, lib.torch.float64)
+        s_ex, eta2 = s.copy(), 0.0
+        for n in range(n_slabs):
+            note("local time inexact slab %d" % n)
+            r = lib.stdg.stdg_slab_solve(mh, n * dt, dt, None, st, inner_prec=1, krylov_prec=1, rtol=1e-12,
+                                         max_iters=2000, max_refine=200, eta_tol=eta_tol, eta_t_final=n_slabs * dt)
+            assert r["status"] == 0, r
+            assert r["eta2"] <= eta_tol ** 2
+            eta2 += r["eta2"]
+            s_ex = d.level_state(d.solve_direct(s_ex, dt), 1)
+        err2 = 2.0 * d.energy(st.cpu().numpy() - s_ex)
+        assert err2 <= eta2, (err2, eta2)
+    finally:
+        lib.stdg.stdg_mesh_free(mh)
 
 
 def test_refusals(lib):

@@ -238,3 +238,30 @@ def test_dual_norm_against_quadrature_gram():
             ref[f] += r @ np.linalg.solve(G, r)
     got = d.dual_norms(R, dt)
     assert np.abs(got - ref).max() < 1e-12 * ref.max()
+
+
+@pytest.mark.parametrize("n_slabs", [1, 3])
+def test_eta_it_bounds_the_iteration_error(n_slabs):
+    # Section 5.3 with the dual norm of the piecewise test space (dt / n per
+    # test level): eta_it still bounds the iteration error of inexact slab
+    # solutions with mixed sub-intervals (the stability behind it is Thm 4.1)
+    v, h = synth.box_mesh((2, 2, 1), hi=(0.6, 0.5, 0.3))
+    rng = np.random.default_rng(30 + n_slabs)
+    d = Discretisation(v, h, np.full(4, 2), rng.integers(1, 4, 4), rng.uniform(1, 4, 4), rng.uniform(1, 2, 4),
+                       nk=np.array([4, 2, 1, 2]))
+    dt = 0.05
+    s_exact = rng.standard_normal(d.state_off[-1])
+    s_inexact = s_exact.copy()
+    eta2 = 0.0
+    for n in range(n_slabs):
+        U_ex = d.solve_direct(s_exact, dt)
+        U_in = d.solve_direct(s_inexact, dt)
+        x = d.unknowns_of(U_in) + 1e-3 * rng.standard_normal(d.unk_off[-1])
+        U_in = d.embed_unknowns(x, s_inexact)
+        R = d.residual(U_in, dt) - d.residual(d.solve_direct(s_inexact, dt), dt)
+        eta2 += d.eta_it_term(R, dt, n_slabs * dt)
+        s_exact = d.level_state(U_ex, 1)
+        s_inexact = d.level_state(U_in, 1)
+    err2 = 2.0 * d.energy(s_inexact - s_exact)
+    assert err2 <= eta2, (err2, eta2)
+    assert err2 > 1e-4 * eta2
