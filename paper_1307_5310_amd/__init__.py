@@ -346,9 +346,10 @@ def stdg_serve_start(ctx, hbm_budget=0, max_active=0, inner_prec=STDG_FP32, rest
 
 
 def stdg_serve_submit(server, vertices, hexes, p, q, eps, mu, t0, dt, n_slabs, source=None, mnl=None,
-                      abc=None, init_state=None, c_diss=0.0):
-    """Queue one request; every array is copied before return.  Returns the ticket."""
-    d, _keep = _mesh_desc(vertices, hexes, p, q, eps, mu)
+                      abc=None, init_state=None, c_diss=0.0, nsub=None):
+    """Queue one request; every array is copied before return.  Returns the ticket.
+    ``nsub``: temporal sub-intervals per element (local time steps), or None."""
+    d, _keep = _mesh_desc(vertices, hexes, p, q, eps, mu, nsub)
     r = Request()
     r.mesh = d
     r.t0, r.dt, r.n_slabs = float(t0), float(dt), int(n_slabs)

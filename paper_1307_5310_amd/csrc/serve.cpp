@@ -159,8 +159,9 @@ size_t footprint_of(const Request& r, const SlabOpts& so) {
   auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const Mesh& m = r.mesh->m;
   size_t b = mesh_device_bytes(m);
-  // preconditioner scratch of meshes with a non-diagonal metric (FP32 then FP64)
-  if (m.n_diag != m.ne) b += r256(sizeof(float) * r.n_unk) + r256(sizeof(double) * r.n_unk);
+  // preconditioner scratch of meshes with a non-diagonal metric or local time
+  // steps (the P^{-1} pre-pass; FP32 then FP64)
+  if (m.n_diag != m.ne || !m.lt.empty()) b += r256(sizeof(float) * r.n_unk) + r256(sizeof(double) * r.n_unk);
   // state, load, projection inputs
   b += r256(sizeof(double) * r.n_state) + (r.src.kind ? r256(sizeof(double) * r.n_unk) : 0) +
        2 * r256(sizeof(double) * 3 * (r.mnl.size() / 3 + 1));
@@ -486,9 +487,6 @@ int stdg_serve_submit(stdg_server* server, const stdg_request* req, uint64_t* ti
   if (d.n_elements <= 0 || d.n_vertices <= 0 || !d.vertices || !d.hexes || !d.p || !d.q || !d.eps || !d.mu)
     return fail(STDG_E_ARG, "stdg_serve_submit: empty mesh or NULL array");
   if (d.n_elements > (int64_t)INT32_MAX) return fail(STDG_E_ARG, "stdg_serve_submit: too many elements");
-  if (d.nsub)
-    for (int64_t e = 0; e < d.n_elements; ++e)
-      if (d.nsub[e] != 1) return fail(STDG_E_UNSUPPORTED, "stdg_serve_submit: local time steps");
   if (!(req->dt > 0.0) || req->n_slabs < 1) return fail(STDG_E_ARG, "stdg_serve_submit: need dt > 0 and n_slabs >= 1");
   if (req->source.kind != 0 && req->source.kind != 1) return fail(STDG_E_ARG, "stdg_serve_submit: unknown source kind");
   if (req->n_modes < 0 || (req->n_modes > 0 && (!req->mnl || !req->abc)))

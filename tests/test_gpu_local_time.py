@@ -214,6 +214,47 @@ def test_dual_norm_and_inexact_march(lib):
         lib.stdg.stdg_mesh_free(mh)
 
 
+def test_serving_request_matches_plain_march(lib):
+    # a serving request with local time steps (a source and a mode-free
+    # initial state) is bitwise the plain march of the same slabs
+    stdg = lib.stdg
+    mesh = _mesh((2, 2, 2), p=2, q=2, nsub=(1, 2, 4), seed=420, mixed=True)
+    src = synth.Source(kind=1, amp=1.0, center=(0.5, 0.5, 0.5), sigma_x=0.2, f0=2.0, t0=0.05,
+                       sigma_t=0.1, dir=(0.0, 0.0, 1.0))
+    init = np.random.default_rng(420).standard_normal(mesh.state_size())
+    dt, n_slabs = 0.04, 3
+    opts = dict(inner_prec=1, rtol=1e-12, max_iters=3000, max_refine=300)
+    srv = stdg.stdg_serve_start(lib.ctx, hbm_budget=1 << 28, **opts)
+    try:
+        note("local time serving request")
+        t = stdg.stdg_serve_submit(srv, mesh.vertices, mesh.hexes, mesh.p, mesh.q, mesh.eps, mesh.mu, 0.0, dt,
+                                   n_slabs, source=src, init_state=init, nsub=mesh.nsub)
+        st_out = np.zeros(mesh.state_size())
+        res = None
+        for _ in range(60000):
+            res = stdg.stdg_serve_poll(srv, t, st_out)
+            if res is not None:
+                break
+            import time
+            time.sleep(0.002)
+        assert res is not None and res["status"] == 0, res
+    finally:
+        stdg.stdg_serve_stop(srv)
+    mh = lib.upload(mesh)
+    try:
+        info = stdg.stdg_mesh_info(mh)
+        st = lib.dev(init, lib.torch.float64)
+        L = lib.torch.zeros(info["unknown_size"], dtype=lib.torch.float64, device="cuda")
+        note("local time plain march")
+        for n in range(n_slabs):
+            stdg.stdg_load_assemble(mh, src, n * dt, dt, L)
+            assert stdg.stdg_slab_solve(mh, n * dt, dt, L, st, **opts)["status"] == 0
+        ref = st.cpu().numpy()
+    finally:
+        stdg.stdg_mesh_free(mh)
+    assert np.array_equal(ref, st_out)
+
+
 def test_refusals(lib):
     stdg = lib.stdg
     mesh = _mesh(p=1, q=1, nsub=(1, 2), seed=415)
