@@ -58,14 +58,15 @@ struct LCfg {
   static constexpr int NT = ((A * A * A + 63) / 64) * 64;  // one spatial position per thread
 };
 
-template <typename T, int A>
+template <typename T, int A, int QM>
 __global__ void __launch_bounds__(LCfg<A>::NT) local_time_kernel(LParams<T> P) {
   if (P.skip && *P.skip == 0) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   constexpr int TW = kMaxLocalLevels + 1;  // row width of the staged tables
   constexpr int a = A, a2 = A * A, a3 = A * A * A;  // this launch's rows all have a = p + 1 = A
   constexpr int NT = LCfg<A>::NT, nf = 24 * a2;     // face items: [face][F_u, F_v, G_u, G_v][face mode]
-  constexpr int QM = kMaxQ + 1;                     // trial levels of one sub-interval, at most
+  // QM >= q + 1: trial levels of one sub-interval, at most (3, 5 or 7: the
+  // register arrays are sized by it)
   const int32_t wk = P.work[blockIdx.x];
   const LTRec* R = P.rec + wk / kMaxSub;  // read through the pointer (no private copy)
   const int jsub = wk % kMaxSub;
@@ -322,12 +323,15 @@ int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* l
   P.dt = (T)dt;
   P.resid = mode == STDG_RESIDUAL ? 1 : 0;
   if constexpr (sizeof(T) == 8) fill_tables_f64(&P.tab); else fill_tables_f32(&P.tab);
-  // one launch per a (rows grouped by a on upload), dynamic LDS for the
-  // largest q among its rows
+  // one launch per a (rows grouped by a on upload), dynamic LDS and the
+  // register arrays sized for the largest q among its rows
   using K = void (*)(LParams<T>);
-  static const K kern[kMaxA + 1] = {nullptr, nullptr, local_time_kernel<T, 2>, local_time_kernel<T, 3>,
-                                    local_time_kernel<T, 4>, local_time_kernel<T, 5>, local_time_kernel<T, 6>,
-                                    local_time_kernel<T, 7>, local_time_kernel<T, 8>, local_time_kernel<T, 9>};
+#define STDG_LT_ROW(AA) {local_time_kernel<T, AA, 3>, local_time_kernel<T, AA, 5>, local_time_kernel<T, AA, 7>}
+  static const K kern[kMaxA + 1][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr},
+                                       STDG_LT_ROW(2), STDG_LT_ROW(3), STDG_LT_ROW(4), STDG_LT_ROW(5),
+                                       STDG_LT_ROW(6), STDG_LT_ROW(7), STDG_LT_ROW(8), STDG_LT_ROW(9)};
+#undef STDG_LT_ROW
+  static_assert(kMaxQ + 1 <= 7, "local-time kernels hold at most 7 trial levels per sub-interval");
   static const int nthreads[kMaxA + 1] = {0, 0, LCfg<2>::NT, LCfg<3>::NT, LCfg<4>::NT, LCfg<5>::NT,
                                           LCfg<6>::NT, LCfg<7>::NT, LCfg<8>::NT, LCfg<9>::NT};
   for (int a = 2; a <= kMaxA; ++a) {
@@ -342,7 +346,8 @@ int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* l
     P.staged = full * sizeof(T) <= kLdsCap ? 1 : 0;
     P.work = m->d_lt_work + b0;
     const size_t lds = (P.staged ? full : base) * sizeof(T);
-    hipLaunchKernelGGL(kern[a], dim3((unsigned)(b1 - b0)), dim3((unsigned)nthreads[a]), lds, s, P);
+    const int qb = qmax <= 2 ? 0 : (qmax <= 4 ? 1 : 2);
+    hipLaunchKernelGGL(kern[a][qb], dim3((unsigned)(b1 - b0)), dim3((unsigned)nthreads[a]), lds, s, P);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? STDG_OK : hip_fail(e, "local-time kernel");
