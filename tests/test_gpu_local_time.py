@@ -13,8 +13,9 @@ kernel groups, p = 6 and 8 (the widest workgroups, FP64 traces gathered per
 level), all three modes (the preconditioned one through the P^{-1}
 pre-pass that mixes the time levels), the allocation-free entry point, slab
 solves in FP64 and FP32 inner precision, the load per sub-interval with a
-source-driven solve, dual norms and an inexact march within eta_it;
-refusals of what the path does not take."""
+source-driven solve, dual norms and an inexact march within eta_it, a
+serving request bitwise the plain march, the full-size 32^3 4/2/1 workload
+on sampled elements; refusals of what the path does not take."""
 import numpy as np
 import pytest
 
@@ -253,6 +254,42 @@ def test_serving_request_matches_plain_march(lib):
     finally:
         stdg.stdg_mesh_free(mh)
     assert np.array_equal(ref, st_out)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_local_time_cavity_32cubed_sampled(lib, prec):
+    # the benchmark's local-time workload at full size (32^3, p = 4, q = 3,
+    # 4 / 2 / 1 sub-intervals) in the launch configuration it times; the
+    # oracle checks sampled elements on both sides of x = 0.25 and x = 0.5
+    stdg = lib.stdg
+    cfg = synth.local_time_cavity()
+    m = cfg["mesh"]
+    dt = cfg["dt"]
+    note("local time 32^3 prec=%d: inputs" % prec)
+    d = oracle_disc(m)
+    x = synth.random_vector(d.unk_off[-1], 0)
+    if prec == 1:
+        x = x.astype(np.float32).astype(np.float64)
+    mh = lib.upload(m)
+    try:
+        rng = np.random.default_rng(43)
+        c = synth.centroids(m.vertices, m.hexes)
+        near = [int(e) for e in np.flatnonzero((np.abs(c[:, 0] - 0.25) < 0.02) | (np.abs(c[:, 0] - 0.5) < 0.02))]
+        sample = sorted(set(int(e) for e in rng.choice(m.n_elements, 24, replace=False)) |
+                        set(int(e) for e in rng.choice(near, 24, replace=False)))
+        needed = sorted(set(sample) | {int(k) for e in sample for k in d.nb[e] if k >= 0})
+        for mode in (stdg.STDG_OPERATOR, stdg.STDG_OPERATOR_PRECOND):
+            note("local time 32^3 prec=%d mode=%d: apply" % (prec, mode))
+            y = lib.apply(mh, dt, prec, mode, x)
+            assert np.all(np.isfinite(y))
+            xin = d.precond_solve(x, needed) if mode == stdg.STDG_OPERATOR_PRECOND else x
+            rows = d.apply_rows(d.embed_unknowns(xin, elements=needed), dt, sample)
+            got = np.concatenate([y[d.unk_off[e]:d.unk_off[e + 1]] for e in sample])
+            ref = np.concatenate([rows[e] for e in sample])
+            note("local time 32^3 prec=%d mode=%d rel err %.3e" % (prec, mode, rel_err(got, ref)))
+            assert rel_err(got, ref) < TOL[prec]
+    finally:
+        stdg.stdg_mesh_free(mh)
 
 
 def test_refusals(lib):
