@@ -289,6 +289,8 @@ int launch_dual_norm_trilinear(const Mesh* m, const double* R, double* partial, 
 int noalloc_scratch_init(int device);
 size_t noalloc_scratch_capacity();
 int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s, const int* skip = nullptr);
+// the same on meshes with local time steps (also the sub-interval time factor; local_time.hip)
+int launch_precond_scale_local(const Mesh* m, int prec, const void* x, void* z, hipStream_t s, const int* skip);
 // One request's operands of a batched preconditioned operator apply (the
 // serving loop's lockstep restart cycles; residual.hip).
 struct BatchApplyArgs {

@@ -302,7 +302,62 @@ __global__ void __launch_bounds__(LCfg<A>::NT) local_time_kernel(LParams<T> P) {
   }
 }
 
+// P^{-1} of meshes with local time steps (every element; P = D_u (x) mass per
+// element): the 3x3 inverse metric per spatial mode and level as on other
+// meshes, and with n > 1 sub-intervals P's time factor is not the identity:
+// row (j, 0) is l_1 - l_0 of sub-interval j, so the value at the right end of
+// sub-interval j (unknown level (j + 1) q, or 0 for the slab end) is the sum
+// of rows (0, 0) .. (j, 0), and rows (j, i > 0) give the interior levels
+// j q + i as they are.  z = P^{-1} x on the unknowns layout.
+template <typename T>
+__global__ void precond_scale_local_kernel(const ElemInfo* info, const ElemMetric* metric, int64_t ne, const T* x,
+                                           T* z, const int* skip) {
+  if (skip && *skip == 0) return;
+  const int64_t e = blockIdx.x;
+  if (e >= ne) return;
+  const ElemInfo I = info[e];
+  const int a3 = I.a * I.a * I.a;
+  const double* mm = metric[e].m;
+  const int q = I.q, ns = I.nsub, nl = q * ns;
+  for (int idx = threadIdx.x; idx < 2 * a3; idx += blockDim.x) {
+    const int f = idx / a3, s = idx - f * a3;
+    const double* Mi = mm + 12 + 6 * f;
+    const T* xb = x + I.unk_off + (int64_t)3 * f * nl * a3 + s;
+    T* zb = z + I.unk_off + (int64_t)3 * f * nl * a3 + s;
+    double cum0 = 0.0, cum1 = 0.0, cum2 = 0.0;
+    for (int L = 0; L < nl; ++L) {
+      const double v0 = xb[(int64_t)L * a3], v1 = xb[(int64_t)(nl + L) * a3], v2 = xb[(int64_t)(2 * nl + L) * a3];
+      const double w0 = Mi[0] * v0 + Mi[3] * v1 + Mi[4] * v2;
+      const double w1 = Mi[3] * v0 + Mi[1] * v1 + Mi[5] * v2;
+      const double w2 = Mi[4] * v0 + Mi[5] * v1 + Mi[2] * v2;
+      const bool node = ns > 1 && L % q == 0;  // one sub-interval: P's time factor is the identity
+      int o = L;
+      if (node) {
+        cum0 += w0;
+        cum1 += w1;
+        cum2 += w2;
+        o = L + q < nl ? L + q : 0;
+      }
+      zb[(int64_t)o * a3] = (T)(node ? cum0 : w0);
+      zb[(int64_t)(nl + o) * a3] = (T)(node ? cum1 : w1);
+      zb[(int64_t)(2 * nl + o) * a3] = (T)(node ? cum2 : w2);
+    }
+  }
+}
+
 }  // namespace
+
+int launch_precond_scale_local(const Mesh* m, int prec, const void* x, void* z, hipStream_t s, const int* skip) {
+  const dim3 grid((unsigned)m->ne), block(256);
+  if (prec == STDG_FP64)
+    hipLaunchKernelGGL(precond_scale_local_kernel<double>, grid, block, 0, s, m->d_info, m->d_metric, m->ne,
+                       (const double*)x, (double*)z, skip);
+  else
+    hipLaunchKernelGGL(precond_scale_local_kernel<float>, grid, block, 0, s, m->d_info, m->d_metric, m->ne,
+                       (const float*)x, (float*)z, skip);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? STDG_OK : hip_fail(e, "precond_scale_local launch");
+}
 
 template <typename T>
 int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* load, T* y, hipStream_t s,

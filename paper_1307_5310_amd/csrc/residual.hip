@@ -207,6 +207,7 @@ int launch_residual_batch(const BatchApplyArgs* a, int count, int prec, hipStrea
 }
 
 int launch_precond_scale(const Mesh* m, int prec, const void* x, void* z, hipStream_t s, const int* skip) {
+  if (!m->lt.empty()) return launch_precond_scale_local(m, prec, x, z, s, skip);
   const dim3 grid((unsigned)m->ne), block(256);
   if (prec == STDG_FP64)
     hipLaunchKernelGGL(precond_scale_kernel<double>, grid, block, 0, s, m->d_info, m->d_metric, m->ne,

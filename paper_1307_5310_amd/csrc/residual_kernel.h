@@ -1070,12 +1070,7 @@ __global__ void __launch_bounds__(KCfg<A>::NT) residual_batch_kernel(BatchKParam
 }
 
 // P^{-1} applied blockwise (3x3 per spatial mode and level), for meshes whose
-// metric is not diagonal or that have local time steps: z = P^{-1} x on the
-// unknowns layout.  With n > 1 sub-intervals P's time factor is not the
-// identity: row (j, 0) is l_1 - l_0 of sub-interval j, so the value at the
-// right end of sub-interval j (unknown level (j + 1) q, or 0 for the slab
-// end) is the sum of rows (0, 0) .. (j, 0), and rows (j, i > 0) give the
-// interior levels j q + i as they are.
+// metric is not diagonal: z = P^{-1} x on the unknowns layout.
 template <typename T>
 __global__ void precond_scale_kernel(const ElemInfo* info, const ElemMetric* metric, int64_t ne, const T* x, T* z,
                                      const int* skip) {
@@ -1084,35 +1079,8 @@ __global__ void precond_scale_kernel(const ElemInfo* info, const ElemMetric* met
   if (e >= ne) return;
   const ElemInfo I = info[e];
   const int a3 = I.a * I.a * I.a;
-  const double* mm = metric[e].m;
-  if (I.nsub > 1) {
-    const int q = I.q, ns = I.nsub, nl = q * ns;
-    for (int idx = threadIdx.x; idx < 2 * a3; idx += blockDim.x) {
-      const int f = idx / a3, s = idx - f * a3;
-      const double* Mi = mm + 12 + 6 * f;
-      const T* xb = x + I.unk_off + (int64_t)3 * f * nl * a3 + s;
-      T* zb = z + I.unk_off + (int64_t)3 * f * nl * a3 + s;
-      double cum0 = 0.0, cum1 = 0.0, cum2 = 0.0;
-      for (int L = 0; L < nl; ++L) {
-        const double v0 = xb[(int64_t)L * a3], v1 = xb[(int64_t)(nl + L) * a3], v2 = xb[(int64_t)(2 * nl + L) * a3];
-        const double w0 = Mi[0] * v0 + Mi[3] * v1 + Mi[4] * v2;
-        const double w1 = Mi[3] * v0 + Mi[1] * v1 + Mi[5] * v2;
-        const double w2 = Mi[4] * v0 + Mi[5] * v1 + Mi[2] * v2;
-        int o = L;
-        if (L % q == 0) {
-          cum0 += w0;
-          cum1 += w1;
-          cum2 += w2;
-          o = L + q < nl ? L + q : 0;
-        }
-        zb[(int64_t)o * a3] = (T)(L % q == 0 ? cum0 : w0);
-        zb[(int64_t)(nl + o) * a3] = (T)(L % q == 0 ? cum1 : w1);
-        zb[(int64_t)(2 * nl + o) * a3] = (T)(L % q == 0 ? cum2 : w2);
-      }
-    }
-    return;
-  }
   const int per = I.q * a3;
+  const double* mm = metric[e].m;
   for (int idx = threadIdx.x; idx < 2 * per; idx += blockDim.x) {
     const int f = idx / per, rest = idx - f * per;
     const double* Mi = mm + 12 + 6 * f;
