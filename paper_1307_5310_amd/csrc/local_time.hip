@@ -86,6 +86,9 @@ __global__ void __launch_bounds__(LCfg<A>::NT) local_time_kernel(LParams<T> P) {
   T* xn = tb + 8 * q * TW;
   T* fl = xn + 6 * a3;
   T* nbt = fl + nf;
+  // staged: per face and neighbour level, whether any of the q coupling rows
+  // uses it (in the face-value area, free until the level loop)
+  unsigned char* used = (unsigned char*)fl;
   const bool staged = P.staged != 0;
   const T* xe = P.x + (P.resid ? Ie->trial_off : Ie->unk_off);
   T* ye = P.y + Ie->unk_off;
@@ -138,6 +141,13 @@ __global__ void __launch_bounds__(LCfg<A>::NT) local_time_kernel(LParams<T> P) {
   };
   __syncthreads();
   if (staged) {
+    for (int t = tid; t < 6 * TW; t += NT) {
+      const int g = t / TW, M = t - g * TW;
+      bool any = false;
+      for (int i = 0; i < q; ++i) any = any || tb[((2 + g) * q + i) * TW + M] != T(0);
+      used[t] = any ? 1 : 0;
+    }
+    __syncthreads();
     for (int t = tid; t < nf; t += NT) {
       for (int i = 0; i < q; ++i) nbt[i * nf + t] = T(0);
       const int g = t / (4 * a2), k = Ie->nb[g];
@@ -161,10 +171,9 @@ __global__ void __launch_bounds__(LCfg<A>::NT) local_time_kernel(LParams<T> P) {
       const int snk = axis_stride(alo, ak);
       const bool neg = (slot_u ? flu : flv) ^ (flu && (fu & 1)) ^ (flv && (fv & 1));
       const T* C = tb + (2 + g) * q * TW;
+      const unsigned char* use = used + g * TW;
       for (int M = m0; M < nck; ++M) {
-        bool any = false;
-        for (int i = 0; i < q; ++i) any = any || C[i * TW + M] != T(0);
-        if (!any) continue;
+        if (!use[M]) continue;
         const T* xp = xk + (int64_t)(M - m0) * ak3;
         T v = T(0);
         for (int l = 0; l < ak; ++l) v += tr[sdo * kMaxA + l] * xp[l * snk];
