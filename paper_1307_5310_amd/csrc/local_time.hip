@@ -99,20 +99,32 @@ __global__ void __launch_bounds__(LCfg<A>::NT) local_time_kernel(LParams<T> P) {
     const int u = t - 2 * kMaxA;
     tr[t] = t < kMaxA ? P.tab.tr0[t] : (t < 2 * kMaxA ? P.tab.tr1[t - kMaxA] : P.tab.Dh[u / kMaxA][u % kMaxA]);
   }
+  // per face: the neighbour's trial levels (0 on a boundary face) and its
+  // coupling table, read once (uniform) before the staging loop
+  int nckf[6], coff[6];
+#pragma unroll
+  for (int g = 0; g < 6; ++g) {
+    const int k = Ie->nb[g];
+    nckf[g] = k >= 0 ? P.info[k].q * P.info[k].nsub + 1 : 0;
+    coff[g] = R->c_off[g];
+  }
+  const int doff = R->d_off, noff = R->n_off;
   for (int t = tid; t < 8 * q * TW; t += NT) {
     const int r = t / (q * TW), rest = t - r * q * TW, i = rest / TW, M = rest - i * TW;
     const int I = jsub * q + i;
-    T v = T(0);
-    if (r == 0 && M < ncol) v = P.bank[R->d_off + I * ncol + M];
-    if (r == 1 && M < ncol) v = P.bank[R->n_off + I * ncol + M];
-    if (r >= 2) {
-      const int g = r - 2, k = Ie->nb[g];
-      if (k >= 0) {
-        const int nck = P.info[k].q * P.info[k].nsub + 1;
-        if (M < nck) v = P.bank[R->c_off[g] + I * nck + M];
+    int off = -1;
+    if (r < 2) {
+      if (M < ncol) off = (r == 0 ? doff : noff) + I * ncol + M;
+    } else {
+      int nck = nckf[0], co = coff[0];
+#pragma unroll
+      for (int h = 1; h < 6; ++h) {  // selects, no indexed private array
+        nck = r - 2 == h ? nckf[h] : nck;
+        co = r - 2 == h ? coff[h] : co;
       }
+      if (M < nck) off = co + I * nck + M;
     }
-    tb[t] = v;
+    tb[t] = off >= 0 ? P.bank[off] : T(0);
   }
   // the trial levels of this sub-interval (own tables have no other columns
   // in its rows), and this thread's position and its own levels in registers
