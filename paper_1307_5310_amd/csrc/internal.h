@@ -232,6 +232,7 @@ struct Mesh {
   std::vector<int32_t> lt_work;  // workgroups of the local-time kernel: record * kMaxSub + sub-interval,
                                  // grouped by a: lt_work[lt_a_off[a] .. lt_a_off[a + 1]) have p + 1 = a
   std::vector<int64_t> lt_a_off;
+  std::vector<int32_t> lt_a_qmax;  // the largest q among the rows with p + 1 = a
   std::vector<double> lt_bank;
   LTRec* d_lt = nullptr;
   int32_t* d_lt_work = nullptr;

@@ -413,8 +413,7 @@ int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* l
   for (int a = 2; a <= kMaxA; ++a) {
     const int64_t b0 = m->lt_a_off[a], b1 = m->lt_a_off[a + 1];
     if (b1 == b0) continue;
-    int qmax = 1;
-    for (int64_t b = b0; b < b1; ++b) qmax = std::max(qmax, m->info[m->lt[m->lt_work[b] / kMaxSub].elem].q);
+    const int qmax = m->lt_a_qmax[a];
     const size_t a2 = (size_t)a * a, a3 = a2 * a;
     const size_t base = 2 * kMaxA + kMaxA * kMaxA + (size_t)8 * qmax * (kMaxLocalLevels + 1) + 6 * a3 + 24 * a2;
     const size_t full = base + (size_t)qmax * 24 * a2;

@@ -695,7 +695,12 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
     });
   }
   m->lt_a_off.assign(kMaxA + 2, 0);
-  for (int32_t w : m->lt_work) ++m->lt_a_off[m->info[m->lt[w / kMaxSub].elem].a + 1];
+  m->lt_a_qmax.assign(kMaxA + 2, 1);
+  for (int32_t w : m->lt_work) {
+    const ElemInfo& I = m->info[m->lt[w / kMaxSub].elem];
+    ++m->lt_a_off[I.a + 1];
+    m->lt_a_qmax[I.a] = std::max(m->lt_a_qmax[I.a], I.q);
+  }
   for (int a = 1; a <= kMaxA + 1; ++a) m->lt_a_off[a] += m->lt_a_off[a - 1];
 
   // kernel groups by (a, q, affine); their work-list order is set below
