@@ -78,7 +78,7 @@ def _check(lib, mesh, dt, seed, name):
         stdg.stdg_mesh_free(mh)
 
 
-@pytest.mark.parametrize("q,nsub", [(1, (1, 2)), (2, (1, 2, 4)), (3, (2, 4)), (1, (1, 8))])
+@pytest.mark.parametrize("q,nsub", [(1, (1, 2)), (2, (1, 2, 4)), (3, (2, 4)), (1, (1, 8)), (5, (1, 2)), (6, (1, 4))])
 def test_uniform_degrees(lib, q, nsub):
     _check(lib, _mesh(p=2, q=q, nsub=nsub, seed=400 + q), 0.06, 400 + q, "local time q%d n%s" % (q, nsub))
 
