@@ -15,7 +15,8 @@ pre-pass that mixes the time levels), the allocation-free entry point, slab
 solves in FP64 and FP32 inner precision, the load per sub-interval with a
 source-driven solve, dual norms and an inexact march within eta_it, a
 serving request bitwise the plain march, the full-size 32^3 4/2/1 workload
-on sampled elements; refusals of what the path does not take."""
+on sampled elements, a march of the manufactured exp solution with the
+nodal order 2 q; refusals of what the path does not take."""
 import numpy as np
 import pytest
 
@@ -290,6 +291,41 @@ def test_local_time_cavity_32cubed_sampled(lib, prec):
             assert rel_err(got, ref) < TOL[prec]
     finally:
         stdg.stdg_mesh_free(mh)
+
+
+def test_temporal_order_march(lib):
+    # Section 6.1.2 with local time steps: the manufactured exp solution
+    # marched by the library (its current integrated by the oracle, since the
+    # library's load takes the Gaussian pulse only) equals the oracle's march
+    # and keeps the nodal order 2 q
+    from oracle import fields
+    F, J = fields.exp_solution()
+    v, h = synth.box_mesh((2, 1, 1))
+    q = 2
+    mesh = synth.Mesh(v, h, np.full(2, 2, np.int32), np.full(2, q, np.int32), np.ones(2), np.ones(2),
+                      nsub=np.array([1, 2], np.int32))
+    d = oracle_disc(mesh)
+    mh = lib.upload(mesh)
+    T, errs = 0.4, []
+    try:
+        for nsteps in (2, 4):
+            dt = T / nsteps
+            s = fields.reference_coefficients(d, F, 0.0)
+            st = lib.dev(s, lib.torch.float64)
+            for n in range(nsteps):
+                L = d.load(J, n * dt, dt, nt=q + 8)
+                s = d.level_state(d.solve_direct(s, dt, L), 1)
+                note("local time exp march %d/%d" % (n, nsteps))
+                r = lib.stdg.stdg_slab_solve(mh, n * dt, dt, lib.dev(L, lib.torch.float64), st, inner_prec=1,
+                                             rtol=1e-13, max_iters=800, max_refine=80, krylov_prec=1)
+                assert r["status"] == 0, r
+            got = st.cpu().numpy()
+            assert rel_err(got, s) < 1e-10
+            errs.append(np.abs(got - fields.reference_coefficients(d, F, T)).max())
+    finally:
+        lib.stdg.stdg_mesh_free(mh)
+    rate = np.log2(errs[0] / errs[1])
+    assert abs(rate - 2 * q) < 0.3, (errs, rate)
 
 
 def test_refusals(lib):

@@ -265,3 +265,23 @@ def test_eta_it_bounds_the_iteration_error(n_slabs):
     err2 = 2.0 * d.energy(s_inexact - s_exact)
     assert err2 <= eta2, (err2, eta2)
     assert err2 > 1e-4 * eta2
+
+
+@pytest.mark.parametrize("q,nk", [(1, (1, 2)), (2, (1, 2)), (2, (2, 4))])
+def test_temporal_order_with_local_time_steps(q, nk):
+    # Section 6.1.2 (local refinement in time): the manufactured exp solution
+    # (spatial part exact for p = 2) keeps the nodal order 2 q when elements
+    # take different numbers of sub-intervals
+    F, J = fields.exp_solution()
+    v, h = synth.box_mesh((2, 1, 1))
+    d = Discretisation(v, h, np.full(2, 2), np.full(2, q), np.ones(2), np.ones(2), nk=np.array(nk))
+    T = 0.4
+    errs = []
+    for nsteps in (2, 4):
+        dt = T / nsteps
+        s = fields.reference_coefficients(d, F, 0.0)
+        for n in range(nsteps):
+            s = d.level_state(d.solve_direct(s, dt, d.load(J, n * dt, dt, nt=q + 8)), 1)
+        errs.append(np.abs(s - fields.reference_coefficients(d, F, T)).max())
+    rate = np.log2(errs[0] / errs[1])
+    assert abs(rate - 2 * q) < 0.3, (errs, rate)
