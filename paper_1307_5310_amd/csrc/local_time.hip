@@ -58,8 +58,12 @@ struct LCfg {
   static constexpr int NT = ((A * A * A + 63) / 64) * 64;  // one spatial position per thread
 };
 
+// FP32, p <= 4, q <= 4: five waves per SIMD (at most 102 VGPRs; they fit
+// without scratch, and the kernel waits on memory most of its time)
 template <typename T, int A, int QM>
-__global__ void __launch_bounds__(LCfg<A>::NT) local_time_kernel(LParams<T> P) {
+__global__ void __launch_bounds__(LCfg<A>::NT)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && A <= 5 && QM <= 5 ? 5 : 1)))
+    local_time_kernel(LParams<T> P) {
   if (P.skip && *P.skip == 0) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   constexpr int TW = kMaxLocalLevels + 1;  // row width of the staged tables
