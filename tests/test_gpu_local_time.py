@@ -99,6 +99,27 @@ def test_larger_mesh_few_local_rows(lib):
     _check(lib, m, 0.04, 412, "local time 4^3")
 
 
+def test_every_element_subdivided(lib):
+    # no kernel groups left: every row runs in the local-time kernel; the
+    # slab solve equals the oracle's (uniform n = 2 is two half slabs there)
+    m = _mesh((2, 2, 1), p=2, q=2, nsub=(2,), seed=421)
+    _check(lib, m, 0.05, 421, "local time all n=2")
+    d = oracle_disc(m)
+    s0 = np.random.default_rng(421).standard_normal(d.state_off[-1])
+    ref = d.level_state(d.solve_direct(s0, 0.08), 1)
+    mh = lib.upload(m)
+    try:
+        assert lib.stdg.stdg_mesh_info(mh)["n_groups"] == 0
+        st = lib.dev(s0, lib.torch.float64)
+        note("local time all n=2: solve")
+        r = lib.stdg.stdg_slab_solve(mh, 0.0, 0.08, None, st, inner_prec=1, rtol=1e-13, max_iters=800,
+                                     max_refine=80, krylov_prec=1)
+        assert r["status"] == 0, r
+        assert rel_err(st.cpu().numpy(), ref) < 1e-10
+    finally:
+        lib.stdg.stdg_mesh_free(mh)
+
+
 def test_high_degrees(lib):
     # p = 6 and 8 side by side: 384 and 768 threads per workgroup, the own
     # levels read at each use for p = 8, and its FP64 neighbour traces
