@@ -285,3 +285,22 @@ def test_temporal_order_with_local_time_steps(q, nk):
         errs.append(np.abs(s - fields.reference_coefficients(d, F, T)).max())
     rate = np.log2(errs[0] / errs[1])
     assert abs(rate - 2 * q) < 0.3, (errs, rate)
+
+
+@pytest.mark.parametrize("nk", [(1, 2, 4, 1), (2, 1, 2, 4)])
+def test_dissipation_with_local_time_steps(nk):
+    # D_h (remark closing Section 4) with the test function projected onto the
+    # common temporal test space of each face's pair: the slab matrix against
+    # the brute-force assembler on a sheared mesh, and the energy decreases
+    v, h = synth.box_mesh((2, 2, 1))
+    v = synth.affine_transform(v, np.array([[1.0, 0.2, -0.1], [0.1, 0.9, 0.15], [-0.05, 0.1, 1.1]]))
+    rng = np.random.default_rng(sum(nk))
+    p, q = rng.integers(1, 3, 4), rng.integers(1, 3, 4)
+    eps, mu = rng.uniform(1, 3, 4), rng.uniform(1, 2, 4)
+    d = Discretisation(v, h, p, q, eps, mu, c_diss=0.7, nk=np.array(nk))
+    Bo = d.slab_matrix(0.1).toarray()
+    Bb = brute.assemble(v, h, p, q, eps, mu, 0.1, c_diss=0.7, nk=np.array(nk))
+    assert np.abs(Bo - Bb).max() / np.abs(Bb).max() < 1e-12
+    s0 = rng.standard_normal(d.state_off[-1])
+    e1 = d.energy(d.level_state(d.solve_direct(s0, 0.1), 1))
+    assert e1 < d.energy(s0)
