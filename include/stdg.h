@@ -166,8 +166,9 @@ typedef struct {
  * projected onto their common temporal test space, piecewise P_{min(q,q')-1}
  * on the coarser of the two partitions.  Such elements and their face
  * neighbours must be affine, and the mesh may not have hanging faces
- * (STDG_E_UNSUPPORTED); D_h and batched applies refuse meshes with local
- * time steps (serving requests with them run their cycles alone).
+ * (STDG_E_UNSUPPORTED); batched applies refuse meshes with local time steps
+ * (serving requests with them run their cycles alone), and D_h takes them
+ * up to p = 4 with q >= 5 (any p below q = 5) within its LDS limit.
  * stdg_load_assemble integrates the source
  * per sub-interval, and the dual norms (stdg_residual_dual_norm, inexact
  * solves) take the test functions of a sub-interval on dt / n. */

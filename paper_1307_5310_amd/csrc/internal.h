@@ -47,6 +47,7 @@ enum : int32_t {
 // j + 1).  Its n q test levels are L_i on sub-interval j at j q + i.
 constexpr int kMaxSub = 8;
 constexpr int kMaxLocalLevels = 24;  // n q <= 24 test levels
+constexpr int kMaxDissLocalA7 = 5;  // D_h with local time steps and q >= 5: p + 1 <= 5
 __host__ __device__ inline int local_trial_level(int q, int n, int j, int m) {
   if (m == 0) return j == 0 ? 0 : 1 + j * q;
   if (m == 1) return j == n - 1 ? 1 : 1 + (j + 1) * q;
@@ -62,10 +63,12 @@ struct LTRec {
   int32_t elem;
   int32_t d_off, n_off;
   int32_t c_off[6];
+  int32_t s_off[6];  // D_h: own trial against the projected test function (interior faces; -1 else)
 };
 // Time tables of local time steps into `bank` (tables.cpp); returns the offset.
 int local_time_tables(int q, int n, std::vector<double>* bank, int32_t* d_off, int32_t* n_off);
 int local_coupling_table(int q, int n, int qk, int nk, std::vector<double>* bank);
+int local_projected_table(int q, int n, int r, int npj, std::vector<double>* bank);
 
 // 2:1 hanging faces (Section 5.2 sums the flux terms of a face over the
 // neighbours that share parts of it): a coarse face covered by the faces of

@@ -44,6 +44,7 @@ struct LParams {
   const T* load;    // residual mode: subtracted (may be NULL)
   T* y;
   const int32_t* work;  // per workgroup: record index * kMaxSub + sub-interval
+  const T* diss;        // D_h coefficients per element (Mesh::kDissWords each), NULL = off
   const int* skip;
   T dt;
   int resid;        // x is the full trial vector (levels 0..), else the unknowns (levels 1..)
@@ -58,11 +59,13 @@ struct LCfg {
   static constexpr int NT = ((A * A * A + 63) / 64) * 64;  // one spatial position per thread
 };
 
-// FP32, p <= 4, q <= 4: five waves per SIMD (at most 102 VGPRs; they fit
-// without scratch, and the kernel waits on memory most of its time)
-template <typename T, int A, int QM>
+// FP32, p <= 4, q <= 4 without D_h: five waves per SIMD (at most 102 VGPRs;
+// they fit without scratch, and the kernel waits on memory most of its time).
+// DIS: with D_h; not instantiated for p >= 5 with q >= 5 (registers spill;
+// stdg_mesh_set_dissipation refuses such rows)
+template <typename T, int A, int QM, bool DIS>
 __global__ void __launch_bounds__(LCfg<A>::NT)
-    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && A <= 5 && QM <= 5 ? 5 : 1)))
+    __attribute__((amdgpu_waves_per_eu(!DIS && sizeof(T) == 4 && A <= 5 && QM <= 5 ? 5 : 1)))
     local_time_kernel(LParams<T> P) {
   if (P.skip && *P.skip == 0) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -84,12 +87,16 @@ __global__ void __launch_bounds__(LCfg<A>::NT)
   // LDS: L_l(0), L_l(1), Dh; the table rows [D, N, C_0..C_5][i][M] of this
   // sub-interval's q test levels; the contracted own fields of one level; the
   // face values; staged: the neighbours' traces contracted for all q levels
+  constexpr bool dis = DIS;  // D_h (P.diss set): 6 more table rows, the jumps, own projected traces
+  const int nrow = dis ? 14 : 8;
   T* tr = (T*)lds_raw;
   T* dh = tr + 2 * kMaxA;
   T* tb = dh + kMaxA * kMaxA;
-  T* xn = tb + 8 * q * TW;
+  T* xn = tb + nrow * q * TW;
   T* fl = xn + 6 * a3;
-  T* nbt = fl + nf;
+  T* jm = fl + nf;                    // D_h jumps, laid out as fl
+  T* nbt = jm + (dis ? nf : 0);
+  T* opt = nbt + q * nf;              // D_h, staged: own traces against the projected test functions
   // staged: per face and neighbour level, whether any of the q coupling rows
   // uses it (in the face-value area, free until the level loop)
   unsigned char* used = (unsigned char*)fl;
@@ -105,28 +112,35 @@ __global__ void __launch_bounds__(LCfg<A>::NT)
   }
   // per face: the neighbour's trial levels (0 on a boundary face) and its
   // coupling table, read once (uniform) before the staging loop
-  int nckf[6], coff[6];
+  int nckf[6], coff[6], soff[6];
 #pragma unroll
   for (int g = 0; g < 6; ++g) {
     const int k = Ie->nb[g];
     nckf[g] = k >= 0 ? P.info[k].q * P.info[k].nsub + 1 : 0;
     coff[g] = R->c_off[g];
+    soff[g] = R->s_off[g];
   }
   const int doff = R->d_off, noff = R->n_off;
-  for (int t = tid; t < 8 * q * TW; t += NT) {
+  for (int t = tid; t < nrow * q * TW; t += NT) {
     const int r = t / (q * TW), rest = t - r * q * TW, i = rest / TW, M = rest - i * TW;
     const int I = jsub * q + i;
     int off = -1;
     if (r < 2) {
       if (M < ncol) off = (r == 0 ? doff : noff) + I * ncol + M;
     } else {
-      int nck = nckf[0], co = coff[0];
+      const int g = r < 8 ? r - 2 : r - 8;
+      int nck = nckf[0], co = coff[0], so = soff[0];
 #pragma unroll
       for (int h = 1; h < 6; ++h) {  // selects, no indexed private array
-        nck = r - 2 == h ? nckf[h] : nck;
-        co = r - 2 == h ? coff[h] : co;
+        nck = g == h ? nckf[h] : nck;
+        co = g == h ? coff[h] : co;
+        so = g == h ? soff[h] : so;
       }
-      if (M < nck) off = co + I * nck + M;
+      if (r < 8) {
+        if (M < nck) off = co + I * nck + M;
+      } else if (nck > 0 && M < ncol) {
+        off = so + I * ncol + M;  // D_h's own part (interior faces)
+      }
     }
     tb[t] = off >= 0 ? P.bank[off] : T(0);
   }
@@ -157,13 +171,37 @@ __global__ void __launch_bounds__(LCfg<A>::NT)
   };
   __syncthreads();
   if (staged) {
-    for (int t = tid; t < 6 * TW; t += NT) {
-      const int g = t / TW, M = t - g * TW;
+    for (int t = tid; t < (dis ? 12 : 6) * TW; t += NT) {
+      const int g = t / TW, M = t - g * TW;  // g >= 6: D_h's own-part rows of face g - 6
       bool any = false;
       for (int i = 0; i < q; ++i) any = any || tb[((2 + g) * q + i) * TW + M] != T(0);
       used[t] = any ? 1 : 0;
     }
     __syncthreads();
+    if (dis) {
+      for (int t = tid; t < nf; t += NT) {
+        for (int i = 0; i < q; ++i) opt[i * nf + t] = T(0);
+        const int g = t / (4 * a2);
+        if (Ie->nb[g] < 0) continue;
+        const int rest = t - g * 4 * a2, ft = rest / a2, jj = rest - ft * a2;
+        const int fu = jj % A, fv = jj / A;
+        const int alpha = g >> 1, side = g & 1;
+        const int ua = alpha == 0 ? 1 : 0, va = alpha == 2 ? 1 : 2;
+        const int fld = (ft >> 1) == 0 ? 1 : 0, d = (ft & 1) == 0 ? ua : va;
+        const T* xs = xe + (int64_t)(3 * fld + d) * nst * a3 + fu * axis_stride(ua, a) + fv * axis_stride(va, a);
+        const int sn = axis_stride(alpha, a);
+        const T* S = tb + (8 + g) * q * TW;
+        const unsigned char* use = used + (6 + g) * TW;
+        for (int M = m0; M < ncol; ++M) {
+          if (!use[M]) continue;
+          const T* xp = xs + (int64_t)(M - m0) * a3;
+          T v = T(0);
+#pragma unroll
+          for (int l = 0; l < A; ++l) v += tr[side * kMaxA + l] * xp[l * sn];
+          for (int i = 0; i < q; ++i) opt[i * nf + t] += S[i * TW + M] * v;
+        }
+      }
+    }
     for (int t = tid; t < nf; t += NT) {
       for (int i = 0; i < q; ++i) nbt[i * nf + t] = T(0);
       const int g = t / (4 * a2), k = Ie->nb[g];
@@ -267,7 +305,28 @@ __global__ void __launch_bounds__(LCfg<A>::NT)
           }
         }
         val = T(0.5) * ((which == 0 ? ts : -ts) + tn);
+        if (dis) {
+          // D_h jump: own trace against the projected test function minus the neighbour's
+          T own_p = T(0);
+          if (staged) {
+            own_p = opt[i * nf + t];
+          } else {
+            const T* S = tb + ((8 + g) * q + i) * TW;
+            const T* xs = xe + (int64_t)(3 * fld + d) * nst * a3 + fu * axis_stride(ua, a) + fv * axis_stride(va, a);
+            for (int M = m0; M < ncol; ++M) {
+              const T w = S[M];
+              if (w == T(0)) continue;
+              const T* xp = xs + (int64_t)(M - m0) * a3;
+              T v = T(0);
+#pragma unroll
+              for (int l = 0; l < A; ++l) v += tr[side * kMaxA + l] * xp[l * sn];
+              own_p += w * v;
+            }
+          }
+          jm[t] = own_p - tn;
+        }
       }
+      if (dis && k < 0) jm[t] = ts;  // PEC face: the own trace, not projected
       fl[t] = val;
     }
     __syncthreads();
@@ -319,8 +378,30 @@ __global__ void __launch_bounds__(LCfg<A>::NT)
           lift += (f == 0 ? epsv : -epsv) * sl * fl[((2 * alpha + side) * 4 + ft) * a2 + jj];
         }
       }
+      // D_h: alpha_f L_{s_alpha}(side) (K J)_c over the four faces whose normal
+      // is not c, jumps of field f itself (alpha_H = 0 on PEC faces)
+      T dl = T(0);
+      if (dis) {
+        const T* dc = P.diss + (int64_t)Mesh::kDissWords * e;
+#pragma unroll
+        for (int alpha = 0; alpha < 3; ++alpha) {
+          if (alpha == c) continue;
+          const int ua = alpha == 0 ? 1 : 0, va = alpha == 2 ? 1 : 2;
+          const int slot_c = c == ua ? 0 : 1;
+          const T kcc = dc[12 + 3 * alpha + (c == (alpha + 1) % 3 ? 0 : 1)], kco = dc[12 + 3 * alpha + 2];
+          const int jj = si(ua) + a * si(va);
+          const int l = si(alpha);
+          const int ftb = f == 0 ? 2 : 0;  // E rows: E jumps; H rows: H jumps
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int g = 2 * alpha + side;
+            const T* J = jm + (g * 4 + ftb) * a2 + jj;
+            dl += dc[6 * f + g] * tr[side * kMaxA + l] * (kcc * J[slot_c * a2] + kco * J[(1 - slot_c) * a2]);
+          }
+        }
+      }
       const int64_t o = ((int64_t)fc * nt + I) * a3 + s;
-      T out = mass + P.dt * (curl + lift);
+      T out = mass + P.dt * (curl + lift + dl);
       if (le) out -= le[o];
       ye[o] = out;
     }
@@ -395,6 +476,7 @@ int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* l
   P.info = m->d_info;
   P.metric = m->d_metric;
   P.rec = m->d_lt;
+  if constexpr (sizeof(T) == 8) P.diss = m->d_diss; else P.diss = m->d_diss32;
   P.bank = (const T*)(sizeof(T) == 8 ? m->d_ltb64 : m->d_ltb32);
   P.x = x;
   P.load = load;
@@ -406,10 +488,17 @@ int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* l
   // one launch per a (rows grouped by a on upload), dynamic LDS and the
   // register arrays sized for the largest q among its rows
   using K = void (*)(LParams<T>);
-#define STDG_LT_ROW(AA) {local_time_kernel<T, AA, 3>, local_time_kernel<T, AA, 5>, local_time_kernel<T, AA, 7>}
+#define STDG_LT_ROW(AA) {local_time_kernel<T, AA, 3, false>, local_time_kernel<T, AA, 5, false>, \
+                         local_time_kernel<T, AA, 7, false>}
   static const K kern[kMaxA + 1][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr},
                                        STDG_LT_ROW(2), STDG_LT_ROW(3), STDG_LT_ROW(4), STDG_LT_ROW(5),
                                        STDG_LT_ROW(6), STDG_LT_ROW(7), STDG_LT_ROW(8), STDG_LT_ROW(9)};
+#undef STDG_LT_ROW
+#define STDG_LT_ROW(AA) {local_time_kernel<T, AA, 3, true>, local_time_kernel<T, AA, 5, true>, \
+                         AA <= kMaxDissLocalA7 ? local_time_kernel<T, AA <= kMaxDissLocalA7 ? AA : 2, 7, true> : nullptr}
+  static const K kern_d[kMaxA + 1][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr},
+                                         STDG_LT_ROW(2), STDG_LT_ROW(3), STDG_LT_ROW(4), STDG_LT_ROW(5),
+                                         STDG_LT_ROW(6), STDG_LT_ROW(7), STDG_LT_ROW(8), STDG_LT_ROW(9)};
 #undef STDG_LT_ROW
   static_assert(kMaxQ + 1 <= 7, "local-time kernels hold at most 7 trial levels per sub-interval");
   static const int nthreads[kMaxA + 1] = {0, 0, LCfg<2>::NT, LCfg<3>::NT, LCfg<4>::NT, LCfg<5>::NT,
@@ -419,14 +508,18 @@ int launch_local_time(const Mesh* m, double dt, int mode, const T* x, const T* l
     if (b1 == b0) continue;
     const int qmax = m->lt_a_qmax[a];
     const size_t a2 = (size_t)a * a, a3 = a2 * a;
-    const size_t base = 2 * kMaxA + kMaxA * kMaxA + (size_t)8 * qmax * (kMaxLocalLevels + 1) + 6 * a3 + 24 * a2;
-    const size_t full = base + (size_t)qmax * 24 * a2;
+    const bool dis = P.diss != nullptr;
+    const size_t base = 2 * kMaxA + kMaxA * kMaxA + (size_t)(dis ? 14 : 8) * qmax * (kMaxLocalLevels + 1) + 6 * a3 +
+                        (dis ? 48 : 24) * a2;
+    const size_t full = base + (size_t)(dis ? 2 : 1) * qmax * 24 * a2;
     constexpr size_t kLdsCap = 65536;
     P.staged = full * sizeof(T) <= kLdsCap ? 1 : 0;
     P.work = m->d_lt_work + b0;
     const size_t lds = (P.staged ? full : base) * sizeof(T);
     const int qb = qmax <= 2 ? 0 : (qmax <= 4 ? 1 : 2);
-    hipLaunchKernelGGL(kern[a][qb], dim3((unsigned)(b1 - b0)), dim3((unsigned)nthreads[a]), lds, s, P);
+    const K k = dis ? kern_d[a][qb] : kern[a][qb];
+    if (!k) return fail(STDG_E_UNSUPPORTED, "local time steps with D_h: no kernel for p = " + std::to_string(a - 1));
+    hipLaunchKernelGGL(k, dim3((unsigned)(b1 - b0)), dim3((unsigned)nthreads[a]), lds, s, P);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? STDG_OK : hip_fail(e, "local-time kernel");

@@ -654,7 +654,7 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
   if (*std::max_element(m->nsub.begin(), m->nsub.end()) > 1) {
     if (!m->hang.empty()) return fail(STDG_E_UNSUPPORTED, "local time steps on meshes with 2:1 hanging faces");
     std::map<std::pair<int, int>, std::pair<int32_t, int32_t>> own;
-    std::map<std::tuple<int, int, int, int>, int32_t> cpl;
+    std::map<std::tuple<int, int, int, int>, int32_t> cpl, prj;
     for (int64_t e = 0; e < ne; ++e) {
       ElemInfo& I = m->info[e];
       bool local = m->nsub[e] > 1;
@@ -676,8 +676,17 @@ int build_mesh_host(const stdg_mesh_desc* d, Mesh* m) {
       R.n_off = ok->second.second;
       for (int f = 0; f < 6; ++f) {
         R.c_off[f] = -1;
+        R.s_off[f] = -1;
         const int32_t k = I.nb[f];
         if (k < 0) continue;
+        {
+          const int r = std::min(m->q[e], m->q[k]), npj = std::min(m->nsub[e], m->nsub[k]);
+          auto pk = std::make_tuple(m->q[e], m->nsub[e], r, npj);
+          auto pt = prj.find(pk);
+          if (pt == prj.end())
+            pt = prj.emplace(pk, local_projected_table(m->q[e], m->nsub[e], r, npj, &m->lt_bank)).first;
+          R.s_off[f] = pt->second;
+        }
         auto key = std::make_tuple(m->q[e], m->nsub[e], m->q[k], m->nsub[k]);
         auto it = cpl.find(key);
         if (it == cpl.end())
@@ -833,8 +842,18 @@ int set_dissipation(Mesh* m, double c) {
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(STDG_E_ARG, "dissipation coefficient must be finite and >= 0");
   if (c > 0.0 && !m->hang.empty())
     return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation on meshes with hanging faces");
-  if (c > 0.0 && !m->lt.empty())
-    return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation with local time steps");
+  if (c > 0.0 && !m->lt.empty()) {
+    // the local-time kernel's LDS with D_h (table rows, contracted fields, face
+    // values and jumps) must fit in 64 KB for the largest rows
+    for (const LTRec& r : m->lt) {
+      const size_t a = (size_t)m->info[r.elem].a, q = (size_t)m->info[r.elem].q;
+      const size_t need = (2 * kMaxA + kMaxA * kMaxA + 14 * q * (kMaxLocalLevels + 1) + 6 * a * a * a + 48 * a * a) *
+                          sizeof(double);
+      if (need > 65536 || (q >= 5 && (int)a > kMaxDissLocalA7))
+        return fail(STDG_E_UNSUPPORTED, "dissipative stabilisation with local time steps at p = " +
+                                            std::to_string(a - 1) + ", q = " + std::to_string(q));
+    }
+  }
   ++m->epoch;
   const size_t bytes = sizeof(double) * Mesh::kDissWords * m->ne, bytes32 = sizeof(float) * Mesh::kDissWords * m->ne;
   if (c == 0.0) {

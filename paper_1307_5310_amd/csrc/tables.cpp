@@ -242,4 +242,49 @@ int local_coupling_table(int q, int n, int qk, int nk, std::vector<double>* bank
   return off;
 }
 
+// D_h's own part with local time steps: T[(j, i)][M] = int_0^1 (pi L_i^(j)) phi_M ds
+// for the element's own trial levels (q, n), pi the projection onto piecewise
+// P_{r-1} on npj <= n equal sub-intervals (the common temporal test space of
+// a face's pair).  npj == n: pi keeps L_i^(j) for i < r.  npj < n: sub-interval
+// j lies in the coarse interval c; pi L_i^(j) = sum_{rho < r} beta_rho L_rho^(c),
+// beta_rho = npj int_{I_j} L_i^(j) L_rho^(c), integrated against the own trial
+// functions of every sub-interval inside I_c (Gauss rule).
+int local_projected_table(int q, int n, int r, int npj, std::vector<double>* bank) {
+  Tables<double> t;
+  fill_double(&t);
+  const int rows = n * q, cols = 1 + n * q;
+  const int off = (int)bank->size();
+  bank->resize(bank->size() + (size_t)rows * cols, 0.0);
+  double* T = bank->data() + off;
+  const int ng = 2 * q + 2;
+  double xg[32], wg[32];
+  gauss_rule01(ng, xg, wg);
+  const int ratio = n / npj;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < q; ++i) {
+      double* row = T + (size_t)(j * q + i) * cols;
+      if (npj == n) {
+        if (i >= r) continue;
+        for (int m = 0; m <= q; ++m) row[local_trial_level(q, n, j, m)] += t.N[i][m] / n;
+        continue;
+      }
+      const int c = j / ratio, jr = j - c * ratio;
+      for (int rho = 0; rho < r; ++rho) {
+        double beta = 0.0;  // npj int_{I_j} L_i(n s - j) L_rho(npj s - c) ds, s = (j + xi) / n
+        for (int g = 0; g < ng; ++g) beta += wg[g] * legendre01(i, xg[g]) * legendre01(rho, (jr + xg[g]) / ratio);
+        beta *= (double)npj / n;
+        for (int jj = 0; jj < ratio; ++jj) {
+          const int jt = c * ratio + jj;  // own sub-interval inside I_c
+          for (int m = 0; m <= q; ++m) {
+            // int_{I_jt} L_rho(npj s - c) l_m(n s - jt) ds, s = (jt + xi) / n, npj s - c = (jj + xi) / ratio
+            double v = 0.0;
+            for (int g = 0; g < ng; ++g) v += wg[g] * legendre01(rho, (jj + xg[g]) / ratio) * ilegendre01(m, xg[g]);
+            row[local_trial_level(q, n, jt, m)] += beta * v / n;
+          }
+        }
+      }
+    }
+  return off;
+}
+
 }  // namespace stdg

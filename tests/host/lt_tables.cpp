@@ -1,6 +1,6 @@
 // Prints the library's local-time tables (own D and N, and the S_h coupling)
 // for the (q, n, q', n') given on the command line, one table per line:
-//   D <q> <n> v...   N <q> <n> v...   C <q> <n> <q'> <n'> v...
+//   D <q> <n> v...   N <q> <n> v...   C <q> <n> <q'> <n'> v...   P <q> <n> <r> <n_p> v...
 // (row-major, n q rows).  Host code only; no device.
 #include <cstdio>
 #include <cstdlib>
@@ -30,6 +30,13 @@ int main(int argc, char** argv) {
   for (int i = 0; i < rows * cols; ++i) std::printf(" %.17g", bank[n_off + i]);
   std::printf("\nC %d %d %d %d", q, n, qk, nk);
   for (int i = 0; i < rows * ccols; ++i) std::printf(" %.17g", bank[c_off + i]);
+  std::printf("\n");
+  // D_h's own part: the own trial against the test function projected onto
+  // the common space of (q, n) and (q', n')
+  const int r = q < qk ? q : qk, npj = n < nk ? n : nk;
+  const int p_off = stdg::local_projected_table(q, n, r, npj, &bank);
+  std::printf("P %d %d %d %d", q, n, r, npj);
+  for (int i = 0; i < rows * cols; ++i) std::printf(" %.17g", bank[p_off + i]);
   std::printf("\n");
   return 0;
 }

@@ -16,7 +16,8 @@ solves in FP64 and FP32 inner precision, the load per sub-interval with a
 source-driven solve, dual norms and an inexact march within eta_it, a
 serving request bitwise the plain march, the full-size 32^3 4/2/1 workload
 on sampled elements, a march of the manufactured exp solution with the
-nodal order 2 q; refusals of what the path does not take."""
+nodal order 2 q, D_h in every mode and precision with a slab solve;
+refusals of what the path does not take."""
 import numpy as np
 import pytest
 
@@ -349,10 +350,50 @@ def test_temporal_order_march(lib):
     assert abs(rate - 2 * q) < 0.3, (errs, rate)
 
 
+@pytest.mark.parametrize("shear", [False, True])
+def test_dissipation(lib, shear):
+    # D_h with local time steps: the test function projected onto each face
+    # pair's common temporal test space (own and neighbour trial), in every
+    # mode and precision, and a slab solve with the oracle's energy drop
+    from oracle.dg import Discretisation
+    stdg = lib.stdg
+    mesh = _mesh((2, 2, 2), p=2, q=2, nsub=(1, 2, 4), seed=422 + shear, mixed=True, shear=shear)
+    c = 0.7
+    d = Discretisation(mesh.vertices, mesh.hexes, mesh.p, mesh.q, mesh.eps, mesh.mu, c_diss=c, nk=mesh.nsub)
+    rng = np.random.default_rng(422)
+    x = rng.standard_normal(d.unk_off[-1])
+    U = rng.standard_normal(d.trial_off[-1])
+    L = rng.standard_normal(d.unk_off[-1])
+    dt = 0.05
+    mh = lib.upload(mesh)
+    try:
+        stdg.stdg_mesh_set_dissipation(mh, c)
+        for prec in (0, 1):
+            cast = (lambda v: v) if prec == 0 else (lambda v: v.astype(np.float32).astype(np.float64))
+            xs, Us, Ls = cast(x), cast(U), cast(L)
+            note("local time D_h shear=%d prec=%d" % (shear, prec))
+            assert rel_err(lib.apply(mh, dt, prec, stdg.STDG_OPERATOR, xs), d.operator(xs, dt)) < TOL[prec]
+            assert rel_err(lib.apply(mh, dt, prec, stdg.STDG_RESIDUAL, Us, Ls), d.residual(Us, dt, Ls)) < TOL[prec]
+            assert rel_err(lib.apply(mh, dt, prec, stdg.STDG_OPERATOR_PRECOND, xs),
+                           d.operator(d.precond_solve(xs), dt)) < TOL[prec]
+        s0 = rng.standard_normal(d.state_off[-1])
+        ref = d.level_state(d.solve_direct(s0, dt), 1)
+        st = lib.dev(s0, lib.torch.float64)
+        note("local time D_h shear=%d: solve" % shear)
+        r = stdg.stdg_slab_solve(mh, 0.0, dt, None, st, inner_prec=1, rtol=1e-13, max_iters=800, max_refine=80,
+                                 krylov_prec=1)
+        assert r["status"] == 0, r
+        assert rel_err(st.cpu().numpy(), ref) < 1e-10
+        assert d.energy(ref) < d.energy(s0)
+    finally:
+        stdg.stdg_mesh_free(mh)
+
+
 def test_refusals(lib):
     stdg = lib.stdg
-    mesh = _mesh(p=1, q=1, nsub=(1, 2), seed=415)
-    mh = lib.upload(mesh)
+    # D_h with local time steps at p = 5, q = 5 (beyond the kernel's registers)
+    big = _mesh((2, 1, 1), p=5, q=5, nsub=(2,), seed=415)
+    mh = lib.upload(big)
     try:
         with pytest.raises(stdg.StdgError) as ei:
             stdg.stdg_mesh_set_dissipation(mh, 1.0)

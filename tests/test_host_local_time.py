@@ -2,7 +2,8 @@
 Section 4.1, eq. bilinearform:S), built on the host from closed forms and
 Gauss rules (tables.cpp), against the oracle's tables, which integrate the
 projected sub-interval test functions against the flattened trial functions
-by composite quadrature.  A g++ build of tables.cpp with a small harness
+by composite quadrature; and D_h's own part (the own trial against the
+projected test function).  A g++ build of tables.cpp with a small harness
 (tests/host/lt_tables.cpp); no device code, no GPU."""
 import os
 import shutil
@@ -39,7 +40,8 @@ def _tables(exe, q, n, qk, nk):
     D = np.array(lines[0].split()[3:], float).reshape(n * q, 1 + n * q)
     N = np.array(lines[1].split()[3:], float).reshape(n * q, 1 + n * q)
     C = np.array(lines[2].split()[5:], float).reshape(n * q, 1 + nk * qk)
-    return D, N, C
+    Pt = np.array(lines[3].split()[5:], float).reshape(n * q, 1 + n * q)
+    return D, N, C, Pt
 
 
 @pytest.mark.parametrize("q,n", [(1, 1), (1, 2), (2, 4), (3, 8), (6, 4), (4, 2)])
@@ -48,8 +50,10 @@ def test_tables_match_the_oracle(harness, q, n):
         for nk in (1, 2, 4, 8):
             if nk * qk > 24:
                 continue
-            D, N, C = _tables(harness, q, n, qk, nk)
+            D, N, C, Pt = _tables(harness, q, n, qk, nk)
             assert np.abs(D - basis.subinterval_time_table(q, n, q, n, deriv=True)).max() < 1e-13
             assert np.abs(N - basis.subinterval_time_table(q, n, q, n)).max() < 1e-13
             Co = basis.subinterval_time_table(q, n, qk, nk, proj=(min(q, qk), min(n, nk)))
             assert np.abs(C - Co).max() < 1e-13, (q, n, qk, nk)
+            Po = basis.subinterval_time_table(q, n, q, n, proj=(min(q, qk), min(n, nk)))
+            assert np.abs(Pt - Po).max() < 1e-13, (q, n, qk, nk)
